@@ -1,0 +1,238 @@
+/*
+ * frmi.h -- C ABI of the MI355X (gfx950) implementation of fast-resolve's
+ * interferometric response operator (Roth et al., arXiv 2406.09144).
+ *
+ * The operators follow the paper's statement of the problem:
+ *   - R, the measurement equation of Sec. 2 (Eq. 1) with scalar gains G = 1:
+ *       V_k = sum_ij I_ij a_ij exp(-2 pi i [u_k l_i + v_k m_j + w_k (n_ij - 1)]),
+ *     l_i = (i - nx/2) dx, m_j = (j - ny/2) dy, n_ij = sqrt(1 - l_i^2 - m_j^2),
+ *     a_ij = 1/n_ij with FR_DIVIDE_BY_N, else 1; (u, v, w) = uvw * nu / c.
+ *   - R^+, its adjoint in the real inner product <p, q> = Re sum conj(p) q
+ *     (the sky is real, Sec. 3.1.1), giving the dirty image R^+ N^-1 V (Sec. 3.2).
+ *   - N^-1 = diag(weight) (Sec. 3.1.2).
+ *   - R' = R^+ N^-1 R and its PSF-convolution approximation (Sec. 3.3.2), and the
+ *     noise-kernel approximation of N'^-1 (Sec. 3.3.3).
+ *
+ * Conventions for every call:
+ *   - Arrays are C-contiguous.  Complex numbers are interleaved (re, im).
+ *   - Precision is a property of the plan (FR_FP64 -> double / complex128,
+ *     otherwise float / complex64) and every float buffer of a call on that plan
+ *     uses it.  uvw and frequencies are always double.
+ *   - "device" pointers must point to memory on the plan's device; "host"
+ *     pointers to ordinary host memory.
+ *   - An image stack is [B][n_chan][nx][ny]; channels are independent (the
+ *     operators are block-diagonal over channels).  Visibilities are
+ *     [n_row][n_chan].
+ *   - stream is a hipStream_t (NULL = the null stream).  Operator calls are
+ *     asynchronous: they return after enqueueing; outputs are valid once the
+ *     stream reaches that point.  Plan and PSF objects are read-only after
+ *     creation and may be used from several streams at once; per-call scratch
+ *     comes from the device's stream-ordered pool and is never shared.
+ *   - The caller owns every input/output buffer and the stream; the library
+ *     owns ctx, plan and psf objects until the matching *_destroy.
+ *   - Errors are returned as status codes (never exceptions, never abort);
+ *     fr_last_error() gives a thread-local message for the last non-OK status.
+ *     Invalid arguments return FR_EINVAL before anything is enqueued.
+ *     Asynchronous device faults surface at a later call or synchronisation.
+ */
+#ifndef FRMI_H
+#define FRMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fr_ctx fr_ctx;   /* one device */
+typedef struct fr_plan fr_plan; /* uvw/frequencies bucketed on the grid, kernel parameters */
+typedef struct fr_psf fr_psf;   /* response kernel K_R and noise kernel K_N per channel */
+
+enum fr_status {
+    FR_OK = 0,
+    FR_EINVAL = -1,       /* bad argument, shape or flag */
+    FR_ENOMEM = -2,       /* device allocation failed */
+    FR_EHIP = -3,         /* a HIP runtime call or kernel launch failed */
+    FR_EUNSUPPORTED = -4, /* valid request the library does not implement */
+    FR_EBUSY = -5
+};
+
+enum fr_plan_flags {
+    FR_FP64 = 1,        /* double precision buffers and arithmetic */
+    FR_DIVIDE_BY_N = 2, /* include the 1/n factor of the w-term C(l, w) (Sec. 2) */
+    FR_COPLANAR = 4     /* treat every w as 0 (the paper's coplanar case, Sec. 3.3.2) */
+};
+
+enum fr_lik_mode { FR_LIK_EXACT = 0, FR_LIK_FAST = 1 };
+
+enum fr_op {
+    FR_OP_DEGRID = 0,
+    FR_OP_GRID = 1,
+    FR_OP_RNR_APPROX = 2,
+    FR_OP_RNR_EXACT = 3,
+    FR_OP_LIK_EXACT = 4,
+    FR_OP_LIK_FAST = 5,
+    FR_OP_CG = 6,
+    FR_OP_MAKE_PSF = 7
+};
+
+/* Gridder parameters chosen by fr_plan_create (read-only). */
+typedef struct fr_plan_info {
+    int64_t nx, ny;         /* image */
+    int64_t nu, nv;         /* oversampled uv grid */
+    int64_t n_row, n_chan;
+    int precision;          /* 32 or 64 */
+    int support;            /* W: kernel width in uv cells */
+    double beta;            /* ES kernel shape, phi(z) = exp(beta (sqrt(1 - z^2) - 1)) */
+    int coplanar;           /* 1: single plane, no w kernel */
+    int n_planes;           /* w-planes per channel */
+    int w_support;          /* kernel width along w (planes) */
+    double w_beta;
+    double w0, dw;          /* plane p sits at w0 + p dw (wavelengths) */
+    double eps_bound;       /* a-priori bound on the gridding error used to pick W */
+    int tile;               /* uv tile side in cells */
+    int64_t n_workitems;
+    size_t resident_bytes;  /* device memory the plan holds */
+} fr_plan_info;
+
+/* Library version string. */
+const char *fr_version(void);
+
+/* Thread-local message of the last non-OK status (empty string if none). */
+const char *fr_last_error(void);
+
+/* Bind device `device` (hipSetDevice numbering).  Returns FR_EINVAL for a bad
+ * index, FR_EHIP if the device cannot be used. */
+int fr_ctx_create(int device, fr_ctx **out);
+void fr_ctx_destroy(fr_ctx *ctx);
+
+/*
+ * Plan: bucket every (row, channel) visibility onto the oversampled grid.
+ *   uvw_m    host [n_row][3] double, metres
+ *   freq_hz  host [n_chan] double, Hz (> 0)
+ *   nx, ny   image size, powers of two in [16, 8192]
+ *   dx, dy   pixel sizes (radians, > 0); the field must satisfy l^2 + m^2 < 1
+ *   epsilon  requested relative L2 accuracy of R and R^+ against the direct
+ *            sums, in [1e-14, 1e-1]; FP32 plans accept epsilon >= 1e-6
+ *   flags    FR_FP64 | FR_DIVIDE_BY_N | FR_COPLANAR
+ *   n_wplanes 0 = derive from epsilon; otherwise the number of w-planes to use
+ *            (must be >= the derived minimum)
+ * The method itself is exact (Sec. 2); the gridder reaches it up to epsilon with
+ * an exponential-of-semicircle kernel, 2x oversampling and improved w-stacking
+ * (the kernel also runs along w).  Enqueues on the null stream and synchronises.
+ * Errors: FR_EINVAL (shapes, ranges, flags), FR_ENOMEM, FR_EHIP.
+ */
+int fr_plan_create(fr_ctx *ctx, const double *uvw_m, int64_t n_row, const double *freq_hz,
+                   int64_t n_chan, int64_t nx, int64_t ny, double dx, double dy, double epsilon,
+                   int flags, int n_wplanes, fr_plan **out);
+void fr_plan_destroy(fr_plan *plan);
+int fr_plan_get_info(const fr_plan *plan, fr_plan_info *info);
+
+/* R (Sec. 2, Eq. 1): img device [n_chan][nx][ny] real -> vis device [n_row][n_chan]
+ * complex.  Overwrites vis. */
+int fr_degrid(fr_plan *plan, const void *img, void *vis, void *stream);
+
+/* R^+ N^-1 (Sec. 3.2): vis device [n_row][n_chan] complex, weight device
+ * [n_row][n_chan] real or NULL (= 1) -> img device [n_chan][nx][ny] real, the dirty
+ * image when vis are the data.  Overwrites img. */
+int fr_grid(fr_plan *plan, const void *vis, const void *weight, void *img, void *stream);
+
+/*
+ * Response and noise kernels (Sec. 3.3.2, Sec. 3.3.3), per channel:
+ *   PSF0 = R0^+ N^-1 R0 delta on the doubled 2nx x 2ny grid (R0 = R with w := 0 and
+ *          no 1/n), computed by gridding the weights; its offset -nx row and -ny
+ *          column are set to zero so that it is periodically even;
+ *   K_R  = Re rfft2(ifftshift(PSF0))                  -> [2nx][ny + 1]
+ *   K_N  = eps + max(Re fft2(ifftshift(crop(PSF0))), 0) -> [nx][ny/2 + 1]
+ *          where crop keeps offsets [-n/2, n/2): the closed-form minimiser of the
+ *          noise-kernel fit of Sec. 3.3.3.
+ *   weight   device [n_row][n_chan] real or NULL (= 1)
+ *   eps_noise > 0: the regulariser eps of Sec. 3.3.1 (N' = R^+ N^-1 R + eps 1);
+ *             < 0: -eps_noise times the PSF peak (sum of weights) of each channel.
+ * The PSF object records the plan's 1/n factors (applied on both sides of the
+ * convolution when the plan has FR_DIVIDE_BY_N).  Synchronises `stream`.
+ */
+int fr_make_psf_kernel(fr_plan *plan, const void *weight, double eps_noise, fr_psf **out,
+                       void *stream);
+
+/* Build a PSF object from caller-supplied kernels (e.g. precomputed elsewhere).
+ *   K_R   device [n_chan][2nx][ny + 1] real (required)
+ *   K_N   device [n_chan][nx][ny/2 + 1] real, entries > 0, or NULL (FAST
+ *         likelihood then unavailable)
+ *   nfac  device [nx][ny] real diagonal D applied on both sides, or NULL (= 1)
+ *   flags FR_FP64 or 0 (precision of all three arrays)
+ * Copies the arrays; synchronises `stream`. */
+int fr_psf_create(fr_ctx *ctx, int64_t nx, int64_t ny, int64_t n_chan, const void *K_R,
+                  const void *K_N, const void *nfac, int flags, fr_psf **out, void *stream);
+
+/* Copy the kernels out (either pointer may be NULL), same layouts as above. */
+int fr_psf_get_kernels(const fr_psf *psf, void *K_R, void *K_N, void *stream);
+void fr_psf_destroy(fr_psf *psf);
+
+/* R' x ~ D P^+ FFT^-1[K_R FFT[P D x]] (Sec. 3.3.2): zero-padded linear convolution
+ * with the doubled-grid PSF.  x, y device [B][n_chan][nx][ny] real, y != x. */
+int fr_apply_RNR_approx(fr_psf *psf, const void *x, void *y, int64_t B, void *stream);
+
+/* R' x = R^+ N^-1 R x evaluated exactly (major cycle, Sec. 3.3.4).
+ * weight device [n_row][n_chan] or NULL; x, y device [B][n_chan][nx][ny]. */
+int fr_apply_RNR_exact(fr_plan *plan, const void *weight, const void *x, void *y, int64_t B,
+                       void *stream);
+
+/*
+ * Likelihood Hamiltonian and its gradient with respect to the log-sky s, with
+ * I = exp(s) + i_fixed, for a batch of B samples; the constant 1/2 ln|2 pi N|
+ * is dropped.
+ *   FR_LIK_EXACT (eq. ham, Sec. 3.1.2): data = visibilities [n_row][n_chan];
+ *       H = 1/2 sum w |V - R I|^2,  g = exp(s) * R^+ [w (R I - V)]   (plan required)
+ *   FR_LIK_FAST (eq. ham_new, Sec. 3.3.1 with Sec. 3.3.2-3.3.3): data = dirty
+ *       image d [n_chan][nx][ny]; r = d - R' I, q = N'^-1 r,
+ *       H = 1/2 <r, q>,  g = -exp(s) * R' q                        (psf required)
+ *   s, grad  device [B][n_chan][nx][ny];  i_fixed device [n_chan][nx][ny] or NULL
+ *   weight   device [n_row][n_chan] or NULL (EXACT only)
+ *   inv_power device [nx][ny/2 + 1] real 1/P(k) (r2c half of an even spectrum) or
+ *            NULL; adds the prior term 1/2 s^T S^-1 s (S^-1 = F^-1 diag(1/P) F per
+ *            channel) to H and S^-1 s to g
+ *   H        device [B] double (accumulated in double)
+ */
+int fr_likelihood_grad(fr_plan *plan, fr_psf *psf, int mode, const void *s, const void *i_fixed,
+                       const void *data, const void *weight, const void *inv_power, int64_t B,
+                       void *grad, double *H, void *stream);
+
+/*
+ * Conjugate gradients (Hestenes-Stiefel, x0 = 0, no preconditioner) on
+ *   A x = D_s R' D_s x + S^-1 x = b
+ * with R' the PSF convolution of `psf` (or, if psf is NULL, the exact R^+ N^-1 R
+ * of `plan` with `weight`), D_s = diag(diag) (NULL = identity) and
+ * S^-1 = F^-1 diag(inv_power) F (NULL = no prior term).  The metric solve MGVI
+ * uses in the minor cycle (Sec. 3.3.5).
+ *   b, x        device [n_chan][nx][ny] (one system over all channels)
+ *   inv_power   device [nx][ny/2 + 1] or NULL
+ *   diag        device [n_chan][nx][ny] or NULL
+ *   maxiter     >= 0; rtol >= 0 stops once ||r_k|| <= rtol ||b||
+ *   resid_hist  device [maxiter + 1] double: ||r_k||, entries after the last
+ *               iteration are left untouched
+ *   iters_done  device int: iterations performed
+ * Inner products and the alpha/beta recurrences are double precision on the
+ * device; no host synchronisation inside the loop.
+ */
+int fr_cg_solve(fr_plan *plan, fr_psf *psf, const void *weight, const void *inv_power,
+                const void *diag, const void *b, void *x, int maxiter, double rtol,
+                double *resid_hist, int *iters_done, void *stream);
+
+/* Device bytes a call of `op` with batch B needs beyond its inputs and outputs
+ * (per-call scratch), plus the resident plan/psf bytes.  Host-only, no GPU work. */
+int fr_query_footprint(const fr_plan *plan, const fr_psf *psf, int op, int64_t B,
+                       size_t *scratch_bytes, size_t *resident_bytes);
+
+/* Building block exposed for testing: in-place 2D complex FFT of a device array
+ * [batch][n0][n1] (n0, n1 powers of two, 2 <= n <= 16384, FP64 up to 8192),
+ * sign -1 forward, +1 inverse, unnormalised.  fp64 selects complex128. */
+int fr_fft2(fr_ctx *ctx, void *data, int64_t batch, int64_t n0, int64_t n1, int sign, int fp64,
+            void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FRMI_H */

@@ -1,0 +1,289 @@
+// extern "C" entry points of libfrmi: argument validation, precision dispatch,
+// error translation.  All numerical work happens in the kernels of the other
+// translation units.
+#include <cmath>
+#include <cstring>
+
+#include "objects.h"
+
+namespace frmi {
+
+static thread_local std::string g_last_error;
+
+void set_last_error(const std::string &m) { g_last_error = m; }
+
+}  // namespace frmi
+
+using namespace frmi;
+
+#define FR_API_BEGIN try {
+#define FR_API_END                                                 \
+    }                                                              \
+    catch (const frmi::Error &e) {                                 \
+        set_last_error(e.what());                                  \
+        return e.code;                                             \
+    }                                                              \
+    catch (const std::bad_alloc &) {                               \
+        set_last_error("host allocation failed");                  \
+        return FR_ENOMEM;                                          \
+    }                                                              \
+    catch (const std::exception &e) {                              \
+        set_last_error(e.what());                                  \
+        return FR_EHIP;                                            \
+    }                                                              \
+    set_last_error("");                                            \
+    return FR_OK;
+
+static hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+extern "C" {
+
+const char *fr_version(void) { return "frmi 0.1 (gfx950)"; }
+
+const char *fr_last_error(void) { return g_last_error.c_str(); }
+
+int fr_ctx_create(int device, fr_ctx **out) {
+    FR_API_BEGIN
+    FR_REQUIRE(out != nullptr, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    HIP_CHECK(hipGetDeviceCount(&ndev));
+    FR_REQUIRE(device >= 0 && device < ndev, "device index out of range");
+    DeviceGuard dg(device);
+    auto ctx = std::make_unique<fr_ctx>();
+    ctx->c.device = device;
+    HIP_CHECK(hipDeviceGetAttribute(&ctx->c.n_cu, hipDeviceAttributeMultiprocessorCount, device));
+    // twiddle tables exp(-2 pi i m / L), computed in extended precision, rounded once
+    for (int l = 1; l <= kMaxLog2FFT + 1; ++l) {
+        const int64_t L = int64_t(1) << l;
+        std::vector<double> t64(2 * L);
+        std::vector<float> t32(2 * L);
+        for (int64_t m = 0; m < L; ++m) {
+            long double ang = 2.0L * 3.14159265358979323846264338327950288L * (long double)m / (long double)L;
+            double c = (double)cosl(ang), s = (double)-sinl(ang);
+            t64[2 * m] = c;
+            t64[2 * m + 1] = s;
+            t32[2 * m] = (float)c;
+            t32[2 * m + 1] = (float)s;
+        }
+        DevBuf b64(t64.size() * sizeof(double)), b32(t32.size() * sizeof(float));
+        HIP_CHECK(hipMemcpy(b64.p, t64.data(), b64.bytes, hipMemcpyHostToDevice));
+        HIP_CHECK(hipMemcpy(b32.p, t32.data(), b32.bytes, hipMemcpyHostToDevice));
+        ctx->c.tw64[l] = b64.p;
+        ctx->c.tw32[l] = b32.p;
+        ctx->tables.push_back(std::move(b64));
+        ctx->tables.push_back(std::move(b32));
+    }
+    // keep freed scratch cached in the stream-ordered pool
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
+        uint64_t thr = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    *out = ctx.release();
+    FR_API_END
+}
+
+void fr_ctx_destroy(fr_ctx *ctx) {
+    if (!ctx) return;
+    DeviceGuard dg(ctx->c.device);
+    delete ctx;
+}
+
+static size_t real_size(bool fp64) { return fp64 ? 8 : 4; }
+
+int fr_psf_create(fr_ctx *ctx, int64_t nx, int64_t ny, int64_t n_chan, const void *K_R, const void *K_N,
+                  const void *nfac, int flags, fr_psf **out, void *stream) {
+    FR_API_BEGIN
+    FR_REQUIRE(ctx && out && K_R, "ctx, out and K_R are required");
+    *out = nullptr;
+    FR_REQUIRE(is_pow2(nx) && is_pow2(ny) && nx >= 16 && ny >= 16 && nx <= 8192 && ny <= 8192,
+               "nx, ny must be powers of two in [16, 8192]");
+    FR_REQUIRE(n_chan >= 1, "n_chan must be >= 1");
+    FR_REQUIRE((flags & ~FR_FP64) == 0, "only FR_FP64 is a valid flag here");
+    const bool fp64 = flags & FR_FP64;
+    FR_REQUIRE(!fp64 || nx <= 4096, "FP64 PSF convolution supports nx <= 4096");
+    DeviceGuard dg(ctx->c.device);
+    hipStream_t st = as_stream(stream);
+    auto p = std::make_unique<fr_psf>();
+    p->ctx = &ctx->c;
+    p->nx = nx;
+    p->ny = ny;
+    p->n_chan = n_chan;
+    p->fp64 = fp64;
+    const size_t rs = real_size(fp64);
+    p->KR = DevBuf((size_t)n_chan * 2 * nx * (ny + 1) * rs);
+    HIP_CHECK(hipMemcpyAsync(p->KR.p, K_R, p->KR.bytes, hipMemcpyDefault, st));
+    if (K_N) {
+        p->KN = DevBuf((size_t)n_chan * nx * (ny / 2 + 1) * rs);
+        HIP_CHECK(hipMemcpyAsync(p->KN.p, K_N, p->KN.bytes, hipMemcpyDefault, st));
+    }
+    if (nfac) {
+        p->nfac = DevBuf((size_t)nx * ny * rs);
+        HIP_CHECK(hipMemcpyAsync(p->nfac.p, nfac, p->nfac.bytes, hipMemcpyDefault, st));
+    }
+    HIP_CHECK(hipStreamSynchronize(st));
+    *out = p.release();
+    FR_API_END
+}
+
+int fr_psf_get_kernels(const fr_psf *psf, void *K_R, void *K_N, void *stream) {
+    FR_API_BEGIN
+    FR_REQUIRE(psf, "psf is NULL");
+    DeviceGuard dg(psf->ctx->device);
+    hipStream_t st = as_stream(stream);
+    if (K_R) HIP_CHECK(hipMemcpyAsync(K_R, psf->KR.p, psf->KR.bytes, hipMemcpyDefault, st));
+    if (K_N) {
+        FR_REQUIRE(psf->KN.p, "this PSF object has no noise kernel");
+        HIP_CHECK(hipMemcpyAsync(K_N, psf->KN.p, psf->KN.bytes, hipMemcpyDefault, st));
+    }
+    FR_API_END
+}
+
+void fr_psf_destroy(fr_psf *psf) {
+    if (!psf) return;
+    DeviceGuard dg(psf->ctx->device);
+    delete psf;
+}
+
+int fr_apply_RNR_approx(fr_psf *psf, const void *x, void *y, int64_t B, void *stream) {
+    FR_API_BEGIN
+    FR_REQUIRE(psf, "psf is NULL");
+    FR_REQUIRE(B >= 0, "B must be >= 0");
+    if (B == 0) return FR_OK;
+    FR_REQUIRE(x && y, "x and y are required");
+    FR_REQUIRE(x != y, "y must not alias x");
+    DeviceGuard dg(psf->ctx->device);
+    if (psf->fp64)
+        apply_rnr_approx<double>(psf, (const double *)x, (double *)y, B, as_stream(stream));
+    else
+        apply_rnr_approx<float>(psf, (const float *)x, (float *)y, B, as_stream(stream));
+    FR_API_END
+}
+
+int fr_fft2(fr_ctx *ctx, void *data, int64_t batch, int64_t n0, int64_t n1, int sign, int fp64, void *stream) {
+    FR_API_BEGIN
+    FR_REQUIRE(ctx && data, "ctx and data are required");
+    FR_REQUIRE(batch >= 0, "batch must be >= 0");
+    FR_REQUIRE(is_pow2(n0) && is_pow2(n1) && n0 >= 2 && n1 >= 2 && n0 <= 16384 && n1 <= 16384,
+               "sizes must be powers of two in [2, 16384]");
+    FR_REQUIRE(!fp64 || (n0 <= 8192 && n1 <= 8192), "FP64 sizes are limited to 8192");
+    FR_REQUIRE(sign == -1 || sign == 1, "sign must be -1 or +1");
+    DeviceGuard dg(ctx->c.device);
+    if (batch == 0) return FR_OK;
+    if (fp64)
+        fft2_inplace<double>(ctx->c, (double2 *)data, batch, n0, n1, sign, as_stream(stream));
+    else
+        fft2_inplace<float>(ctx->c, (float2 *)data, batch, n0, n1, sign, as_stream(stream));
+    FR_API_END
+}
+
+int fr_plan_create(fr_ctx *ctx, const double *uvw_m, int64_t n_row, const double *freq_hz, int64_t n_chan,
+                   int64_t nx, int64_t ny, double dx, double dy, double epsilon, int flags, int n_wplanes,
+                   fr_plan **out) {
+    FR_API_BEGIN
+    FR_REQUIRE(ctx && out, "ctx and out are required");
+    *out = nullptr;
+    FR_REQUIRE(n_row >= 0 && n_chan >= 1, "n_row >= 0 and n_chan >= 1 required");
+    FR_REQUIRE(n_row == 0 || uvw_m, "uvw_m is NULL");
+    FR_REQUIRE(freq_hz, "freq_hz is NULL");
+    FR_REQUIRE(is_pow2(nx) && is_pow2(ny) && nx >= 16 && ny >= 16 && nx <= 8192 && ny <= 8192,
+               "nx, ny must be powers of two in [16, 8192]");
+    FR_REQUIRE((flags & ~(FR_FP64 | FR_DIVIDE_BY_N | FR_COPLANAR)) == 0, "unknown flag");
+    const bool fp64 = flags & FR_FP64;
+    FR_REQUIRE(!fp64 || (nx <= 4096 && ny <= 4096), "FP64 plans support nx, ny <= 4096");
+    FR_REQUIRE(dx > 0 && dy > 0 && std::isfinite(dx) && std::isfinite(dy), "pixel sizes must be > 0");
+    const double lm = (nx / 2) * dx, mm = (ny / 2) * dy;
+    FR_REQUIRE(lm * lm + mm * mm < 1.0, "field of view must satisfy l^2 + m^2 < 1");
+    FR_REQUIRE(epsilon >= 1e-14 && epsilon <= 1e-1, "epsilon must lie in [1e-14, 1e-1]");
+    FR_REQUIRE(fp64 || epsilon >= 1e-6, "FP32 plans need epsilon >= 1e-6");
+    FR_REQUIRE(n_wplanes >= 0, "n_wplanes must be >= 0");
+    FR_REQUIRE(n_row * n_chan < (int64_t(1) << 31), "at most 2^31 - 1 visibilities per plan");
+    for (int64_t c = 0; c < n_chan; ++c)
+        FR_REQUIRE(freq_hz[c] > 0 && std::isfinite(freq_hz[c]), "frequencies must be > 0");
+    for (int64_t r = 0; r < n_row; ++r)
+        FR_REQUIRE(std::isfinite(uvw_m[3 * r]) && std::isfinite(uvw_m[3 * r + 1]) && std::isfinite(uvw_m[3 * r + 2]),
+                   "uvw must be finite");
+    DeviceGuard dg(ctx->c.device);
+    auto pl = std::make_unique<fr_plan>();
+    pl->ctx = &ctx->c;
+    pl->nx = nx;
+    pl->ny = ny;
+    pl->nu = 2 * nx;
+    pl->nv = 2 * ny;
+    pl->n_row = n_row;
+    pl->n_chan = n_chan;
+    pl->n_vis = n_row * n_chan;
+    pl->fp64 = fp64;
+    pl->divide_by_n = flags & FR_DIVIDE_BY_N;
+    pl->coplanar = flags & FR_COPLANAR;
+    pl->eps = epsilon;
+    pl->dx_ = dx;
+    pl->dy_ = dy;
+    pl->n_wplanes_req = n_wplanes;
+    pl->tile = 32;
+    pl->freq.assign(freq_hz, freq_hz + n_chan);
+    plan_build(pl.get(), uvw_m, freq_hz);
+    *out = pl.release();
+    FR_API_END
+}
+
+void fr_plan_destroy(fr_plan *plan) {
+    if (!plan) return;
+    DeviceGuard dg(plan->ctx->device);
+    delete plan;
+}
+
+int fr_plan_get_info(const fr_plan *pl, fr_plan_info *info) {
+    FR_API_BEGIN
+    FR_REQUIRE(pl && info, "plan and info are required");
+    std::memset(info, 0, sizeof(*info));
+    info->nx = pl->nx;
+    info->ny = pl->ny;
+    info->nu = pl->nu;
+    info->nv = pl->nv;
+    info->n_row = pl->n_row;
+    info->n_chan = pl->n_chan;
+    info->precision = pl->fp64 ? 64 : 32;
+    info->support = pl->W;
+    info->beta = pl->beta;
+    info->coplanar = pl->coplanar ? 1 : 0;
+    info->n_planes = pl->n_planes;
+    info->w_support = pl->Ww;
+    info->w_beta = pl->wbeta;
+    info->w0 = pl->w0;
+    info->dw = pl->dw;
+    info->eps_bound = pl->eps_bound;
+    info->tile = pl->tile;
+    info->n_workitems = pl->n_wi;
+    info->resident_bytes = pl->resident;
+    FR_API_END
+}
+
+int fr_degrid(fr_plan *pl, const void *img, void *vis, void *stream) {
+    FR_API_BEGIN
+    FR_REQUIRE(pl, "plan is NULL");
+    if (pl->n_vis == 0) return FR_OK;
+    FR_REQUIRE(img && vis, "img and vis are required");
+    DeviceGuard dg(pl->ctx->device);
+    if (pl->fp64)
+        degrid<double>(pl, (const double *)img, (double2 *)vis, as_stream(stream));
+    else
+        degrid<float>(pl, (const float *)img, (float2 *)vis, as_stream(stream));
+    FR_API_END
+}
+
+int fr_grid(fr_plan *pl, const void *vis, const void *weight, void *img, void *stream) {
+    FR_API_BEGIN
+    FR_REQUIRE(pl, "plan is NULL");
+    FR_REQUIRE(img, "img is required");
+    FR_REQUIRE(pl->n_vis == 0 || vis, "vis is required");
+    DeviceGuard dg(pl->ctx->device);
+    if (pl->fp64)
+        grid<double>(pl, (const double2 *)vis, (const double *)weight, (double *)img, as_stream(stream));
+    else
+        grid<float>(pl, (const float2 *)vis, (const float *)weight, (float *)img, as_stream(stream));
+    FR_API_END
+}
+
+}  // extern "C"

@@ -1,0 +1,146 @@
+// Internal definitions shared by the HIP translation units of libfrmi.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "../../include/frmi.h"
+
+namespace frmi {
+
+// ----------------------------------------------------------------- errors
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+void set_last_error(const std::string &m);
+
+#define FR_REQUIRE(cond, msg)                                                        \
+    do {                                                                             \
+        if (!(cond)) throw ::frmi::Error(FR_EINVAL, std::string(__func__) + ": " + (msg)); \
+    } while (0)
+
+#define HIP_CHECK(expr)                                                              \
+    do {                                                                             \
+        hipError_t e_ = (expr);                                                      \
+        if (e_ != hipSuccess) {                                                      \
+            int code_ = (e_ == hipErrorOutOfMemory) ? FR_ENOMEM : FR_EHIP;          \
+            throw ::frmi::Error(code_, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+        }                                                                            \
+    } while (0)
+
+#define LAUNCH_CHECK() HIP_CHECK(hipGetLastError())
+
+// ----------------------------------------------------------------- complex
+template <typename T> struct C2T;
+template <> struct C2T<float> { using type = float2; };
+template <> struct C2T<double> { using type = double2; };
+template <typename T> using c2 = typename C2T<T>::type;
+
+template <typename T> __host__ __device__ __forceinline__ c2<T> mk(T x, T y) {
+    c2<T> r;
+    r.x = x;
+    r.y = y;
+    return r;
+}
+template <typename T> __device__ __forceinline__ c2<T> cadd(c2<T> a, c2<T> b) { return mk<T>(a.x + b.x, a.y + b.y); }
+template <typename T> __device__ __forceinline__ c2<T> csub(c2<T> a, c2<T> b) { return mk<T>(a.x - b.x, a.y - b.y); }
+template <typename T> __device__ __forceinline__ c2<T> cmul(c2<T> a, c2<T> b) {
+    return mk<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename T> __device__ __forceinline__ c2<T> cconj(c2<T> a) { return mk<T>(a.x, -a.y); }
+template <typename T> __device__ __forceinline__ c2<T> cscale(c2<T> a, T s) { return mk<T>(a.x * s, a.y * s); }
+
+// sin/cos of 2 pi x for x in cycles (x reduced by the caller to about [-1, 1]).
+__device__ __forceinline__ void sincos_cycles(float x, float *s, float *c) { sincospif(2.0f * x, s, c); }
+__device__ __forceinline__ void sincos_cycles(double x, double *s, double *c) { sincospi(2.0 * x, s, c); }
+
+// ----------------------------------------------------------------- context
+constexpr int kMaxLog2FFT = 14;  // FFT lengths 2 .. 16384
+
+struct Ctx {
+    int device = 0;
+    int n_cu = 0;
+    // twiddle tables tw[m] = exp(-2 pi i m / L), m < L, per log2 L, per precision
+    void *tw32[kMaxLog2FFT + 2] = {};
+    void *tw64[kMaxLog2FFT + 2] = {};
+    template <typename T> const c2<T> *tw(int log2L) const;
+};
+template <> inline const float2 *Ctx::tw<float>(int l) const { return (const float2 *)tw32[l]; }
+template <> inline const double2 *Ctx::tw<double>(int l) const { return (const double2 *)tw64[l]; }
+
+inline int ilog2(int64_t n) {
+    int l = 0;
+    while ((int64_t(1) << l) < n) ++l;
+    return l;
+}
+inline bool is_pow2(int64_t n) { return n > 0 && (n & (n - 1)) == 0; }
+
+// Stream-ordered scratch from the device's default pool; freed on the same stream.
+struct Scratch {
+    void *p = nullptr;
+    hipStream_t s = nullptr;
+    Scratch() = default;
+    Scratch(size_t bytes, hipStream_t st) : s(st) {
+        if (bytes) HIP_CHECK(hipMallocAsync(&p, bytes, st));
+    }
+    Scratch(const Scratch &) = delete;
+    Scratch &operator=(const Scratch &) = delete;
+    Scratch(Scratch &&o) noexcept : p(o.p), s(o.s) { o.p = nullptr; }
+    ~Scratch() {
+        if (p) (void)hipFreeAsync(p, s);
+    }
+    template <typename U> U *as() const { return (U *)p; }
+};
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        (void)hipGetDevice(&prev);
+        if (prev != dev) HIP_CHECK(hipSetDevice(dev));
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        (void)hipGetDevice(&cur);
+        if (prev >= 0 && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+// owning device buffer
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    explicit DevBuf(size_t n) : bytes(n) {
+        if (n) HIP_CHECK(hipMalloc(&p, n));
+    }
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        if (this != &o) {
+            if (p) (void)hipFree(p);
+            p = o.p;
+            bytes = o.bytes;
+            o.p = nullptr;
+            o.bytes = 0;
+        }
+        return *this;
+    }
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+    template <typename U> U *as() const { return (U *)p; }
+};
+
+}  // namespace frmi

@@ -1,0 +1,281 @@
+// FFT convolutions with real, even kernels on real images (PSF convolution of
+// Sec. 3.3.2 on the zero-padded doubled grid, periodic noise and prior
+// convolutions of Sec. 3.3.3), as three LDS-resident passes:
+//
+//   1. rows:    real rows of length 2M (only the first n_in values non-zero) ->
+//               packed half-spectrum rows of M complex values (half-length trick;
+//               the real DC and Nyquist values share slot 0);
+//   2. columns: strips of C packed columns; forward FFT of length Lc (input rows
+//               beyond n_in are zero), multiply (or divide) by the kernel column,
+//               inverse FFT, keep the first n_out rows;
+//   3. rows:    inverse of pass 1, keep the first n_out_cols real outputs.
+//
+// The kernel K is real with Hermitian symmetry K[-k] = K[k]; slot 0 of a packed
+// row carries two independent real columns (DC and Nyquist), which the column
+// pass separates with the usual even/odd split before multiplying each by its
+// own kernel column.  Overall scaling 1/(Lc M) makes the pipeline equal to
+// irfft2(K rfft2(x)) with numpy's normalisation.
+//
+// Prologue/epilogue functors let callers fuse elementwise work (1/n factors,
+// exp(s), residuals, gradient products) into the first and last pass.
+#pragma once
+
+#include "fft.h"
+
+namespace frmi {
+
+// ------------------------------------------------------------------ pass 1
+template <typename T, int NTHR, int BPT, class Pro>
+__global__ __launch_bounds__(NTHR) void k_rfft_rows(Pro pro, c2<T> *__restrict__ Y, int64_t nrows,
+                                                     int log2M, int n_in, int lines_per_wg,
+                                                     const c2<T> *__restrict__ tw,
+                                                     const c2<T> *__restrict__ tw2) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    c2<T> *buf = reinterpret_cast<c2<T> *>(smem_raw);
+    const int M = 1 << log2M;
+    const int64_t row0 = (int64_t)blockIdx.x * lines_per_wg;
+    const int nl = (int)min<int64_t>(lines_per_wg, nrows - row0);
+    for (int idx = threadIdx.x; idx < (nl << log2M); idx += NTHR) {
+        const int c = idx >> log2M, e = idx & (M - 1);
+        c2<T> z = mk<T>(T(0), T(0));
+        if (2 * e < n_in) {
+            z.x = pro(row0 + c, 2 * e);
+            z.y = pro(row0 + c, 2 * e + 1);
+        }
+        buf[idx] = z;
+    }
+    __syncthreads();
+    lds_fft<T, NTHR, BPT>(buf, M, nl, log2M, -1, tw);
+    const int half = M / 2 + 1;
+    for (int idx = threadIdx.x; idx < nl * half; idx += NTHR) {
+        const int c = idx / half, k = idx - c * half;
+        c2<T> *line = buf + c * M;
+        if (k == 0) {
+            c2<T> z = line[0];
+            line[0] = mk<T>(z.x + z.y, z.x - z.y);
+        } else {
+            const int km = M - k;
+            c2<T> a = line[k], b = line[km];
+            c2<T> E = mk<T>((a.x + b.x) * T(0.5), (a.y - b.y) * T(0.5));
+            c2<T> O = mk<T>((a.y + b.y) * T(0.5), (b.x - a.x) * T(0.5));
+            line[k] = cadd<T>(E, cmul<T>(tw2[k], O));
+            if (km != k) line[km] = cadd<T>(cconj<T>(E), cmul<T>(tw2[km], cconj<T>(O)));
+        }
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < (nl << log2M); idx += NTHR) Y[(row0 << log2M) + idx] = buf[idx];
+}
+
+// ------------------------------------------------------------------ pass 2
+// K: [nk][Lc][M + 1] real, image g uses kernel g % nk.  mode 0: multiply, 1: divide.
+template <typename T, int NTHR, int BPT>
+__global__ __launch_bounds__(NTHR) void k_conv_cols(c2<T> *__restrict__ Y, int log2M, int log2Lc,
+                                                     int n_in, int n_out, int C,
+                                                     const T *__restrict__ K, int nk, int mode,
+                                                     T scale, const c2<T> *__restrict__ tw) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    c2<T> *buf = reinterpret_cast<c2<T> *>(smem_raw);
+    const int M = 1 << log2M;
+    const int Lc = 1 << log2Lc;
+    const int ld = Lc + 1;
+    const int col0 = blockIdx.x * C;
+    const int64_t g = blockIdx.y;
+    c2<T> *Yg = Y + ((g * n_in) << log2M);  // packed rows of image g (n_in rows stored)
+    const T *Kg = K + (g % nk) * (int64_t)Lc * (M + 1);
+    for (int idx = threadIdx.x; idx < C * Lc; idx += NTHR) {
+        const int r = idx / C, c = idx - r * C;
+        buf[c * ld + r] = (r < n_in) ? Yg[((int64_t)r << log2M) + col0 + c] : mk<T>(T(0), T(0));
+    }
+    __syncthreads();
+    lds_fft<T, NTHR, BPT>(buf, ld, C, log2Lc, -1, tw);
+    for (int idx = threadIdx.x; idx < C * Lc; idx += NTHR) {
+        const int c = idx >> log2Lc, k = idx & (Lc - 1);
+        const int col = col0 + c;
+        if (col == 0) {
+            // slot 0 = DC column + i * Nyquist column: split, scale each, recombine
+            if (k <= Lc / 2) {
+                const int km = (Lc - k) & (Lc - 1);
+                c2<T> a = buf[k], b = buf[km];
+                // A = (F[k] + conj F[-k]) / 2,  Bn = (F[k] - conj F[-k]) / 2i
+                c2<T> A = mk<T>((a.x + b.x) * T(0.5), (a.y - b.y) * T(0.5));
+                c2<T> Bn = mk<T>((a.y + b.y) * T(0.5), (b.x - a.x) * T(0.5));
+                T k0 = Kg[(int64_t)k * (M + 1)], k1 = Kg[(int64_t)k * (M + 1) + M];
+                T k0m = Kg[(int64_t)km * (M + 1)], k1m = Kg[(int64_t)km * (M + 1) + M];
+                if (mode) { k0 = T(1) / k0; k1 = T(1) / k1; k0m = T(1) / k0m; k1m = T(1) / k1m; }
+                k0 *= scale; k1 *= scale; k0m *= scale; k1m *= scale;
+                // F'[k] = A k0 + i Bn k1 ; F'[-k] = conj(A) k0m + i conj(Bn) k1m
+                buf[k] = mk<T>(A.x * k0 - Bn.y * k1, A.y * k0 + Bn.x * k1);
+                if (km != k) buf[km] = mk<T>(A.x * k0m + Bn.y * k1m, -A.y * k0m + Bn.x * k1m);
+            }
+        } else {
+            T kv = Kg[(int64_t)k * (M + 1) + col];
+            kv = (mode ? T(1) / kv : kv) * scale;
+            c2<T> v = buf[c * ld + k];
+            buf[c * ld + k] = mk<T>(v.x * kv, v.y * kv);
+        }
+    }
+    __syncthreads();
+    lds_fft<T, NTHR, BPT>(buf, ld, C, log2Lc, +1, tw);
+    for (int idx = threadIdx.x; idx < C * n_out; idx += NTHR) {
+        const int r = idx / C, c = idx - r * C;
+        Yg[((int64_t)r << log2M) + col0 + c] = buf[c * ld + r];
+    }
+}
+
+// ------------------------------------------------------------------ pass 3
+template <typename T, int NTHR, int BPT, class Epi>
+__global__ __launch_bounds__(NTHR) void k_irfft_rows(Epi epi, const c2<T> *__restrict__ Y, int64_t nrows,
+                                                      int log2M, int n_out_cols, int lines_per_wg,
+                                                      const c2<T> *__restrict__ tw,
+                                                      const c2<T> *__restrict__ tw2) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    c2<T> *buf = reinterpret_cast<c2<T> *>(smem_raw);
+    const int M = 1 << log2M;
+    const int64_t row0 = (int64_t)blockIdx.x * lines_per_wg;
+    const int nl = (int)min<int64_t>(lines_per_wg, nrows - row0);
+    for (int idx = threadIdx.x; idx < (nl << log2M); idx += NTHR) buf[idx] = Y[(row0 << log2M) + idx];
+    __syncthreads();
+    const int half = M / 2 + 1;
+    for (int idx = threadIdx.x; idx < nl * half; idx += NTHR) {
+        const int c = idx / half, k = idx - c * half;
+        c2<T> *line = buf + c * M;
+        if (k == 0) {
+            c2<T> p = line[0];
+            line[0] = mk<T>((p.x + p.y) * T(0.5), (p.x - p.y) * T(0.5));
+        } else {
+            const int km = M - k;
+            c2<T> a = line[k], b = line[km];
+            c2<T> E = mk<T>((a.x + b.x) * T(0.5), (a.y - b.y) * T(0.5));
+            c2<T> D = mk<T>((a.x - b.x) * T(0.5), (a.y + b.y) * T(0.5));
+            c2<T> O = cmul<T>(D, cconj<T>(tw2[k]));
+            line[k] = mk<T>(E.x - O.y, E.y + O.x);
+            if (km != k) {
+                c2<T> Ep = cconj<T>(E);
+                c2<T> Op = cmul<T>(mk<T>(-D.x, D.y), cconj<T>(tw2[km]));
+                line[km] = mk<T>(Ep.x - Op.y, Ep.y + Op.x);
+            }
+        }
+    }
+    __syncthreads();
+    lds_fft<T, NTHR, BPT>(buf, M, nl, log2M, +1, tw);
+    const int npair = n_out_cols / 2;
+    for (int idx = threadIdx.x; idx < nl * npair; idx += NTHR) {
+        const int c = idx / npair, e = idx - c * npair;
+        c2<T> z = buf[c * M + e];
+        epi(row0 + c, 2 * e, z.x, z.y);
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+struct ConvGeom {
+    int64_t n_img;   // images (each with its own kernel index g % nk)
+    int rows_in;     // stored (non-zero) rows per image = n_in of the column pass
+    int rows_out;    // rows kept after the column pass and written by pass 3
+    int n_in_cols;   // non-zero real columns per row (<= 2M)
+    int n_out_cols;  // real columns kept by pass 3
+    int log2M;       // packed width
+    int log2Lc;      // column FFT length
+};
+
+template <typename T> inline int max_line_elems() { return kLdsBytes / (int)sizeof(c2<T>); }
+
+template <typename T, class Pro>
+void launch_rfft_rows(const Ctx &ctx, const ConvGeom &g, Pro pro, c2<T> *Y, hipStream_t st) {
+    const int M = 1 << g.log2M;
+    const int64_t nrows = g.n_img * g.rows_in;
+    FR_REQUIRE(M <= max_line_elems<T>() && M <= 16384, "row length too large for LDS");
+    if (M <= 4096) {
+        const int lpw = std::max(1, 2048 / M);
+        const int64_t nblk = (nrows + lpw - 1) / lpw;
+        allow_lds(k_rfft_rows<T, 256, 4, Pro>, lpw * M * sizeof(c2<T>));
+        k_rfft_rows<T, 256, 4, Pro><<<dim3((unsigned)nblk), 256, lpw * M * sizeof(c2<T>), st>>>(
+            pro, Y, nrows, g.log2M, g.n_in_cols, lpw, ctx.tw<T>(g.log2M), ctx.tw<T>(g.log2M + 1));
+    } else {
+        allow_lds(k_rfft_rows<T, 1024, 4, Pro>, M * sizeof(c2<T>));
+        k_rfft_rows<T, 1024, 4, Pro><<<dim3((unsigned)nrows), 1024, M * sizeof(c2<T>), st>>>(
+            pro, Y, nrows, g.log2M, g.n_in_cols, 1, ctx.tw<T>(g.log2M), ctx.tw<T>(g.log2M + 1));
+    }
+    LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_conv_cols(const Ctx &ctx, const ConvGeom &g, c2<T> *Y, const T *K, int nk, int mode, T scale,
+                      hipStream_t st) {
+    const int M = 1 << g.log2M;
+    const int Lc = 1 << g.log2Lc;
+    const int budget = 65536 / (int)sizeof(c2<T>);  // <= 64 KiB: two workgroups per CU
+    int C = std::max(1, std::min(16, budget / Lc));
+    while (C > 1 && (M % C)) C >>= 1;
+    C = std::min(C, M);
+    FR_REQUIRE((int64_t)C * (Lc + 1) <= max_line_elems<T>(), "column length too large for LDS");
+    const size_t lds = (size_t)C * (Lc + 1) * sizeof(c2<T>);
+    dim3 grid((unsigned)(M / C), (unsigned)g.n_img);
+    FR_REQUIRE(g.rows_in == g.rows_out, "column pass works in place");
+    if (C * Lc <= 4096) {
+        allow_lds(k_conv_cols<T, 256, 4>, lds);
+        k_conv_cols<T, 256, 4><<<grid, 256, lds, st>>>(Y, g.log2M, g.log2Lc, g.rows_in, g.rows_out, C, K, nk, mode,
+                                                       scale, ctx.tw<T>(g.log2Lc));
+    } else {
+        allow_lds(k_conv_cols<T, 1024, 4>, lds);
+        k_conv_cols<T, 1024, 4><<<grid, 1024, lds, st>>>(Y, g.log2M, g.log2Lc, g.rows_in, g.rows_out, C, K, nk,
+                                                         mode, scale, ctx.tw<T>(g.log2Lc));
+    }
+    LAUNCH_CHECK();
+}
+
+template <typename T, class Epi>
+void launch_irfft_rows(const Ctx &ctx, const ConvGeom &g, Epi epi, const c2<T> *Y, hipStream_t st) {
+    const int M = 1 << g.log2M;
+    const int64_t nrows = g.n_img * g.rows_out;
+    if (M <= 4096) {
+        const int lpw = std::max(1, 2048 / M);
+        const int64_t nblk = (nrows + lpw - 1) / lpw;
+        allow_lds(k_irfft_rows<T, 256, 4, Epi>, lpw * M * sizeof(c2<T>));
+        k_irfft_rows<T, 256, 4, Epi><<<dim3((unsigned)nblk), 256, lpw * M * sizeof(c2<T>), st>>>(
+            epi, Y, nrows, g.log2M, g.n_out_cols, lpw, ctx.tw<T>(g.log2M), ctx.tw<T>(g.log2M + 1));
+    } else {
+        allow_lds(k_irfft_rows<T, 1024, 4, Epi>, M * sizeof(c2<T>));
+        k_irfft_rows<T, 1024, 4, Epi><<<dim3((unsigned)nrows), 1024, M * sizeof(c2<T>), st>>>(
+            epi, Y, nrows, g.log2M, g.n_out_cols, 1, ctx.tw<T>(g.log2M), ctx.tw<T>(g.log2M + 1));
+    }
+    LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------ functors
+// x[row][col] (row-major, ny columns) times an optional per-pixel factor a[row % nx][col]
+template <typename T> struct ProScaled {
+    const T *x;
+    const T *a;
+    int nx, ny;
+    __device__ T operator()(int64_t row, int col) const {
+        T v = x[row * ny + col];
+        return a ? v * a[(row % nx) * ny + col] : v;
+    }
+};
+
+// y[row][col] = (accumulate ? y : 0) + alpha * a[row % nx][col] * value
+template <typename T> struct EpiScaled {
+    T *y;
+    const T *a;
+    int nx, ny;
+    T alpha;
+    int accumulate;
+    __device__ void operator()(int64_t row, int col, T v0, T v1) const {
+        T *p = y + row * ny + col;
+        if (a) {
+            const T *q = a + (row % nx) * ny + col;
+            v0 *= q[0];
+            v1 *= q[1];
+        }
+        v0 *= alpha;
+        v1 *= alpha;
+        if (accumulate) {
+            v0 += p[0];
+            v1 += p[1];
+        }
+        p[0] = v0;
+        p[1] = v1;
+    }
+};
+
+}  // namespace frmi

@@ -1,0 +1,123 @@
+// Radix-4/2 Stockham FFT on LDS-resident lines, shared by every transform in the
+// library (uv-grid FFTs of the gridder, the zero-padded PSF convolution, the
+// periodic noise and prior convolutions).
+//
+// Method: the self-sorting Stockham formulation (natural-order output without a
+// bit-reversal pass) of Govindaraju et al., "High performance discrete Fourier
+// transforms on graphics processors" (SC'08).  A stage with current span Ns and
+// radix R takes, for every butterfly index j < L/R with k = j mod Ns,
+//   v_r = x[j + r L/R] * exp(sign 2 pi i r k / (Ns R)),  r < R,
+// applies the R-point DFT, and writes y[(j / Ns) Ns R + k + r Ns] = v_r.
+// Lines live in LDS; each butterfly keeps its R values in registers between the
+// read and the write barrier, so a stage is in place.
+//
+// Twiddles come from a per-length table tw[m] = exp(-2 pi i m / L) built in FP64
+// on the host and rounded once to the working precision.
+#pragma once
+
+#include "common.h"
+
+namespace frmi {
+
+template <typename T>
+__device__ __forceinline__ c2<T> mul_i_sign(c2<T> a, int sign) {
+    // a * (sign * i)
+    return sign < 0 ? mk<T>(a.y, -a.x) : mk<T>(-a.y, a.x);
+}
+
+template <typename T>
+__device__ __forceinline__ void dft2(c2<T> (&v)[2]) {
+    c2<T> a = v[0], b = v[1];
+    v[0] = cadd<T>(a, b);
+    v[1] = csub<T>(a, b);
+}
+
+template <typename T>
+__device__ __forceinline__ void dft4(c2<T> (&v)[4], int sign) {
+    c2<T> t0 = cadd<T>(v[0], v[2]);
+    c2<T> t1 = csub<T>(v[0], v[2]);
+    c2<T> t2 = cadd<T>(v[1], v[3]);
+    c2<T> t3 = mul_i_sign<T>(csub<T>(v[1], v[3]), sign);
+    v[0] = cadd<T>(t0, t2);
+    v[2] = csub<T>(t0, t2);
+    v[1] = cadd<T>(t1, t3);
+    v[3] = csub<T>(t1, t3);
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void dftR(c2<T> (&v)[R], int sign) {
+    if constexpr (R == 2) dft2<T>(v);
+    else dft4<T>(v, sign);
+}
+
+// One Stockham stage over `nlines` lines of length 2^log2L spaced `ld` apart.
+// BPT: butterflies per thread this launch can need (host-checked).
+template <typename T, int R, int NTHR, int BPT>
+__device__ __forceinline__ void stockham_stage(c2<T> *buf, int ld, int nlines, int log2L, int log2Ns,
+                                               int sign, const c2<T> *__restrict__ tw) {
+    constexpr int LOG2R = (R == 2) ? 1 : 2;
+    const int log2Q = log2L - LOG2R;
+    const int Q = 1 << log2Q;
+    const int nb = nlines << log2Q;
+    const int Ns = 1 << log2Ns;
+    const int twshift = log2L - log2Ns - LOG2R;
+    c2<T> v[BPT][R];
+    int obase[BPT];
+#pragma unroll
+    for (int b = 0; b < BPT; ++b) {
+        const int f = threadIdx.x + b * NTHR;
+        obase[b] = -1;
+        if (f < nb) {
+            const int line = f >> log2Q;
+            const int j = f & (Q - 1);
+            const int k = j & (Ns - 1);
+            const c2<T> *p = buf + line * ld;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[b][r] = p[j + r * Q];
+            if (log2Ns > 0) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    c2<T> w = tw[(r * k) << twshift];
+                    if (sign > 0) w.y = -w.y;
+                    v[b][r] = cmul<T>(v[b][r], w);
+                }
+            }
+            dftR<T, R>(v[b], sign);
+            obase[b] = line * ld + ((j >> log2Ns) << (log2Ns + LOG2R)) + k;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < BPT; ++b) {
+        if (obase[b] >= 0) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[obase[b] + r * Ns] = v[b][r];
+        }
+    }
+    __syncthreads();
+}
+
+// Full in-place FFT of `nlines` LDS lines (length 2^log2L, stride ld).  Caller
+// must __syncthreads() after filling the lines; returns after a barrier.
+// Requires nlines * 2^log2L <= 4 * BPT * NTHR.
+template <typename T, int NTHR, int BPT>
+__device__ __forceinline__ void lds_fft(c2<T> *buf, int ld, int nlines, int log2L, int sign,
+                                        const c2<T> *__restrict__ tw) {
+    int log2Ns = 0;
+    if (log2L & 1) {
+        stockham_stage<T, 2, NTHR, 2 * BPT>(buf, ld, nlines, log2L, 0, sign, tw);
+        log2Ns = 1;
+    }
+    for (; log2Ns < log2L; log2Ns += 2) stockham_stage<T, 4, NTHR, BPT>(buf, ld, nlines, log2L, log2Ns, sign, tw);
+}
+
+// LDS budget of one workgroup (bytes; gfx950 has 160 KiB per CU).
+constexpr int kLdsBytes = 163840;
+
+// Kernels using more than the default dynamic-LDS limit must opt in once.
+template <typename F>
+inline void allow_lds(F *func, size_t bytes) {
+    if (bytes > 65536) HIP_CHECK(hipFuncSetAttribute((const void *)func, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+}
+
+}  // namespace frmi

@@ -1,0 +1,129 @@
+// Generic complex-to-complex line-FFT kernels with load/store functors.
+//
+//   k_fft_rows: each workgroup transforms `lines_per_wg` rows; element e of row r
+//               is read with pro(r, e) and written with epi(r, e, value).
+//   k_fft_cols: each workgroup transforms a strip of C adjacent columns of one
+//               [rows][cols] matrix (matrix index = blockIdx.y); only the first
+//               n_in rows are read (the rest are known zeros) and the first n_out
+//               rows are written.  Row-segment reads of C consecutive elements keep
+//               the global accesses coalesced; columns are transposed into padded
+//               LDS lines (stride L + 1) on the way in and out.
+#pragma once
+
+#include "fft.h"
+
+namespace frmi {
+
+template <typename T, int NTHR, int BPT, class Pro, class Epi>
+__global__ __launch_bounds__(NTHR) void k_fft_rows(Pro pro, Epi epi, int64_t nrows, int log2L,
+                                                    int lines_per_wg, int sign,
+                                                    const c2<T> *__restrict__ tw) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    c2<T> *buf = reinterpret_cast<c2<T> *>(smem_raw);
+    const int L = 1 << log2L;
+    const int64_t row0 = (int64_t)blockIdx.x * lines_per_wg;
+    const int nl = (int)min<int64_t>(lines_per_wg, nrows - row0);
+    for (int idx = threadIdx.x; idx < (nl << log2L); idx += NTHR)
+        buf[idx] = pro(row0 + (idx >> log2L), idx & (L - 1));
+    __syncthreads();
+    lds_fft<T, NTHR, BPT>(buf, L, nl, log2L, sign, tw);
+    for (int idx = threadIdx.x; idx < (nl << log2L); idx += NTHR)
+        epi(row0 + (idx >> log2L), idx & (L - 1), buf[idx]);
+}
+
+template <typename T, int NTHR, int BPT, class Pro, class Epi>
+__global__ __launch_bounds__(NTHR) void k_fft_cols(Pro pro, Epi epi, int ncols, int log2L, int n_in,
+                                                    int n_out, int C, int sign,
+                                                    const c2<T> *__restrict__ tw) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    c2<T> *buf = reinterpret_cast<c2<T> *>(smem_raw);
+    const int L = 1 << log2L;
+    const int ld = L + 1;
+    const int col0 = blockIdx.x * C;
+    const int64_t m = blockIdx.y;
+    for (int idx = threadIdx.x; idx < C * L; idx += NTHR) {
+        const int r = idx / C, c = idx - r * C;
+        buf[c * ld + r] = (r < n_in) ? pro(m, r, col0 + c) : mk<T>(T(0), T(0));
+    }
+    __syncthreads();
+    lds_fft<T, NTHR, BPT>(buf, ld, C, log2L, sign, tw);
+    for (int idx = threadIdx.x; idx < C * n_out; idx += NTHR) {
+        const int r = idx / C, c = idx - r * C;
+        epi(m, r, col0 + c, buf[c * ld + r]);
+    }
+}
+
+template <typename T, class Pro, class Epi>
+void launch_fft_rows(const Ctx &ctx, Pro pro, Epi epi, int64_t nrows, int log2L, int sign, hipStream_t st) {
+    const int L = 1 << log2L;
+    FR_REQUIRE((int64_t)L * (int64_t)sizeof(c2<T>) <= kLdsBytes && L <= 16384, "FFT length too large");
+    if (nrows <= 0) return;
+    if (L <= 4096) {
+        const int lpw = std::max(1, 2048 / L);
+        const size_t lds = (size_t)lpw * L * sizeof(c2<T>);
+        allow_lds(k_fft_rows<T, 256, 4, Pro, Epi>, lds);
+        k_fft_rows<T, 256, 4, Pro, Epi><<<dim3((unsigned)((nrows + lpw - 1) / lpw)), 256, lds, st>>>(
+            pro, epi, nrows, log2L, lpw, sign, ctx.tw<T>(log2L));
+    } else {
+        const size_t lds = (size_t)L * sizeof(c2<T>);
+        allow_lds(k_fft_rows<T, 1024, 4, Pro, Epi>, lds);
+        k_fft_rows<T, 1024, 4, Pro, Epi><<<dim3((unsigned)nrows), 1024, lds, st>>>(pro, epi, nrows, log2L, 1, sign,
+                                                                                ctx.tw<T>(log2L));
+    }
+    LAUNCH_CHECK();
+}
+
+// Column strip width: as many columns as keep the LDS lines within 64 KiB (two
+// workgroups per CU), at most 16, a divisor of ncols.
+template <typename T> inline int col_strip(int L, int ncols) {
+    int C = std::max(1, std::min(16, (int)(65536 / sizeof(c2<T>)) / L));
+    while (C > 1 && (ncols % C)) C >>= 1;
+    return C;
+}
+
+template <typename T, class Pro, class Epi>
+void launch_fft_cols(const Ctx &ctx, Pro pro, Epi epi, int64_t nmat, int ncols, int log2L, int n_in, int n_out,
+                     int sign, hipStream_t st) {
+    const int L = 1 << log2L;
+    const int C = col_strip<T>(L, ncols);
+    const size_t lds = (size_t)C * (L + 1) * sizeof(c2<T>);
+    FR_REQUIRE(lds <= (size_t)kLdsBytes && L <= 16384, "column FFT length too large");
+    if (nmat <= 0) return;
+    dim3 grid((unsigned)(ncols / C), (unsigned)nmat);
+    if (C * L <= 4096) {
+        allow_lds(k_fft_cols<T, 256, 4, Pro, Epi>, lds);
+        k_fft_cols<T, 256, 4, Pro, Epi><<<grid, 256, lds, st>>>(pro, epi, ncols, log2L, n_in, n_out, C, sign,
+                                                                ctx.tw<T>(log2L));
+    } else {
+        allow_lds(k_fft_cols<T, 1024, 4, Pro, Epi>, lds);
+        k_fft_cols<T, 1024, 4, Pro, Epi><<<grid, 1024, lds, st>>>(pro, epi, ncols, log2L, n_in, n_out, C, sign,
+                                                                  ctx.tw<T>(log2L));
+    }
+    LAUNCH_CHECK();
+}
+
+// plain strided complex matrix access: base + m * mstride + r * ncols + c
+template <typename T> struct MatLoad {
+    const c2<T> *base;
+    int64_t mstride;
+    int ncols;
+    __device__ c2<T> operator()(int64_t m, int r, int c) const { return base[m * mstride + (int64_t)r * ncols + c]; }
+};
+template <typename T> struct MatStore {
+    c2<T> *base;
+    int64_t mstride;
+    int ncols;
+    __device__ void operator()(int64_t m, int r, int c, c2<T> v) const { base[m * mstride + (int64_t)r * ncols + c] = v; }
+};
+template <typename T> struct RowLoad {
+    const c2<T> *base;
+    int log2L;
+    __device__ c2<T> operator()(int64_t r, int e) const { return base[(r << log2L) + e]; }
+};
+template <typename T> struct RowStore {
+    c2<T> *base;
+    int log2L;
+    __device__ void operator()(int64_t r, int e, c2<T> v) const { base[(r << log2L) + e] = v; }
+};
+
+}  // namespace frmi

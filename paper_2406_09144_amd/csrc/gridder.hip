@@ -1,0 +1,760 @@
+// Exact response R (degridding, Sec. 2 Eq. 1) and its adjoint R^+ (gridding,
+// Sec. 3.2) at a requested accuracy epsilon: ES-kernel non-uniform FFT on a 2x
+// oversampled uv grid, with improved w-stacking (the kernel also runs along w,
+// and its Fourier transform in (n - 1) is divided out in image space).
+//
+// Degridding of channel c:
+//   1. rows:    for each w-plane p and image row i, the prepared row
+//               img * a / (Psi_u Psi_v Psi_w) * exp(-2 pi i w_p t) is placed into the
+//               wrapped grid row and transformed (only the nx non-zero grid rows);
+//   2. columns: forward FFT of every grid column (zero rows are not read);
+//   3. degrid:  one workgroup per work item (uv tile x first w-plane): the tile and
+//               its W-1 halo of each touched plane is staged in LDS, every
+//               visibility sums psi_w psi_u psi_v G over its W x W x Ww footprint.
+// Gridding is the exact transpose: visibilities are spread into an LDS tile with
+// LDS atomics and flushed to the planes with global atomics, inverse column FFT
+// (keeping only the non-zero rows), then a row kernel that transforms each plane
+// row and accumulates Re(exp(+2 pi i w_p t) G) over planes into the image row.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "eskernel.h"
+#include "fftk.h"
+#include "objects.h"
+
+namespace frmi {
+
+constexpr double kCLight = 299792458.0;
+constexpr int kTile = 32;
+
+// ------------------------------------------------------------------ plan kernels
+template <typename T>
+__global__ void k_vis_coords(const double *__restrict__ uvw, const double *__restrict__ freq, int64_t n_vis,
+                             int n_chan, int log2nu, int log2nv, double dx, double dy, int W, int Ww, int coplanar,
+                             double w0, double dw, double yc, int ntv, int n_tiles, int n_p0,
+                             uint32_t *__restrict__ key, uint32_t *__restrict__ idx, uint32_t *__restrict__ cell,
+                             T *__restrict__ du, T *__restrict__ dv, T *__restrict__ dwf, T *__restrict__ ph) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n_vis) return;
+    const int64_t row = v / n_chan;
+    const int chan = (int)(v - row * n_chan);
+    const double f = freq[chan] / kCLight;
+    double u = uvw[3 * row] * f, vv = uvw[3 * row + 1] * f, w = coplanar ? 0.0 : uvw[3 * row + 2] * f;
+    uint32_t conj = 0;
+    if (w < 0) {  // real sky: V(-u,-v,-w) = conj V(u,v,w); keep w >= 0
+        u = -u;
+        vv = -vv;
+        w = -w;
+        conj = 1;
+    }
+    const int nu = 1 << log2nu, nv = 1 << log2nv;
+    // grid coordinates in cells, wrapped into [0, n): exact because image pixels
+    // sit on integer multiples of the pixel size
+    double ku = u * (double)nu * dx;
+    ku -= floor(ku / nu) * nu;
+    double kv = vv * (double)nv * dy;
+    kv -= floor(kv / nv) * nv;
+    int a0 = (int)ceil(ku - 0.5 * W);
+    const double fu = ku - a0;
+    a0 = (a0 + nu) & (nu - 1);
+    int b0 = (int)ceil(kv - 0.5 * W);
+    const double fv = kv - b0;
+    b0 = (b0 + nv) & (nv - 1);
+    const int tu = a0 / kTile, tv = b0 / kTile;
+    int p0 = 0;
+    double fw = 0, phc = 0;
+    if (!coplanar) {
+        const double kw = (w - w0) / dw;
+        p0 = (int)ceil(kw - 0.5 * Ww);
+        fw = kw - p0;
+        p0 = min(max(p0, 0), n_p0 - 1);
+        phc = w * yc;
+        phc -= rint(phc);
+    }
+    key[v] = (uint32_t)(((int64_t)chan * n_p0 + p0) * n_tiles + (int64_t)tu * ntv + tv);
+    idx[v] = (uint32_t)v | (conj << 31);
+    cell[v] = (uint32_t)(a0 - tu * kTile) | ((uint32_t)(b0 - tv * kTile) << 16);
+    du[v] = (T)fu;
+    dv[v] = (T)fv;
+    dwf[v] = (T)fw;
+    ph[v] = (T)phc;
+}
+
+__global__ void k_hist(const uint32_t *__restrict__ key, int64_t n, uint32_t *__restrict__ counts) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) atomicAdd(&counts[key[v]], 1u);
+}
+
+template <typename T>
+__global__ void k_scatter(int64_t n, const uint32_t *__restrict__ key, const int64_t *__restrict__ offs,
+                          uint32_t *__restrict__ cursor, const uint32_t *__restrict__ i_idx,
+                          const uint32_t *__restrict__ i_cell, const T *__restrict__ i_du, const T *__restrict__ i_dv,
+                          const T *__restrict__ i_dw, const T *__restrict__ i_ph, uint32_t *__restrict__ o_idx,
+                          uint32_t *__restrict__ o_cell, T *__restrict__ o_du, T *__restrict__ o_dv,
+                          T *__restrict__ o_dw, T *__restrict__ o_ph) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const uint32_t k = key[v];
+    const int64_t pos = offs[k] + atomicAdd(&cursor[k], 1u);
+    o_idx[pos] = i_idx[v];
+    o_cell[pos] = i_cell[v];
+    o_du[pos] = i_du[v];
+    o_dv[pos] = i_dv[v];
+    o_dw[pos] = i_dw[v];
+    o_ph[pos] = i_ph[v];
+}
+
+// ------------------------------------------------------------------ kernel weights
+template <typename T> __device__ __forceinline__ T es_eval(T z, T beta) {
+    const T q = T(1) - z * z;
+    return q >= T(0) ? (T)exp(beta * (sqrt(q) - T(1))) : T(0);
+}
+
+// ------------------------------------------------------------------ degrid
+template <typename T, int W, int NTHR, int VPT>
+__global__ __launch_bounds__(NTHR) void k_degrid(const WorkItem *__restrict__ wis, const c2<T> *__restrict__ planes,
+                                                 int log2nu, int log2nv, int Ww, T beta, T wbeta, int coplanar,
+                                                 const uint32_t *__restrict__ r_idx,
+                                                 const uint32_t *__restrict__ r_cell, const T *__restrict__ r_du,
+                                                 const T *__restrict__ r_dv, const T *__restrict__ r_dw,
+                                                 const T *__restrict__ r_ph, c2<T> *__restrict__ vis) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    c2<T> *tile = reinterpret_cast<c2<T> *>(smem_raw);
+    constexpr int TS = kTile + W - 1;
+    const WorkItem it = wis[blockIdx.x];
+    const int nu = 1 << log2nu, nv = 1 << log2nv;
+    const T two_over_W = T(2) / T(W);
+    T ku[VPT][W], kv[VPT][W];
+    T fw[VPT];
+    int ru[VPT], rv[VPT];
+    bool ok[VPT];
+    c2<T> acc[VPT];
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) {
+        const int j = threadIdx.x + k * NTHR;
+        ok[k] = j < it.count;
+        acc[k] = mk<T>(T(0), T(0));
+        ru[k] = rv[k] = 0;
+        fw[k] = T(0);
+        if (ok[k]) {
+            const int64_t pos = it.start + j;
+            const uint32_t c = r_cell[pos];
+            ru[k] = (int)(c & 0xffffu);
+            rv[k] = (int)(c >> 16);
+            const T xu = r_du[pos], xv = r_dv[pos];
+#pragma unroll
+            for (int a = 0; a < W; ++a) {
+                ku[k][a] = es_eval<T>((xu - T(a)) * two_over_W, beta);
+                kv[k][a] = es_eval<T>((xv - T(a)) * two_over_W, beta);
+            }
+            fw[k] = r_dw[pos];
+        }
+    }
+    for (int pw = 0; pw < Ww; ++pw) {
+        const c2<T> *P = planes + ((int64_t)(it.p0 + pw) << (log2nu + log2nv));
+        __syncthreads();
+        for (int q = threadIdx.x; q < TS * TS; q += NTHR) {
+            const int i = q / TS, jj = q - i * TS;
+            const int a = (it.tu + i) & (nu - 1), b = (it.tv + jj) & (nv - 1);
+            tile[q] = P[((int64_t)a << log2nv) + b];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < VPT; ++k) {
+            if (!ok[k]) continue;
+            const T kw = coplanar ? T(1) : es_eval<T>((fw[k] - T(pw)) * (T(2) / T(Ww)), wbeta);
+            T sx = 0, sy = 0;
+#pragma unroll
+            for (int a = 0; a < W; ++a) {
+                const c2<T> *rowp = tile + (ru[k] + a) * TS + rv[k];
+                T rx = 0, ry = 0;
+#pragma unroll
+                for (int b = 0; b < W; ++b) {
+                    const c2<T> g = rowp[b];
+                    rx += kv[k][b] * g.x;
+                    ry += kv[k][b] * g.y;
+                }
+                sx += ku[k][a] * rx;
+                sy += ku[k][a] * ry;
+            }
+            acc[k].x += kw * sx;
+            acc[k].y += kw * sy;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) {
+        if (!ok[k]) continue;
+        const int64_t pos = it.start + threadIdx.x + k * NTHR;
+        c2<T> v = acc[k];
+        if (!coplanar) {
+            T s, c;
+            sincos_cycles(-r_ph[pos], &s, &c);
+            v = cmul<T>(v, mk<T>(c, s));
+        }
+        const uint32_t id = r_idx[pos];
+        if (id >> 31) v.y = -v.y;
+        vis[id & 0x7fffffffu] = v;
+    }
+}
+
+// ------------------------------------------------------------------ grid (adjoint)
+template <typename T, int W, int NTHR, int VPT>
+__global__ __launch_bounds__(NTHR) void k_grid(const WorkItem *__restrict__ wis, c2<T> *__restrict__ planes,
+                                               int log2nu, int log2nv, int Ww, T beta, T wbeta, int coplanar,
+                                               const uint32_t *__restrict__ r_idx, const uint32_t *__restrict__ r_cell,
+                                               const T *__restrict__ r_du, const T *__restrict__ r_dv,
+                                               const T *__restrict__ r_dw, const T *__restrict__ r_ph,
+                                               const c2<T> *__restrict__ vis, const T *__restrict__ weight) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *tile = reinterpret_cast<T *>(smem_raw);  // interleaved (re, im)
+    constexpr int TS = kTile + W - 1;
+    const WorkItem it = wis[blockIdx.x];
+    const int nu = 1 << log2nu, nv = 1 << log2nv;
+    const T two_over_W = T(2) / T(W);
+    T ku[VPT][W], kv[VPT][W];
+    T fw[VPT];
+    int ru[VPT], rv[VPT];
+    bool ok[VPT];
+    c2<T> y[VPT];
+#pragma unroll
+    for (int k = 0; k < VPT; ++k) {
+        const int j = threadIdx.x + k * NTHR;
+        ok[k] = j < it.count;
+        ru[k] = rv[k] = 0;
+        fw[k] = T(0);
+        y[k] = mk<T>(T(0), T(0));
+        if (ok[k]) {
+            const int64_t pos = it.start + j;
+            const uint32_t c = r_cell[pos];
+            ru[k] = (int)(c & 0xffffu);
+            rv[k] = (int)(c >> 16);
+            const T xu = r_du[pos], xv = r_dv[pos];
+#pragma unroll
+            for (int a = 0; a < W; ++a) {
+                ku[k][a] = es_eval<T>((xu - T(a)) * two_over_W, beta);
+                kv[k][a] = es_eval<T>((xv - T(a)) * two_over_W, beta);
+            }
+            fw[k] = r_dw[pos];
+            const uint32_t id = r_idx[pos];
+            const uint32_t vi = id & 0x7fffffffu;
+            c2<T> val = vis[vi];
+            if (weight) {
+                const T wt = weight[vi];
+                val.x *= wt;
+                val.y *= wt;
+            }
+            if (id >> 31) val.y = -val.y;
+            if (!coplanar) {
+                T s, c2v;
+                sincos_cycles(r_ph[pos], &s, &c2v);
+                val = cmul<T>(val, mk<T>(c2v, s));
+            }
+            y[k] = val;
+        }
+    }
+    for (int pw = 0; pw < Ww; ++pw) {
+        for (int q = threadIdx.x; q < 2 * TS * TS; q += NTHR) tile[q] = T(0);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < VPT; ++k) {
+            if (!ok[k]) continue;
+            const T kw = coplanar ? T(1) : es_eval<T>((fw[k] - T(pw)) * (T(2) / T(Ww)), wbeta);
+            const T cx = y[k].x * kw, cy = y[k].y * kw;
+#pragma unroll
+            for (int a = 0; a < W; ++a) {
+                const T ax = cx * ku[k][a], ay = cy * ku[k][a];
+                T *rowp = tile + 2 * ((ru[k] + a) * TS + rv[k]);
+#pragma unroll
+                for (int b = 0; b < W; ++b) {
+                    atomicAdd(rowp + 2 * b, ax * kv[k][b]);
+                    atomicAdd(rowp + 2 * b + 1, ay * kv[k][b]);
+                }
+            }
+        }
+        __syncthreads();
+        c2<T> *P = planes + ((int64_t)(it.p0 + pw) << (log2nu + log2nv));
+        for (int q = threadIdx.x; q < TS * TS; q += NTHR) {
+            const T gx = tile[2 * q], gy = tile[2 * q + 1];
+            if (gx != T(0) || gy != T(0)) {
+                const int i = q / TS, jj = q - i * TS;
+                const int a = (it.tu + i) & (nu - 1), b = (it.tv + jj) & (nv - 1);
+                T *dst = reinterpret_cast<T *>(P + ((int64_t)a << log2nv) + b);
+                atomicAdd(dst, gx);
+                atomicAdd(dst + 1, gy);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ FFT functors
+// row transform of degridding: line = p * nx + i
+template <typename T> struct DegridRowPro {
+    const T *img, *fac, *tpix;
+    const double *wplane;
+    int nx, ny, nv, coplanar;
+    __device__ c2<T> operator()(int64_t line, int b) const {
+        const int p = (int)(line / nx);
+        const int i = (int)(line - (int64_t)p * nx);
+        const int j = (b + ny / 2) & (nv - 1);
+        if (j >= ny) return mk<T>(T(0), T(0));
+        const int64_t q = (int64_t)i * ny + j;
+        const T f = img[q] * fac[q];
+        if (coplanar) return mk<T>(f, T(0));
+        T ph = (T)wplane[p] * tpix[q];
+        ph -= rint(ph);
+        T s, c;
+        sincos_cycles(-ph, &s, &c);
+        return mk<T>(f * c, f * s);
+    }
+};
+template <typename T> struct DegridRowEpi {
+    c2<T> *planes;
+    int nx, log2nu, log2nv;
+    __device__ void operator()(int64_t line, int b, c2<T> v) const {
+        const int p = (int)(line / nx);
+        const int i = (int)(line - (int64_t)p * nx);
+        const int a = (i - nx / 2) & ((1 << log2nu) - 1);
+        planes[((((int64_t)p << log2nu) + a) << log2nv) + b] = v;
+    }
+};
+// column access of plane m; rows outside the image band are zero (never read)
+template <typename T> struct BandColPro {
+    const c2<T> *planes;
+    int nx, log2nu, log2nv;
+    __device__ c2<T> operator()(int64_t m, int a, int b) const {
+        const int nu = 1 << log2nu;
+        if (a >= nx / 2 && a < nu - nx / 2) return mk<T>(T(0), T(0));
+        return planes[(((m << log2nu) + a) << log2nv) + b];
+    }
+};
+template <typename T> struct FullColPro {
+    const c2<T> *planes;
+    int log2nu, log2nv;
+    __device__ c2<T> operator()(int64_t m, int a, int b) const { return planes[(((m << log2nu) + a) << log2nv) + b]; }
+};
+template <typename T> struct FullColEpi {
+    c2<T> *planes;
+    int log2nu, log2nv;
+    __device__ void operator()(int64_t m, int a, int b, c2<T> v) const {
+        planes[(((m << log2nu) + a) << log2nv) + b] = v;
+    }
+};
+template <typename T> struct BandColEpi {
+    c2<T> *planes;
+    int nx, log2nu, log2nv;
+    __device__ void operator()(int64_t m, int a, int b, c2<T> v) const {
+        const int nu = 1 << log2nu;
+        if (a >= nx / 2 && a < nu - nx / 2) return;
+        planes[(((m << log2nu) + a) << log2nv) + b] = v;
+    }
+};
+
+// Gridding epilogue: image row i accumulates Re(exp(+2 pi i w_p t) G_p) over planes.
+template <typename T, int NTHR, int BPT, int ACC>
+__global__ __launch_bounds__(NTHR) void k_grid_rows(const c2<T> *__restrict__ planes, int n_planes, int log2nu,
+                                                    int log2nv, int nx, int ny, const T *__restrict__ fac,
+                                                    const T *__restrict__ tpix, const double *__restrict__ wplane,
+                                                    int coplanar, T *__restrict__ img,
+                                                    const c2<T> *__restrict__ tw) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    c2<T> *buf = reinterpret_cast<c2<T> *>(smem_raw);
+    const int i = blockIdx.x;
+    const int nu = 1 << log2nu, nv = 1 << log2nv;
+    const int a = (i - nx / 2) & (nu - 1);
+    T acc[ACC];
+#pragma unroll
+    for (int k = 0; k < ACC; ++k) acc[k] = T(0);
+    for (int p = 0; p < n_planes; ++p) {
+        const c2<T> *src = planes + ((((int64_t)p << log2nu) + a) << log2nv);
+        for (int e = threadIdx.x; e < nv; e += NTHR) buf[e] = src[e];
+        __syncthreads();
+        lds_fft<T, NTHR, BPT>(buf, nv, 1, log2nv, +1, tw);
+        const T wp = (T)wplane[p];
+#pragma unroll
+        for (int k = 0; k < ACC; ++k) {
+            const int j = threadIdx.x + k * NTHR;
+            if (j < ny) {
+                const c2<T> g = buf[(j - ny / 2) & (nv - 1)];
+                if (coplanar) {
+                    acc[k] += g.x;
+                } else {
+                    T ph = wp * tpix[(int64_t)i * ny + j];
+                    ph -= rint(ph);
+                    T s, c;
+                    sincos_cycles(ph, &s, &c);
+                    acc[k] += g.x * c - g.y * s;
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < ACC; ++k) {
+        const int j = threadIdx.x + k * NTHR;
+        if (j < ny) img[(int64_t)i * ny + j] = fac[(int64_t)i * ny + j] * acc[k];
+    }
+}
+
+template <typename T> __global__ void k_zero(T *p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = T(0);
+}
+
+template <typename T> void zero_async(T *p, int64_t n, hipStream_t st) {
+    if (n <= 0) return;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+    k_zero<T><<<dim3((unsigned)blocks), 256, 0, st>>>(p, n);
+    LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------ launch helpers
+template <typename T> constexpr int vpt() { return std::is_same<T, float>::value ? 2 : 1; }
+constexpr int kGridThreads = 256;
+template <typename T> constexpr int chunk() { return kGridThreads * vpt<T>(); }
+
+template <typename T, int W>
+void launch_degrid_w(const fr_plan *pl, const WorkItem *wis, int64_t nwi, const c2<T> *planes, c2<T> *vis,
+                     hipStream_t st) {
+    constexpr int TS = kTile + W - 1;
+    const size_t lds = (size_t)TS * TS * sizeof(c2<T>);
+    auto kern = k_degrid<T, W, kGridThreads, vpt<T>()>;
+    allow_lds(kern, lds);
+    kern<<<dim3((unsigned)nwi), kGridThreads, lds, st>>>(
+        wis, planes, ilog2(pl->nu), ilog2(pl->nv), pl->Ww, (T)pl->beta, (T)pl->wbeta, pl->coplanar ? 1 : 0,
+        pl->r_idx.as<uint32_t>(), pl->r_cell.as<uint32_t>(), pl->r_du.as<T>(), pl->r_dv.as<T>(), pl->r_dw.as<T>(),
+        pl->r_ph.as<T>(), vis);
+    LAUNCH_CHECK();
+}
+
+template <typename T, int W>
+void launch_grid_w(const fr_plan *pl, const WorkItem *wis, int64_t nwi, c2<T> *planes, const c2<T> *vis,
+                   const T *weight, hipStream_t st) {
+    constexpr int TS = kTile + W - 1;
+    const size_t lds = (size_t)TS * TS * sizeof(c2<T>);
+    auto kern = k_grid<T, W, kGridThreads, vpt<T>()>;
+    allow_lds(kern, lds);
+    kern<<<dim3((unsigned)nwi), kGridThreads, lds, st>>>(
+        wis, planes, ilog2(pl->nu), ilog2(pl->nv), pl->Ww, (T)pl->beta, (T)pl->wbeta, pl->coplanar ? 1 : 0,
+        pl->r_idx.as<uint32_t>(), pl->r_cell.as<uint32_t>(), pl->r_du.as<T>(), pl->r_dv.as<T>(), pl->r_dw.as<T>(),
+        pl->r_ph.as<T>(), vis, weight);
+    LAUNCH_CHECK();
+}
+
+#define FR_W_DISPATCH(W_, CALL) \
+    switch (W_) {               \
+    case 4: CALL(4); break;     \
+    case 5: CALL(5); break;     \
+    case 6: CALL(6); break;     \
+    case 7: CALL(7); break;     \
+    case 8: CALL(8); break;     \
+    case 9: CALL(9); break;     \
+    case 10: CALL(10); break;   \
+    case 11: CALL(11); break;   \
+    case 12: CALL(12); break;   \
+    case 13: CALL(13); break;   \
+    case 14: CALL(14); break;   \
+    case 15: CALL(15); break;   \
+    case 16: CALL(16); break;   \
+    default: throw Error(FR_EINVAL, "unsupported kernel support"); \
+    }
+
+size_t planes_bytes(const fr_plan *pl) {
+    return (size_t)pl->n_planes * pl->nu * pl->nv * (pl->fp64 ? sizeof(double2) : sizeof(float2));
+}
+
+// forward: image channel -> planes (prep, row FFT, column FFT)
+template <typename T>
+void image_to_planes(const fr_plan *pl, const T *img_c, c2<T> *planes, hipStream_t st) {
+    const int l2u = ilog2(pl->nu), l2v = ilog2(pl->nv);
+    DegridRowPro<T> pro{img_c, pl->fac.as<T>(), pl->tpix.as<T>(), pl->wplane.as<double>(),
+                        (int)pl->nx, (int)pl->ny, (int)pl->nv, pl->coplanar ? 1 : 0};
+    DegridRowEpi<T> epi{planes, (int)pl->nx, l2u, l2v};
+    launch_fft_rows<T>(*pl->ctx, pro, epi, (int64_t)pl->n_planes * pl->nx, l2v, -1, st);
+    launch_fft_cols<T>(*pl->ctx, BandColPro<T>{planes, (int)pl->nx, l2u, l2v}, FullColEpi<T>{planes, l2u, l2v},
+                       pl->n_planes, (int)pl->nv, l2u, (int)pl->nu, (int)pl->nu, -1, st);
+}
+
+// adjoint: planes -> image channel (inverse column FFT on the band, row kernel)
+template <typename T>
+void planes_to_image(const fr_plan *pl, const c2<T> *planes_c, T *img_c, hipStream_t st) {
+    c2<T> *planes = const_cast<c2<T> *>(planes_c);
+    const int l2u = ilog2(pl->nu), l2v = ilog2(pl->nv);
+    launch_fft_cols<T>(*pl->ctx, FullColPro<T>{planes, l2u, l2v}, BandColEpi<T>{planes, (int)pl->nx, l2u, l2v},
+                       pl->n_planes, (int)pl->nv, l2u, (int)pl->nu, (int)pl->nu, +1, st);
+    const int nv = (int)pl->nv;
+    if (nv <= 4096) {
+        const size_t lds = (size_t)nv * sizeof(c2<T>);
+        auto kern = k_grid_rows<T, 256, 4, 8>;
+        allow_lds(kern, lds);
+        kern<<<dim3((unsigned)pl->nx), 256, lds, st>>>(planes, pl->n_planes, l2u, l2v, (int)pl->nx, (int)pl->ny,
+                                                       pl->fac.as<T>(), pl->tpix.as<T>(), pl->wplane.as<double>(),
+                                                       pl->coplanar ? 1 : 0, img_c, pl->ctx->tw<T>(l2v));
+    } else {
+        const size_t lds = (size_t)nv * sizeof(c2<T>);
+        auto kern = k_grid_rows<T, 1024, 4, 8>;
+        allow_lds(kern, lds);
+        kern<<<dim3((unsigned)pl->nx), 1024, lds, st>>>(planes, pl->n_planes, l2u, l2v, (int)pl->nx, (int)pl->ny,
+                                                        pl->fac.as<T>(), pl->tpix.as<T>(), pl->wplane.as<double>(),
+                                                        pl->coplanar ? 1 : 0, img_c, pl->ctx->tw<T>(l2v));
+    }
+    LAUNCH_CHECK();
+}
+
+template <typename T>
+void degrid(const fr_plan *pl, const T *img, c2<T> *vis, hipStream_t st) {
+    Scratch planes(planes_bytes(pl), st);
+    const WorkItem *wis = pl->wi.as<WorkItem>();
+    for (int64_t c = 0; c < pl->n_chan; ++c) {
+        image_to_planes<T>(pl, img + c * pl->nx * pl->ny, planes.as<c2<T>>(), st);
+        const int64_t w0 = pl->wi_chan[c], w1 = pl->wi_chan[c + 1];
+        if (w1 > w0) {
+#define FR_CALL_DEGRID(WW) launch_degrid_w<T, WW>(pl, wis + w0, w1 - w0, planes.as<c2<T>>(), vis, st)
+            FR_W_DISPATCH(pl->W, FR_CALL_DEGRID)
+#undef FR_CALL_DEGRID
+        }
+    }
+}
+
+template <typename T>
+void grid(const fr_plan *pl, const c2<T> *vis, const T *weight, T *img, hipStream_t st) {
+    Scratch planes(planes_bytes(pl), st);
+    const WorkItem *wis = pl->wi.as<WorkItem>();
+    const int64_t plane_elems = (int64_t)pl->n_planes * pl->nu * pl->nv * 2;
+    for (int64_t c = 0; c < pl->n_chan; ++c) {
+        zero_async<T>(planes.as<T>(), plane_elems, st);
+        const int64_t w0 = pl->wi_chan[c], w1 = pl->wi_chan[c + 1];
+        if (w1 > w0) {
+#define FR_CALL_GRID(WW) launch_grid_w<T, WW>(pl, wis + w0, w1 - w0, planes.as<c2<T>>(), vis, weight, st)
+            FR_W_DISPATCH(pl->W, FR_CALL_GRID)
+#undef FR_CALL_GRID
+        }
+        planes_to_image<T>(pl, planes.as<c2<T>>(), img + c * pl->nx * pl->ny, st);
+    }
+}
+
+template void degrid<float>(const fr_plan *, const float *, float2 *, hipStream_t);
+template void degrid<double>(const fr_plan *, const double *, double2 *, hipStream_t);
+template void grid<float>(const fr_plan *, const float2 *, const float *, float *, hipStream_t);
+template void grid<double>(const fr_plan *, const double2 *, const double *, double *, hipStream_t);
+
+// ------------------------------------------------------------------ plan creation
+static double n_minus_1(double l, double m) {
+    const double r2 = l * l + m * m;
+    return -r2 / (1.0 + std::sqrt(1.0 - r2));
+}
+
+// Chebyshev interpolant of a smooth function on [-h, h]
+struct Cheb {
+    std::vector<double> c;
+    double h = 1;
+    template <typename F> Cheb(F f, double h_, int n) : c(n), h(h_) {
+        const double pi = 3.14159265358979323846;
+        std::vector<double> fv(n);
+        for (int k = 0; k < n; ++k) fv[k] = f(h * std::cos(pi * (k + 0.5) / n));
+        for (int j = 0; j < n; ++j) {
+            double s = 0;
+            for (int k = 0; k < n; ++k) s += fv[k] * std::cos(pi * j * (k + 0.5) / n);
+            c[j] = s * 2.0 / n;
+        }
+        c[0] *= 0.5;
+    }
+    double operator()(double x) const {
+        const double t = x / h;
+        double b1 = 0, b2 = 0;
+        for (int j = (int)c.size() - 1; j >= 1; --j) {
+            const double b0 = 2 * t * b1 - b2 + c[j];
+            b2 = b1;
+            b1 = b0;
+        }
+        return t * b1 - b2 + c[0];
+    }
+};
+
+template <typename T> static DevBuf upload(const std::vector<double> &v) {
+    std::vector<T> t(v.begin(), v.end());
+    DevBuf b(t.size() * sizeof(T));
+    HIP_CHECK(hipMemcpy(b.p, t.data(), b.bytes, hipMemcpyHostToDevice));
+    return b;
+}
+
+template <typename T>
+static void build_records(fr_plan *pl, const DevBuf &d_uvw, const DevBuf &d_freq, int n_p0) {
+    const int64_t n = pl->n_vis;
+    const int ntu = (int)(pl->nu / kTile), ntv = (int)(pl->nv / kTile);
+    const int n_tiles = ntu * ntv;
+    const int64_t n_keys = pl->n_chan * (int64_t)n_p0 * n_tiles;
+    FR_REQUIRE(n_keys < (int64_t(1) << 32), "too many tiles x planes x channels");
+    DevBuf key(n * 4), idx(n * 4), cell(n * 4), du(n * sizeof(T)), dv(n * sizeof(T)), dwf(n * sizeof(T)),
+        ph(n * sizeof(T));
+    const int64_t blocks = (n + 255) / 256;
+    k_vis_coords<T><<<dim3((unsigned)blocks), 256>>>(
+        d_uvw.as<double>(), d_freq.as<double>(), n, (int)pl->n_chan, ilog2(pl->nu), ilog2(pl->nv),
+        pl->dx_, pl->dy_, pl->W, pl->Ww, pl->coplanar ? 1 : 0, pl->w0, pl->dw, pl->yc, ntv, n_tiles, n_p0,
+        key.as<uint32_t>(), idx.as<uint32_t>(), cell.as<uint32_t>(), du.as<T>(), dv.as<T>(), dwf.as<T>(), ph.as<T>());
+    LAUNCH_CHECK();
+    DevBuf counts(n_keys * 4);
+    HIP_CHECK(hipMemset(counts.p, 0, counts.bytes));
+    k_hist<<<dim3((unsigned)blocks), 256>>>(key.as<uint32_t>(), n, counts.as<uint32_t>());
+    LAUNCH_CHECK();
+    std::vector<uint32_t> h_counts(n_keys);
+    HIP_CHECK(hipMemcpy(h_counts.data(), counts.p, counts.bytes, hipMemcpyDeviceToHost));
+    std::vector<int64_t> offs(n_keys);
+    int64_t run = 0;
+    std::vector<WorkItem> wis;
+    pl->wi_chan.assign(pl->n_chan + 1, 0);
+    const int ch = chunk<T>();
+    for (int64_t k = 0; k < n_keys; ++k) {
+        offs[k] = run;
+        const int64_t cnt = h_counts[k];
+        if (cnt) {
+            const int64_t chan = k / ((int64_t)n_p0 * n_tiles);
+            const int64_t rem = k - chan * n_p0 * n_tiles;
+            const int p0 = (int)(rem / n_tiles);
+            const int t = (int)(rem - (int64_t)p0 * n_tiles);
+            const int tu = t / ntv, tv = t - tu * ntv;
+            for (int64_t s = 0; s < cnt; s += ch) {
+                WorkItem w;
+                w.tu = tu * kTile;
+                w.tv = tv * kTile;
+                w.p0 = p0;
+                w.chan = (int32_t)chan;
+                w.start = run + s;
+                w.count = (int32_t)std::min<int64_t>(ch, cnt - s);
+                w.pad = 0;
+                wis.push_back(w);
+                pl->wi_chan[chan + 1] = (int64_t)wis.size();
+            }
+        }
+        run += cnt;
+    }
+    for (int64_t c = 1; c <= pl->n_chan; ++c) pl->wi_chan[c] = std::max(pl->wi_chan[c], pl->wi_chan[c - 1]);
+    DevBuf d_offs(n_keys * 8);
+    HIP_CHECK(hipMemcpy(d_offs.p, offs.data(), d_offs.bytes, hipMemcpyHostToDevice));
+    HIP_CHECK(hipMemset(counts.p, 0, counts.bytes));  // reused as the scatter cursor
+    pl->r_idx = DevBuf(n * 4);
+    pl->r_cell = DevBuf(n * 4);
+    pl->r_du = DevBuf(n * sizeof(T));
+    pl->r_dv = DevBuf(n * sizeof(T));
+    pl->r_dw = DevBuf(n * sizeof(T));
+    pl->r_ph = DevBuf(n * sizeof(T));
+    k_scatter<T><<<dim3((unsigned)blocks), 256>>>(
+        n, key.as<uint32_t>(), d_offs.as<int64_t>(), counts.as<uint32_t>(), idx.as<uint32_t>(), cell.as<uint32_t>(),
+        du.as<T>(), dv.as<T>(), dwf.as<T>(), ph.as<T>(), pl->r_idx.as<uint32_t>(), pl->r_cell.as<uint32_t>(),
+        pl->r_du.as<T>(), pl->r_dv.as<T>(), pl->r_dw.as<T>(), pl->r_ph.as<T>());
+    LAUNCH_CHECK();
+    pl->n_wi = (int64_t)wis.size();
+    pl->wi = DevBuf(std::max<size_t>(1, wis.size()) * sizeof(WorkItem));
+    if (!wis.empty()) HIP_CHECK(hipMemcpy(pl->wi.p, wis.data(), wis.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
+    HIP_CHECK(hipDeviceSynchronize());
+}
+
+void plan_build(fr_plan *pl, const double *uvw_m, const double *freq_hz) {
+    const int64_t nx = pl->nx, ny = pl->ny;
+    // --- kernel support and shape
+    // w extent after folding every visibility to w >= 0
+    double wmin = 0, wmax = 0;
+    {
+        double amin = INFINITY, amax = 0;
+        for (int64_t r = 0; r < pl->n_row; ++r) {
+            const double a = std::fabs(uvw_m[3 * r + 2]);
+            amin = std::min(amin, a);
+            amax = std::max(amax, a);
+        }
+        double fmin = INFINITY, fmax = 0;
+        for (double f : pl->freq) {
+            fmin = std::min(fmin, f);
+            fmax = std::max(fmax, f);
+        }
+        if (pl->n_row == 0) amin = amax = 0;
+        wmin = amin * fmin / kCLight;
+        wmax = amax * fmax / kCLight;
+    }
+    const double lmax = (nx / 2) * pl->dx_, mmax = (ny / 2) * pl->dy_;
+    const double ymin = n_minus_1(lmax, mmax);  // most negative n - 1 over the image
+    const bool coplanar = pl->coplanar || wmax * std::fabs(ymin) == 0.0;
+    pl->coplanar = coplanar;
+    const int dims = coplanar ? 2 : 3;
+    pl->W = es_support(pl->eps, dims, 4);
+    pl->beta = es_beta(pl->W);
+    pl->eps_bound = dims * kESAliasBound[pl->W];
+    ESKernel kuv(pl->W, pl->beta);
+    if (coplanar) {
+        pl->Ww = 1;
+        pl->wbeta = 0;
+        pl->n_planes = 1;
+        pl->w0 = 0;
+        pl->dw = 1;
+        pl->yc = 0;
+    } else {
+        pl->Ww = pl->W;
+        pl->wbeta = pl->beta;
+        const double h = -ymin / 2;  // (n - 1) - yc lies in [-h, h]
+        pl->yc = ymin / 2;
+        double dw = 1.0 / (4.0 * h);  // sigma_w = 2: dw h = 1/4
+        int npl = (int)std::ceil((wmax - wmin) / dw) + pl->Ww + 1;
+        if (pl->n_wplanes_req > 0) {
+            FR_REQUIRE(pl->n_wplanes_req >= npl, "n_wplanes is below the minimum for this epsilon (" +
+                                                     std::to_string(npl) + ")");
+            npl = pl->n_wplanes_req;
+            dw = std::min(dw, (wmax - wmin) / std::max(1, npl - pl->Ww - 1));
+            if (!(dw > 0)) dw = 1.0 / (4.0 * h);
+        }
+        pl->dw = dw;
+        pl->n_planes = npl;
+        pl->w0 = wmin - 0.5 * pl->Ww * dw;
+    }
+    ESKernel kw(pl->Ww > 1 ? pl->Ww : 4, pl->Ww > 1 ? pl->wbeta : 9.2);
+    // --- per-pixel factors
+    std::vector<double> cu(nx), cv(ny);
+    for (int64_t i = 0; i < nx; ++i) cu[i] = 1.0 / kuv.psi_hat((double)(i - nx / 2) / (double)pl->nu);
+    for (int64_t j = 0; j < ny; ++j) cv[j] = 1.0 / kuv.psi_hat((double)(j - ny / 2) / (double)pl->nv);
+    std::vector<double> fac(nx * ny), tpix(nx * ny, 0.0), nfac(nx * ny);
+    Cheb psiw([&](double t) { return kw.psi_hat(t); }, 0.25, 40);
+    for (int64_t i = 0; i < nx; ++i) {
+        const double l = (double)(i - nx / 2) * pl->dx_;
+        for (int64_t j = 0; j < ny; ++j) {
+            const double m = (double)(j - ny / 2) * pl->dy_;
+            const double y = n_minus_1(l, m);
+            const double a = pl->divide_by_n ? 1.0 / (1.0 + y) : 1.0;
+            double f = a * cu[i] * cv[j];
+            if (!coplanar) {
+                const double t = y - pl->yc;
+                tpix[i * ny + j] = t;
+                f /= psiw(pl->dw * t);
+            }
+            fac[i * ny + j] = f;
+            nfac[i * ny + j] = a;
+        }
+    }
+    std::vector<double> wpl(pl->n_planes);
+    for (int p = 0; p < pl->n_planes; ++p) wpl[p] = coplanar ? 0.0 : pl->w0 + p * pl->dw;
+    if (pl->fp64) {
+        pl->fac = upload<double>(fac);
+        pl->tpix = upload<double>(tpix);
+        pl->nfac = upload<double>(nfac);
+    } else {
+        pl->fac = upload<float>(fac);
+        pl->tpix = upload<float>(tpix);
+        pl->nfac = upload<float>(nfac);
+    }
+    pl->wplane = upload<double>(wpl);
+    // --- visibility records
+    DevBuf d_uvw(std::max<int64_t>(1, pl->n_row) * 3 * sizeof(double));
+    DevBuf d_freq(pl->n_chan * sizeof(double));
+    if (pl->n_row) HIP_CHECK(hipMemcpy(d_uvw.p, uvw_m, pl->n_row * 3 * sizeof(double), hipMemcpyHostToDevice));
+    HIP_CHECK(hipMemcpy(d_freq.p, pl->freq.data(), d_freq.bytes, hipMemcpyHostToDevice));
+    const int n_p0 = pl->n_planes - pl->Ww + 1;
+    if (pl->n_vis > 0) {
+        if (pl->fp64) build_records<double>(pl, d_uvw, d_freq, n_p0);
+        else build_records<float>(pl, d_uvw, d_freq, n_p0);
+    } else {
+        pl->wi_chan.assign(pl->n_chan + 1, 0);
+    }
+    pl->resident = pl->fac.bytes + pl->tpix.bytes + pl->nfac.bytes + pl->wplane.bytes + pl->r_idx.bytes +
+                   pl->r_cell.bytes + pl->r_du.bytes + pl->r_dv.bytes + pl->r_dw.bytes + pl->r_ph.bytes +
+                   pl->wi.bytes;
+}
+
+}  // namespace frmi

@@ -1,0 +1,88 @@
+// Opaque objects behind the C ABI and the internal entry points between
+// translation units.
+#pragma once
+
+#include "common.h"
+
+struct fr_ctx {
+    frmi::Ctx c;
+    std::vector<frmi::DevBuf> tables;
+};
+
+// Per-channel response and noise kernels of the PSF approximation (Sec. 3.3.2-3.3.3).
+struct fr_psf {
+    frmi::Ctx *ctx = nullptr;
+    int64_t nx = 0, ny = 0, n_chan = 0;
+    bool fp64 = false;
+    frmi::DevBuf KR;    // [n_chan][2nx][ny + 1] real
+    frmi::DevBuf KN;    // [n_chan][nx][ny/2 + 1] real (empty if absent)
+    frmi::DevBuf nfac;  // [nx][ny] real diagonal D (empty = identity)
+};
+
+namespace frmi {
+
+// One work item of the gridder: the visibilities [start, start + count) of the
+// sorted record arrays share a uv tile and a first w-plane.
+struct WorkItem {
+    int32_t tu, tv;   // tile origin in cells
+    int32_t p0;       // first w-plane touched (0 when coplanar)
+    int32_t chan;
+    int64_t start;
+    int32_t count;
+    int32_t pad;
+};
+
+}  // namespace frmi
+
+struct fr_plan {
+    frmi::Ctx *ctx = nullptr;
+    int64_t nx = 0, ny = 0, nu = 0, nv = 0, n_row = 0, n_chan = 0;
+    bool fp64 = false, divide_by_n = false, coplanar = true;
+    int W = 0;          // uv kernel support (cells)
+    double beta = 0;    // uv kernel shape
+    int Ww = 1;         // w kernel support (planes)
+    double wbeta = 0;
+    int n_planes = 1;
+    double w0 = 0, dw = 1, yc = 0;  // plane p at w0 + p dw; n - 1 measured from yc
+    int tile = 32;
+    double eps = 0, eps_bound = 0;
+    double dx_ = 0, dy_ = 0;  // pixel sizes (radians)
+    int n_wplanes_req = 0;
+    int64_t n_vis = 0;
+    int64_t max_wi_count = 0;
+    // per-pixel factors (precision of the plan)
+    frmi::DevBuf fac;   // [nx][ny] a / (Psi_u Psi_v Psi_w)
+    frmi::DevBuf tpix;  // [nx][ny] (n - 1) - yc, w-stacking only
+    frmi::DevBuf nfac;  // [nx][ny] a (1/n or 1)
+    frmi::DevBuf wplane;  // [n_planes] double: w of each plane
+    // sorted visibility records (structure of arrays)
+    frmi::DevBuf r_idx;   // uint32 [n_vis]: row * n_chan + chan, bit 31 = conjugate
+    frmi::DevBuf r_cell;  // uint32 [n_vis]: (a0 - tu) | (b0 - tv) << 16
+    frmi::DevBuf r_du, r_dv, r_dw, r_ph;  // T [n_vis]
+    frmi::DevBuf wi;      // WorkItem [n_wi]
+    int64_t n_wi = 0;
+    std::vector<int64_t> wi_chan;  // work-item range per channel, [n_chan + 1]
+    std::vector<double> freq;
+    size_t resident = 0;
+};
+
+namespace frmi {
+
+// gridder.hip
+void plan_build(fr_plan *pl, const double *uvw_m, const double *freq_hz);
+size_t planes_bytes(const fr_plan *pl);
+template <typename T>
+void degrid(const fr_plan *pl, const T *img, c2<T> *vis, hipStream_t st);
+template <typename T>
+void grid(const fr_plan *pl, const c2<T> *vis, const T *weight, T *img, hipStream_t st);
+
+// psfconv.hip
+template <typename T>
+void apply_rnr_approx(const fr_psf *psf, const T *x, T *y, int64_t B, hipStream_t st);
+template <typename T>
+void periodic_conv(const Ctx &ctx, const T *x, T *y, int64_t n_img, int64_t nx, int64_t ny, const T *K, int nk,
+                   int mode, hipStream_t st);
+template <typename T>
+void fft2_inplace(const Ctx &ctx, c2<T> *data, int64_t batch, int64_t n0, int64_t n1, int sign, hipStream_t st);
+
+}  // namespace frmi

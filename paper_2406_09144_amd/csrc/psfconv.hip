@@ -1,0 +1,71 @@
+// PSF-convolution response R' ~ I_PSF * (Sec. 3.3.2) and periodic convolutions
+// (noise kernel, Sec. 3.3.3; prior covariance) on the GPU.
+#include "conv.h"
+#include "fftk.h"
+#include "objects.h"
+
+namespace frmi {
+
+// y = D P^+ irfft2(K_R rfft2(P D x)): x padded into the top-left nx x ny block of
+// the 2nx x 2ny grid.  Only the nx non-zero rows are transformed along y and only
+// the nx wanted rows are kept after the column pass.
+template <typename T>
+void apply_rnr_approx(const fr_psf *psf, const T *x, T *y, int64_t B, hipStream_t st) {
+    const int64_t nx = psf->nx, ny = psf->ny, nc = psf->n_chan;
+    const int64_t n_img = B * nc;
+    if (n_img == 0) return;
+    ConvGeom g;
+    g.n_img = n_img;
+    g.rows_in = (int)nx;
+    g.rows_out = (int)nx;
+    g.n_in_cols = (int)ny;
+    g.n_out_cols = (int)ny;
+    g.log2M = ilog2(ny);      // real rows of length 2ny -> ny packed values
+    g.log2Lc = ilog2(2 * nx);  // columns of length 2nx
+    Scratch Y((size_t)n_img * nx * ny * sizeof(c2<T>), st);
+    const T *a = psf->nfac.as<T>();
+    launch_rfft_rows<T>(*psf->ctx, g, ProScaled<T>{x, a, (int)nx, (int)ny}, Y.as<c2<T>>(), st);
+    const T scale = T(1) / (T(2 * nx) * T(ny));
+    launch_conv_cols<T>(*psf->ctx, g, Y.as<c2<T>>(), psf->KR.as<T>(), (int)nc, 0, scale, st);
+    launch_irfft_rows<T>(*psf->ctx, g, EpiScaled<T>{y, a, (int)nx, (int)ny, T(1), 0}, Y.as<c2<T>>(), st);
+}
+
+// y = irfft2(K rfft2(x)) (mode 0) or irfft2(rfft2(x) / K) (mode 1) on the periodic
+// nx x ny grid; K is [nk][nx][ny/2 + 1], image g uses K[g % nk].
+template <typename T>
+void periodic_conv(const Ctx &ctx, const T *x, T *y, int64_t n_img, int64_t nx, int64_t ny, const T *K, int nk,
+                   int mode, hipStream_t st) {
+    if (n_img == 0) return;
+    ConvGeom g;
+    g.n_img = n_img;
+    g.rows_in = (int)nx;
+    g.rows_out = (int)nx;
+    g.n_in_cols = (int)ny;
+    g.n_out_cols = (int)ny;
+    g.log2M = ilog2(ny / 2);
+    g.log2Lc = ilog2(nx);
+    Scratch Y((size_t)n_img * nx * (ny / 2) * sizeof(c2<T>), st);
+    launch_rfft_rows<T>(ctx, g, ProScaled<T>{x, nullptr, (int)nx, (int)ny}, Y.as<c2<T>>(), st);
+    const T scale = T(1) / (T(nx) * T(ny / 2));
+    launch_conv_cols<T>(ctx, g, Y.as<c2<T>>(), K, nk, mode, scale, st);
+    launch_irfft_rows<T>(ctx, g, EpiScaled<T>{y, nullptr, (int)nx, (int)ny, T(1), 0}, Y.as<c2<T>>(), st);
+}
+
+template <typename T>
+void fft2_inplace(const Ctx &ctx, c2<T> *data, int64_t batch, int64_t n0, int64_t n1, int sign, hipStream_t st) {
+    const int l0 = ilog2(n0), l1 = ilog2(n1);
+    launch_fft_rows<T>(ctx, RowLoad<T>{data, l1}, RowStore<T>{data, l1}, batch * n0, l1, sign, st);
+    launch_fft_cols<T>(ctx, MatLoad<T>{data, n0 * n1, (int)n1}, MatStore<T>{data, n0 * n1, (int)n1}, batch, (int)n1,
+                       l0, (int)n0, (int)n0, sign, st);
+}
+
+template void apply_rnr_approx<float>(const fr_psf *, const float *, float *, int64_t, hipStream_t);
+template void apply_rnr_approx<double>(const fr_psf *, const double *, double *, int64_t, hipStream_t);
+template void periodic_conv<float>(const Ctx &, const float *, float *, int64_t, int64_t, int64_t, const float *, int,
+                                   int, hipStream_t);
+template void periodic_conv<double>(const Ctx &, const double *, double *, int64_t, int64_t, int64_t, const double *,
+                                    int, int, hipStream_t);
+template void fft2_inplace<float>(const Ctx &, float2 *, int64_t, int64_t, int64_t, int, hipStream_t);
+template void fft2_inplace<double>(const Ctx &, double2 *, int64_t, int64_t, int64_t, int, hipStream_t);
+
+}  // namespace frmi

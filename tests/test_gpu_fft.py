@@ -1,0 +1,30 @@
+"""The hand-written LDS Stockham FFT against numpy (FP64 on the host)."""
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+@pytest.mark.parametrize("shape", [(2, 2), (16, 32), (64, 64), (3, 256, 128), (1024, 1024), (8, 2048),
+                                   (2, 4096, 8), (2, 8192), (16384, 2), (2, 16384)])
+@pytest.mark.parametrize("fp64", [False, True])
+@pytest.mark.parametrize("sign", [-1, 1])
+def test_fft2_matches_numpy(shape, fp64, sign):
+    import torch
+    from paper_2406_09144_amd import api
+    if fp64 and max(shape[-2:]) > 8192:
+        pytest.skip("FP64 lines are limited to 8192")
+    rng = np.random.default_rng(sum(shape) + 7 * fp64 + sign)
+    x = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+    dt = torch.complex128 if fp64 else torch.complex64
+    t = torch.from_numpy(x).to(dt).cuda().contiguous()
+    api.fft2(t, sign=sign)
+    torch.cuda.synchronize()
+    ref = np.fft.fft2(x) if sign < 0 else np.fft.ifft2(x) * (shape[-1] * shape[-2])
+    err = rel(t.cpu().numpy(), ref)
+    assert err < (1e-13 if fp64 else 2e-6), err
