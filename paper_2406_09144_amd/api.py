@@ -139,3 +139,200 @@ def fft2(x, sign=-1, ctx=None, stream=None):
     L.check(_lib().fr_fft2(ctx.handle, _ptr(x), batch, n0, n1, int(sign),
                            int(x.dtype == torch.complex128), _stream(stream)))
     return x
+
+
+class Plan:
+    """Visibilities of one observation bucketed on the oversampled uv grid.
+
+    uvw: host float64 [n_row, 3] metres; freq: host float64 [n_chan] Hz;
+    nx, ny image size; dx, dy pixel sizes (radians); eps requested accuracy."""
+
+    def __init__(self, uvw, freq, nx, ny, dx, dy, eps=1e-5, fp64=False, divide_by_n=True,
+                 coplanar=False, n_wplanes=0, ctx=None, device=None):
+        import numpy as np
+        self.ctx = ctx or Context.get(device)
+        uvw = np.ascontiguousarray(uvw, dtype=np.float64).reshape(-1, 3)
+        freq = np.ascontiguousarray(np.atleast_1d(freq), dtype=np.float64)
+        flags = (L.FR_FP64 if fp64 else 0) | (L.FR_DIVIDE_BY_N if divide_by_n else 0) | \
+            (L.FR_COPLANAR if coplanar else 0)
+        h = ctypes.c_void_p()
+        L.check(_lib().fr_plan_create(self.ctx.handle, uvw.ctypes.data_as(ctypes.c_void_p), uvw.shape[0],
+                                      freq.ctypes.data_as(ctypes.c_void_p), freq.shape[0], int(nx), int(ny),
+                                      float(dx), float(dy), float(eps), flags, int(n_wplanes), ctypes.byref(h)))
+        self.handle = h
+        self.nx, self.ny = int(nx), int(ny)
+        self.n_row, self.n_chan = uvw.shape[0], freq.shape[0]
+        self.fp64 = bool(fp64)
+        self.divide_by_n = bool(divide_by_n)
+
+    @property
+    def info(self):
+        inf = L.fr_plan_info()
+        L.check(_lib().fr_plan_get_info(self.handle, ctypes.byref(inf)))
+        return inf.as_dict()
+
+    @property
+    def device(self):
+        return torch.device("cuda", self.ctx.device)
+
+    def img_shape(self, B=None):
+        s = (self.n_chan, self.nx, self.ny)
+        return s if B is None else (B,) + s
+
+    def __del__(self):
+        try:
+            if self.handle:
+                _lib().fr_plan_destroy(self.handle)
+        except Exception:
+            pass
+
+
+def _img3(plan, img, name):
+    if img.dim() == 2:
+        img = img[None]
+    return _need(img, _real_dtype(plan.fp64), plan.img_shape(), name)
+
+
+def degrid(plan, img, out=None, stream=None):
+    """R: image [n_chan, nx, ny] (or [nx, ny]) -> visibilities [n_row, n_chan] complex."""
+    img = _img3(plan, img, "img")
+    vis = out if out is not None else torch.empty((plan.n_row, plan.n_chan), dtype=_cplx_dtype(plan.fp64),
+                                                  device=img.device)
+    _need(vis, _cplx_dtype(plan.fp64), (plan.n_row, plan.n_chan), "vis")
+    L.check(_lib().fr_degrid(plan.handle, _ptr(img), _ptr(vis), _stream(stream)))
+    return vis
+
+
+def grid(plan, vis, weight=None, out=None, stream=None):
+    """R^+ N^-1: visibilities [n_row, n_chan] complex (weights real, optional) -> image [n_chan, nx, ny]."""
+    vis = _need(vis.reshape(plan.n_row, plan.n_chan), _cplx_dtype(plan.fp64), (plan.n_row, plan.n_chan), "vis")
+    if weight is not None:
+        weight = _need(weight.reshape(plan.n_row, plan.n_chan), _real_dtype(plan.fp64),
+                       (plan.n_row, plan.n_chan), "weight")
+    img = out if out is not None else torch.empty(plan.img_shape(), dtype=_real_dtype(plan.fp64), device=vis.device)
+    _need(img, _real_dtype(plan.fp64), plan.img_shape(), "img")
+    L.check(_lib().fr_grid(plan.handle, _ptr(vis), _ptr(weight), _ptr(img), _stream(stream)))
+    return img
+
+
+class Degrid(torch.autograd.Function):
+    """V = R I.  For a real loss, torch hands backward g = dL/dRe V + i dL/dIm V,
+    and dL/dI = Re R^H g = R^+ g, i.e. fr_grid without weights."""
+
+    @staticmethod
+    def forward(ctx, img, plan):
+        ctx.plan = plan
+        return degrid(plan, img.contiguous())
+
+    @staticmethod
+    def backward(ctx, g):
+        gi = grid(ctx.plan, g.contiguous())
+        return gi, None
+
+
+class Grid(torch.autograd.Function):
+    """I = R^+ (w V).  The gradient with respect to V in torch's convention is
+    w (R g), i.e. fr_degrid followed by the weights."""
+
+    @staticmethod
+    def forward(ctx, vis, plan, weight=None):
+        ctx.plan = plan
+        ctx.weight = weight
+        return grid(plan, vis.contiguous(), weight)
+
+    @staticmethod
+    def backward(ctx, g):
+        gv = degrid(ctx.plan, g.contiguous())
+        if ctx.weight is not None:
+            gv = gv * ctx.weight.reshape(gv.shape)
+        return gv, None, None
+
+
+def make_psf_kernel(plan, weight=None, eps_noise=-1e-6, stream=None):
+    """Response kernel K_R and noise kernel K_N of `plan` (weights [n_row, n_chan] or None).
+    eps_noise > 0 is the absolute regulariser; < 0 is relative to the PSF peak."""
+    if weight is not None:
+        weight = _need(weight.reshape(plan.n_row, plan.n_chan), _real_dtype(plan.fp64),
+                       (plan.n_row, plan.n_chan), "weight")
+    h = ctypes.c_void_p()
+    L.check(_lib().fr_make_psf_kernel(plan.handle, _ptr(weight), float(eps_noise), ctypes.byref(h),
+                                      _stream(stream)))
+    return PSF(h, plan.nx, plan.ny, plan.n_chan, plan.fp64, plan.ctx)
+
+
+def apply_RNR_exact(plan, x, weight=None, out=None, stream=None):
+    """R^+ N^-1 R x exactly; x [B, n_chan, nx, ny] or [n_chan, nx, ny]."""
+    squeeze = x.dim() == 3
+    xb = x[None] if squeeze else x
+    B = xb.shape[0]
+    _need(xb, _real_dtype(plan.fp64), plan.img_shape(B), "x")
+    if weight is not None:
+        weight = _need(weight.reshape(plan.n_row, plan.n_chan), _real_dtype(plan.fp64),
+                       (plan.n_row, plan.n_chan), "weight")
+    y = out if out is not None else torch.empty_like(xb)
+    L.check(_lib().fr_apply_RNR_exact(plan.handle, _ptr(weight), _ptr(xb), _ptr(y), B, _stream(stream)))
+    return y[0] if squeeze and out is None else y
+
+
+def likelihood_grad(mode, s, data, plan=None, psf=None, weight=None, i_fixed=None, inv_power=None,
+                    stream=None):
+    """(H [B] float64, grad [B, n_chan, nx, ny]) of the EXACT (data = visibilities) or FAST
+    (data = dirty image) likelihood with respect to the log-sky s [B, n_chan, nx, ny]."""
+    obj = plan if mode == L.FR_LIK_EXACT else psf
+    fp64 = obj.fp64
+    rd = _real_dtype(fp64)
+    B = s.shape[0]
+    n_chan = obj.n_chan
+    _need(s, rd, (B, n_chan, obj.nx, obj.ny), "s")
+    if mode == L.FR_LIK_EXACT:
+        _need(data, _cplx_dtype(fp64), (plan.n_row, plan.n_chan), "data")
+        if weight is not None:
+            weight = _need(weight.reshape(plan.n_row, plan.n_chan), rd, (plan.n_row, plan.n_chan), "weight")
+    else:
+        data = _need(data.reshape(n_chan, obj.nx, obj.ny), rd, (n_chan, obj.nx, obj.ny), "data")
+    if i_fixed is not None:
+        i_fixed = _need(i_fixed.reshape(n_chan, obj.nx, obj.ny), rd, (n_chan, obj.nx, obj.ny), "i_fixed")
+    if inv_power is not None:
+        inv_power = _need(inv_power, rd, (obj.nx, obj.ny // 2 + 1), "inv_power")
+    g = torch.empty_like(s)
+    H = torch.empty(B, dtype=torch.float64, device=s.device)
+    L.check(_lib().fr_likelihood_grad(plan.handle if plan is not None else None,
+                                      psf.handle if psf is not None else None, int(mode), _ptr(s), _ptr(i_fixed),
+                                      _ptr(data), _ptr(weight), _ptr(inv_power), B, _ptr(g), _ptr(H),
+                                      _stream(stream)))
+    return H, g
+
+
+def cg_solve(b, psf=None, plan=None, weight=None, inv_power=None, diag=None, maxiter=50, rtol=0.0,
+             stream=None):
+    """Solve (D R' D + S^-1) x = b by conjugate gradients; R' is the PSF convolution
+    of `psf`, or the exact operator of `plan` when psf is None.  b [n_chan, nx, ny].
+    Returns x, the residual-norm history [maxiter + 1] (float64) and the
+    iteration count (0-d int32 tensor), all on the device."""
+    obj = psf if psf is not None else plan
+    rd = _real_dtype(obj.fp64)
+    shape = (obj.n_chan, obj.nx, obj.ny)
+    b = _need(b.reshape(shape), rd, shape, "b")
+    if diag is not None:
+        diag = _need(diag.reshape(shape), rd, shape, "diag")
+    if inv_power is not None:
+        inv_power = _need(inv_power, rd, (obj.nx, obj.ny // 2 + 1), "inv_power")
+    if weight is not None:
+        weight = _need(weight.reshape(plan.n_row, plan.n_chan), rd, (plan.n_row, plan.n_chan), "weight")
+    x = torch.empty_like(b)
+    hist = torch.zeros(maxiter + 1, dtype=torch.float64, device=b.device)
+    iters = torch.zeros((), dtype=torch.int32, device=b.device)
+    L.check(_lib().fr_cg_solve(plan.handle if plan is not None else None,
+                               psf.handle if psf is not None else None, _ptr(weight), _ptr(inv_power), _ptr(diag),
+                               _ptr(b), _ptr(x), int(maxiter), float(rtol), _ptr(hist), _ptr(iters),
+                               _stream(stream)))
+    return x, hist, iters
+
+
+def query_footprint(op, B=1, plan=None, psf=None):
+    """(scratch_bytes, resident_bytes) of one call of `op` (host-only)."""
+    s, r = ctypes.c_size_t(), ctypes.c_size_t()
+    L.check(_lib().fr_query_footprint(plan.handle if plan is not None else None,
+                                      psf.handle if psf is not None else None, int(op), int(B),
+                                      ctypes.byref(s), ctypes.byref(r)))
+    return s.value, r.value

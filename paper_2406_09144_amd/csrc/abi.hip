@@ -52,6 +52,7 @@ int fr_ctx_create(int device, fr_ctx **out) {
     DeviceGuard dg(device);
     auto ctx = std::make_unique<fr_ctx>();
     ctx->c.device = device;
+    ctx->c.owner = ctx.get();
     HIP_CHECK(hipDeviceGetAttribute(&ctx->c.n_cu, hipDeviceAttributeMultiprocessorCount, device));
     // twiddle tables exp(-2 pi i m / L), computed in extended precision, rounded once
     for (int l = 1; l <= kMaxLog2FFT + 1; ++l) {
@@ -223,6 +224,7 @@ int fr_plan_create(fr_ctx *ctx, const double *uvw_m, int64_t n_row, const double
     pl->n_wplanes_req = n_wplanes;
     pl->tile = 32;
     pl->freq.assign(freq_hz, freq_hz + n_chan);
+    pl->uvw_host.assign(uvw_m, uvw_m + 3 * n_row);
     plan_build(pl.get(), uvw_m, freq_hz);
     *out = pl.release();
     FR_API_END
@@ -283,6 +285,125 @@ int fr_grid(fr_plan *pl, const void *vis, const void *weight, void *img, void *s
         grid<double>(pl, (const double2 *)vis, (const double *)weight, (double *)img, as_stream(stream));
     else
         grid<float>(pl, (const float2 *)vis, (const float *)weight, (float *)img, as_stream(stream));
+    FR_API_END
+}
+
+int fr_make_psf_kernel(fr_plan *pl, const void *weight, double eps_noise, fr_psf **out, void *stream) {
+    FR_API_BEGIN
+    FR_REQUIRE(pl && out, "plan and out are required");
+    *out = nullptr;
+    FR_REQUIRE(eps_noise != 0 && std::isfinite(eps_noise), "eps_noise must be non-zero and finite");
+    FR_REQUIRE(pl->nx <= 4096 && pl->ny <= 4096, "PSF kernels need nx, ny <= 4096 (doubled grid)");
+    FR_REQUIRE(!pl->fp64 || (pl->nx <= 2048 && pl->ny <= 2048), "FP64 PSF kernels need nx, ny <= 2048");
+    DeviceGuard dg(pl->ctx->device);
+    auto p = std::make_unique<fr_psf>();
+    p->ctx = pl->ctx;
+    p->nx = pl->nx;
+    p->ny = pl->ny;
+    p->n_chan = pl->n_chan;
+    p->fp64 = pl->fp64;
+    if (pl->fp64)
+        make_psf<double>(pl, (const double *)weight, eps_noise, p.get(), as_stream(stream));
+    else
+        make_psf<float>(pl, (const float *)weight, eps_noise, p.get(), as_stream(stream));
+    *out = p.release();
+    FR_API_END
+}
+
+int fr_apply_RNR_exact(fr_plan *pl, const void *weight, const void *x, void *y, int64_t B, void *stream) {
+    FR_API_BEGIN
+    FR_REQUIRE(pl, "plan is NULL");
+    FR_REQUIRE(B >= 0, "B must be >= 0");
+    if (B == 0) return FR_OK;
+    FR_REQUIRE(x && y && x != y, "x and y are required and must differ");
+    DeviceGuard dg(pl->ctx->device);
+    if (pl->fp64)
+        apply_rnr_exact<double>(pl, (const double *)weight, (const double *)x, (double *)y, B, as_stream(stream));
+    else
+        apply_rnr_exact<float>(pl, (const float *)weight, (const float *)x, (float *)y, B, as_stream(stream));
+    FR_API_END
+}
+
+int fr_likelihood_grad(fr_plan *pl, fr_psf *psf, int mode, const void *s, const void *i_fixed, const void *data,
+                       const void *weight, const void *inv_power, int64_t B, void *grad, double *H, void *stream) {
+    FR_API_BEGIN
+    FR_REQUIRE(mode == FR_LIK_EXACT || mode == FR_LIK_FAST, "mode must be FR_LIK_EXACT or FR_LIK_FAST");
+    FR_REQUIRE(mode != FR_LIK_EXACT || pl, "FR_LIK_EXACT needs a plan");
+    FR_REQUIRE(mode != FR_LIK_FAST || psf, "FR_LIK_FAST needs a PSF object");
+    FR_REQUIRE(mode != FR_LIK_FAST || psf->KN.p, "FR_LIK_FAST needs a PSF object with a noise kernel");
+    FR_REQUIRE(B >= 0, "B must be >= 0");
+    if (B == 0) return FR_OK;
+    FR_REQUIRE(s && data && grad && H, "s, data, grad and H are required");
+    const bool fp64 = mode == FR_LIK_FAST ? psf->fp64 : pl->fp64;
+    DeviceGuard dg(mode == FR_LIK_FAST ? psf->ctx->device : pl->ctx->device);
+    if (fp64)
+        likelihood_grad<double>(pl, psf, mode, (const double *)s, (const double *)i_fixed, data,
+                                (const double *)weight, (const double *)inv_power, B, (double *)grad, H,
+                                as_stream(stream));
+    else
+        likelihood_grad<float>(pl, psf, mode, (const float *)s, (const float *)i_fixed, data, (const float *)weight,
+                               (const float *)inv_power, B, (float *)grad, H, as_stream(stream));
+    FR_API_END
+}
+
+int fr_cg_solve(fr_plan *pl, fr_psf *psf, const void *weight, const void *inv_power, const void *diag,
+                const void *b, void *x, int maxiter, double rtol, double *resid_hist, int *iters_done, void *stream) {
+    FR_API_BEGIN
+    FR_REQUIRE(pl || psf, "a plan or a PSF object is required");
+    FR_REQUIRE(b && x && resid_hist && iters_done, "b, x, resid_hist and iters_done are required");
+    FR_REQUIRE(b != x, "x must not alias b");
+    FR_REQUIRE(maxiter >= 0 && rtol >= 0 && std::isfinite(rtol), "maxiter >= 0 and rtol >= 0 required");
+    const bool fp64 = psf ? psf->fp64 : pl->fp64;
+    if (psf && pl)
+        FR_REQUIRE(pl->nx == psf->nx && pl->ny == psf->ny && pl->n_chan == psf->n_chan && pl->fp64 == psf->fp64,
+                   "plan and PSF object disagree on shape or precision");
+    DeviceGuard dg(psf ? psf->ctx->device : pl->ctx->device);
+    if (fp64)
+        cg_solve<double>(pl, psf, (const double *)weight, (const double *)inv_power, (const double *)diag,
+                         (const double *)b, (double *)x, maxiter, rtol, resid_hist, iters_done, as_stream(stream));
+    else
+        cg_solve<float>(pl, psf, (const float *)weight, (const float *)inv_power, (const float *)diag,
+                        (const float *)b, (float *)x, maxiter, rtol, resid_hist, iters_done, as_stream(stream));
+    FR_API_END
+}
+
+int fr_query_footprint(const fr_plan *pl, const fr_psf *psf, int op, int64_t B, size_t *scratch_bytes,
+                       size_t *resident_bytes) {
+    FR_API_BEGIN
+    FR_REQUIRE(scratch_bytes && resident_bytes, "outputs are required");
+    FR_REQUIRE(B >= 0, "B must be >= 0");
+    FR_REQUIRE(op >= FR_OP_DEGRID && op <= FR_OP_MAKE_PSF, "unknown op");
+    const bool need_plan = op == FR_OP_DEGRID || op == FR_OP_GRID || op == FR_OP_RNR_EXACT ||
+                           op == FR_OP_LIK_EXACT || op == FR_OP_MAKE_PSF;
+    FR_REQUIRE(!need_plan || pl, "this op needs a plan");
+    FR_REQUIRE(need_plan || op == FR_OP_CG || psf, "this op needs a PSF object");
+    FR_REQUIRE(op != FR_OP_CG || pl || psf, "CG needs a plan or a PSF object");
+    const bool fp64 = pl ? pl->fp64 : psf->fp64;
+    const size_t rs = fp64 ? 8 : 4, cs = 2 * rs;
+    const int64_t nx = pl ? pl->nx : psf->nx, ny = pl ? pl->ny : psf->ny, nc = pl ? pl->n_chan : psf->n_chan;
+    const size_t img = (size_t)nc * nx * ny;
+    const size_t conv = img * cs;  // packed half-spectrum of one image (doubled grid: 2x rows, half width)
+    const size_t red = (size_t)std::max<int64_t>(B, 1) * 64 * sizeof(double);
+    size_t s = 0;
+    switch (op) {
+    case FR_OP_DEGRID:
+    case FR_OP_GRID: s = planes_bytes(pl); break;
+    case FR_OP_RNR_APPROX: s = B * conv; break;
+    case FR_OP_RNR_EXACT: s = planes_bytes(pl) + pl->n_vis * cs; break;
+    case FR_OP_LIK_FAST: s = 3 * B * img * rs + B * conv + red; break;
+    case FR_OP_LIK_EXACT: s = 3 * B * img * rs + planes_bytes(pl) + pl->n_vis * cs + B * conv + red; break;
+    case FR_OP_CG:
+        s = 6 * img * rs + conv + red + (psf ? 0 : planes_bytes(pl) + pl->n_vis * cs);
+        break;
+    case FR_OP_MAKE_PSF:
+        s = (size_t)nc * 16 * nx * ny * cs + (size_t)nc * 4 * nx * ny * (rs + cs) + pl->n_vis * 28;
+        break;
+    }
+    *scratch_bytes = s;
+    size_t r = 0;
+    if (pl) r += pl->resident;
+    if (psf) r += psf->KR.bytes + psf->KN.bytes + psf->nfac.bytes;
+    *resident_bytes = r;
     FR_API_END
 }
 

@@ -69,6 +69,7 @@ __device__ __forceinline__ void sincos_cycles(double x, double *s, double *c) { 
 constexpr int kMaxLog2FFT = 14;  // FFT lengths 2 .. 16384
 
 struct Ctx {
+    void *owner = nullptr;  // the fr_ctx holding this context
     int device = 0;
     int n_cu = 0;
     // twiddle tables tw[m] = exp(-2 pi i m / L), m < L, per log2 L, per precision
@@ -97,6 +98,15 @@ struct Scratch {
     Scratch(const Scratch &) = delete;
     Scratch &operator=(const Scratch &) = delete;
     Scratch(Scratch &&o) noexcept : p(o.p), s(o.s) { o.p = nullptr; }
+    Scratch &operator=(Scratch &&o) noexcept {
+        if (this != &o) {
+            if (p) (void)hipFreeAsync(p, s);
+            p = o.p;
+            s = o.s;
+            o.p = nullptr;
+        }
+        return *this;
+    }
     ~Scratch() {
         if (p) (void)hipFreeAsync(p, s);
     }

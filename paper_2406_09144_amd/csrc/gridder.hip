@@ -238,7 +238,7 @@ __global__ __launch_bounds__(NTHR) void k_grid(const WorkItem *__restrict__ wis,
             fw[k] = r_dw[pos];
             const uint32_t id = r_idx[pos];
             const uint32_t vi = id & 0x7fffffffu;
-            c2<T> val = vis[vi];
+            c2<T> val = vis ? vis[vi] : mk<T>(T(1), T(0));  // NULL: all ones (PSF)
             if (weight) {
                 const T wt = weight[vi];
                 val.x *= wt;

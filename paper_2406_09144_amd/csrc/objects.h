@@ -63,6 +63,7 @@ struct fr_plan {
     int64_t n_wi = 0;
     std::vector<int64_t> wi_chan;  // work-item range per channel, [n_chan + 1]
     std::vector<double> freq;
+    std::vector<double> uvw_host;  // [n_row][3] metres, kept to derive the PSF plan
     size_t resident = 0;
 };
 
@@ -75,6 +76,22 @@ template <typename T>
 void degrid(const fr_plan *pl, const T *img, c2<T> *vis, hipStream_t st);
 template <typename T>
 void grid(const fr_plan *pl, const c2<T> *vis, const T *weight, T *img, hipStream_t st);
+
+// psf.hip
+template <typename T>
+void make_psf(fr_plan *pl, const T *weight, double eps_noise, fr_psf *out, hipStream_t st);
+
+// lik.hip
+template <typename T>
+void apply_rnr_exact(const fr_plan *pl, const T *weight, const T *x, T *y, int64_t B, hipStream_t st);
+template <typename T>
+void likelihood_grad(const fr_plan *pl, const fr_psf *psf, int mode, const T *s, const T *i_fixed, const void *data,
+                     const T *weight, const T *inv_power, int64_t B, T *grad, double *H, hipStream_t st);
+
+// cg.hip
+template <typename T>
+void cg_solve(const fr_plan *pl, const fr_psf *psf, const T *weight, const T *inv_power, const T *diag, const T *b,
+              T *x, int maxiter, double rtol, double *hist, int *iters_done, hipStream_t st);
 
 // psfconv.hip
 template <typename T>

@@ -1,0 +1,212 @@
+"""make_psf_kernel, apply_RNR_exact and likelihood_grad against the FP64 oracle,
+plus the differentiation checks (autograd pair, finite differences).
+
+Tolerances (relative L2): K_R, K_N <= 1e-5 (FP32) / 1e-10 (FP64); PSF apply with
+GPU kernels <= 2e-5; exact R' <= 2e-5 / 1e-10; likelihood gradients <= 1e-5 (FAST),
+2e-5 (EXACT) / 1e-10; H to the same bounds.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from synthetic import make_config
+from synthetic.skies import inv_power_half, power_spectrum
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+def obs_case(name):
+    if name == "cfg1":
+        return make_config(1, n=32, n_int=24, with_sky=False)
+    if name == "cfg3_2chan":
+        return make_config(3, n=32, n_int=2, n_chan=2, with_sky=False)
+    if name == "cfg0":
+        return make_config(0, n=32, n_int=8, with_sky=False)
+    raise KeyError(name)
+
+
+def tdev(x, fp64, cplx=False):
+    import torch
+    dt = (torch.complex128 if fp64 else torch.complex64) if cplx else (torch.float64 if fp64 else torch.float32)
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dt).cuda()
+
+
+@pytest.mark.parametrize("name", ["cfg1", "cfg3_2chan", "cfg0"])
+@pytest.mark.parametrize("fp64", [False, True])
+def test_make_psf_kernel_vs_oracle(name, fp64):
+    from paper_2406_09144_amd import api
+    o = obs_case(name)
+    rng = np.random.default_rng(21)
+    wt = rng.uniform(0.5, 2.0, (o.n_row, o.n_chan))
+    pl = api.Plan(o.uvw, o.freq, o.nx, o.ny, o.dx, o.dy, eps=1e-11 if fp64 else 1e-5, fp64=fp64)
+    eps_abs = 1e-3 * wt.sum(axis=0).max()
+    psf = api.make_psf_kernel(pl, tdev(wt, fp64), eps_noise=eps_abs)
+    KR, KN = [k.cpu().numpy() for k in psf.kernels()]
+    tol = 1e-10 if fp64 else 1e-5
+    for c in range(o.n_chan):
+        p0 = O.psf0(o.uvw, o.freq, o.nx, o.ny, o.dx, o.dy, wt, chan=c)
+        assert rel(KR[c], O.response_kernel(p0)) < tol
+        kn = O.noise_kernel(p0, eps_abs)[:, : o.ny // 2 + 1]
+        assert rel(KN[c], kn) < tol
+    # relative regulariser: eps = 1e-4 x PSF peak of each channel
+    psf2 = api.make_psf_kernel(pl, tdev(wt, fp64), eps_noise=-1e-4)
+    KN2 = psf2.kernels()[1].cpu().numpy()
+    p0 = O.psf0(o.uvw, o.freq, o.nx, o.ny, o.dx, o.dy, wt, chan=0)
+    assert rel(KN2[0], O.noise_kernel(p0, 1e-4 * wt[:, 0].sum())[:, : o.ny // 2 + 1]) < tol
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+def test_psf_apply_with_gpu_kernel_and_coplanar_exactness(fp64):
+    """With w = 0 the PSF convolution equals the exact R^+ N^-1 R (Sec. 3.3.2):
+    GPU apply_RNR_approx (GPU-made kernel) vs GPU apply_RNR_exact vs the oracle."""
+    from paper_2406_09144_amd import api
+    o = make_config(0, n=32, n_int=12, with_sky=False)
+    rng = np.random.default_rng(22)
+    wt = rng.uniform(0.5, 2.0, (o.n_row, 1))
+    pl = api.Plan(o.uvw, o.freq, o.nx, o.ny, o.dx, o.dy, eps=1e-11 if fp64 else 1e-5, fp64=fp64)
+    psf = api.make_psf_kernel(pl, tdev(wt, fp64), eps_noise=-1e-3)
+    x = rng.standard_normal((2, 1, o.nx, o.ny))
+    ya = api.apply_RNR_approx(psf, tdev(x, fp64)).cpu().numpy()
+    ye = api.apply_RNR_exact(pl, tdev(x, fp64), tdev(wt, fp64)).cpu().numpy()
+    ref = O.rnr_exact(o.uvw, o.freq, o.nx, o.ny, o.dx, o.dy, x[1], wt)
+    tol = 1e-10 if fp64 else 2e-5
+    assert rel(ye[1], ref) < tol
+    assert rel(ya[1], ref) < tol
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+def test_apply_rnr_exact_wstack_vs_oracle(fp64):
+    from paper_2406_09144_amd import api
+    o = obs_case("cfg3_2chan")
+    rng = np.random.default_rng(23)
+    wt = rng.uniform(0.5, 2.0, (o.n_row, o.n_chan))
+    pl = api.Plan(o.uvw, o.freq, o.nx, o.ny, o.dx, o.dy, eps=1e-11 if fp64 else 1e-5, fp64=fp64)
+    x = rng.standard_normal((2, o.n_chan, o.nx, o.ny))
+    y = api.apply_RNR_exact(pl, tdev(x, fp64), tdev(wt, fp64)).cpu().numpy()
+    ref = O.rnr_exact(o.uvw, o.freq, o.nx, o.ny, o.dx, o.dy, x[0], wt)
+    assert rel(y[0], ref) < (1e-10 if fp64 else 2e-5)
+
+
+def _fast_inputs(n=32, seed=24, fp64=False):
+    o = make_config(1, n=n, n_int=24, with_sky=False)
+    rng = np.random.default_rng(seed)
+    wt = rng.uniform(0.5, 2.0, o.n_row)
+    p0 = O.psf0(o.uvw, o.freq, n, n, o.dx, o.dy, wt)
+    K = O.response_kernel(p0)
+    KN = O.noise_kernel(p0, 1e-3 * wt.sum())
+    a = O.n_factor(n, n, o.dx, o.dy)
+    return o, rng, K, KN, a
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+@pytest.mark.parametrize("prior", [False, True])
+def test_likelihood_fast_vs_oracle(fp64, prior):
+    import torch
+    from paper_2406_09144_amd import api
+    from paper_2406_09144_amd._lib import FR_LIK_FAST
+    n = 32
+    o, rng, K, KN, a = _fast_inputs(n)
+    psf = api.PSF.from_kernels(tdev(K[None], fp64), tdev(KN[:, : n // 2 + 1][None], fp64), tdev(a, fp64))
+    B = 3
+    s = 0.5 * rng.standard_normal((B, 1, n, n))
+    d = O.psf_conv_fft(np.exp(rng.standard_normal((n, n))), K, a) + 0.1 * rng.standard_normal((n, n))
+    ifix = np.zeros((n, n))
+    ifix[5, 9] = 3.0
+    ip = 1.0 / power_spectrum(n, n) if prior else None
+    H, g = api.likelihood_grad(FR_LIK_FAST, tdev(s, fp64), tdev(d, fp64), psf=psf, i_fixed=tdev(ifix, fp64),
+                               inv_power=tdev(ip[:, : n // 2 + 1], fp64) if prior else None)
+    torch.cuda.synchronize()
+    H, g = H.cpu().numpy(), g.cpu().numpy()
+    tol = 1e-10 if fp64 else 1e-5
+    for b in range(B):
+        Hr, gr = O.likelihood_fast(s[b, 0], d, K, KN, a, i_fixed=ifix, inv_power=ip)
+        assert abs(H[b] - Hr) < tol * abs(Hr), (b, H[b], Hr)
+        assert rel(g[b, 0], gr) < tol
+
+
+@pytest.mark.parametrize("fp64", [False, True])
+def test_likelihood_exact_vs_oracle(fp64):
+    import torch
+    from paper_2406_09144_amd import api
+    from paper_2406_09144_amd._lib import FR_LIK_EXACT
+    n = 32
+    o = make_config(1, n=n, n_int=16, with_sky=False)
+    rng = np.random.default_rng(25)
+    wt = rng.uniform(0.5, 2.0, (o.n_row, 1))
+    V = rng.standard_normal((o.n_row, 1)) + 1j * rng.standard_normal((o.n_row, 1))
+    pl = api.Plan(o.uvw, o.freq, n, n, o.dx, o.dy, eps=1e-11 if fp64 else 1e-5, fp64=fp64)
+    B = 2
+    s = 0.3 * rng.standard_normal((B, 1, n, n))
+    ip = 1.0 / power_spectrum(n, n)
+    H, g = api.likelihood_grad(FR_LIK_EXACT, tdev(s, fp64), tdev(V, fp64, cplx=True), plan=pl,
+                               weight=tdev(wt, fp64), inv_power=tdev(ip[:, : n // 2 + 1], fp64))
+    torch.cuda.synchronize()
+    H, g = H.cpu().numpy(), g.cpu().numpy()
+    fwd = lambda I: O.degrid(o.uvw, o.freq, n, n, o.dx, o.dy, I)
+    adj = lambda y: O.grid(o.uvw, o.freq, n, n, o.dx, o.dy, y)[0]
+    tol = 1e-10 if fp64 else 2e-5
+    for b in range(B):
+        Hr, gr = O.likelihood_exact(s[b, 0], V, wt, fwd, adj, inv_power=ip)
+        assert abs(H[b] - Hr) < tol * abs(Hr)
+        assert rel(g[b, 0], gr) < tol
+
+
+def test_autograd_pair_matches_handwritten_gradient():
+    """The Degrid/Grid autograd.Function pair reproduces the hand-written EXACT
+    gradient, and torch.autograd.gradcheck passes on a tiny FP64 plan."""
+    import torch
+    from paper_2406_09144_amd import api
+    from paper_2406_09144_amd._lib import FR_LIK_EXACT
+    n = 16
+    o = make_config(1, n=n, n_int=6, with_sky=False)
+    rng = np.random.default_rng(26)
+    pl = api.Plan(o.uvw, o.freq, n, n, o.dx, o.dy, eps=1e-11, fp64=True)
+    wt = torch.from_numpy(rng.uniform(0.5, 2.0, (o.n_row, 1))).cuda()
+    V = torch.from_numpy(rng.standard_normal((o.n_row, 1)) + 1j * rng.standard_normal((o.n_row, 1))).cuda()
+    s = torch.from_numpy(0.3 * rng.standard_normal((1, 1, n, n))).cuda().requires_grad_(True)
+    model = api.Degrid.apply(torch.exp(s[0]), pl)
+    H = 0.5 * (wt * (model - V).abs() ** 2).sum()
+    H.backward()
+    H2, g2 = api.likelihood_grad(FR_LIK_EXACT, s.detach(), V, plan=pl, weight=wt)
+    assert abs(H.item() - H2.item()) < 1e-12 * abs(H2.item())
+    assert rel(s.grad.cpu().numpy(), g2.cpu().numpy()) < 1e-12
+    x = torch.from_numpy(rng.standard_normal((1, n, n))).cuda().requires_grad_(True)
+    assert torch.autograd.gradcheck(lambda t: api.Degrid.apply(t, pl), (x,), eps=1e-6, atol=1e-8)
+    y = torch.from_numpy(rng.standard_normal((o.n_row, 1)) + 1j * rng.standard_normal((o.n_row, 1))).cuda()
+    y.requires_grad_(True)
+    assert torch.autograd.gradcheck(lambda t: api.Grid.apply(t, pl, wt), (y,), eps=1e-6, atol=1e-8)
+
+
+def test_fp32_gradient_vs_finite_differences():
+    """FD of the FP64-accumulated H (step 1e-4) along random directions agrees
+    with the FP32 gradient to ~1e-3 (FP32 noise in H / h bounds it)."""
+    import torch
+    from paper_2406_09144_amd import api
+    from paper_2406_09144_amd._lib import FR_LIK_FAST, FR_LIK_EXACT
+    n = 64
+    o = make_config(2, n=n, n_int=64, with_sky=False)
+    rng = np.random.default_rng(27)
+    wt = rng.uniform(0.5, 2.0, (o.n_row, 1))
+    pl = api.Plan(o.uvw, o.freq, n, n, o.dx, o.dy, eps=1e-5)
+    psf = api.make_psf_kernel(pl, tdev(wt, False), eps_noise=-1e-3)
+    V = rng.standard_normal((o.n_row, 1)) + 1j * rng.standard_normal((o.n_row, 1))
+    d = api.grid(pl, tdev(V, False, True), tdev(wt, False))
+    s0 = 0.3 * rng.standard_normal((1, 1, n, n))
+    for mode, data, kw in [(FR_LIK_FAST, d, dict(psf=psf)),
+                           (FR_LIK_EXACT, tdev(V, False, True), dict(plan=pl, weight=tdev(wt, False)))]:
+        H, g = api.likelihood_grad(mode, tdev(s0, False), data, **kw)
+        g = g.cpu().numpy().astype(np.float64)
+        for _ in range(2):
+            dd = rng.standard_normal(s0.shape)
+            dd /= np.linalg.norm(dd)
+            h = 1e-4
+            Hp, _ = api.likelihood_grad(mode, tdev(s0 + h * dd, False), data, **kw)
+            Hm, _ = api.likelihood_grad(mode, tdev(s0 - h * dd, False), data, **kw)
+            fd = (Hp.item() - Hm.item()) / (2 * h)
+            an = float(np.sum(g * dd))
+            assert abs(fd - an) < 1e-3 * max(abs(an), 1e-3 * np.linalg.norm(g)), (mode, fd, an)
