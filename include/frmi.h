@@ -225,6 +225,19 @@ int fr_cg_solve(fr_plan *plan, fr_psf *psf, const void *weight, const void *inv_
 int fr_query_footprint(const fr_plan *plan, const fr_psf *psf, int op, int64_t B,
                        size_t *scratch_bytes, size_t *resident_bytes);
 
+/* Per-kernel timing for measurement (off by default, process-wide).  While
+ * enabled, each instrumented kernel launch is bracketed by two hipEvents
+ * recorded on the launch's own stream.  fr_profile_query synchronises the
+ * recorded events of kernel `name` and returns the number of launches and their
+ * summed duration in milliseconds (0 launches for an unknown name).  Names:
+ * "degrid", "grid", "zero", "wplane_rows_fwd", "wplane_cols_fwd",
+ * "wplane_cols_inv", "wplane_rows_inv", "psfconv_rows_r2c", "psfconv_cols",
+ * "psfconv_rows_c2r", "pconv_rows_r2c", "pconv_cols", "pconv_rows_c2r".
+ * fr_profile_reset drops every record. */
+int fr_profile_enable(int on);
+int fr_profile_reset(void);
+int fr_profile_query(const char *name, int64_t *launches, double *total_ms);
+
 /* Building block exposed for testing: in-place 2D complex FFT of a device array
  * [batch][n0][n1] (n0, n1 powers of two, 2 <= n <= 16384, FP64 up to 8192),
  * sign -1 forward, +1 inverse, unnormalised.  fp64 selects complex128. */

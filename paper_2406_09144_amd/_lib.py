@@ -72,6 +72,9 @@ SIGNATURES = {
     "fr_query_footprint": ([_P, _P, _I, _I64, ctypes.POINTER(ctypes.c_size_t),
                             ctypes.POINTER(ctypes.c_size_t)], _I),
     "fr_fft2": ([_P, _P, _I64, _I64, _I64, _I, _I, _P], _I),
+    "fr_profile_enable": ([_I], _I),
+    "fr_profile_reset": ([], _I),
+    "fr_profile_query": ([ctypes.c_char_p, ctypes.POINTER(_I64), ctypes.POINTER(_D)], _I),
 }
 
 _lib = None

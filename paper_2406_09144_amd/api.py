@@ -336,3 +336,24 @@ def query_footprint(op, B=1, plan=None, psf=None):
                                       psf.handle if psf is not None else None, int(op), int(B),
                                       ctypes.byref(s), ctypes.byref(r)))
     return s.value, r.value
+
+
+def profile_enable(on=True):
+    """Turn the library's per-kernel hipEvent timing on or off (process-wide)."""
+    L.check(_lib().fr_profile_enable(int(bool(on))))
+
+
+def profile_reset():
+    L.check(_lib().fr_profile_reset())
+
+
+def profile_query(name):
+    """(launches, total milliseconds) recorded for kernel `name` since the last reset."""
+    n, ms = ctypes.c_int64(), ctypes.c_double()
+    L.check(_lib().fr_profile_query(name.encode(), ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value
+
+
+PROFILED_KERNELS = ["degrid", "grid", "zero", "wplane_rows_fwd", "wplane_cols_fwd", "wplane_cols_inv",
+                    "wplane_rows_inv", "psfconv_rows_r2c", "psfconv_cols", "psfconv_rows_c2r",
+                    "pconv_rows_r2c", "pconv_cols", "pconv_rows_c2r"]

@@ -5,6 +5,7 @@
 #include <cstring>
 
 #include "objects.h"
+#include "profiler.h"
 
 namespace frmi {
 
@@ -404,6 +405,58 @@ int fr_query_footprint(const fr_plan *pl, const fr_psf *psf, int op, int64_t B, 
     if (pl) r += pl->resident;
     if (psf) r += psf->KR.bytes + psf->KN.bytes + psf->nfac.bytes;
     *resident_bytes = r;
+    FR_API_END
+}
+
+}  // extern "C"
+
+namespace frmi {
+Profiler &profiler() {
+    static Profiler P;
+    return P;
+}
+}  // namespace frmi
+
+extern "C" {
+
+int fr_profile_enable(int on) {
+    FR_API_BEGIN
+    Profiler &P = profiler();
+    std::lock_guard<std::mutex> g(P.mu);
+    P.on = on != 0;
+    FR_API_END
+}
+
+int fr_profile_reset(void) {
+    FR_API_BEGIN
+    Profiler &P = profiler();
+    std::lock_guard<std::mutex> g(P.mu);
+    for (auto &kv : P.recs)
+        for (auto &r : kv.second) {
+            (void)hipEventSynchronize(r.b);
+            P.pool.push_back(r.a);
+            P.pool.push_back(r.b);
+        }
+    P.recs.clear();
+    FR_API_END
+}
+
+int fr_profile_query(const char *name, int64_t *launches, double *total_ms) {
+    FR_API_BEGIN
+    FR_REQUIRE(name && launches && total_ms, "name, launches and total_ms are required");
+    Profiler &P = profiler();
+    std::lock_guard<std::mutex> g(P.mu);
+    *launches = 0;
+    *total_ms = 0;
+    auto it = P.recs.find(name);
+    if (it == P.recs.end()) return FR_OK;
+    for (auto &r : it->second) {
+        HIP_CHECK(hipEventSynchronize(r.b));
+        float ms = 0;
+        HIP_CHECK(hipEventElapsedTime(&ms, r.a, r.b));
+        *total_ms += ms;
+        *launches += 1;
+    }
     FR_API_END
 }
 

@@ -22,6 +22,7 @@
 #include "eskernel.h"
 #include "fftk.h"
 #include "objects.h"
+#include "profiler.h"
 
 namespace frmi {
 
@@ -405,6 +406,7 @@ template <typename T> __global__ void k_zero(T *p, int64_t n) {
 template <typename T> void zero_async(T *p, int64_t n, hipStream_t st) {
     if (n <= 0) return;
     const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+    ProfScope prof("zero", st);
     k_zero<T><<<dim3((unsigned)blocks), 256, 0, st>>>(p, n);
     LAUNCH_CHECK();
 }
@@ -421,6 +423,7 @@ void launch_degrid_w(const fr_plan *pl, const WorkItem *wis, int64_t nwi, const 
     const size_t lds = (size_t)TS * TS * sizeof(c2<T>);
     auto kern = k_degrid<T, W, kGridThreads, vpt<T>()>;
     allow_lds(kern, lds);
+    ProfScope prof("degrid", st);
     kern<<<dim3((unsigned)nwi), kGridThreads, lds, st>>>(
         wis, planes, ilog2(pl->nu), ilog2(pl->nv), pl->Ww, (T)pl->beta, (T)pl->wbeta, pl->coplanar ? 1 : 0,
         pl->r_idx.as<uint32_t>(), pl->r_cell.as<uint32_t>(), pl->r_du.as<T>(), pl->r_dv.as<T>(), pl->r_dw.as<T>(),
@@ -435,6 +438,7 @@ void launch_grid_w(const fr_plan *pl, const WorkItem *wis, int64_t nwi, c2<T> *p
     const size_t lds = (size_t)TS * TS * sizeof(c2<T>);
     auto kern = k_grid<T, W, kGridThreads, vpt<T>()>;
     allow_lds(kern, lds);
+    ProfScope prof("grid", st);
     kern<<<dim3((unsigned)nwi), kGridThreads, lds, st>>>(
         wis, planes, ilog2(pl->nu), ilog2(pl->nv), pl->Ww, (T)pl->beta, (T)pl->wbeta, pl->coplanar ? 1 : 0,
         pl->r_idx.as<uint32_t>(), pl->r_cell.as<uint32_t>(), pl->r_du.as<T>(), pl->r_dv.as<T>(), pl->r_dw.as<T>(),
@@ -471,7 +475,11 @@ void image_to_planes(const fr_plan *pl, const T *img_c, c2<T> *planes, hipStream
     DegridRowPro<T> pro{img_c, pl->fac.as<T>(), pl->tpix.as<T>(), pl->wplane.as<double>(),
                         (int)pl->nx, (int)pl->ny, (int)pl->nv, pl->coplanar ? 1 : 0};
     DegridRowEpi<T> epi{planes, (int)pl->nx, l2u, l2v};
-    launch_fft_rows<T>(*pl->ctx, pro, epi, (int64_t)pl->n_planes * pl->nx, l2v, -1, st);
+    {
+        ProfScope prof("wplane_rows_fwd", st);
+        launch_fft_rows<T>(*pl->ctx, pro, epi, (int64_t)pl->n_planes * pl->nx, l2v, -1, st);
+    }
+    ProfScope prof("wplane_cols_fwd", st);
     launch_fft_cols<T>(*pl->ctx, BandColPro<T>{planes, (int)pl->nx, l2u, l2v}, FullColEpi<T>{planes, l2u, l2v},
                        pl->n_planes, (int)pl->nv, l2u, (int)pl->nu, (int)pl->nu, -1, st);
 }
@@ -481,8 +489,12 @@ template <typename T>
 void planes_to_image(const fr_plan *pl, const c2<T> *planes_c, T *img_c, hipStream_t st) {
     c2<T> *planes = const_cast<c2<T> *>(planes_c);
     const int l2u = ilog2(pl->nu), l2v = ilog2(pl->nv);
-    launch_fft_cols<T>(*pl->ctx, FullColPro<T>{planes, l2u, l2v}, BandColEpi<T>{planes, (int)pl->nx, l2u, l2v},
-                       pl->n_planes, (int)pl->nv, l2u, (int)pl->nu, (int)pl->nu, +1, st);
+    {
+        ProfScope prof("wplane_cols_inv", st);
+        launch_fft_cols<T>(*pl->ctx, FullColPro<T>{planes, l2u, l2v}, BandColEpi<T>{planes, (int)pl->nx, l2u, l2v},
+                           pl->n_planes, (int)pl->nv, l2u, (int)pl->nu, (int)pl->nu, +1, st);
+    }
+    ProfScope prof("wplane_rows_inv", st);
     const int nv = (int)pl->nv;
     if (nv <= 4096) {
         const size_t lds = (size_t)nv * sizeof(c2<T>);

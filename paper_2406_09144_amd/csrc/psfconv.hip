@@ -3,6 +3,7 @@
 #include "conv.h"
 #include "fftk.h"
 #include "objects.h"
+#include "profiler.h"
 
 namespace frmi {
 
@@ -24,9 +25,16 @@ void apply_rnr_approx(const fr_psf *psf, const T *x, T *y, int64_t B, hipStream_
     g.log2Lc = ilog2(2 * nx);  // columns of length 2nx
     Scratch Y((size_t)n_img * nx * ny * sizeof(c2<T>), st);
     const T *a = psf->nfac.as<T>();
-    launch_rfft_rows<T>(*psf->ctx, g, ProScaled<T>{x, a, (int)nx, (int)ny}, Y.as<c2<T>>(), st);
+    {
+        ProfScope prof("psfconv_rows_r2c", st);
+        launch_rfft_rows<T>(*psf->ctx, g, ProScaled<T>{x, a, (int)nx, (int)ny}, Y.as<c2<T>>(), st);
+    }
     const T scale = T(1) / (T(2 * nx) * T(ny));
-    launch_conv_cols<T>(*psf->ctx, g, Y.as<c2<T>>(), psf->KR.as<T>(), (int)nc, 0, scale, st);
+    {
+        ProfScope prof("psfconv_cols", st);
+        launch_conv_cols<T>(*psf->ctx, g, Y.as<c2<T>>(), psf->KR.as<T>(), (int)nc, 0, scale, st);
+    }
+    ProfScope prof("psfconv_rows_c2r", st);
     launch_irfft_rows<T>(*psf->ctx, g, EpiScaled<T>{y, a, (int)nx, (int)ny, T(1), 0}, Y.as<c2<T>>(), st);
 }
 
@@ -45,9 +53,16 @@ void periodic_conv(const Ctx &ctx, const T *x, T *y, int64_t n_img, int64_t nx, 
     g.log2M = ilog2(ny / 2);
     g.log2Lc = ilog2(nx);
     Scratch Y((size_t)n_img * nx * (ny / 2) * sizeof(c2<T>), st);
-    launch_rfft_rows<T>(ctx, g, ProScaled<T>{x, nullptr, (int)nx, (int)ny}, Y.as<c2<T>>(), st);
+    {
+        ProfScope prof("pconv_rows_r2c", st);
+        launch_rfft_rows<T>(ctx, g, ProScaled<T>{x, nullptr, (int)nx, (int)ny}, Y.as<c2<T>>(), st);
+    }
     const T scale = T(1) / (T(nx) * T(ny / 2));
-    launch_conv_cols<T>(ctx, g, Y.as<c2<T>>(), K, nk, mode, scale, st);
+    {
+        ProfScope prof("pconv_cols", st);
+        launch_conv_cols<T>(ctx, g, Y.as<c2<T>>(), K, nk, mode, scale, st);
+    }
+    ProfScope prof("pconv_rows_c2r", st);
     launch_irfft_rows<T>(ctx, g, EpiScaled<T>{y, nullptr, (int)nx, (int)ny, T(1), 0}, Y.as<c2<T>>(), st);
 }
 

@@ -24,7 +24,8 @@ def system(n=32, seed=31):
     rng = np.random.default_rng(seed)
     wt = rng.uniform(0.5, 2.0, o.n_row)
     p0 = O.psf0(o.uvw, o.freq, n, n, o.dx, o.dy, wt)
-    K = O.response_kernel(p0) / p0.max()
+    K = O.response_kernel(p0)
+    K = K / np.abs(K).max()  # R' eigenvalues in [0, 1]: kappa(A) stays below ~1e2
     ip = 1.0 / power_spectrum(n, n)
     ip = ip / ip.max() + 0.05
     a = O.n_factor(n, n, o.dx, o.dy)
@@ -80,34 +81,37 @@ def test_cg_fp64_converges_to_dense_solution_and_rtol_stops():
     assert h[k] <= 1e-12 * h[0] and h[k - 1] > 1e-12 * h[0]
 
 
-def test_cg_fp32_residual_at_config2_scale():
-    """50 iterations at N = 512 (the configuration's size): FP32 vectors, FP64
-    scalars; the true residual of the returned x agrees with the recorded one
-    and both decrease."""
+def test_cg_fp32_at_config2_scale_vs_oracle():
+    """50 iterations at N = 512 (the differentiated-likelihood workload's size):
+    FP32 vectors with FP64 scalars against the FP64 oracle CG on the same system.
+    Stated per result: relative distance of x and the ratio of true residuals."""
     import torch
     from paper_2406_09144_amd import api
     n = 512
-    o = make_config(2, n=n, n_int=64, with_sky=False)
+    o = make_config(2, n=n, n_int=16, with_sky=False)
     rng = np.random.default_rng(33)
-    wt = torch.from_numpy(rng.uniform(0.5, 2.0, (o.n_row, 1))).float().cuda()
-    pl = api.Plan(o.uvw, o.freq, n, n, o.dx, o.dy, eps=1e-5)
-    psf = api.make_psf_kernel(pl, wt, eps_noise=-1e-4)
-    KR = psf.kernels()[0]
-    scale = float(KR.abs().max())
-    ip = torch.from_numpy(1.0 / power_spectrum(n, n)[:, : n // 2 + 1]).float().cuda() * scale * 1e-3
-    b = torch.from_numpy(rng.standard_normal((1, n, n))).float().cuda()
-    x, hist, it = api.cg_solve(b, psf=psf, inv_power=ip, maxiter=50)
+    wt = rng.uniform(0.5, 2.0, o.n_row)
+    p0 = O.psf0(o.uvw, o.freq, n, n, o.dx, o.dy, wt)
+    K = O.response_kernel(p0)
+    ip = 1.0 / power_spectrum(n, n)
+    ip = ip * (np.abs(K).max() * 1e-3 / ip.min())  # prior floor at 1e-3 of the PSF spectrum peak
+    a = O.n_factor(n, n, o.dx, o.dy)
+    b = rng.standard_normal((n, n))
+    psf = api.PSF.from_kernels(tdev(K[None], False), nfac=tdev(a, False))
+    x, hist, it = api.cg_solve(tdev(b[None], False), psf=psf, inv_power=tdev(ip[:, : n // 2 + 1], False),
+                               maxiter=50)
     torch.cuda.synchronize()
     assert int(it) == 50
-    h = hist.cpu().numpy()
-    assert h[50] < 0.5 * h[0]
-    Ax = api.apply_RNR_approx(psf, x[None])[0]
-    # prior term through numpy on the host (independent of the library)
-    xs = x.cpu().numpy().astype(np.float64)[0]
-    ipf = (1.0 / power_spectrum(n, n)) * scale * 1e-3
-    Ax = Ax.cpu().numpy().astype(np.float64)[0] + np.real(np.fft.ifft2(np.fft.fft2(xs) * ipf))
-    true_res = np.linalg.norm(b.cpu().numpy()[0] - Ax)
-    assert abs(true_res - h[50]) < 0.05 * h[0]
+    op = lambda v: O.metric_apply(v, K, ip, a)
+    xr, hr = O.cg(op, b, maxiter=50)
+    xg = x.cpu().numpy().astype(np.float64)[0]
+    dist = rel(xg, xr)
+    res_g = np.linalg.norm(b - op(xg))
+    res_o = np.linalg.norm(b - op(xr))
+    print(f"config-2 CG: ||x - x_oracle|| / ||x_oracle|| = {dist:.3e}, "
+          f"true residual GPU / oracle = {res_g / res_o:.4f}, oracle ||r50||/||b|| = {res_o / hr[0]:.3e}")
+    assert dist < 1e-2
+    assert res_g < 1.5 * res_o
 
 
 def test_cg_exact_operator_fp64():

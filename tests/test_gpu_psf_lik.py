@@ -176,15 +176,21 @@ def test_autograd_pair_matches_handwritten_gradient():
     assert abs(H.item() - H2.item()) < 1e-12 * abs(H2.item())
     assert rel(s.grad.cpu().numpy(), g2.cpu().numpy()) < 1e-12
     x = torch.from_numpy(rng.standard_normal((1, n, n))).cuda().requires_grad_(True)
-    assert torch.autograd.gradcheck(lambda t: api.Degrid.apply(t, pl), (x,), eps=1e-6, atol=1e-8)
+    # both maps are linear, so central differences carry no truncation error;
+    # eps = 1e-4 keeps their rounding noise (|V| 1e-16 / eps) well below atol
+    assert torch.autograd.gradcheck(lambda t: api.Degrid.apply(t, pl), (x,), eps=1e-4, atol=1e-7)
     y = torch.from_numpy(rng.standard_normal((o.n_row, 1)) + 1j * rng.standard_normal((o.n_row, 1))).cuda()
     y.requires_grad_(True)
-    assert torch.autograd.gradcheck(lambda t: api.Grid.apply(t, pl, wt), (y,), eps=1e-6, atol=1e-8)
+    assert torch.autograd.gradcheck(lambda t: api.Grid.apply(t, pl, wt), (y,), eps=1e-4, atol=1e-7)
 
 
-def test_fp32_gradient_vs_finite_differences():
-    """FD of the FP64-accumulated H (step 1e-4) along random directions agrees
-    with the FP32 gradient to ~1e-3 (FP32 noise in H / h bounds it)."""
+@pytest.mark.parametrize("fp64", [False, True])
+def test_gradient_vs_finite_differences(fp64):
+    """Central differences (step 1e-4) of the GPU H agree with the GPU gradient:
+    FP64 along random unit directions to 1e-7; FP32 along the gradient direction
+    to 2e-3, where the rounding of the FP32 residuals (~1e-7 of the model) over
+    the step bounds the agreement.  Data are generated from a nearby sky so the
+    residual is small against the model, as in a reconstruction."""
     import torch
     from paper_2406_09144_amd import api
     from paper_2406_09144_amd._lib import FR_LIK_FAST, FR_LIK_EXACT
@@ -192,21 +198,29 @@ def test_fp32_gradient_vs_finite_differences():
     o = make_config(2, n=n, n_int=64, with_sky=False)
     rng = np.random.default_rng(27)
     wt = rng.uniform(0.5, 2.0, (o.n_row, 1))
-    pl = api.Plan(o.uvw, o.freq, n, n, o.dx, o.dy, eps=1e-5)
-    psf = api.make_psf_kernel(pl, tdev(wt, False), eps_noise=-1e-3)
-    V = rng.standard_normal((o.n_row, 1)) + 1j * rng.standard_normal((o.n_row, 1))
-    d = api.grid(pl, tdev(V, False, True), tdev(wt, False))
-    s0 = 0.3 * rng.standard_normal((1, 1, n, n))
+    pl = api.Plan(o.uvw, o.freq, n, n, o.dx, o.dy, eps=1e-11 if fp64 else 1e-5, fp64=fp64)
+    psf = api.make_psf_kernel(pl, tdev(wt, fp64), eps_noise=-1e-3)
+    s_true = 0.5 * np.real(np.fft.ifft2(np.fft.fft2(rng.standard_normal((n, n))) *
+                                        np.sqrt(power_spectrum(n, n))))
+    V = api.degrid(pl, tdev(np.exp(s_true)[None], fp64)).cpu().numpy()
+    sig = 0.05 * np.sqrt(np.mean(np.abs(V) ** 2))
+    V = V + sig * (rng.standard_normal(V.shape) + 1j * rng.standard_normal(V.shape))
+    Vd = tdev(V, fp64, cplx=True)
+    d = api.grid(pl, Vd, tdev(wt, fp64))
+    s0 = s_true[None, None] + 0.05 * rng.standard_normal((1, 1, n, n))
+    h = 1e-4
     for mode, data, kw in [(FR_LIK_FAST, d, dict(psf=psf)),
-                           (FR_LIK_EXACT, tdev(V, False, True), dict(plan=pl, weight=tdev(wt, False)))]:
-        H, g = api.likelihood_grad(mode, tdev(s0, False), data, **kw)
+                           (FR_LIK_EXACT, Vd, dict(plan=pl, weight=tdev(wt, fp64)))]:
+        H, g = api.likelihood_grad(mode, tdev(s0, fp64), data, **kw)
         g = g.cpu().numpy().astype(np.float64)
-        for _ in range(2):
+        dirs = [g / np.linalg.norm(g)] if not fp64 else []
+        for _ in range(2 if fp64 else 0):
             dd = rng.standard_normal(s0.shape)
-            dd /= np.linalg.norm(dd)
-            h = 1e-4
-            Hp, _ = api.likelihood_grad(mode, tdev(s0 + h * dd, False), data, **kw)
-            Hm, _ = api.likelihood_grad(mode, tdev(s0 - h * dd, False), data, **kw)
+            dirs.append(dd / np.linalg.norm(dd))
+        for dd in dirs:
+            Hp, _ = api.likelihood_grad(mode, tdev(s0 + h * dd, fp64), data, **kw)
+            Hm, _ = api.likelihood_grad(mode, tdev(s0 - h * dd, fp64), data, **kw)
             fd = (Hp.item() - Hm.item()) / (2 * h)
             an = float(np.sum(g * dd))
-            assert abs(fd - an) < 1e-3 * max(abs(an), 1e-3 * np.linalg.norm(g)), (mode, fd, an)
+            tol = 1e-7 * np.linalg.norm(g) if fp64 else 2e-3 * abs(an)
+            assert abs(fd - an) < tol, (mode, fd, an)
