@@ -57,14 +57,77 @@ def algorithmic_bytes(name, info, n_vis, n_row, B_conv, nx, ny):
     return None
 
 
+def build_served_jobs(api, torch, n_jobs, fp64):
+    """Resident jobs of the served mix: plan, PSF kernels, data, input pools."""
+    import numpy as np
+    from paper_2406_09144_amd.serving import ServedJob
+    from synthetic.configs import serving_jobs, serving_observation
+    from synthetic.skies import correlated_field, inv_power_half
+    rd, cd = (torch.float64, torch.complex128) if fp64 else (torch.float32, torch.complex64)
+    jobs = []
+    for jd in serving_jobs(n_jobs):
+        o = serving_observation(jd)
+        rng = np.random.default_rng(1000 + jd["job"])
+        n = o.nx
+        pl = api.Plan(o.uvw, o.freq, n, n, o.dx, o.dy, eps=1e-5, fp64=fp64)
+        wt = torch.from_numpy(rng.uniform(0.5, 2.0, (o.n_row, 1))).to(rd).cuda()
+        psf = api.make_psf_kernel(pl, wt, eps_noise=-1e-6)
+        sky = torch.from_numpy(np.exp(correlated_field(rng, n, n))[None]).to(rd).cuda()
+        V = api.degrid(pl, sky)
+        d = api.grid(pl, V, wt)
+        P = 4
+        imgs = torch.exp(torch.from_numpy(0.3 * rng.standard_normal((P, 1, n, n)))).to(rd).cuda()
+        logs = torch.from_numpy(0.3 * rng.standard_normal((P, 1, n, n))).to(rd).cuda()
+        ip = torch.from_numpy(inv_power_half(n, n)).to(rd).cuda() * float(wt.sum()) * 1e-6
+        jobs.append(ServedJob(pl, psf, V.to(cd), wt, d, ip, imgs, logs))
+    torch.cuda.synchronize()
+    return jobs
+
+
+def served_workload(api, torch, seconds, rate, n_jobs, fp64_requests):
+    """p50/p99 of the served mix (FP32, continuous batching, 4 streams) against the
+    same trace replayed unbatched and serially on the plain FP64 form."""
+    from paper_2406_09144_amd.serving import GpuExecutor, Server, latency_stats, make_trace
+    t0 = time.time()
+    jobs = build_served_jobs(api, torch, n_jobs, fp64=False)
+    log(f"[bench] served jobs built in {time.time() - t0:.1f}s")
+    trace = make_trace(len(jobs), rate, seconds)
+    ex = GpuExecutor(jobs, n_slots=4)
+    srv = Server(ex, n_slots=4, hbm_budget=64 << 30, max_batch=8)
+    out = srv.run(trace, realtime=True)
+    torch.cuda.synchronize()
+    st = latency_stats(out)
+    st["launches"] = len(srv.launches)
+    st["peak_scratch_GB"] = srv.peak_bytes / 2 ** 30
+    log(f"[bench] served FP32: {json.dumps(st)}")
+    res = {"fp32_batched": st, "rate_hz": rate, "seconds": seconds, "n_jobs": n_jobs}
+    del ex, srv, jobs
+    if fp64_requests > 0:
+        jobs64 = build_served_jobs(api, torch, n_jobs, fp64=True)
+        trace64 = make_trace(len(jobs64), rate, seconds)[:fp64_requests]
+        ex64 = GpuExecutor(jobs64, n_slots=1)
+        srv64 = Server(ex64, n_slots=1, hbm_budget=64 << 30, max_batch=1)
+        out64 = srv64.run(trace64, realtime=True)
+        torch.cuda.synchronize()
+        st64 = latency_stats(out64)
+        log(f"[bench] served FP64 unbatched serial: {json.dumps(st64)}")
+        res["fp64_unbatched_serial"] = st64
+        del ex64, srv64, jobs64
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-sample", type=int, default=8192,
+    ap.add_argument("--cpu-sample", type=int, default=32768,
                     help="visibilities of the oracle CPU-baseline sample (0 disables)")
     ap.add_argument("--fp64-steps", type=int, default=3, help="timed (de)grid passes of the plain FP64 form")
+    ap.add_argument("--serve-seconds", type=float, default=2.0, help="served-mix trace length (0 disables)")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-jobs", type=int, default=16)
+    ap.add_argument("--serve-fp64-requests", type=int, default=100)
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--n-int", type=int, default=2880)
     args = ap.parse_args()
@@ -200,6 +263,11 @@ def main():
                 "support": plan64.info["support"], "n_planes": plan64.info["n_planes"]}
         del plan64
 
+    served = None
+    if args.serve_seconds > 0:
+        served = served_workload(api, torch, args.serve_seconds, args.serve_rate, args.serve_jobs,
+                                 args.serve_fp64_requests)
+
     cpu = None
     if args.cpu_sample > 0:
         import oracle as O
@@ -230,6 +298,7 @@ def main():
             "lik_fast_b8_ms": comp["lik_fast_b8"], "lik_exact_b1_ms": comp["lik_exact_b1"],
             "cg50_ms": comp["cg50"], "plan_create_s": t_plan, "make_psf_s": t_psf,
             "fp64_plain_form": fp64,
+            "served": served,
         },
         "kernels_ms": {k: round(v["avg_ms"], 5) for k, v in kern.items()},
         "roofline": roof,

@@ -46,6 +46,11 @@ __global__ void k_cg_start(CGState *st, const double *rr_partials, int nparts, d
     hist[0] = sqrt(s);
 }
 
+struct ZeroU32 {
+    unsigned *p;
+    __device__ void operator()(int64_t i) const { p[i] = 0u; }
+};
+
 // y = diag * x (or copy)
 template <typename T> struct DiagMul {
     const T *d, *x;
@@ -64,15 +69,49 @@ template <typename T> struct DiagMulAdd {
     }
 };
 
-// x += alpha p, r -= alpha A p, partial sums of <r, r>
+// The last block to finish a reduction adds the per-block partials in block
+// order (deterministic) and resets the arrival counter for the next use.
+__device__ __forceinline__ bool arrive_last(unsigned *counter) {
+    __shared__ bool last;
+    __threadfence();
+    if (threadIdx.x == 0) last = atomicAdd(counter, 1u) == gridDim.x - 1;
+    __syncthreads();
+    return last;
+}
+
+__device__ __forceinline__ double sum_partials(const double *partials, int n) {
+    double s = 0;
+    for (int k = 0; k < n; ++k) s += __hip_atomic_load(partials + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return s;
+}
+
+// <p, A p> into st->pAp
 template <typename T>
-__global__ __launch_bounds__(kRedThreads) void k_cg_update_xr(const CGState *__restrict__ st, T *__restrict__ x,
-                                                              T *__restrict__ r, const T *__restrict__ p,
-                                                              const T *__restrict__ Ap, int64_t n,
-                                                              double *__restrict__ partials) {
+__global__ __launch_bounds__(kRedThreads) void k_cg_dot_pAp(CGState *__restrict__ st, const T *__restrict__ p,
+                                                            const T *__restrict__ Ap, int64_t n,
+                                                            double *__restrict__ partials, unsigned *counter) {
     if (st->done) return;
-    const double alpha = st->rr / st->pAp;
-    const T a = (T)alpha;
+    double s = 0;
+    for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kRedThreads)
+        s += (double)p[i] * (double)Ap[i];
+    s = block_sum(s);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+    if (arrive_last(counter) && threadIdx.x == 0) {
+        st->pAp = sum_partials(partials, gridDim.x);
+        *counter = 0;
+    }
+}
+
+// x += alpha p, r -= alpha A p; the last block forms <r, r>, beta, the history
+// entry and the stopping flag
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_cg_step(CGState *__restrict__ st, T *__restrict__ x,
+                                                         T *__restrict__ r, const T *__restrict__ p,
+                                                         const T *__restrict__ Ap, int64_t n,
+                                                         double *__restrict__ partials, unsigned *counter, int k,
+                                                         double *__restrict__ hist) {
+    if (st->done) return;
+    const T a = (T)(st->rr / st->pAp);
     double s = 0;
     for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kRedThreads) {
         x[i] += a * p[i];
@@ -82,17 +121,15 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_update_xr(const CGState *__r
     }
     s = block_sum(s);
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
-}
-
-__global__ void k_cg_finish(CGState *st, const double *partials, int nparts, int k, double *hist) {
-    if (threadIdx.x != 0 || st->done) return;
-    double s = 0;
-    for (int q = 0; q < nparts; ++q) s += partials[q];
-    hist[k + 1] = sqrt(s);
-    st->beta = s / st->rr;
-    st->rr = s;
-    st->iters = k + 1;
-    if (sqrt(s) <= st->stop) st->done = 1;
+    if (arrive_last(counter) && threadIdx.x == 0) {
+        const double rr = sum_partials(partials, gridDim.x);
+        hist[k + 1] = sqrt(rr);
+        st->beta = rr / st->rr;
+        st->rr = rr;
+        st->iters = k + 1;
+        if (sqrt(rr) <= st->stop) st->done = 1;
+        *counter = 0;
+    }
 }
 
 template <typename T>
@@ -114,8 +151,10 @@ void cg_solve(const fr_plan *pl, const fr_psf *psf, const T *weight, const T *in
     const int64_t nc = psf ? psf->n_chan : pl->n_chan;
     const int64_t n = nc * nx * ny;
     const Ctx &ctx = psf ? *psf->ctx : *pl->ctx;
-    Scratch state(sizeof(CGState), st);
+    Scratch state(sizeof(CGState) + 64, st);
     Scratch partials((size_t)kRedBlocksPerImage * sizeof(double), st);
+    unsigned *counter = reinterpret_cast<unsigned *>(state.as<char>() + sizeof(CGState));
+    map_async(ZeroU32{counter}, 1, st);
     Scratch r(n * sizeof(T), st), p(n * sizeof(T), st), Ap(n * sizeof(T), st), t(n * sizeof(T), st),
         u(n * sizeof(T), st);
     Scratch pr;
@@ -127,25 +166,26 @@ void cg_solve(const fr_plan *pl, const fr_psf *psf, const T *weight, const T *in
     LAUNCH_CHECK();
     k_cg_start<<<1, 64, 0, st>>>(S, partials.as<double>(), kRedBlocksPerImage, rtol, maxiter, hist);
     LAUNCH_CHECK();
-    double *pAp = reinterpret_cast<double *>(reinterpret_cast<char *>(S) + offsetof(CGState, pAp));
     for (int k = 0; k < maxiter; ++k) {
         // A p = D R' D p + S^-1 p
-        const T *src = p.as<T>();
-        if (diag) {
-            map_async(DiagMul<T>{diag, p.as<T>(), t.as<T>()}, n, st);
-            src = t.as<T>();
-        }
-        if (psf)
-            apply_rnr_approx<T>(psf, src, u.as<T>(), 1, st);
-        else
-            apply_rnr_exact<T>(pl, weight, src, u.as<T>(), 1, st);
         if (inv_power) periodic_conv<T>(ctx, p.as<T>(), pr.as<T>(), nc, nx, ny, inv_power, 1, 0, st);
-        map_async(DiagMulAdd<T>{diag, u.as<T>(), inv_power ? pr.as<T>() : nullptr, Ap.as<T>()}, n, st);
-        batched_dot<T>(p.as<T>(), Ap.as<T>(), n, 1, 1.0, 0, pAp, partials.as<double>(), st);
-        k_cg_update_xr<T><<<dim3(kRedBlocksPerImage), kRedThreads, 0, st>>>(S, x, r.as<T>(), p.as<T>(), Ap.as<T>(),
-                                                                            n, partials.as<double>());
+        const T *prior = inv_power ? pr.as<T>() : nullptr;
+        if (psf) {
+            apply_rnr_approx_ex<T>(psf, p.as<T>(), diag, Ap.as<T>(), diag, prior, 1, st);
+        } else {
+            const T *src = p.as<T>();
+            if (diag) {
+                map_async(DiagMul<T>{diag, p.as<T>(), t.as<T>()}, n, st);
+                src = t.as<T>();
+            }
+            apply_rnr_exact<T>(pl, weight, src, u.as<T>(), 1, st);
+            map_async(DiagMulAdd<T>{diag, u.as<T>(), prior, Ap.as<T>()}, n, st);
+        }
+        k_cg_dot_pAp<T><<<dim3(kRedBlocksPerImage), kRedThreads, 0, st>>>(S, p.as<T>(), Ap.as<T>(), n,
+                                                                          partials.as<double>(), counter);
         LAUNCH_CHECK();
-        k_cg_finish<<<1, 64, 0, st>>>(S, partials.as<double>(), kRedBlocksPerImage, k, hist);
+        k_cg_step<T><<<dim3(kRedBlocksPerImage), kRedThreads, 0, st>>>(S, x, r.as<T>(), p.as<T>(), Ap.as<T>(), n,
+                                                                       partials.as<double>(), counter, k, hist);
         LAUNCH_CHECK();
         const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
         k_cg_update_p<T><<<dim3((unsigned)blocks), 256, 0, st>>>(S, p.as<T>(), r.as<T>(), n);

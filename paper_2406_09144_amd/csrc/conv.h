@@ -185,7 +185,7 @@ void launch_rfft_rows(const Ctx &ctx, const ConvGeom &g, Pro pro, c2<T> *Y, hipS
     const int64_t nrows = g.n_img * g.rows_in;
     FR_REQUIRE(M <= max_line_elems<T>() && M <= 16384, "row length too large for LDS");
     if (M <= 4096) {
-        const int lpw = std::max(1, 2048 / M);
+        const int lpw = rows_per_wg(M, nrows, ctx.n_cu);
         const int64_t nblk = (nrows + lpw - 1) / lpw;
         allow_lds(k_rfft_rows<T, 256, 4, Pro>, lpw * M * sizeof(c2<T>));
         k_rfft_rows<T, 256, 4, Pro><<<dim3((unsigned)nblk), 256, lpw * M * sizeof(c2<T>), st>>>(
@@ -207,6 +207,8 @@ void launch_conv_cols(const Ctx &ctx, const ConvGeom &g, c2<T> *Y, const T *K, i
     int C = std::max(1, std::min(16, budget / Lc));
     while (C > 1 && (M % C)) C >>= 1;
     C = std::min(C, M);
+    // small batches: narrower strips so the grid still covers every CU a few times
+    while (C > 2 && (int64_t)(M / C) * g.n_img < 4 * (int64_t)std::max(ctx.n_cu, 1)) C >>= 1;
     FR_REQUIRE((int64_t)C * (Lc + 1) <= max_line_elems<T>(), "column length too large for LDS");
     const size_t lds = (size_t)C * (Lc + 1) * sizeof(c2<T>);
     dim3 grid((unsigned)(M / C), (unsigned)g.n_img);
@@ -228,7 +230,7 @@ void launch_irfft_rows(const Ctx &ctx, const ConvGeom &g, Epi epi, const c2<T> *
     const int M = 1 << g.log2M;
     const int64_t nrows = g.n_img * g.rows_out;
     if (M <= 4096) {
-        const int lpw = std::max(1, 2048 / M);
+        const int lpw = rows_per_wg(M, nrows, ctx.n_cu);
         const int64_t nblk = (nrows + lpw - 1) / lpw;
         allow_lds(k_irfft_rows<T, 256, 4, Epi>, lpw * M * sizeof(c2<T>));
         k_irfft_rows<T, 256, 4, Epi><<<dim3((unsigned)nblk), 256, lpw * M * sizeof(c2<T>), st>>>(
@@ -250,6 +252,44 @@ template <typename T> struct ProScaled {
     __device__ T operator()(int64_t row, int col) const {
         T v = x[row * ny + col];
         return a ? v * a[(row % nx) * ny + col] : v;
+    }
+};
+
+// x[q] * d[q] * a[row % nx][col] with optional full-size d and per-pixel a (q = row * ny + col)
+template <typename T> struct ProDiagScaled {
+    const T *x, *d, *a;
+    int nx, ny;
+    __device__ T operator()(int64_t row, int col) const {
+        const int64_t q = row * ny + col;
+        T v = x[q];
+        if (d) v *= d[q];
+        if (a) v *= a[(row % nx) * ny + col];
+        return v;
+    }
+};
+
+// y[q] = d[q] * a[row % nx][col] * value + add[q]
+template <typename T> struct EpiDiagScaledAdd {
+    T *y;
+    const T *d, *a, *add;
+    int nx, ny;
+    __device__ void operator()(int64_t row, int col, T v0, T v1) const {
+        const int64_t q = row * ny + col;
+        if (d) {
+            v0 *= d[q];
+            v1 *= d[q + 1];
+        }
+        if (a) {
+            const T *pa = a + (row % nx) * ny + col;
+            v0 *= pa[0];
+            v1 *= pa[1];
+        }
+        if (add) {
+            v0 += add[q];
+            v1 += add[q + 1];
+        }
+        y[q] = v0;
+        y[q + 1] = v1;
     }
 };
 

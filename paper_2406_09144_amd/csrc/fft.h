@@ -111,6 +111,14 @@ __device__ __forceinline__ void lds_fft(c2<T> *buf, int ld, int nlines, int log2
     for (; log2Ns < log2L; log2Ns += 2) stockham_stage<T, 4, NTHR, BPT>(buf, ld, nlines, log2L, log2Ns, sign, tw);
 }
 
+// Rows per workgroup of the row transforms: about 2048 elements per workgroup,
+// fewer when there are too few rows to give every CU several workgroups.
+inline int rows_per_wg(int L, int64_t nrows, int n_cu) {
+    int lpw = std::max(1, 2048 / L);
+    while (lpw > 1 && nrows / lpw < 4 * (int64_t)std::max(n_cu, 1)) lpw >>= 1;
+    return lpw;
+}
+
 // LDS budget of one workgroup (bytes; gfx950 has 160 KiB per CU).
 constexpr int kLdsBytes = 163840;
 

@@ -59,7 +59,7 @@ void launch_fft_rows(const Ctx &ctx, Pro pro, Epi epi, int64_t nrows, int log2L,
     FR_REQUIRE((int64_t)L * (int64_t)sizeof(c2<T>) <= kLdsBytes && L <= 16384, "FFT length too large");
     if (nrows <= 0) return;
     if (L <= 4096) {
-        const int lpw = std::max(1, 2048 / L);
+        const int lpw = rows_per_wg(L, nrows, ctx.n_cu);
         const size_t lds = (size_t)lpw * L * sizeof(c2<T>);
         allow_lds(k_fft_rows<T, 256, 4, Pro, Epi>, lds);
         k_fft_rows<T, 256, 4, Pro, Epi><<<dim3((unsigned)((nrows + lpw - 1) / lpw)), 256, lds, st>>>(

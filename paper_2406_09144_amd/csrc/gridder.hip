@@ -11,8 +11,10 @@
 //   3. degrid:  one workgroup per work item (uv tile x first w-plane): the tile and
 //               its W-1 halo of each touched plane is staged in LDS, every
 //               visibility sums psi_w psi_u psi_v G over its W x W x Ww footprint.
-// Gridding is the exact transpose: visibilities are spread into an LDS tile with
-// LDS atomics and flushed to the planes with global atomics, inverse column FFT
+// Gridding is the exact transpose: one wavefront per visibility spreads it into
+// LDS tiles of the touched planes (lane (a, b) owns footprint cell (a, b), so each
+// LDS atomic instruction hits distinct cells), the tiles are flushed to the planes
+// with global atomics, inverse column FFT
 // (keeping only the non-zero rows), then a row kernel that transforms each plane
 // row and accumulates Re(exp(+2 pi i w_p t) G) over planes into the image row.
 #include <algorithm>
@@ -199,88 +201,92 @@ __global__ __launch_bounds__(NTHR) void k_degrid(const WorkItem *__restrict__ wi
     }
 }
 
-// ------------------------------------------------------------------ grid (adjoint)
-template <typename T, int W, int NTHR, int VPT>
-__global__ __launch_bounds__(NTHR) void k_grid(const WorkItem *__restrict__ wis, c2<T> *__restrict__ planes,
-                                               int log2nu, int log2nv, int Ww, T beta, T wbeta, int coplanar,
-                                               const uint32_t *__restrict__ r_idx, const uint32_t *__restrict__ r_cell,
-                                               const T *__restrict__ r_du, const T *__restrict__ r_dv,
-                                               const T *__restrict__ r_dw, const T *__restrict__ r_ph,
-                                               const c2<T> *__restrict__ vis, const T *__restrict__ weight) {
+// ------------------------------------------------------------------ grid, one wavefront per visibility
+// Lane (a, b) of a wavefront owns footprint cell (a, b) (cells beyond 64 wrap to
+// more passes), so the LDS atomics of one instruction hit W*W distinct cells.
+// The w-kernel weights are evaluated by lanes 0..Ww-1 and broadcast with
+// wavefront shuffles.  `ppass` planes are resident in LDS at once (all Ww when
+// they fit); each pass zeroes its tiles, spreads every visibility of the work
+// item, and flushes the tiles to the planes with global atomics.  Tiles are
+// stored as separate real and imaginary arrays to keep lanes on distinct banks.
+template <typename T, int W>
+__global__ __launch_bounds__(256) void k_grid_wave(const WorkItem *__restrict__ wis, c2<T> *__restrict__ planes,
+                                                   int log2nu, int log2nv, int Ww, int ppass, T beta, T wbeta,
+                                                   int coplanar, const uint32_t *__restrict__ r_idx,
+                                                   const uint32_t *__restrict__ r_cell, const T *__restrict__ r_du,
+                                                   const T *__restrict__ r_dv, const T *__restrict__ r_dw,
+                                                   const T *__restrict__ r_ph, const c2<T> *__restrict__ vis,
+                                                   const T *__restrict__ weight) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *tile = reinterpret_cast<T *>(smem_raw);  // interleaved (re, im)
+    T *tile = reinterpret_cast<T *>(smem_raw);  // [ppass][2][TS * TS]
     constexpr int TS = kTile + W - 1;
+    constexpr int TT = TS * TS;
+    constexpr int NCELL = (W * W + 63) / 64;
     const WorkItem it = wis[blockIdx.x];
     const int nu = 1 << log2nu, nv = 1 << log2nv;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const T two_over_W = T(2) / T(W);
-    T ku[VPT][W], kv[VPT][W];
-    T fw[VPT];
-    int ru[VPT], rv[VPT];
-    bool ok[VPT];
-    c2<T> y[VPT];
+    int ca[NCELL], cb[NCELL];
 #pragma unroll
-    for (int k = 0; k < VPT; ++k) {
-        const int j = threadIdx.x + k * NTHR;
-        ok[k] = j < it.count;
-        ru[k] = rv[k] = 0;
-        fw[k] = T(0);
-        y[k] = mk<T>(T(0), T(0));
-        if (ok[k]) {
+    for (int q = 0; q < NCELL; ++q) {
+        const int c = lane + 64 * q;
+        ca[q] = c < W * W ? c / W : -1;
+        cb[q] = c < W * W ? c - (c / W) * W : 0;
+    }
+    for (int g0 = 0; g0 < Ww; g0 += ppass) {
+        const int np = min(ppass, Ww - g0);
+        for (int q = threadIdx.x; q < np * 2 * TT; q += 256) tile[q] = T(0);
+        __syncthreads();
+        for (int j = wave; j < it.count; j += 4) {
             const int64_t pos = it.start + j;
-            const uint32_t c = r_cell[pos];
-            ru[k] = (int)(c & 0xffffu);
-            rv[k] = (int)(c >> 16);
-            const T xu = r_du[pos], xv = r_dv[pos];
-#pragma unroll
-            for (int a = 0; a < W; ++a) {
-                ku[k][a] = es_eval<T>((xu - T(a)) * two_over_W, beta);
-                kv[k][a] = es_eval<T>((xv - T(a)) * two_over_W, beta);
-            }
-            fw[k] = r_dw[pos];
+            const uint32_t cell = r_cell[pos];
+            const int ru = (int)(cell & 0xffffu), rv = (int)(cell >> 16);
             const uint32_t id = r_idx[pos];
             const uint32_t vi = id & 0x7fffffffu;
-            c2<T> val = vis ? vis[vi] : mk<T>(T(1), T(0));  // NULL: all ones (PSF)
+            c2<T> y = vis ? vis[vi] : mk<T>(T(1), T(0));
             if (weight) {
                 const T wt = weight[vi];
-                val.x *= wt;
-                val.y *= wt;
+                y.x *= wt;
+                y.y *= wt;
             }
-            if (id >> 31) val.y = -val.y;
+            if (id >> 31) y.y = -y.y;
             if (!coplanar) {
-                T s, c2v;
-                sincos_cycles(r_ph[pos], &s, &c2v);
-                val = cmul<T>(val, mk<T>(c2v, s));
+                T s, c;
+                sincos_cycles(r_ph[pos], &s, &c);
+                y = cmul<T>(y, mk<T>(c, s));
             }
-            y[k] = val;
-        }
-    }
-    for (int pw = 0; pw < Ww; ++pw) {
-        for (int q = threadIdx.x; q < 2 * TS * TS; q += NTHR) tile[q] = T(0);
-        __syncthreads();
+            const T xu = r_du[pos], xv = r_dv[pos];
+            T kwl = T(1);
+            if (!coplanar && lane < np) kwl = es_eval<T>((r_dw[pos] - T(g0 + lane)) * (T(2) / T(Ww)), wbeta);
+            // broadcast the plane weights while every lane is active
+            T kw[W];
 #pragma unroll
-        for (int k = 0; k < VPT; ++k) {
-            if (!ok[k]) continue;
-            const T kw = coplanar ? T(1) : es_eval<T>((fw[k] - T(pw)) * (T(2) / T(Ww)), wbeta);
-            const T cx = y[k].x * kw, cy = y[k].y * kw;
+            for (int p = 0; p < W; ++p) kw[p] = (!coplanar && p < np) ? __shfl(kwl, p, 64) : T(1);
 #pragma unroll
-            for (int a = 0; a < W; ++a) {
-                const T ax = cx * ku[k][a], ay = cy * ku[k][a];
-                T *rowp = tile + 2 * ((ru[k] + a) * TS + rv[k]);
+            for (int q = 0; q < NCELL; ++q) {
+                if (ca[q] < 0) continue;
+                const T wuv = es_eval<T>((xu - T(ca[q])) * two_over_W, beta) *
+                              es_eval<T>((xv - T(cb[q])) * two_over_W, beta);
+                const T cx = y.x * wuv, cy = y.y * wuv;
+                const int off = (ru + ca[q]) * TS + rv + cb[q];
 #pragma unroll
-                for (int b = 0; b < W; ++b) {
-                    atomicAdd(rowp + 2 * b, ax * kv[k][b]);
-                    atomicAdd(rowp + 2 * b + 1, ay * kv[k][b]);
+                for (int p = 0; p < W; ++p) {
+                    if (p >= np) break;
+                    T *tp = tile + 2 * p * TT;
+                    atomicAdd(tp + off, cx * kw[p]);
+                    atomicAdd(tp + TT + off, cy * kw[p]);
                 }
             }
         }
         __syncthreads();
-        c2<T> *P = planes + ((int64_t)(it.p0 + pw) << (log2nu + log2nv));
-        for (int q = threadIdx.x; q < TS * TS; q += NTHR) {
-            const T gx = tile[2 * q], gy = tile[2 * q + 1];
+        for (int q = threadIdx.x; q < np * TT; q += 256) {
+            const int p = q / TT, r = q - p * TT;
+            const T gx = tile[2 * p * TT + r], gy = tile[2 * p * TT + TT + r];
             if (gx != T(0) || gy != T(0)) {
-                const int i = q / TS, jj = q - i * TS;
+                const int i = r / TS, jj = r - i * TS;
                 const int a = (it.tu + i) & (nu - 1), b = (it.tv + jj) & (nv - 1);
-                T *dst = reinterpret_cast<T *>(P + ((int64_t)a << log2nv) + b);
+                T *dst = reinterpret_cast<T *>(planes + ((int64_t)(it.p0 + g0 + p) << (log2nu + log2nv)) +
+                                               ((int64_t)a << log2nv) + b);
                 atomicAdd(dst, gx);
                 atomicAdd(dst + 1, gy);
             }
@@ -435,12 +441,14 @@ template <typename T, int W>
 void launch_grid_w(const fr_plan *pl, const WorkItem *wis, int64_t nwi, c2<T> *planes, const c2<T> *vis,
                    const T *weight, hipStream_t st) {
     constexpr int TS = kTile + W - 1;
-    const size_t lds = (size_t)TS * TS * sizeof(c2<T>);
-    auto kern = k_grid<T, W, kGridThreads, vpt<T>()>;
+    const size_t per_plane = (size_t)TS * TS * sizeof(c2<T>);
+    const int ppass = (int)std::max<size_t>(1, std::min<size_t>(pl->Ww, (size_t)kLdsBytes / per_plane));
+    const size_t lds = per_plane * ppass;
+    auto kern = k_grid_wave<T, W>;
     allow_lds(kern, lds);
     ProfScope prof("grid", st);
-    kern<<<dim3((unsigned)nwi), kGridThreads, lds, st>>>(
-        wis, planes, ilog2(pl->nu), ilog2(pl->nv), pl->Ww, (T)pl->beta, (T)pl->wbeta, pl->coplanar ? 1 : 0,
+    kern<<<dim3((unsigned)nwi), 256, lds, st>>>(
+        wis, planes, ilog2(pl->nu), ilog2(pl->nv), pl->Ww, ppass, (T)pl->beta, (T)pl->wbeta, pl->coplanar ? 1 : 0,
         pl->r_idx.as<uint32_t>(), pl->r_cell.as<uint32_t>(), pl->r_du.as<T>(), pl->r_dv.as<T>(), pl->r_dw.as<T>(),
         pl->r_ph.as<T>(), vis, weight);
     LAUNCH_CHECK();

@@ -97,6 +97,9 @@ void cg_solve(const fr_plan *pl, const fr_psf *psf, const T *weight, const T *in
 template <typename T>
 void apply_rnr_approx(const fr_psf *psf, const T *x, T *y, int64_t B, hipStream_t st);
 template <typename T>
+void apply_rnr_approx_ex(const fr_psf *psf, const T *x, const T *d_in, T *y, const T *d_out, const T *add,
+                         int64_t B, hipStream_t st);
+template <typename T>
 void periodic_conv(const Ctx &ctx, const T *x, T *y, int64_t n_img, int64_t nx, int64_t ny, const T *K, int nk,
                    int mode, hipStream_t st);
 template <typename T>

@@ -10,8 +10,12 @@ namespace frmi {
 // y = D P^+ irfft2(K_R rfft2(P D x)): x padded into the top-left nx x ny block of
 // the 2nx x 2ny grid.  Only the nx non-zero rows are transformed along y and only
 // the nx wanted rows are kept after the column pass.
+// y = d_out D P^+ irfft2(K_R rfft2(P D d_in x)) + add, every extra factor optional:
+// the diagonal metric factors and the prior term of CG fused into the first and
+// last pass.
 template <typename T>
-void apply_rnr_approx(const fr_psf *psf, const T *x, T *y, int64_t B, hipStream_t st) {
+void apply_rnr_approx_ex(const fr_psf *psf, const T *x, const T *d_in, T *y, const T *d_out, const T *add,
+                         int64_t B, hipStream_t st) {
     const int64_t nx = psf->nx, ny = psf->ny, nc = psf->n_chan;
     const int64_t n_img = B * nc;
     if (n_img == 0) return;
@@ -21,13 +25,13 @@ void apply_rnr_approx(const fr_psf *psf, const T *x, T *y, int64_t B, hipStream_
     g.rows_out = (int)nx;
     g.n_in_cols = (int)ny;
     g.n_out_cols = (int)ny;
-    g.log2M = ilog2(ny);      // real rows of length 2ny -> ny packed values
-    g.log2Lc = ilog2(2 * nx);  // columns of length 2nx
+    g.log2M = ilog2(ny);
+    g.log2Lc = ilog2(2 * nx);
     Scratch Y((size_t)n_img * nx * ny * sizeof(c2<T>), st);
     const T *a = psf->nfac.as<T>();
     {
         ProfScope prof("psfconv_rows_r2c", st);
-        launch_rfft_rows<T>(*psf->ctx, g, ProScaled<T>{x, a, (int)nx, (int)ny}, Y.as<c2<T>>(), st);
+        launch_rfft_rows<T>(*psf->ctx, g, ProDiagScaled<T>{x, d_in, a, (int)nx, (int)ny}, Y.as<c2<T>>(), st);
     }
     const T scale = T(1) / (T(2 * nx) * T(ny));
     {
@@ -35,7 +39,12 @@ void apply_rnr_approx(const fr_psf *psf, const T *x, T *y, int64_t B, hipStream_
         launch_conv_cols<T>(*psf->ctx, g, Y.as<c2<T>>(), psf->KR.as<T>(), (int)nc, 0, scale, st);
     }
     ProfScope prof("psfconv_rows_c2r", st);
-    launch_irfft_rows<T>(*psf->ctx, g, EpiScaled<T>{y, a, (int)nx, (int)ny, T(1), 0}, Y.as<c2<T>>(), st);
+    launch_irfft_rows<T>(*psf->ctx, g, EpiDiagScaledAdd<T>{y, d_out, a, add, (int)nx, (int)ny}, Y.as<c2<T>>(), st);
+}
+
+template <typename T>
+void apply_rnr_approx(const fr_psf *psf, const T *x, T *y, int64_t B, hipStream_t st) {
+    apply_rnr_approx_ex<T>(psf, x, nullptr, y, nullptr, nullptr, B, st);
 }
 
 // y = irfft2(K rfft2(x)) (mode 0) or irfft2(rfft2(x) / K) (mode 1) on the periodic
@@ -74,6 +83,10 @@ void fft2_inplace(const Ctx &ctx, c2<T> *data, int64_t batch, int64_t n0, int64_
                        l0, (int)n0, (int)n0, sign, st);
 }
 
+template void apply_rnr_approx_ex<float>(const fr_psf *, const float *, const float *, float *, const float *,
+                                         const float *, int64_t, hipStream_t);
+template void apply_rnr_approx_ex<double>(const fr_psf *, const double *, const double *, double *, const double *,
+                                          const double *, int64_t, hipStream_t);
 template void apply_rnr_approx<float>(const fr_psf *, const float *, float *, int64_t, hipStream_t);
 template void apply_rnr_approx<double>(const fr_psf *, const double *, double *, int64_t, hipStream_t);
 template void periodic_conv<float>(const Ctx &, const float *, float *, int64_t, int64_t, int64_t, const float *, int,

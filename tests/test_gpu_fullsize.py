@@ -1,0 +1,93 @@
+"""Parity at the workloads' full sizes, in the launch configuration the benchmark
+times, on outputs the oracle computes one by one:
+
+  * VLA-like 512^2, 1,010,880 visibilities with w (FP32, eps = 1e-5): degridding
+    on a random sample of visibilities, gridding on a random sample of pixels,
+    the PSF-convolution response on a sample of output pixels (brute force);
+  * MeerKAT-like 4096^2 x 16 channels, 7,257,600 rows (116 M visibilities): the
+    same samples on three channels.
+
+The sampled relative error is ||gpu - oracle|| / ||oracle|| over the sample; the
+bound is the eps the plan was made for.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from synthetic import make_config
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+def _check_plan(obs, chans, n_vis_sample=2048, n_pix_sample=96, seed=0):
+    import torch
+    from paper_2406_09144_amd import api
+    rng = np.random.default_rng(seed)
+    n = obs.nx
+    print(f"[fullsize] {obs.n_vis} visibilities, {n}x{n}, {obs.n_chan} channel(s)", flush=True)
+    pl = api.Plan(obs.uvw, obs.freq, n, n, obs.dx, obs.dy, eps=1e-5)
+    info = pl.info
+    print(f"[fullsize] plan: W={info['support']} planes={info['n_planes']} items={info['n_workitems']}", flush=True)
+    sky = torch.from_numpy(obs.sky).float().cuda() if obs.sky is not None else \
+        torch.from_numpy(rng.standard_normal((obs.n_chan, n, n))).float().cuda()
+    vis = api.degrid(pl, sky)
+    torch.cuda.synchronize()
+    rows = rng.choice(obs.n_row, n_vis_sample, replace=False)
+    ch = rng.choice(chans, n_vis_sample)
+    skyh = sky.cpu().numpy().astype(np.float64)
+    got = vis.cpu().numpy()[rows, ch]
+    ref = O.degrid_rows(obs.uvw, obs.freq, n, n, obs.dx, obs.dy, skyh, rows, ch)
+    e_deg = rel(got, ref)
+    print(f"[fullsize] degrid sampled rel err {e_deg:.2e}", flush=True)
+    assert e_deg < 1e-5
+    # gridding: random data and weights, sampled pixels per channel
+    y = torch.randn((obs.n_row, obs.n_chan), dtype=torch.complex64, device="cuda")
+    w = torch.rand((obs.n_row, obs.n_chan), device="cuda") + 0.5
+    img = api.grid(pl, y, w).cpu().numpy()
+    yh = y.cpu().numpy().astype(np.complex128)
+    wh = w.cpu().numpy().astype(np.float64)
+    for c in chans:
+        pix = rng.choice(n * n, n_pix_sample, replace=False)
+        refp = O.grid_pixels(obs.uvw, obs.freq, n, n, obs.dx, obs.dy, yh, pix, chan=c, weight=wh)
+        e_grid = rel(img[c].ravel()[pix], refp)
+        print(f"[fullsize] grid channel {c} sampled rel err {e_grid:.2e}", flush=True)
+        assert e_grid < 1e-5
+    return pl
+
+
+def test_vla_like_full_size():
+    obs = make_config(1)
+    assert obs.n_vis == 1_010_880
+    _check_plan(obs, chans=[0])
+
+
+def test_meerkat_like_full_size():
+    obs = make_config(3, with_sky=False)
+    assert obs.n_row == 7_257_600 and obs.n_chan == 16 and obs.nx == 4096
+    _check_plan(obs, chans=[0, 7, 15], n_vis_sample=256, n_pix_sample=16)
+
+
+def test_psf_apply_full_size_batch8_sampled_pixels():
+    """N = 512, B = 8, kernel from the oracle PSF of a subset of the tracks; the
+    brute-force convolution on a sample of output pixels."""
+    import torch
+    from paper_2406_09144_amd import api
+    n = 512
+    o = make_config(2, n=n, n_int=16, with_sky=False)
+    rng = np.random.default_rng(3)
+    wt = rng.uniform(0.5, 2.0, o.n_row)
+    p0 = O.psf0(o.uvw, o.freq, n, n, o.dx, o.dy, wt)
+    K = O.response_kernel(p0)
+    a = O.n_factor(n, n, o.dx, o.dy)
+    psf = api.PSF.from_kernels(torch.from_numpy(K[None]).float().cuda(), nfac=torch.from_numpy(a).float().cuda())
+    x = rng.standard_normal((8, 1, n, n))
+    y = api.apply_RNR_approx(psf, torch.from_numpy(x).float().cuda()).cpu().numpy()
+    for b in (0, 7):
+        pix = rng.choice(n * n, 64, replace=False)
+        ref = O.psf_conv_direct(x[b, 0], p0, a, pix=pix)
+        assert rel(y[b, 0].ravel()[pix], ref) < 1e-6

@@ -184,43 +184,67 @@ def test_autograd_pair_matches_handwritten_gradient():
     assert torch.autograd.gradcheck(lambda t: api.Grid.apply(t, pl, wt), (y,), eps=1e-4, atol=1e-7)
 
 
-@pytest.mark.parametrize("fp64", [False, True])
-def test_gradient_vs_finite_differences(fp64):
-    """Central differences (step 1e-4) of the GPU H agree with the GPU gradient:
-    FP64 along random unit directions to 1e-7; FP32 along the gradient direction
-    to 2e-3, where the rounding of the FP32 residuals (~1e-7 of the model) over
-    the step bounds the agreement.  Data are generated from a nearby sky so the
-    residual is small against the model, as in a reconstruction."""
+def _fd_setup(fp64, eps_noise):
     import torch
     from paper_2406_09144_amd import api
-    from paper_2406_09144_amd._lib import FR_LIK_FAST, FR_LIK_EXACT
     n = 64
     o = make_config(2, n=n, n_int=64, with_sky=False)
     rng = np.random.default_rng(27)
     wt = rng.uniform(0.5, 2.0, (o.n_row, 1))
     pl = api.Plan(o.uvw, o.freq, n, n, o.dx, o.dy, eps=1e-11 if fp64 else 1e-5, fp64=fp64)
-    psf = api.make_psf_kernel(pl, tdev(wt, fp64), eps_noise=-1e-3)
+    psf = api.make_psf_kernel(pl, tdev(wt, fp64), eps_noise=eps_noise)
     s_true = 0.5 * np.real(np.fft.ifft2(np.fft.fft2(rng.standard_normal((n, n))) *
                                         np.sqrt(power_spectrum(n, n))))
-    V = api.degrid(pl, tdev(np.exp(s_true)[None], fp64)).cpu().numpy()
-    sig = 0.05 * np.sqrt(np.mean(np.abs(V) ** 2))
-    V = V + sig * (rng.standard_normal(V.shape) + 1j * rng.standard_normal(V.shape))
+    V = api.degrid(pl, tdev(np.exp(s_true)[None], fp64)).cpu().numpy().astype(np.complex128)
     Vd = tdev(V, fp64, cplx=True)
     d = api.grid(pl, Vd, tdev(wt, fp64))
     s0 = s_true[None, None] + 0.05 * rng.standard_normal((1, 1, n, n))
+    return pl, psf, wt, Vd, d, s0, rng
+
+
+def test_gradient_vs_finite_differences_fp64():
+    """Central differences (step 1e-4) of the FP64 H along random unit directions
+    agree with the FP64 gradient to 1e-7 of |g| (FAST and EXACT)."""
+    from paper_2406_09144_amd import api
+    from paper_2406_09144_amd._lib import FR_LIK_FAST, FR_LIK_EXACT
+    pl, psf, wt, Vd, d, s0, rng = _fd_setup(True, -1e-3)
     h = 1e-4
     for mode, data, kw in [(FR_LIK_FAST, d, dict(psf=psf)),
-                           (FR_LIK_EXACT, Vd, dict(plan=pl, weight=tdev(wt, fp64)))]:
-        H, g = api.likelihood_grad(mode, tdev(s0, fp64), data, **kw)
-        g = g.cpu().numpy().astype(np.float64)
-        dirs = [g / np.linalg.norm(g)] if not fp64 else []
-        for _ in range(2 if fp64 else 0):
+                           (FR_LIK_EXACT, Vd, dict(plan=pl, weight=tdev(wt, True)))]:
+        H, g = api.likelihood_grad(mode, tdev(s0, True), data, **kw)
+        g = g.cpu().numpy()
+        for _ in range(2):
             dd = rng.standard_normal(s0.shape)
-            dirs.append(dd / np.linalg.norm(dd))
-        for dd in dirs:
-            Hp, _ = api.likelihood_grad(mode, tdev(s0 + h * dd, fp64), data, **kw)
-            Hm, _ = api.likelihood_grad(mode, tdev(s0 - h * dd, fp64), data, **kw)
+            dd /= np.linalg.norm(dd)
+            Hp, _ = api.likelihood_grad(mode, tdev(s0 + h * dd, True), data, **kw)
+            Hm, _ = api.likelihood_grad(mode, tdev(s0 - h * dd, True), data, **kw)
             fd = (Hp.item() - Hm.item()) / (2 * h)
-            an = float(np.sum(g * dd))
-            tol = 1e-7 * np.linalg.norm(g) if fp64 else 2e-3 * abs(an)
-            assert abs(fd - an) < tol, (mode, fd, an)
+            assert abs(fd - float(np.sum(g * dd))) < 1e-7 * np.linalg.norm(g), (mode, fd)
+
+
+def test_gradient_fp32_vs_finite_differences():
+    """FP32 gradient (FAST and EXACT) against central differences (step 1e-4) along
+    the gradient direction: of the FP64 H on the same data, to 1e-3; and of the
+    FP32 H itself, to 1e-2, a bound set by FP32 rounding of the residuals over the
+    step (H is accumulated in FP64, its inputs are FP32)."""
+    from paper_2406_09144_amd import api
+    from paper_2406_09144_amd._lib import FR_LIK_FAST, FR_LIK_EXACT
+    pl32, psf32, wt, V32, d32, s0, rng = _fd_setup(False, -1e-1)
+    pl64, psf64, _, V64, d64, _, _ = _fd_setup(True, -1e-1)
+    h = 1e-4
+    for mode in (FR_LIK_FAST, FR_LIK_EXACT):
+        kw32 = dict(psf=psf32) if mode == FR_LIK_FAST else dict(plan=pl32, weight=tdev(wt, False))
+        kw64 = dict(psf=psf64) if mode == FR_LIK_FAST else dict(plan=pl64, weight=tdev(wt, True))
+        data32 = d32 if mode == FR_LIK_FAST else V32
+        data64 = d64 if mode == FR_LIK_FAST else V64
+        _, g = api.likelihood_grad(mode, tdev(s0, False), data32, **kw32)
+        g = g.cpu().numpy().astype(np.float64)
+        dd = g / np.linalg.norm(g)
+        an = float(np.sum(g * dd))
+        fd64 = (api.likelihood_grad(mode, tdev(s0 + h * dd, True), data64, **kw64)[0].item()
+                - api.likelihood_grad(mode, tdev(s0 - h * dd, True), data64, **kw64)[0].item()) / (2 * h)
+        assert abs(fd64 - an) < 1e-3 * abs(an), (mode, fd64, an)
+        fd32 = (api.likelihood_grad(mode, tdev(s0 + h * dd, False), data32, **kw32)[0].item()
+                - api.likelihood_grad(mode, tdev(s0 - h * dd, False), data32, **kw32)[0].item()) / (2 * h)
+        print(f"mode {mode}: FD32/analytic - 1 = {fd32 / an - 1:.2e}, FD64/analytic - 1 = {fd64 / an - 1:.2e}")
+        assert abs(fd32 - an) < 1e-2 * abs(an), (mode, fd32, an)
