@@ -128,6 +128,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-jobs", type=int, default=16)
     ap.add_argument("--serve-fp64-requests", type=int, default=100)
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="only run 5 plain copies of this many bytes (counter calibration)")
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--n-int", type=int, default=2880)
     args = ap.parse_args()
@@ -136,6 +138,19 @@ def main():
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU sharding is a "
               f"design, not a measured path", file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_calibration > 0:
+        # a plain device-to-device copy of known size: the reference for scaling
+        # the HBM byte counters (FETCH_SIZE / WRITE_SIZE) of the other kernels
+        import torch
+        nb = int(args.copy_calibration)
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nb, "copies": 5}), flush=True)
+        return
 
     import numpy as np
     import torch
