@@ -41,7 +41,9 @@ def algorithmic_bytes(name, info, n_vis, n_row, B_conv, nx, ny):
     if name == "degrid":
         return planes + 8 * n_vis + 24 * n_row          # every plane read once, vis written, uvw
     if name == "grid":
-        return planes + 12 * n_vis + 24 * n_row         # planes written once, vis + weights read
+        return 12 * n_vis + 24 * n_row                  # vis + weights read (spread into per-item tiles)
+    if name == "grid_assemble":
+        return planes                                   # every plane cell written once
     if name in ("wplane_rows_fwd",):
         return 4 * nx * ny + info["n_planes"] * nx * info["nv"] * 8
     if name in ("wplane_cols_fwd", "wplane_cols_inv"):

@@ -230,7 +230,7 @@ int fr_query_footprint(const fr_plan *plan, const fr_psf *psf, int op, int64_t B
  * recorded on the launch's own stream.  fr_profile_query synchronises the
  * recorded events of kernel `name` and returns the number of launches and their
  * summed duration in milliseconds (0 launches for an unknown name).  Names:
- * "degrid", "grid", "zero", "wplane_rows_fwd", "wplane_cols_fwd",
+ * "degrid", "grid", "grid_assemble", "zero", "wplane_rows_fwd", "wplane_cols_fwd",
  * "wplane_cols_inv", "wplane_rows_inv", "psfconv_rows_r2c", "psfconv_cols",
  * "psfconv_rows_c2r", "pconv_rows_r2c", "pconv_cols", "pconv_rows_c2r".
  * fr_profile_reset drops every record. */

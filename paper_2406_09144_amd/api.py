@@ -354,6 +354,6 @@ def profile_query(name):
     return n.value, ms.value
 
 
-PROFILED_KERNELS = ["degrid", "grid", "zero", "wplane_rows_fwd", "wplane_cols_fwd", "wplane_cols_inv",
+PROFILED_KERNELS = ["degrid", "grid", "grid_assemble", "zero", "wplane_rows_fwd", "wplane_cols_fwd", "wplane_cols_inv",
                     "wplane_rows_inv", "psfconv_rows_r2c", "psfconv_cols", "psfconv_rows_c2r",
                     "pconv_rows_r2c", "pconv_cols", "pconv_rows_c2r"]

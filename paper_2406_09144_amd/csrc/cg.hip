@@ -79,10 +79,17 @@ __device__ __forceinline__ bool arrive_last(unsigned *counter) {
     return last;
 }
 
+// Called by every thread of the last block: the partials are fetched in
+// parallel (device-coherent loads), then added by thread 0 in block order.
 __device__ __forceinline__ double sum_partials(const double *partials, int n) {
+    __shared__ double sh[kRedBlocksPerImage];
+    for (int k = threadIdx.x; k < n; k += blockDim.x)
+        sh[k] = __hip_atomic_load(partials + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
     double s = 0;
-    for (int k = 0; k < n; ++k) s += __hip_atomic_load(partials + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return s;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < n; ++k) s += sh[k];
+    return s;  // valid in thread 0
 }
 
 // <p, A p> into st->pAp
@@ -96,9 +103,12 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_dot_pAp(CGState *__restrict_
         s += (double)p[i] * (double)Ap[i];
     s = block_sum(s);
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
-    if (arrive_last(counter) && threadIdx.x == 0) {
-        st->pAp = sum_partials(partials, gridDim.x);
-        *counter = 0;
+    if (arrive_last(counter)) {
+        const double t = sum_partials(partials, gridDim.x);
+        if (threadIdx.x == 0) {
+            st->pAp = t;
+            *counter = 0;
+        }
     }
 }
 
@@ -121,14 +131,16 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_step(CGState *__restrict__ s
     }
     s = block_sum(s);
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
-    if (arrive_last(counter) && threadIdx.x == 0) {
+    if (arrive_last(counter)) {
         const double rr = sum_partials(partials, gridDim.x);
-        hist[k + 1] = sqrt(rr);
-        st->beta = rr / st->rr;
-        st->rr = rr;
-        st->iters = k + 1;
-        if (sqrt(rr) <= st->stop) st->done = 1;
-        *counter = 0;
+        if (threadIdx.x == 0) {
+            hist[k + 1] = sqrt(rr);
+            st->beta = rr / st->rr;
+            st->rr = rr;
+            st->iters = k + 1;
+            if (sqrt(rr) <= st->stop) st->done = 1;
+            *counter = 0;
+        }
     }
 }
 

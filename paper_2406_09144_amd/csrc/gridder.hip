@@ -201,29 +201,33 @@ __global__ __launch_bounds__(NTHR) void k_degrid(const WorkItem *__restrict__ wi
     }
 }
 
-// ------------------------------------------------------------------ grid, one wavefront per visibility
-// Lane (a, b) of a wavefront owns footprint cell (a, b) (cells beyond 64 wrap to
-// more passes), so the LDS atomics of one instruction hit W*W distinct cells.
-// The w-kernel weights are evaluated by lanes 0..Ww-1 and broadcast with
-// wavefront shuffles.  `ppass` planes are resident in LDS at once (all Ww when
-// they fit); each pass zeroes its tiles, spreads every visibility of the work
-// item, and flushes the tiles to the planes with global atomics.  Tiles are
-// stored as separate real and imaginary arrays to keep lanes on distinct banks.
-template <typename T, int W>
-__global__ __launch_bounds__(256) void k_grid_wave(const WorkItem *__restrict__ wis, c2<T> *__restrict__ planes,
-                                                   int log2nu, int log2nv, int Ww, int ppass, T beta, T wbeta,
-                                                   int coplanar, const uint32_t *__restrict__ r_idx,
-                                                   const uint32_t *__restrict__ r_cell, const T *__restrict__ r_du,
-                                                   const T *__restrict__ r_dv, const T *__restrict__ r_dw,
-                                                   const T *__restrict__ r_ph, const c2<T> *__restrict__ vis,
-                                                   const T *__restrict__ weight) {
+// ------------------------------------------------------------------ grid: partial tiles
+// One workgroup per gridding item (a chunk of the visibilities of one uv tile
+// and first w-plane).  One wavefront per visibility: lane (a, b) owns footprint
+// cell (a, b) (cells beyond 64 wrap to more passes), so the LDS atomics of one
+// instruction hit W*W distinct cells; the w-kernel weights are evaluated by
+// lanes 0..Ww-1 and broadcast with wavefront shuffles.  `ppass` planes are
+// resident in LDS at once (all Ww when they fit).  The accumulated tiles, halo
+// included, are written with plain stores to the item's slot of the partial
+// buffer [item][Ww][TS*TS] (complex); k_grid_assemble adds them up.  Tiles are
+// stored in LDS as separate real and imaginary arrays to keep lanes on distinct
+// banks.
+template <typename T, int W, int NTHR>
+__global__ __launch_bounds__(NTHR) void k_grid_partial(const WorkItem *__restrict__ wis, c2<T> *__restrict__ partial,
+                                                       int Ww, int ppass, T beta, T wbeta, int coplanar,
+                                                       const uint32_t *__restrict__ r_idx,
+                                                       const uint32_t *__restrict__ r_cell,
+                                                       const T *__restrict__ r_du, const T *__restrict__ r_dv,
+                                                       const T *__restrict__ r_dw, const T *__restrict__ r_ph,
+                                                       const c2<T> *__restrict__ vis, const T *__restrict__ weight) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *tile = reinterpret_cast<T *>(smem_raw);  // [ppass][2][TS * TS]
     constexpr int TS = kTile + W - 1;
     constexpr int TT = TS * TS;
     constexpr int NCELL = (W * W + 63) / 64;
+    constexpr int NWAVE = NTHR / 64;
     const WorkItem it = wis[blockIdx.x];
-    const int nu = 1 << log2nu, nv = 1 << log2nv;
+    c2<T> *out = partial + (int64_t)blockIdx.x * Ww * TT;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const T two_over_W = T(2) / T(W);
     int ca[NCELL], cb[NCELL];
@@ -235,9 +239,9 @@ __global__ __launch_bounds__(256) void k_grid_wave(const WorkItem *__restrict__ 
     }
     for (int g0 = 0; g0 < Ww; g0 += ppass) {
         const int np = min(ppass, Ww - g0);
-        for (int q = threadIdx.x; q < np * 2 * TT; q += 256) tile[q] = T(0);
+        for (int q = threadIdx.x; q < np * 2 * TT; q += NTHR) tile[q] = T(0);
         __syncthreads();
-        for (int j = wave; j < it.count; j += 4) {
+        for (int j = wave; j < it.count; j += NWAVE) {
             const int64_t pos = it.start + j;
             const uint32_t cell = r_cell[pos];
             const int ru = (int)(cell & 0xffffu), rv = (int)(cell >> 16);
@@ -279,19 +283,57 @@ __global__ __launch_bounds__(256) void k_grid_wave(const WorkItem *__restrict__ 
             }
         }
         __syncthreads();
-        for (int q = threadIdx.x; q < np * TT; q += 256) {
+        for (int q = threadIdx.x; q < np * TT; q += NTHR) {
             const int p = q / TT, r = q - p * TT;
-            const T gx = tile[2 * p * TT + r], gy = tile[2 * p * TT + TT + r];
-            if (gx != T(0) || gy != T(0)) {
-                const int i = r / TS, jj = r - i * TS;
-                const int a = (it.tu + i) & (nu - 1), b = (it.tv + jj) & (nv - 1);
-                T *dst = reinterpret_cast<T *>(planes + ((int64_t)(it.p0 + g0 + p) << (log2nu + log2nv)) +
-                                               ((int64_t)a << log2nv) + b);
-                atomicAdd(dst, gx);
-                atomicAdd(dst + 1, gy);
-            }
+            out[(int64_t)(g0 + p) * TT + r] = mk<T>(tile[2 * p * TT + r], tile[2 * p * TT + TT + r]);
         }
         __syncthreads();
+    }
+}
+
+// Owner-computes assembly: workgroup (tile, plane p) writes the 32 x 32 cells it
+// owns, each the sum, in a fixed order, of the partial tiles that cover it: the
+// items of its own tile and of the tiles up to one step back in u and v (their
+// W - 1 halo reaches into this tile), for every first plane p0 with
+// p - Ww < p0 <= p.  Every plane cell is written exactly once, so the planes need
+// no clearing and the result does not depend on scheduling.
+template <typename T, int W>
+__global__ __launch_bounds__(256) void k_grid_assemble(const c2<T> *__restrict__ partial,
+                                                       const uint32_t *__restrict__ gkey_first, int64_t item0,
+                                                       int64_t key0, int n_p0, int ntu, int ntv, int Ww,
+                                                       int log2nu, int log2nv, c2<T> *__restrict__ planes) {
+    constexpr int TS = kTile + W - 1;
+    constexpr int TT = TS * TS;
+    const int t = blockIdx.x;
+    const int p = blockIdx.y;
+    const int tu = t / ntv, tv = t - tu * ntv;
+    const int n_tiles = ntu * ntv;
+    const int pmin = max(0, p - Ww + 1), pmax = min(p, n_p0 - 1);
+    for (int q = threadIdx.x; q < kTile * kTile; q += 256) {
+        const int i = q / kTile, j = q - i * kTile;
+        T sx = 0, sy = 0;
+        for (int di = 0; di < 2; ++di) {
+            const int li = i + di * kTile;
+            if (li >= TS) continue;
+            const int tu2 = (tu - di + ntu) % ntu;
+            for (int dj = 0; dj < 2; ++dj) {
+                const int lj = j + dj * kTile;
+                if (lj >= TS) continue;
+                const int tv2 = (tv - dj + ntv) % ntv;
+                const int t2 = tu2 * ntv + tv2;
+                for (int p0 = pmin; p0 <= pmax; ++p0) {
+                    const int64_t key = key0 + (int64_t)p0 * n_tiles + t2;
+                    const uint32_t b = gkey_first[key], e = gkey_first[key + 1];
+                    for (uint32_t it = b; it < e; ++it) {
+                        const c2<T> v = partial[((int64_t)(it - item0) * Ww + (p - p0)) * TT + li * TS + lj];
+                        sx += v.x;
+                        sy += v.y;
+                    }
+                }
+            }
+        }
+        const int a = tu * kTile + i, b2 = tv * kTile + j;
+        planes[((((int64_t)p << log2nu) + a) << log2nv) + b2] = mk<T>(sx, sy);
     }
 }
 
@@ -438,20 +480,35 @@ void launch_degrid_w(const fr_plan *pl, const WorkItem *wis, int64_t nwi, const 
 }
 
 template <typename T, int W>
-void launch_grid_w(const fr_plan *pl, const WorkItem *wis, int64_t nwi, c2<T> *planes, const c2<T> *vis,
-                   const T *weight, hipStream_t st) {
+void launch_grid_w(const fr_plan *pl, int64_t chan, c2<T> *planes, const c2<T> *vis, const T *weight,
+                   hipStream_t st) {
     constexpr int TS = kTile + W - 1;
+    constexpr int NTHR = 1024;
+    const int64_t i0 = pl->gwi_chan[chan], i1 = pl->gwi_chan[chan + 1];
     const size_t per_plane = (size_t)TS * TS * sizeof(c2<T>);
-    const int ppass = (int)std::max<size_t>(1, std::min<size_t>(pl->Ww, (size_t)kLdsBytes / per_plane));
-    const size_t lds = per_plane * ppass;
-    auto kern = k_grid_wave<T, W>;
-    allow_lds(kern, lds);
-    ProfScope prof("grid", st);
-    kern<<<dim3((unsigned)nwi), 256, lds, st>>>(
-        wis, planes, ilog2(pl->nu), ilog2(pl->nv), pl->Ww, ppass, (T)pl->beta, (T)pl->wbeta, pl->coplanar ? 1 : 0,
-        pl->r_idx.as<uint32_t>(), pl->r_cell.as<uint32_t>(), pl->r_du.as<T>(), pl->r_dv.as<T>(), pl->r_dw.as<T>(),
-        pl->r_ph.as<T>(), vis, weight);
-    LAUNCH_CHECK();
+    if (i1 > i0) {
+        Scratch partial((size_t)(i1 - i0) * pl->Ww * per_plane, st);
+        const int ppass = (int)std::max<size_t>(1, std::min<size_t>(pl->Ww, (size_t)kLdsBytes / per_plane));
+        const size_t lds = per_plane * ppass;
+        auto kern = k_grid_partial<T, W, NTHR>;
+        allow_lds(kern, lds);
+        {
+            ProfScope prof("grid", st);
+            kern<<<dim3((unsigned)(i1 - i0)), NTHR, lds, st>>>(
+                pl->gwi.as<WorkItem>() + i0, partial.as<c2<T>>(), pl->Ww, ppass, (T)pl->beta, (T)pl->wbeta,
+                pl->coplanar ? 1 : 0, pl->r_idx.as<uint32_t>(), pl->r_cell.as<uint32_t>(), pl->r_du.as<T>(),
+                pl->r_dv.as<T>(), pl->r_dw.as<T>(), pl->r_ph.as<T>(), vis, weight);
+            LAUNCH_CHECK();
+        }
+        ProfScope prof("grid_assemble", st);
+        k_grid_assemble<T, W><<<dim3((unsigned)pl->n_tiles, (unsigned)pl->n_planes), 256, 0, st>>>(
+            partial.as<c2<T>>(), pl->gkey_first.as<uint32_t>(), i0, chan * pl->n_p0 * (int64_t)pl->n_tiles,
+            pl->n_p0, pl->ntu, pl->ntv, pl->Ww, ilog2(pl->nu), ilog2(pl->nv), planes);
+        LAUNCH_CHECK();
+    } else {
+        // no visibilities in this channel: the planes are zero
+        zero_async<T>(reinterpret_cast<T *>(planes), (int64_t)pl->n_planes * pl->nu * pl->nv * 2, st);
+    }
 }
 
 #define FR_W_DISPATCH(W_, CALL) \
@@ -540,16 +597,10 @@ void degrid(const fr_plan *pl, const T *img, c2<T> *vis, hipStream_t st) {
 template <typename T>
 void grid(const fr_plan *pl, const c2<T> *vis, const T *weight, T *img, hipStream_t st) {
     Scratch planes(planes_bytes(pl), st);
-    const WorkItem *wis = pl->wi.as<WorkItem>();
-    const int64_t plane_elems = (int64_t)pl->n_planes * pl->nu * pl->nv * 2;
     for (int64_t c = 0; c < pl->n_chan; ++c) {
-        zero_async<T>(planes.as<T>(), plane_elems, st);
-        const int64_t w0 = pl->wi_chan[c], w1 = pl->wi_chan[c + 1];
-        if (w1 > w0) {
-#define FR_CALL_GRID(WW) launch_grid_w<T, WW>(pl, wis + w0, w1 - w0, planes.as<c2<T>>(), vis, weight, st)
-            FR_W_DISPATCH(pl->W, FR_CALL_GRID)
+#define FR_CALL_GRID(WW) launch_grid_w<T, WW>(pl, c, planes.as<c2<T>>(), vis, weight, st)
+        FR_W_DISPATCH(pl->W, FR_CALL_GRID)
 #undef FR_CALL_GRID
-        }
         planes_to_image<T>(pl, planes.as<c2<T>>(), img + c * pl->nx * pl->ny, st);
     }
 }
@@ -599,11 +650,23 @@ template <typename T> static DevBuf upload(const std::vector<double> &v) {
     return b;
 }
 
+// Visibilities per gridding item: large enough that the partial tiles written per
+// item stay few, small enough to give every CU about two items.
+static int grid_chunk(int64_t n_vis_per_chan, int n_cu) {
+    int64_t c = n_vis_per_chan / (2 * (int64_t)std::max(n_cu, 1));
+    c = std::min<int64_t>(std::max<int64_t>(c, 1024), 16384);
+    return (int)((c + 255) / 256 * 256);
+}
+
 template <typename T>
 static void build_records(fr_plan *pl, const DevBuf &d_uvw, const DevBuf &d_freq, int n_p0) {
     const int64_t n = pl->n_vis;
     const int ntu = (int)(pl->nu / kTile), ntv = (int)(pl->nv / kTile);
     const int n_tiles = ntu * ntv;
+    pl->n_p0 = n_p0;
+    pl->n_tiles = n_tiles;
+    pl->ntu = ntu;
+    pl->ntv = ntv;
     const int64_t n_keys = pl->n_chan * (int64_t)n_p0 * n_tiles;
     FR_REQUIRE(n_keys < (int64_t(1) << 32), "too many tiles x planes x channels");
     DevBuf key(n * 4), idx(n * 4), cell(n * 4), du(n * sizeof(T)), dv(n * sizeof(T)), dwf(n * sizeof(T)),
@@ -622,11 +685,15 @@ static void build_records(fr_plan *pl, const DevBuf &d_uvw, const DevBuf &d_freq
     HIP_CHECK(hipMemcpy(h_counts.data(), counts.p, counts.bytes, hipMemcpyDeviceToHost));
     std::vector<int64_t> offs(n_keys);
     int64_t run = 0;
-    std::vector<WorkItem> wis;
+    std::vector<WorkItem> wis, gwis;
+    std::vector<uint32_t> gfirst(n_keys + 1, 0);
     pl->wi_chan.assign(pl->n_chan + 1, 0);
+    pl->gwi_chan.assign(pl->n_chan + 1, 0);
     const int ch = chunk<T>();
+    const int gch = grid_chunk(n / std::max<int64_t>(1, pl->n_chan), pl->ctx->n_cu);
     for (int64_t k = 0; k < n_keys; ++k) {
         offs[k] = run;
+        gfirst[k] = (uint32_t)gwis.size();
         const int64_t cnt = h_counts[k];
         if (cnt) {
             const int64_t chan = k / ((int64_t)n_p0 * n_tiles);
@@ -634,22 +701,38 @@ static void build_records(fr_plan *pl, const DevBuf &d_uvw, const DevBuf &d_freq
             const int p0 = (int)(rem / n_tiles);
             const int t = (int)(rem - (int64_t)p0 * n_tiles);
             const int tu = t / ntv, tv = t - tu * ntv;
+            WorkItem w;
+            w.tu = tu * kTile;
+            w.tv = tv * kTile;
+            w.p0 = p0;
+            w.chan = (int32_t)chan;
+            w.pad = 0;
             for (int64_t s = 0; s < cnt; s += ch) {
-                WorkItem w;
-                w.tu = tu * kTile;
-                w.tv = tv * kTile;
-                w.p0 = p0;
-                w.chan = (int32_t)chan;
                 w.start = run + s;
                 w.count = (int32_t)std::min<int64_t>(ch, cnt - s);
-                w.pad = 0;
                 wis.push_back(w);
                 pl->wi_chan[chan + 1] = (int64_t)wis.size();
+            }
+            for (int64_t s = 0; s < cnt; s += gch) {
+                w.start = run + s;
+                w.count = (int32_t)std::min<int64_t>(gch, cnt - s);
+                gwis.push_back(w);
+                pl->gwi_chan[chan + 1] = (int64_t)gwis.size();
             }
         }
         run += cnt;
     }
-    for (int64_t c = 1; c <= pl->n_chan; ++c) pl->wi_chan[c] = std::max(pl->wi_chan[c], pl->wi_chan[c - 1]);
+    gfirst[n_keys] = (uint32_t)gwis.size();
+    for (int64_t c = 1; c <= pl->n_chan; ++c) {
+        pl->wi_chan[c] = std::max(pl->wi_chan[c], pl->wi_chan[c - 1]);
+        pl->gwi_chan[c] = std::max(pl->gwi_chan[c], pl->gwi_chan[c - 1]);
+    }
+    pl->n_gwi = (int64_t)gwis.size();
+    pl->gwi = DevBuf(std::max<size_t>(1, gwis.size()) * sizeof(WorkItem));
+    if (!gwis.empty())
+        HIP_CHECK(hipMemcpy(pl->gwi.p, gwis.data(), gwis.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
+    pl->gkey_first = DevBuf(gfirst.size() * sizeof(uint32_t));
+    HIP_CHECK(hipMemcpy(pl->gkey_first.p, gfirst.data(), pl->gkey_first.bytes, hipMemcpyHostToDevice));
     DevBuf d_offs(n_keys * 8);
     HIP_CHECK(hipMemcpy(d_offs.p, offs.data(), d_offs.bytes, hipMemcpyHostToDevice));
     HIP_CHECK(hipMemset(counts.p, 0, counts.bytes));  // reused as the scatter cursor
@@ -713,17 +796,37 @@ void plan_build(fr_plan *pl, const double *uvw_m, const double *freq_hz) {
         const double h = -ymin / 2;  // (n - 1) - yc lies in [-h, h]
         pl->yc = ymin / 2;
         double dw = 1.0 / (4.0 * h);  // sigma_w = 2: dw h = 1/4
-        int npl = (int)std::ceil((wmax - wmin) / dw) + pl->Ww + 1;
+        // With w0 = wmin - (Ww/2 - 1 + delta) dw, the first plane a visibility
+        // touches is ceil((w - wmin)/dw + delta - 1), so delta in (0, 1] can be
+        // chosen to centre the w-range inside the fewest first-plane slots:
+        // n_p0 = max(1, ceil(range/dw)) planes of origin, Ww - 1 more planes.
+        auto layout = [&](double dw_, double &delta, int &n_p0) {
+            const double f = (wmax - wmin) / dw_;
+            const double cf = std::ceil(f);
+            if (cf - f > 1e-6) {
+                delta = 0.5 * (cf - f);
+                n_p0 = std::max(1, (int)cf);
+            } else {
+                delta = 1.0;  // range is a whole number of planes (or zero)
+                n_p0 = (int)cf + 1;
+            }
+        };
+        double delta = 1.0;
+        int n_p0 = 1;
+        layout(dw, delta, n_p0);
+        int npl = n_p0 + pl->Ww - 1;
         if (pl->n_wplanes_req > 0) {
             FR_REQUIRE(pl->n_wplanes_req >= npl, "n_wplanes is below the minimum for this epsilon (" +
                                                      std::to_string(npl) + ")");
+            // spend the extra planes on a finer w-grid (larger oversampling in w)
+            const int want_p0 = pl->n_wplanes_req - pl->Ww + 1;
+            if (wmax > wmin && want_p0 > 1) dw = std::min(dw, (wmax - wmin) / (want_p0 - 0.5));
+            layout(dw, delta, n_p0);
             npl = pl->n_wplanes_req;
-            dw = std::min(dw, (wmax - wmin) / std::max(1, npl - pl->Ww - 1));
-            if (!(dw > 0)) dw = 1.0 / (4.0 * h);
         }
         pl->dw = dw;
         pl->n_planes = npl;
-        pl->w0 = wmin - 0.5 * pl->Ww * dw;
+        pl->w0 = wmin - (0.5 * pl->Ww - 1.0 + delta) * dw;
     }
     ESKernel kw(pl->Ww > 1 ? pl->Ww : 4, pl->Ww > 1 ? pl->wbeta : 9.2);
     // --- per-pixel factors
@@ -771,6 +874,11 @@ void plan_build(fr_plan *pl, const double *uvw_m, const double *freq_hz) {
         else build_records<float>(pl, d_uvw, d_freq, n_p0);
     } else {
         pl->wi_chan.assign(pl->n_chan + 1, 0);
+        pl->gwi_chan.assign(pl->n_chan + 1, 0);
+        pl->n_p0 = n_p0;
+        pl->ntu = (int)(pl->nu / kTile);
+        pl->ntv = (int)(pl->nv / kTile);
+        pl->n_tiles = pl->ntu * pl->ntv;
     }
     pl->resident = pl->fac.bytes + pl->tpix.bytes + pl->nfac.bytes + pl->wplane.bytes + pl->r_idx.bytes +
                    pl->r_cell.bytes + pl->r_du.bytes + pl->r_dv.bytes + pl->r_dw.bytes + pl->r_ph.bytes +

@@ -62,6 +62,12 @@ struct fr_plan {
     frmi::DevBuf wi;      // WorkItem [n_wi]
     int64_t n_wi = 0;
     std::vector<int64_t> wi_chan;  // work-item range per channel, [n_chan + 1]
+    // gridding items: larger chunks of one key each, and per key the first item
+    frmi::DevBuf gwi;        // WorkItem [n_gwi]
+    int64_t n_gwi = 0;
+    std::vector<int64_t> gwi_chan;
+    frmi::DevBuf gkey_first;  // uint32 [n_keys + 1]
+    int n_p0 = 1, n_tiles = 1, ntu = 1, ntv = 1;
     std::vector<double> freq;
     std::vector<double> uvw_host;  // [n_row][3] metres, kept to derive the PSF plan
     size_t resident = 0;

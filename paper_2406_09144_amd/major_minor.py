@@ -29,7 +29,7 @@ def _H_and_grad(psf, s, d, i_fixed, inv_power):
     return H, g
 
 
-def minor_cycle(psf, d, s, i_prev, inv_power, n_steps=5, cg_iters=20, log=None):
+def minor_cycle(psf, d, s, i_prev, inv_power, n_steps=5, cg_iters=20, max_step=2.0, log=None):
     """Gauss-Newton MAP steps on the FAST likelihood; d is the minor cycle's data
     image, i_prev the sky the previous major cycle subtracted (None at first)."""
     ifix = None if i_prev is None else (-i_prev).contiguous()
@@ -38,11 +38,16 @@ def minor_cycle(psf, d, s, i_prev, inv_power, n_steps=5, cg_iters=20, log=None):
     for k in range(n_steps):
         D = torch.exp(sb[0])
         ds, hist, it = api.cg_solve((-g[0]).contiguous(), psf=psf, inv_power=inv_power, diag=D, maxiter=cg_iters)
-        t = 1.0
+        # the metric linearises exp(s): cap the log-sky change of a step at max_step
+        # so a large Gauss-Newton step cannot overflow the sky, then backtrack on H
+        dmax = float(ds.abs().max())
+        if not dmax > 0:
+            break
+        t = min(1.0, max_step / dmax)
         while True:
             cand = (sb + t * ds[None]).contiguous()
             Hc, gc = _H_and_grad(psf, cand, d, ifix, inv_power)
-            if float(Hc[0]) <= float(H[0]) or t < 1e-3:
+            if float(Hc[0]) <= float(H[0]) or t < 1e-6:
                 break
             t *= 0.5
         if float(Hc[0]) > float(H[0]):
