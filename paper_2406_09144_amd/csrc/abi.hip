@@ -424,6 +424,12 @@ int fr_profile_enable(int on) {
     Profiler &P = profiler();
     std::lock_guard<std::mutex> g(P.mu);
     P.on = on != 0;
+    // create the events up front so that timed regions only record them
+    while (P.on && P.pool.size() < kProfilerPoolEvents) {
+        hipEvent_t e;
+        HIP_CHECK(hipEventCreate(&e));
+        P.pool.push_back(e);
+    }
     FR_API_END
 }
 

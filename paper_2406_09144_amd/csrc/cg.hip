@@ -6,7 +6,9 @@
 // double precision scalars that live on the device.  Every kernel reads them
 // from device memory, so the host enqueues `maxiter` iterations without ever
 // synchronising; once ||r|| <= rtol ||b|| a device flag turns the remaining
-// update kernels into no-ops.
+// kernels into no-ops.  Reductions need no fences or atomics: a kernel writes
+// per-block partial sums and every block of the next kernel adds them itself,
+// in the same fixed order, so all blocks agree on alpha and beta.
 #include "conv.h"
 #include "elementwise.h"
 #include "objects.h"
@@ -14,10 +16,7 @@
 namespace frmi {
 
 struct CGState {
-    double rr;     // <r, r>
-    double pAp;    // <p, A p>
-    double beta;
-    double stop;   // rtol ||b||
+    double stop;  // rtol ||b||
     int done;
     int iters;
 };
@@ -33,23 +32,17 @@ template <typename T> struct CGInit {
     }
 };
 
-__global__ void k_cg_start(CGState *st, const double *rr_partials, int nparts, double rtol, int maxiter,
-                           double *hist) {
+// rr[0] = <b, b> from the partials of k_dot_partials, stopping threshold, history
+__global__ __launch_bounds__(kRedThreads) void k_cg_start(CGState *st, const double *rr_partials, int nparts,
+                                                          double rtol, int maxiter, double *rr, double *hist) {
+    const double s = block_sum_partials(rr_partials, nparts);
     if (threadIdx.x != 0) return;
-    double s = 0;
-    for (int k = 0; k < nparts; ++k) s += rr_partials[k];
-    st->rr = s;
+    rr[0] = s;
     st->stop = rtol * sqrt(s);
     st->iters = 0;
     st->done = (s == 0.0 || maxiter == 0) ? 1 : 0;
-    st->beta = 0;
     hist[0] = sqrt(s);
 }
-
-struct ZeroU32 {
-    unsigned *p;
-    __device__ void operator()(int64_t i) const { p[i] = 0u; }
-};
 
 // y = diag * x (or copy)
 template <typename T> struct DiagMul {
@@ -69,86 +62,70 @@ template <typename T> struct DiagMulAdd {
     }
 };
 
-// The last block to finish a reduction adds the per-block partials in block
-// order (deterministic) and resets the arrival counter for the next use.
-__device__ __forceinline__ bool arrive_last(unsigned *counter) {
-    __shared__ bool last;
-    __threadfence();
-    if (threadIdx.x == 0) last = atomicAdd(counter, 1u) == gridDim.x - 1;
-    __syncthreads();
-    return last;
+__device__ __forceinline__ bool cg_done(const CGState *st) {
+    return __hip_atomic_load(&st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
 }
 
-// Called by every thread of the last block: the partials are fetched in
-// parallel (device-coherent loads), then added by thread 0 in block order.
-__device__ __forceinline__ double sum_partials(const double *partials, int n) {
-    __shared__ double sh[kRedBlocksPerImage];
-    for (int k = threadIdx.x; k < n; k += blockDim.x)
-        sh[k] = __hip_atomic_load(partials + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    double s = 0;
-    if (threadIdx.x == 0)
-        for (int k = 0; k < n; ++k) s += sh[k];
-    return s;  // valid in thread 0
-}
-
-// <p, A p> into st->pAp
+// partials of <p, A p>
 template <typename T>
-__global__ __launch_bounds__(kRedThreads) void k_cg_dot_pAp(CGState *__restrict__ st, const T *__restrict__ p,
+__global__ __launch_bounds__(kRedThreads) void k_cg_dot_pAp(const CGState *__restrict__ st, const T *__restrict__ p,
                                                             const T *__restrict__ Ap, int64_t n,
-                                                            double *__restrict__ partials, unsigned *counter) {
-    if (st->done) return;
-    double s = 0;
-    for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kRedThreads)
-        s += (double)p[i] * (double)Ap[i];
+                                                            double *__restrict__ pAp_partials) {
+    if (cg_done(st)) return;
+    double s = grid_stride_sum(n, [&](int64_t i) { return (double)p[i] * (double)Ap[i]; });
     s = block_sum(s);
-    if (threadIdx.x == 0) partials[blockIdx.x] = s;
-    if (arrive_last(counter)) {
-        const double t = sum_partials(partials, gridDim.x);
-        if (threadIdx.x == 0) {
-            st->pAp = t;
-            *counter = 0;
-        }
-    }
+    if (threadIdx.x == 0) pAp_partials[blockIdx.x] = s;
 }
 
-// x += alpha p, r -= alpha A p; the last block forms <r, r>, beta, the history
-// entry and the stopping flag
+// alpha = rr[k] / <p, A p>; x += alpha p, r -= alpha A p; partials of <r, r>
 template <typename T>
-__global__ __launch_bounds__(kRedThreads) void k_cg_step(CGState *__restrict__ st, T *__restrict__ x,
+__global__ __launch_bounds__(kRedThreads) void k_cg_step(const CGState *__restrict__ st, T *__restrict__ x,
                                                          T *__restrict__ r, const T *__restrict__ p,
                                                          const T *__restrict__ Ap, int64_t n,
-                                                         double *__restrict__ partials, unsigned *counter, int k,
-                                                         double *__restrict__ hist) {
-    if (st->done) return;
-    const T a = (T)(st->rr / st->pAp);
-    double s = 0;
-    for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kRedThreads) {
-        x[i] += a * p[i];
-        const T rv = r[i] - a * Ap[i];
+                                                         const double *__restrict__ pAp_partials, int n_pAp,
+                                                         const double *__restrict__ rr, int k,
+                                                         double *__restrict__ rr_partials) {
+    if (cg_done(st)) return;
+    __shared__ double alpha_sh;
+    const double pAp = block_sum_partials(pAp_partials, n_pAp);
+    if (threadIdx.x == 0) alpha_sh = rr[k] / pAp;
+    __syncthreads();
+    const T a = (T)alpha_sh;
+    double s = grid_stride_sum(n, [&](int64_t i) {
+        const T pv = p[i], apv = Ap[i], xv = x[i], rv0 = r[i];
+        x[i] = xv + a * pv;
+        const T rv = rv0 - a * apv;
         r[i] = rv;
-        s += (double)rv * (double)rv;
-    }
+        return (double)rv * (double)rv;
+    });
     s = block_sum(s);
-    if (threadIdx.x == 0) partials[blockIdx.x] = s;
-    if (arrive_last(counter)) {
-        const double rr = sum_partials(partials, gridDim.x);
-        if (threadIdx.x == 0) {
-            hist[k + 1] = sqrt(rr);
-            st->beta = rr / st->rr;
-            st->rr = rr;
-            st->iters = k + 1;
-            if (sqrt(rr) <= st->stop) st->done = 1;
-            *counter = 0;
-        }
-    }
+    if (threadIdx.x == 0) rr_partials[blockIdx.x] = s;
 }
 
+// rr[k+1] = <r, r>, beta = rr[k+1] / rr[k], p = r + beta p; block 0 records the
+// history and the stopping flag (blocks that already see the flag skip the
+// update of p, which is no longer used)
 template <typename T>
-__global__ void k_cg_update_p(const CGState *__restrict__ st, T *__restrict__ p, const T *__restrict__ r, int64_t n) {
-    if (st->done) return;
-    const T beta = (T)st->beta;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+__global__ __launch_bounds__(kRedThreads) void k_cg_update_p(CGState *__restrict__ st, T *__restrict__ p,
+                                                             const T *__restrict__ r, int64_t n,
+                                                             const double *__restrict__ rr_partials, int n_rr,
+                                                             double *__restrict__ rr, int k,
+                                                             double *__restrict__ hist) {
+    if (cg_done(st)) return;
+    __shared__ double beta_sh;
+    const double rn = block_sum_partials(rr_partials, n_rr);
+    if (threadIdx.x == 0) {
+        beta_sh = rn / rr[k];
+        if (blockIdx.x == 0) {
+            rr[k + 1] = rn;
+            hist[k + 1] = sqrt(rn);
+            st->iters = k + 1;
+            if (sqrt(rn) <= st->stop) __hip_atomic_store(&st->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    __syncthreads();
+    const T beta = (T)beta_sh;
+    for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kRedThreads)
         p[i] = r[i] + beta * p[i];
 }
 
@@ -163,20 +140,20 @@ void cg_solve(const fr_plan *pl, const fr_psf *psf, const T *weight, const T *in
     const int64_t nc = psf ? psf->n_chan : pl->n_chan;
     const int64_t n = nc * nx * ny;
     const Ctx &ctx = psf ? *psf->ctx : *pl->ctx;
-    Scratch state(sizeof(CGState) + 64, st);
-    Scratch partials((size_t)kRedBlocksPerImage * sizeof(double), st);
-    unsigned *counter = reinterpret_cast<unsigned *>(state.as<char>() + sizeof(CGState));
-    map_async(ZeroU32{counter}, 1, st);
+    Scratch state(sizeof(CGState), st);
+    const int nb = red_blocks(n);
+    Scratch partials((size_t)2 * nb * sizeof(double), st);
+    Scratch rr((size_t)(maxiter + 1) * sizeof(double), st);
+    double *pAp_part = partials.as<double>(), *rr_part = partials.as<double>() + nb;
     Scratch r(n * sizeof(T), st), p(n * sizeof(T), st), Ap(n * sizeof(T), st), t(n * sizeof(T), st),
         u(n * sizeof(T), st);
     Scratch pr;
     if (inv_power) pr = Scratch(n * sizeof(T), st);
     CGState *S = state.as<CGState>();
     map_async(CGInit<T>{b, x, r.as<T>(), p.as<T>()}, n, st);
-    k_dot_partials<T><<<dim3(kRedBlocksPerImage, 1), kRedThreads, 0, st>>>(r.as<T>(), nullptr, n,
-                                                                         partials.as<double>());
+    k_dot_partials<T><<<dim3((unsigned)nb, 1), kRedThreads, 0, st>>>(r.as<T>(), nullptr, n, rr_part);
     LAUNCH_CHECK();
-    k_cg_start<<<1, 64, 0, st>>>(S, partials.as<double>(), kRedBlocksPerImage, rtol, maxiter, hist);
+    k_cg_start<<<1, kRedThreads, 0, st>>>(S, rr_part, nb, rtol, maxiter, rr.as<double>(), hist);
     LAUNCH_CHECK();
     for (int k = 0; k < maxiter; ++k) {
         // A p = D R' D p + S^-1 p
@@ -193,14 +170,13 @@ void cg_solve(const fr_plan *pl, const fr_psf *psf, const T *weight, const T *in
             apply_rnr_exact<T>(pl, weight, src, u.as<T>(), 1, st);
             map_async(DiagMulAdd<T>{diag, u.as<T>(), prior, Ap.as<T>()}, n, st);
         }
-        k_cg_dot_pAp<T><<<dim3(kRedBlocksPerImage), kRedThreads, 0, st>>>(S, p.as<T>(), Ap.as<T>(), n,
-                                                                          partials.as<double>(), counter);
+        k_cg_dot_pAp<T><<<dim3((unsigned)nb), kRedThreads, 0, st>>>(S, p.as<T>(), Ap.as<T>(), n, pAp_part);
         LAUNCH_CHECK();
-        k_cg_step<T><<<dim3(kRedBlocksPerImage), kRedThreads, 0, st>>>(S, x, r.as<T>(), p.as<T>(), Ap.as<T>(), n,
-                                                                       partials.as<double>(), counter, k, hist);
+        k_cg_step<T><<<dim3((unsigned)nb), kRedThreads, 0, st>>>(S, x, r.as<T>(), p.as<T>(), Ap.as<T>(), n, pAp_part,
+                                                                  nb, rr.as<double>(), k, rr_part);
         LAUNCH_CHECK();
-        const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
-        k_cg_update_p<T><<<dim3((unsigned)blocks), 256, 0, st>>>(S, p.as<T>(), r.as<T>(), n);
+        k_cg_update_p<T><<<dim3((unsigned)nb), kRedThreads, 0, st>>>(S, p.as<T>(), r.as<T>(), n, rr_part, nb,
+                                                                      rr.as<double>(), k, hist);
         LAUNCH_CHECK();
     }
     k_cg_report<<<1, 64, 0, st>>>(S, iters_done);

@@ -125,7 +125,17 @@ constexpr int kLdsBytes = 163840;
 // Kernels using more than the default dynamic-LDS limit must opt in once.
 template <typename F>
 inline void allow_lds(F *func, size_t bytes) {
-    if (bytes > 65536) HIP_CHECK(hipFuncSetAttribute((const void *)func, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    // the attribute is raised once per kernel and device to the largest size asked for
+    if (bytes <= 65536) return;
+    static std::mutex mu;
+    static std::map<std::pair<int, const void *>, size_t> done;
+    int dev = 0;
+    HIP_CHECK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> g(mu);
+    size_t &have = done[{dev, (const void *)func}];
+    if (have >= bytes) return;
+    HIP_CHECK(hipFuncSetAttribute((const void *)func, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    have = bytes;
 }
 
 }  // namespace frmi

@@ -11,15 +11,20 @@
 //   3. degrid:  one workgroup per work item (uv tile x first w-plane): the tile and
 //               its W-1 halo of each touched plane is staged in LDS, every
 //               visibility sums psi_w psi_u psi_v G over its W x W x Ww footprint.
-// Gridding is the exact transpose: one wavefront per visibility spreads it into
-// LDS tiles of the touched planes (lane (a, b) owns footprint cell (a, b), so each
-// LDS atomic instruction hits distinct cells), the tiles are flushed to the planes
-// with global atomics, inverse column FFT
-// (keeping only the non-zero rows), then a row kernel that transforms each plane
-// row and accumulates Re(exp(+2 pi i w_p t) G) over planes into the image row.
+// Gridding is the exact transpose: each wavefront of a work item's workgroup takes
+// batches of 64 visibilities (one coalesced load per batch, values broadcast
+// lane-to-lane) and spreads each into LDS tiles of the touched planes (lane (a, b)
+// owns footprint cell (a, b), so each LDS atomic instruction hits distinct cells);
+// every work item stores its tiles as a partial result, an owner-computes pass
+// sums the partials covering each plane tile in a fixed order (no global
+// atomics, no clearing, deterministic), inverse column FFT (keeping only the
+// non-zero rows), then a row kernel that transforms each plane row and
+// accumulates Re(exp(+2 pi i w_p t) G) over planes into the image row.
 #include <algorithm>
 #include <cmath>
 #include <numeric>
+
+#include <rocprim/device/device_radix_sort.hpp>
 
 #include "eskernel.h"
 #include "fftk.h"
@@ -84,22 +89,43 @@ __global__ void k_vis_coords(const double *__restrict__ uvw, const double *__res
     ph[v] = (T)phc;
 }
 
-__global__ void k_hist(const uint32_t *__restrict__ key, int64_t n, uint32_t *__restrict__ counts) {
+// Sort key of a visibility: its bucket (channel, first plane, tile) above the
+// position of its base cell inside the tile, so that a bucket's visibilities
+// come out grouped by base cell (runs that the gridder accumulates in
+// registers).  The radix sort is stable, which makes the record order, and
+// hence every summation order, a function of the input alone.
+__global__ void k_sort_keys(const uint32_t *__restrict__ key, const uint32_t *__restrict__ cell, int64_t n,
+                            uint64_t *__restrict__ k64, uint32_t *__restrict__ perm) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v < n) atomicAdd(&counts[key[v]], 1u);
+    if (v >= n) return;
+    const uint32_t c = cell[v];
+    k64[v] = ((uint64_t)key[v] << 10) | (uint64_t)((c & 0xffffu) * kTile + (c >> 16));
+    perm[v] = (uint32_t)v;
+}
+
+// offs[k] = first sorted position whose bucket is >= k, for k = 0 .. n_keys
+__global__ void k_bucket_bounds(const uint64_t *__restrict__ k64, int64_t n, int64_t n_keys,
+                                int64_t *__restrict__ offs) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k > n_keys) return;
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)(k64[mid] >> 10) < k) lo = mid + 1;
+        else hi = mid;
+    }
+    offs[k] = lo;
 }
 
 template <typename T>
-__global__ void k_scatter(int64_t n, const uint32_t *__restrict__ key, const int64_t *__restrict__ offs,
-                          uint32_t *__restrict__ cursor, const uint32_t *__restrict__ i_idx,
-                          const uint32_t *__restrict__ i_cell, const T *__restrict__ i_du, const T *__restrict__ i_dv,
-                          const T *__restrict__ i_dw, const T *__restrict__ i_ph, uint32_t *__restrict__ o_idx,
-                          uint32_t *__restrict__ o_cell, T *__restrict__ o_du, T *__restrict__ o_dv,
-                          T *__restrict__ o_dw, T *__restrict__ o_ph) {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= n) return;
-    const uint32_t k = key[v];
-    const int64_t pos = offs[k] + atomicAdd(&cursor[k], 1u);
+__global__ void k_gather_records(int64_t n, const uint32_t *__restrict__ perm, const uint32_t *__restrict__ i_idx,
+                                 const uint32_t *__restrict__ i_cell, const T *__restrict__ i_du,
+                                 const T *__restrict__ i_dv, const T *__restrict__ i_dw, const T *__restrict__ i_ph,
+                                 uint32_t *__restrict__ o_idx, uint32_t *__restrict__ o_cell, T *__restrict__ o_du,
+                                 T *__restrict__ o_dv, T *__restrict__ o_dw, T *__restrict__ o_ph) {
+    const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pos >= n) return;
+    const uint32_t v = perm[pos];
     o_idx[pos] = i_idx[v];
     o_cell[pos] = i_cell[v];
     o_du[pos] = i_du[v];
@@ -112,6 +138,14 @@ __global__ void k_scatter(int64_t n, const uint32_t *__restrict__ key, const int
 template <typename T> __device__ __forceinline__ T es_eval(T z, T beta) {
     const T q = T(1) - z * z;
     return q >= T(0) ? (T)exp(beta * (sqrt(q) - T(1))) : T(0);
+}
+// FP32: the hardware square root and base-2 exponential.  Rounding the argument
+// beta (sqrt(q) - 1) (|.| <= beta ~ 2.3 W) to FP32 already costs about 1e-6
+// relative in the result, so the correctly rounded library routines buy nothing.
+template <> __device__ __forceinline__ float es_eval<float>(float z, float beta) {
+    const float q = 1.0f - z * z;
+    constexpr float kLog2e = 1.4426950408889634f;
+    return q >= 0.0f ? __builtin_amdgcn_exp2f(beta * kLog2e * (__builtin_amdgcn_sqrtf(q) - 1.0f)) : 0.0f;
 }
 
 // ------------------------------------------------------------------ degrid
@@ -201,17 +235,45 @@ __global__ __launch_bounds__(NTHR) void k_degrid(const WorkItem *__restrict__ wi
     }
 }
 
+// value of lane k (wave-uniform k) in every lane
+__device__ __forceinline__ float wave_bcast(float v, int k) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
+__device__ __forceinline__ double wave_bcast(double v, int k) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), k);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // ------------------------------------------------------------------ grid: partial tiles
+// Planes held in registers per pass of the gridding kernel: lane (a, b) keeps,
+// for each footprint cell it owns and each plane of the pass, the running sum of
+// the current run of visibilities (about 48 VGPRs at most).
+template <typename T, int W> constexpr int grid_reg_planes() {
+    constexpr int ncell = (W * W + 63) / 64;
+    constexpr int per_plane = ncell * 2 * (int)sizeof(T) / 4;
+    return 48 / per_plane < 1 ? 1 : 48 / per_plane;
+}
+
 // One workgroup per gridding item (a chunk of the visibilities of one uv tile
-// and first w-plane).  One wavefront per visibility: lane (a, b) owns footprint
-// cell (a, b) (cells beyond 64 wrap to more passes), so the LDS atomics of one
-// instruction hit W*W distinct cells; the w-kernel weights are evaluated by
-// lanes 0..Ww-1 and broadcast with wavefront shuffles.  `ppass` planes are
-// resident in LDS at once (all Ww when they fit).  The accumulated tiles, halo
-// included, are written with plain stores to the item's slot of the partial
-// buffer [item][Ww][TS*TS] (complex); k_grid_assemble adds them up.  Tiles are
-// stored in LDS as separate real and imaginary arrays to keep lanes on distinct
-// banks.
+// and first w-plane; the plan orders them by base cell inside the tile).  Each
+// wavefront takes a contiguous share of the item and walks it one visibility
+// at a time: lane (a, b) owns footprint cell (a, b) (cells beyond 64 wrap to
+// more registers), the record fields and the w-kernel weights (evaluated by
+// lanes 0..Ww-1) are broadcast with readlane.  While consecutive visibilities
+// share a base cell their contributions add up in registers; when the cell
+// changes the run is flushed to the LDS tiles with one atomic per (cell, plane)
+// and part.  The LDS tiles hold 64-bit fixed-point integers: every contribution
+// to a component is at most bound = count * max(|Re y| + |Im y|) of the call
+// (kernel values are <= 1), so scaling by 2^k with bound * 2^k < 2^61 keeps
+// every partial sum in range, integer atomics (much faster than LDS float
+// atomics) add them exactly, and the tile sums do not depend on the order in
+// which waves flush.  `ppass` planes are done per pass (bounded by LDS and
+// registers).  The accumulated tiles, halo included, are written with plain
+// stores to the item's slot of the partial buffer [item][Ww][TS*TS] (complex);
+// k_grid_assemble adds them up.  Tiles are stored in LDS as separate real and
+// imaginary arrays.
 template <typename T, int W, int NTHR>
 __global__ __launch_bounds__(NTHR) void k_grid_partial(const WorkItem *__restrict__ wis, c2<T> *__restrict__ partial,
                                                        int Ww, int ppass, T beta, T wbeta, int coplanar,
@@ -219,14 +281,34 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial(const WorkItem *__restric
                                                        const uint32_t *__restrict__ r_cell,
                                                        const T *__restrict__ r_du, const T *__restrict__ r_dv,
                                                        const T *__restrict__ r_dw, const T *__restrict__ r_ph,
-                                                       const c2<T> *__restrict__ vis, const T *__restrict__ weight) {
+                                                       const c2<T> *__restrict__ vis, const T *__restrict__ weight,
+                                                       const float *__restrict__ ybound_partials, int n_ybound) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *tile = reinterpret_cast<T *>(smem_raw);  // [ppass][2][TS * TS]
+    long long *tile = reinterpret_cast<long long *>(smem_raw);  // [ppass][2][TS * TS]
     constexpr int TS = kTile + W - 1;
     constexpr int TT = TS * TS;
     constexpr int NCELL = (W * W + 63) / 64;
     constexpr int NWAVE = NTHR / 64;
+    constexpr int PR = grid_reg_planes<T, W>() < W ? grid_reg_planes<T, W>() : W;
     const WorkItem it = wis[blockIdx.x];
+    // fixed-point exponent from the bound on every contribution
+    __shared__ float wmax[NWAVE];
+    {
+        float m = 0.0f;
+        for (int q = threadIdx.x; q < n_ybound; q += NTHR) m = fmaxf(m, ybound_partials[q]);
+        for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+        if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+    }
+    __syncthreads();
+    float ymax = 0.0f;
+#pragma unroll
+    for (int q = 0; q < NWAVE; ++q) ymax = fmaxf(ymax, wmax[q]);
+    int kexp = 0;
+    if (ymax > 0.0f && ymax <= 3.0e38f) {
+        int e;
+        frexp(2.0 * (double)ymax * (double)it.count, &e);  // bound < 2^(e-1)
+        kexp = 62 - e;
+    }
     c2<T> *out = partial + (int64_t)blockIdx.x * Ww * TT;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const T two_over_W = T(2) / T(W);
@@ -237,58 +319,121 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial(const WorkItem *__restric
         ca[q] = c < W * W ? c / W : -1;
         cb[q] = c < W * W ? c - (c / W) * W : 0;
     }
-    for (int g0 = 0; g0 < Ww; g0 += ppass) {
-        const int np = min(ppass, Ww - g0);
-        for (int q = threadIdx.x; q < np * 2 * TT; q += NTHR) tile[q] = T(0);
+    // this wavefront's contiguous share of the item
+    const int share = (it.count + NWAVE - 1) / NWAVE;
+    const int v_begin = min(it.count, wave * share), v_end = min(it.count, v_begin + share);
+    const int pp = min(ppass, PR);
+    for (int g0 = 0; g0 < Ww; g0 += pp) {
+        const int np = min(pp, Ww - g0);
+        for (int q = threadIdx.x; q < np * 2 * TT; q += NTHR) tile[q] = 0;
         __syncthreads();
-        for (int j = wave; j < it.count; j += NWAVE) {
-            const int64_t pos = it.start + j;
-            const uint32_t cell = r_cell[pos];
-            const int ru = (int)(cell & 0xffffu), rv = (int)(cell >> 16);
-            const uint32_t id = r_idx[pos];
-            const uint32_t vi = id & 0x7fffffffu;
-            c2<T> y = vis ? vis[vi] : mk<T>(T(1), T(0));
-            if (weight) {
-                const T wt = weight[vi];
-                y.x *= wt;
-                y.y *= wt;
-            }
-            if (id >> 31) y.y = -y.y;
-            if (!coplanar) {
-                T s, c;
-                sincos_cycles(r_ph[pos], &s, &c);
-                y = cmul<T>(y, mk<T>(c, s));
-            }
-            const T xu = r_du[pos], xv = r_dv[pos];
-            T kwl = T(1);
-            if (!coplanar && lane < np) kwl = es_eval<T>((r_dw[pos] - T(g0 + lane)) * (T(2) / T(Ww)), wbeta);
-            // broadcast the plane weights while every lane is active
-            T kw[W];
+        T acc_re[NCELL][PR], acc_im[NCELL][PR];
 #pragma unroll
-            for (int p = 0; p < W; ++p) kw[p] = (!coplanar && p < np) ? __shfl(kwl, p, 64) : T(1);
+        for (int q = 0; q < NCELL; ++q)
+#pragma unroll
+            for (int p = 0; p < PR; ++p) acc_re[q][p] = acc_im[q][p] = T(0);
+        int run_cell = -1;  // base cell of the run held in acc (wave-uniform)
+        auto flush = [&]() {
+            const int ru = run_cell & 0xffff, rv = run_cell >> 16;
 #pragma unroll
             for (int q = 0; q < NCELL; ++q) {
                 if (ca[q] < 0) continue;
-                const T wuv = es_eval<T>((xu - T(ca[q])) * two_over_W, beta) *
-                              es_eval<T>((xv - T(cb[q])) * two_over_W, beta);
-                const T cx = y.x * wuv, cy = y.y * wuv;
                 const int off = (ru + ca[q]) * TS + rv + cb[q];
 #pragma unroll
-                for (int p = 0; p < W; ++p) {
+                for (int p = 0; p < PR; ++p) {
                     if (p >= np) break;
-                    T *tp = tile + 2 * p * TT;
-                    atomicAdd(tp + off, cx * kw[p]);
-                    atomicAdd(tp + TT + off, cy * kw[p]);
+                    unsigned long long *tp = reinterpret_cast<unsigned long long *>(tile + 2 * p * TT);
+                    const long long vr = (long long)rint(ldexp((double)acc_re[q][p], kexp));
+                    const long long vi = (long long)rint(ldexp((double)acc_im[q][p], kexp));
+                    atomicAdd(tp + off, (unsigned long long)vr);
+                    atomicAdd(tp + TT + off, (unsigned long long)vi);
+                    acc_re[q][p] = acc_im[q][p] = T(0);
+                }
+            }
+        };
+        for (int b0 = v_begin; b0 < v_end; b0 += 64) {
+            // lane k loads visibility b0 + k: one memory round trip per 64
+            const int nb = min(64, v_end - b0);
+            int l_cell = 0;
+            T l_xu = T(0), l_xv = T(0), l_xw = T(0);
+            c2<T> l_y = mk<T>(T(0), T(0));
+            if (lane < nb) {
+                const int64_t pos = it.start + b0 + lane;
+                l_cell = (int)r_cell[pos];
+                const uint32_t id = r_idx[pos];
+                const uint32_t vi = id & 0x7fffffffu;
+                c2<T> y = vis ? vis[vi] : mk<T>(T(1), T(0));
+                if (weight) {
+                    const T wt = weight[vi];
+                    y.x *= wt;
+                    y.y *= wt;
+                }
+                if (id >> 31) y.y = -y.y;
+                if (!coplanar) {
+                    T sn, cs;
+                    sincos_cycles(r_ph[pos], &sn, &cs);
+                    y = cmul<T>(y, mk<T>(cs, sn));
+                }
+                l_y = y;
+                l_xu = r_du[pos];
+                l_xv = r_dv[pos];
+                l_xw = r_dw[pos];
+            }
+            for (int k = 0; k < nb; ++k) {
+                const int cell = __builtin_amdgcn_readlane(l_cell, k);
+                if (cell != run_cell) {
+                    if (run_cell >= 0) flush();
+                    run_cell = cell;
+                }
+                const T yx = wave_bcast(l_y.x, k), yy = wave_bcast(l_y.y, k);
+                const T xu = wave_bcast(l_xu, k), xv = wave_bcast(l_xv, k), xw = wave_bcast(l_xw, k);
+                T kwl = T(1);
+                if (!coplanar && lane < np) kwl = es_eval<T>((xw - T(g0 + lane)) * (T(2) / T(Ww)), wbeta);
+                T kw[PR];
+#pragma unroll
+                for (int p = 0; p < PR; ++p) kw[p] = (!coplanar && p < np) ? wave_bcast(kwl, p) : T(1);
+#pragma unroll
+                for (int q = 0; q < NCELL; ++q) {
+                    const T wuv = ca[q] < 0 ? T(0)
+                                            : es_eval<T>((xu - T(ca[q])) * two_over_W, beta) *
+                                                  es_eval<T>((xv - T(cb[q])) * two_over_W, beta);
+                    const T cx = yx * wuv, cy = yy * wuv;
+#pragma unroll
+                    for (int p = 0; p < PR; ++p) {
+                        acc_re[q][p] += cx * kw[p];
+                        acc_im[q][p] += cy * kw[p];
+                    }
                 }
             }
         }
+        if (run_cell >= 0) flush();
         __syncthreads();
         for (int q = threadIdx.x; q < np * TT; q += NTHR) {
             const int p = q / TT, r = q - p * TT;
-            out[(int64_t)(g0 + p) * TT + r] = mk<T>(tile[2 * p * TT + r], tile[2 * p * TT + TT + r]);
+            out[(int64_t)(g0 + p) * TT + r] = mk<T>((T)ldexp((double)tile[2 * p * TT + r], -kexp),
+                                                    (T)ldexp((double)tile[2 * p * TT + TT + r], -kexp));
         }
         __syncthreads();
     }
+}
+
+// partials[b] = block b's maximum over visibilities of (|Re v| + |Im v|) |w|
+// (v = 1 without visibilities, w = 1 without weights), rounded up to FP32
+template <typename T>
+__global__ __launch_bounds__(256) void k_vis_bound(const c2<T> *__restrict__ vis, const T *__restrict__ weight,
+                                                   int64_t n, float *__restrict__ partials) {
+    float m = 0.0f;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        double a = 1.0;
+        if (vis) a = fabs((double)vis[i].x) + fabs((double)vis[i].y);
+        if (weight) a *= fabs((double)weight[i]);
+        m = fmaxf(m, __double2float_ru(a));
+    }
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    __shared__ float sh[4];
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) partials[blockIdx.x] = fmaxf(fmaxf(sh[0], sh[1]), fmaxf(sh[2], sh[3]));
 }
 
 // Owner-computes assembly: workgroup (tile, plane p) writes the 32 x 32 cells it
@@ -481,15 +626,18 @@ void launch_degrid_w(const fr_plan *pl, const WorkItem *wis, int64_t nwi, const 
 
 template <typename T, int W>
 void launch_grid_w(const fr_plan *pl, int64_t chan, c2<T> *planes, const c2<T> *vis, const T *weight,
-                   hipStream_t st) {
+                   const float *ybound, int nbb, hipStream_t st) {
     constexpr int TS = kTile + W - 1;
-    constexpr int NTHR = 1024;
+    constexpr int NTHR = sizeof(T) == 8 ? 512 : 1024;  // FP64 runs need the larger register file share
     const int64_t i0 = pl->gwi_chan[chan], i1 = pl->gwi_chan[chan + 1];
     const size_t per_plane = (size_t)TS * TS * sizeof(c2<T>);
+    const size_t per_plane_lds = (size_t)TS * TS * 2 * sizeof(long long);
     if (i1 > i0) {
         Scratch partial((size_t)(i1 - i0) * pl->Ww * per_plane, st);
-        const int ppass = (int)std::max<size_t>(1, std::min<size_t>(pl->Ww, (size_t)kLdsBytes / per_plane));
-        const size_t lds = per_plane * ppass;
+        // static LDS of the kernel: one float per wavefront
+        const size_t lds_dyn = (size_t)kLdsBytes - (NTHR / 64) * sizeof(float);
+        const int ppass = (int)std::max<size_t>(1, std::min<size_t>(pl->Ww, lds_dyn / per_plane_lds));
+        const size_t lds = per_plane_lds * ppass;
         auto kern = k_grid_partial<T, W, NTHR>;
         allow_lds(kern, lds);
         {
@@ -497,7 +645,7 @@ void launch_grid_w(const fr_plan *pl, int64_t chan, c2<T> *planes, const c2<T> *
             kern<<<dim3((unsigned)(i1 - i0)), NTHR, lds, st>>>(
                 pl->gwi.as<WorkItem>() + i0, partial.as<c2<T>>(), pl->Ww, ppass, (T)pl->beta, (T)pl->wbeta,
                 pl->coplanar ? 1 : 0, pl->r_idx.as<uint32_t>(), pl->r_cell.as<uint32_t>(), pl->r_du.as<T>(),
-                pl->r_dv.as<T>(), pl->r_dw.as<T>(), pl->r_ph.as<T>(), vis, weight);
+                pl->r_dv.as<T>(), pl->r_dw.as<T>(), pl->r_ph.as<T>(), vis, weight, ybound, nbb);
             LAUNCH_CHECK();
         }
         ProfScope prof("grid_assemble", st);
@@ -597,8 +745,15 @@ void degrid(const fr_plan *pl, const T *img, c2<T> *vis, hipStream_t st) {
 template <typename T>
 void grid(const fr_plan *pl, const c2<T> *vis, const T *weight, T *img, hipStream_t st) {
     Scratch planes(planes_bytes(pl), st);
+    // bound on every gridded contribution (sets the fixed-point scale of the tiles)
+    const int nbb = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (pl->n_vis + 1023) / 1024));
+    Scratch ybound((size_t)nbb * sizeof(float), st);
+    if (pl->n_vis > 0) {
+        k_vis_bound<T><<<dim3((unsigned)nbb), 256, 0, st>>>(vis, weight, pl->n_vis, ybound.as<float>());
+        LAUNCH_CHECK();
+    }
     for (int64_t c = 0; c < pl->n_chan; ++c) {
-#define FR_CALL_GRID(WW) launch_grid_w<T, WW>(pl, c, planes.as<c2<T>>(), vis, weight, st)
+#define FR_CALL_GRID(WW) launch_grid_w<T, WW>(pl, c, planes.as<c2<T>>(), vis, weight, ybound.as<float>(), nbb, st)
         FR_W_DISPATCH(pl->W, FR_CALL_GRID)
 #undef FR_CALL_GRID
         planes_to_image<T>(pl, planes.as<c2<T>>(), img + c * pl->nx * pl->ny, st);
@@ -677,13 +832,26 @@ static void build_records(fr_plan *pl, const DevBuf &d_uvw, const DevBuf &d_freq
         pl->dx_, pl->dy_, pl->W, pl->Ww, pl->coplanar ? 1 : 0, pl->w0, pl->dw, pl->yc, ntv, n_tiles, n_p0,
         key.as<uint32_t>(), idx.as<uint32_t>(), cell.as<uint32_t>(), du.as<T>(), dv.as<T>(), dwf.as<T>(), ph.as<T>());
     LAUNCH_CHECK();
-    DevBuf counts(n_keys * 4);
-    HIP_CHECK(hipMemset(counts.p, 0, counts.bytes));
-    k_hist<<<dim3((unsigned)blocks), 256>>>(key.as<uint32_t>(), n, counts.as<uint32_t>());
+    // stable radix sort of (bucket, cell in tile) keys; the permutation gathers the records
+    DevBuf k64(n * 8), k64s(n * 8), perm(n * 4), perms(n * 4);
+    k_sort_keys<<<dim3((unsigned)blocks), 256>>>(key.as<uint32_t>(), cell.as<uint32_t>(), n, k64.as<uint64_t>(),
+                                                 perm.as<uint32_t>());
     LAUNCH_CHECK();
-    std::vector<uint32_t> h_counts(n_keys);
-    HIP_CHECK(hipMemcpy(h_counts.data(), counts.p, counts.bytes, hipMemcpyDeviceToHost));
-    std::vector<int64_t> offs(n_keys);
+    int key_bits = 1;
+    while ((int64_t(1) << key_bits) < n_keys) ++key_bits;
+    const unsigned end_bit = (unsigned)(10 + key_bits);
+    size_t tmp_bytes = 0;
+    HIP_CHECK(rocprim::radix_sort_pairs(nullptr, tmp_bytes, k64.as<uint64_t>(), k64s.as<uint64_t>(),
+                                        perm.as<uint32_t>(), perms.as<uint32_t>(), (size_t)n, 0u, end_bit));
+    DevBuf tmp(std::max<size_t>(tmp_bytes, 1));
+    HIP_CHECK(rocprim::radix_sort_pairs(tmp.p, tmp_bytes, k64.as<uint64_t>(), k64s.as<uint64_t>(),
+                                        perm.as<uint32_t>(), perms.as<uint32_t>(), (size_t)n, 0u, end_bit));
+    DevBuf d_bounds((n_keys + 1) * 8);
+    k_bucket_bounds<<<dim3((unsigned)((n_keys + 1 + 255) / 256)), 256>>>(k64s.as<uint64_t>(), n, n_keys,
+                                                                          d_bounds.as<int64_t>());
+    LAUNCH_CHECK();
+    std::vector<int64_t> bounds(n_keys + 1);
+    HIP_CHECK(hipMemcpy(bounds.data(), d_bounds.p, d_bounds.bytes, hipMemcpyDeviceToHost));
     int64_t run = 0;
     std::vector<WorkItem> wis, gwis;
     std::vector<uint32_t> gfirst(n_keys + 1, 0);
@@ -692,9 +860,8 @@ static void build_records(fr_plan *pl, const DevBuf &d_uvw, const DevBuf &d_freq
     const int ch = chunk<T>();
     const int gch = grid_chunk(n / std::max<int64_t>(1, pl->n_chan), pl->ctx->n_cu);
     for (int64_t k = 0; k < n_keys; ++k) {
-        offs[k] = run;
         gfirst[k] = (uint32_t)gwis.size();
-        const int64_t cnt = h_counts[k];
+        const int64_t cnt = bounds[k + 1] - bounds[k];
         if (cnt) {
             const int64_t chan = k / ((int64_t)n_p0 * n_tiles);
             const int64_t rem = k - chan * n_p0 * n_tiles;
@@ -733,19 +900,16 @@ static void build_records(fr_plan *pl, const DevBuf &d_uvw, const DevBuf &d_freq
         HIP_CHECK(hipMemcpy(pl->gwi.p, gwis.data(), gwis.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
     pl->gkey_first = DevBuf(gfirst.size() * sizeof(uint32_t));
     HIP_CHECK(hipMemcpy(pl->gkey_first.p, gfirst.data(), pl->gkey_first.bytes, hipMemcpyHostToDevice));
-    DevBuf d_offs(n_keys * 8);
-    HIP_CHECK(hipMemcpy(d_offs.p, offs.data(), d_offs.bytes, hipMemcpyHostToDevice));
-    HIP_CHECK(hipMemset(counts.p, 0, counts.bytes));  // reused as the scatter cursor
     pl->r_idx = DevBuf(n * 4);
     pl->r_cell = DevBuf(n * 4);
     pl->r_du = DevBuf(n * sizeof(T));
     pl->r_dv = DevBuf(n * sizeof(T));
     pl->r_dw = DevBuf(n * sizeof(T));
     pl->r_ph = DevBuf(n * sizeof(T));
-    k_scatter<T><<<dim3((unsigned)blocks), 256>>>(
-        n, key.as<uint32_t>(), d_offs.as<int64_t>(), counts.as<uint32_t>(), idx.as<uint32_t>(), cell.as<uint32_t>(),
-        du.as<T>(), dv.as<T>(), dwf.as<T>(), ph.as<T>(), pl->r_idx.as<uint32_t>(), pl->r_cell.as<uint32_t>(),
-        pl->r_du.as<T>(), pl->r_dv.as<T>(), pl->r_dw.as<T>(), pl->r_ph.as<T>());
+    k_gather_records<T><<<dim3((unsigned)blocks), 256>>>(
+        n, perms.as<uint32_t>(), idx.as<uint32_t>(), cell.as<uint32_t>(), du.as<T>(), dv.as<T>(), dwf.as<T>(),
+        ph.as<T>(), pl->r_idx.as<uint32_t>(), pl->r_cell.as<uint32_t>(), pl->r_du.as<T>(), pl->r_dv.as<T>(),
+        pl->r_dw.as<T>(), pl->r_ph.as<T>());
     LAUNCH_CHECK();
     pl->n_wi = (int64_t)wis.size();
     pl->wi = DevBuf(std::max<size_t>(1, wis.size()) * sizeof(WorkItem));

@@ -55,14 +55,13 @@ template <typename T>
 __global__ __launch_bounds__(kRedThreads) void k_vis_residual(c2<T> *__restrict__ model, const c2<T> *__restrict__ V,
                                                               const T *__restrict__ w, int64_t n,
                                                               double *__restrict__ partials) {
-    double s = 0;
-    for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kRedThreads) {
+    double s = grid_stride_sum(n, [&](int64_t i) {
         const c2<T> m = model[i], v = V[i];
         const T wt = w ? w[i] : T(1);
         const T dx = m.x - v.x, dy = m.y - v.y;
-        s += (double)wt * ((double)dx * dx + (double)dy * dy);
         model[i] = mk<T>(wt * dx, wt * dy);
-    }
+        return (double)wt * ((double)dx * dx + (double)dy * dy);
+    });
     s = block_sum(s);
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
@@ -76,7 +75,7 @@ void likelihood_grad(const fr_plan *pl, const fr_psf *psf, int mode, const T *s,
     const int64_t n_img = nc * nx * ny;  // one sample
     const int64_t n_all = B * n_img;
     const Ctx &ctx = mode == FR_LIK_FAST ? *psf->ctx : *pl->ctx;
-    Scratch partials((size_t)std::max<int64_t>(B, 1) * kRedBlocksPerImage * sizeof(double), st);
+    Scratch partials((size_t)std::max<int64_t>(B, 1) * kRedMaxBlocks * sizeof(double), st);
     Scratch Ib((size_t)n_all * sizeof(T), st);
     Scratch ub((size_t)n_all * sizeof(T), st);
     map_async(SkyFromLog<T>{s, i_fixed, Ib.as<T>(), n_img}, n_all, st);
@@ -94,13 +93,13 @@ void likelihood_grad(const fr_plan *pl, const fr_psf *psf, int mode, const T *s,
         apply_rnr_approx<T>(psf, Ib.as<T>(), ub.as<T>(), B, st);
     } else {
         Scratch vis((size_t)pl->n_vis * sizeof(c2<T>), st);
-        const int nblk = kRedBlocksPerImage;
+        const int nblk = red_blocks(pl->n_vis);
         for (int64_t b = 0; b < B; ++b) {
             degrid<T>(pl, Ib.as<T>() + b * n_img, vis.as<c2<T>>(), st);
             k_vis_residual<T><<<dim3(nblk), kRedThreads, 0, st>>>(vis.as<c2<T>>(), (const c2<T> *)data, weight,
                                                                   pl->n_vis, partials.as<double>());
             LAUNCH_CHECK();
-            k_finish_sums<<<1, 64, 0, st>>>(partials.as<double>(), nblk, 1, 0.5, 0, H + b);
+            k_finish_sums<<<1, kRedThreads, 0, st>>>(partials.as<double>(), nblk, 0.5, 0, H + b);
             LAUNCH_CHECK();
             grid<T>(pl, vis.as<c2<T>>(), nullptr, ub.as<T>() + b * n_img, st);
         }

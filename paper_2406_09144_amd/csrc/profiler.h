@@ -7,6 +7,8 @@
 
 namespace frmi {
 
+constexpr size_t kProfilerPoolEvents = 8192;
+
 struct ProfRec {
     hipEvent_t a, b;
 };
