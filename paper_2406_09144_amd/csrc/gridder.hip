@@ -117,6 +117,19 @@ __global__ void k_bucket_bounds(const uint64_t *__restrict__ k64, int64_t n, int
     offs[k] = lo;
 }
 
+// rows of the tile (halo included) that gridding item i touches: its records are
+// sorted by base cell, so the first and last hold the smallest and largest
+// base row
+__global__ void k_item_rows(WorkItem *__restrict__ items, int64_t n_items, const uint32_t *__restrict__ r_cell,
+                            int W) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_items) return;
+    WorkItem it = items[i];
+    const int r0 = (int)(r_cell[it.start] & 0xffffu);
+    const int r1 = (int)(r_cell[it.start + it.count - 1] & 0xffffu) + W - 1;
+    items[i].rows = r0 | (r1 << 16);
+}
+
 template <typename T>
 __global__ void k_gather_records(int64_t n, const uint32_t *__restrict__ perm, const uint32_t *__restrict__ i_idx,
                                  const uint32_t *__restrict__ i_cell, const T *__restrict__ i_du,
@@ -258,10 +271,13 @@ template <typename T, int W> constexpr int grid_reg_planes() {
 
 // One workgroup per gridding item (a chunk of the visibilities of one uv tile
 // and first w-plane; the plan orders them by base cell inside the tile).  Each
-// wavefront takes a contiguous share of the item and walks it one visibility
-// at a time: lane (a, b) owns footprint cell (a, b) (cells beyond 64 wrap to
-// more registers), the record fields and the w-kernel weights (evaluated by
-// lanes 0..Ww-1) are broadcast with readlane.  While consecutive visibilities
+// wavefront takes a contiguous share of the item in batches of 64: lane j loads
+// record j and forms y_j times the w-kernel weight of every plane; the 1-D kernel
+// values psi(du - a), psi(dv - a) are evaluated for 64 / W visibilities at a time
+// (one lane per value).  The walk then takes one visibility at a time: lane
+// (a, b) owns footprint cell (a, b) (cells beyond 64 wrap to more registers),
+// fetches its psi pair with lane permutes and the plane values with readlane,
+// and accumulates psi_u psi_v y psi_w per plane.  While consecutive visibilities
 // share a base cell their contributions add up in registers; when the cell
 // changes the run is flushed to the LDS tiles with one atomic per (cell, plane)
 // and part.  The LDS tiles hold 64-bit fixed-point integers: every contribution
@@ -290,6 +306,7 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial(const WorkItem *__restric
     constexpr int NCELL = (W * W + 63) / 64;
     constexpr int NWAVE = NTHR / 64;
     constexpr int PR = grid_reg_planes<T, W>() < W ? grid_reg_planes<T, W>() : W;
+    constexpr int VPB = 64 / W;  // visibilities per kernel-evaluation step
     const WorkItem it = wis[blockIdx.x];
     // fixed-point exponent from the bound on every contribution
     __shared__ float wmax[NWAVE];
@@ -352,11 +369,15 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial(const WorkItem *__restric
             }
         };
         for (int b0 = v_begin; b0 < v_end; b0 += 64) {
-            // lane k loads visibility b0 + k: one memory round trip per 64
+            // lane k loads visibility b0 + k (one memory round trip per 64) and
+            // forms its weighted value times the w-kernel weight of every plane of
+            // the pass; the walk below broadcasts them with readlane
             const int nb = min(64, v_end - b0);
             int l_cell = 0;
-            T l_xu = T(0), l_xv = T(0), l_xw = T(0);
-            c2<T> l_y = mk<T>(T(0), T(0));
+            T l_xu = T(0), l_xv = T(0);
+            T l_yr[PR], l_yi[PR];
+#pragma unroll
+            for (int p = 0; p < PR; ++p) l_yr[p] = l_yi[p] = T(0);
             if (lane < nb) {
                 const int64_t pos = it.start + b0 + lane;
                 l_cell = (int)r_cell[pos];
@@ -369,47 +390,62 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial(const WorkItem *__restric
                     y.y *= wt;
                 }
                 if (id >> 31) y.y = -y.y;
-                if (!coplanar) {
+                l_xu = r_du[pos];
+                l_xv = r_dv[pos];
+                if (coplanar) {
+                    l_yr[0] = y.x;
+                    l_yi[0] = y.y;
+                } else {
                     T sn, cs;
                     sincos_cycles(r_ph[pos], &sn, &cs);
                     y = cmul<T>(y, mk<T>(cs, sn));
-                }
-                l_y = y;
-                l_xu = r_du[pos];
-                l_xv = r_dv[pos];
-                l_xw = r_dw[pos];
-            }
-            for (int k = 0; k < nb; ++k) {
-                const int cell = __builtin_amdgcn_readlane(l_cell, k);
-                if (cell != run_cell) {
-                    if (run_cell >= 0) flush();
-                    run_cell = cell;
-                }
-                const T yx = wave_bcast(l_y.x, k), yy = wave_bcast(l_y.y, k);
-                const T xu = wave_bcast(l_xu, k), xv = wave_bcast(l_xv, k), xw = wave_bcast(l_xw, k);
-                T kwl = T(1);
-                if (!coplanar && lane < np) kwl = es_eval<T>((xw - T(g0 + lane)) * (T(2) / T(Ww)), wbeta);
-                T kw[PR];
-#pragma unroll
-                for (int p = 0; p < PR; ++p) kw[p] = (!coplanar && p < np) ? wave_bcast(kwl, p) : T(1);
-#pragma unroll
-                for (int q = 0; q < NCELL; ++q) {
-                    const T wuv = ca[q] < 0 ? T(0)
-                                            : es_eval<T>((xu - T(ca[q])) * two_over_W, beta) *
-                                                  es_eval<T>((xv - T(cb[q])) * two_over_W, beta);
-                    const T cx = yx * wuv, cy = yy * wuv;
+                    const T xw = r_dw[pos];
 #pragma unroll
                     for (int p = 0; p < PR; ++p) {
-                        acc_re[q][p] += cx * kw[p];
-                        acc_im[q][p] += cy * kw[p];
+                        const T kw = p < np ? es_eval<T>((xw - T(g0 + p)) * (T(2) / T(Ww)), wbeta) : T(0);
+                        l_yr[p] = y.x * kw;
+                        l_yi[p] = y.y * kw;
+                    }
+                }
+            }
+            // the separable kernel values: lane v W + a (v < VPB, a < W) evaluates
+            // psi(du - a) and psi(dv - a) of visibility k0 + v, and lane (a, b) of
+            // the walk fetches its pair with two lane permutes
+            for (int k0 = 0; k0 < nb; k0 += VPB) {
+                const int vv = lane / W, aa = lane - (lane / W) * W;
+                const int src = min(k0 + vv, 63);
+                const T xu_v = __shfl(l_xu, src, 64), xv_v = __shfl(l_xv, src, 64);
+                const T phu = es_eval<T>((xu_v - T(aa)) * two_over_W, beta);
+                const T phv = es_eval<T>((xv_v - T(aa)) * two_over_W, beta);
+                const int kend = min(k0 + VPB, nb);
+                for (int k = k0; k < kend; ++k) {
+                    const int cell = __builtin_amdgcn_readlane(l_cell, k);
+                    if (cell != run_cell) {
+                        if (run_cell >= 0) flush();
+                        run_cell = cell;
+                    }
+                    const int base = (k - k0) * W;
+#pragma unroll
+                    for (int q = 0; q < NCELL; ++q) {
+                        const T wu = __shfl(phu, base + max(ca[q], 0), 64);
+                        const T wv = __shfl(phv, base + cb[q], 64);
+                        const T w = ca[q] < 0 ? T(0) : wu * wv;
+#pragma unroll
+                        for (int p = 0; p < PR; ++p) {
+                            acc_re[q][p] += w * wave_bcast(l_yr[p], k);
+                            acc_im[q][p] += w * wave_bcast(l_yi[p], k);
+                        }
                     }
                 }
             }
         }
         if (run_cell >= 0) flush();
         __syncthreads();
-        for (int q = threadIdx.x; q < np * TT; q += NTHR) {
-            const int p = q / TT, r = q - p * TT;
+        // only the rows the item touched are stored (the assembly reads no others)
+        const int r0 = it.rows & 0xffff, r1 = it.rows >> 16;
+        const int band = (r1 - r0 + 1) * TS;
+        for (int q = threadIdx.x; q < np * band; q += NTHR) {
+            const int p = q / band, r = r0 * TS + (q - p * band);
             out[(int64_t)(g0 + p) * TT + r] = mk<T>((T)ldexp((double)tile[2 * p * TT + r], -kexp),
                                                     (T)ldexp((double)tile[2 * p * TT + TT + r], -kexp));
         }
@@ -436,50 +472,85 @@ __global__ __launch_bounds__(256) void k_vis_bound(const c2<T> *__restrict__ vis
     if (threadIdx.x == 0) partials[blockIdx.x] = fmaxf(fmaxf(sh[0], sh[1]), fmaxf(sh[2], sh[3]));
 }
 
-// Owner-computes assembly: workgroup (tile, plane p) writes the 32 x 32 cells it
-// owns, each the sum, in a fixed order, of the partial tiles that cover it: the
-// items of its own tile and of the tiles up to one step back in u and v (their
-// W - 1 halo reaches into this tile), for every first plane p0 with
-// p - Ww < p0 <= p.  Every plane cell is written exactly once, so the planes need
-// no clearing and the result does not depend on scheduling.
+// Owner-computes assembly: workgroup (active tile, plane p) writes the 32 x 32
+// cells it owns, one per thread, each the sum, in a fixed order, of the partial tiles that
+// cover it: the items of its own tile and of the tiles up to one step back in u
+// and v (their W - 1 halo reaches into this tile), for every first plane p0 with
+// p - Ww < p0 <= p.  The items of a tile are sorted by base cell, so those that
+// touch a given tile row form a contiguous run, found by binary search on their
+// first and last rows.  Every cell of an active tile is written exactly once;
+// the inverse column transform reads zeros for the other tiles, so the planes
+// need no clearing and the result does not depend on scheduling.  Eight partial
+// loads are kept in flight per thread.
 template <typename T, int W>
-__global__ __launch_bounds__(256) void k_grid_assemble(const c2<T> *__restrict__ partial,
-                                                       const uint32_t *__restrict__ gkey_first, int64_t item0,
-                                                       int64_t key0, int n_p0, int ntu, int ntv, int Ww,
-                                                       int log2nu, int log2nv, c2<T> *__restrict__ planes) {
+__global__ __launch_bounds__(kTile * kTile) void k_grid_assemble(const c2<T> *__restrict__ partial,
+                                                                 const int32_t *__restrict__ atile,
+                                                                 const WorkItem *__restrict__ items,
+                                                                 const uint32_t *__restrict__ gkey_first,
+                                                                 int64_t item0, int64_t key0, int n_p0, int ntu,
+                                                                 int ntv, int Ww, int log2nu, int log2nv,
+                                                                 c2<T> *__restrict__ planes) {
     constexpr int TS = kTile + W - 1;
     constexpr int TT = TS * TS;
-    const int t = blockIdx.x;
+    constexpr int U = 8;
+    const int t = atile[blockIdx.x];
     const int p = blockIdx.y;
     const int tu = t / ntv, tv = t - tu * ntv;
     const int n_tiles = ntu * ntv;
     const int pmin = max(0, p - Ww + 1), pmax = min(p, n_p0 - 1);
-    for (int q = threadIdx.x; q < kTile * kTile; q += 256) {
-        const int i = q / kTile, j = q - i * kTile;
-        T sx = 0, sy = 0;
-        for (int di = 0; di < 2; ++di) {
-            const int li = i + di * kTile;
-            if (li >= TS) continue;
-            const int tu2 = (tu - di + ntu) % ntu;
-            for (int dj = 0; dj < 2; ++dj) {
-                const int lj = j + dj * kTile;
-                if (lj >= TS) continue;
-                const int tv2 = (tv - dj + ntv) % ntv;
-                const int t2 = tu2 * ntv + tv2;
-                for (int p0 = pmin; p0 <= pmax; ++p0) {
-                    const int64_t key = key0 + (int64_t)p0 * n_tiles + t2;
-                    const uint32_t b = gkey_first[key], e = gkey_first[key + 1];
-                    for (uint32_t it = b; it < e; ++it) {
-                        const c2<T> v = partial[((int64_t)(it - item0) * Ww + (p - p0)) * TT + li * TS + lj];
-                        sx += v.x;
-                        sy += v.y;
+    const int64_t stride = (int64_t)Ww * TT;  // between consecutive items
+    const int i = threadIdx.x / kTile, j = threadIdx.x - (threadIdx.x / kTile) * kTile;
+    T sx = 0, sy = 0;
+    for (int di = 0; di < 2; ++di) {
+        const int li = i + di * kTile;
+        if (li >= TS) continue;
+        const int tu2 = (tu - di + ntu) % ntu;
+        for (int dj = 0; dj < 2; ++dj) {
+            const int lj = j + dj * kTile;
+            if (lj >= TS) continue;
+            const int tv2 = (tv - dj + ntv) % ntv;
+            const int t2 = tu2 * ntv + tv2;
+            for (int p0 = pmin; p0 <= pmax; ++p0) {
+                const int64_t key = key0 + (int64_t)p0 * n_tiles + t2;
+                uint32_t b = gkey_first[key], e = gkey_first[key + 1];
+                // first item whose last row reaches li, then first whose first row passes it
+                uint32_t lo = b, hi = e;
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if ((items[mid].rows >> 16) < li) lo = mid + 1;
+                    else hi = mid;
+                }
+                b = lo;
+                hi = e;
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if ((items[mid].rows & 0xffff) <= li) lo = mid + 1;
+                    else hi = mid;
+                }
+                e = lo;
+                const c2<T> *src = partial + ((int64_t)(b - item0) * Ww + (p - p0)) * TT + li * TS + lj;
+                const uint32_t n = e - b;
+                uint32_t k = 0;
+                for (; k + U <= n; k += U) {
+                    c2<T> v[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) v[u] = src[(int64_t)(k + u) * stride];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        sx += v[u].x;
+                        sy += v[u].y;
                     }
+                }
+                for (; k < n; ++k) {
+                    const c2<T> v = src[(int64_t)k * stride];
+                    sx += v.x;
+                    sy += v.y;
                 }
             }
         }
-        const int a = tu * kTile + i, b2 = tv * kTile + j;
-        planes[((((int64_t)p << log2nu) + a) << log2nv) + b2] = mk<T>(sx, sy);
     }
+    const int a = tu * kTile + i, b2 = tv * kTile + j;
+    planes[((((int64_t)p << log2nu) + a) << log2nv) + b2] = mk<T>(sx, sy);
 }
 
 // ------------------------------------------------------------------ FFT functors
@@ -527,6 +598,16 @@ template <typename T> struct FullColPro {
     const c2<T> *planes;
     int log2nu, log2nv;
     __device__ c2<T> operator()(int64_t m, int a, int b) const { return planes[(((m << log2nu) + a) << log2nv) + b]; }
+};
+// gridded planes: tiles without active flag are zero and not read
+template <typename T> struct ActiveColPro {
+    const c2<T> *planes;
+    const uint8_t *active;  // [n_tiles] of the channel
+    int log2nu, log2nv, ntv;
+    __device__ c2<T> operator()(int64_t m, int a, int b) const {
+        if (!active[(a / kTile) * ntv + b / kTile]) return mk<T>(T(0), T(0));
+        return planes[(((m << log2nu) + a) << log2nv) + b];
+    }
 };
 template <typename T> struct FullColEpi {
     c2<T> *planes;
@@ -628,7 +709,8 @@ template <typename T, int W>
 void launch_grid_w(const fr_plan *pl, int64_t chan, c2<T> *planes, const c2<T> *vis, const T *weight,
                    const float *ybound, int nbb, hipStream_t st) {
     constexpr int TS = kTile + W - 1;
-    constexpr int NTHR = sizeof(T) == 8 ? 512 : 1024;  // FP64 runs need the larger register file share
+    // FP64 and wide kernels hold more registers per lane: smaller groups, larger register share
+    constexpr int NTHR = (sizeof(T) == 8 || W * W > 64) ? 512 : 1024;
     const int64_t i0 = pl->gwi_chan[chan], i1 = pl->gwi_chan[chan + 1];
     const size_t per_plane = (size_t)TS * TS * sizeof(c2<T>);
     const size_t per_plane_lds = (size_t)TS * TS * 2 * sizeof(long long);
@@ -649,14 +731,14 @@ void launch_grid_w(const fr_plan *pl, int64_t chan, c2<T> *planes, const c2<T> *
             LAUNCH_CHECK();
         }
         ProfScope prof("grid_assemble", st);
-        k_grid_assemble<T, W><<<dim3((unsigned)pl->n_tiles, (unsigned)pl->n_planes), 256, 0, st>>>(
-            partial.as<c2<T>>(), pl->gkey_first.as<uint32_t>(), i0, chan * pl->n_p0 * (int64_t)pl->n_tiles,
+        const int64_t a0 = pl->atile_chan[chan], a1 = pl->atile_chan[chan + 1];
+        k_grid_assemble<T, W><<<dim3((unsigned)(a1 - a0), (unsigned)pl->n_planes), kTile * kTile, 0, st>>>(
+            partial.as<c2<T>>(), pl->atile.as<int32_t>() + a0, pl->gwi.as<WorkItem>(), pl->gkey_first.as<uint32_t>(), i0,
+            chan * pl->n_p0 * (int64_t)pl->n_tiles,
             pl->n_p0, pl->ntu, pl->ntv, pl->Ww, ilog2(pl->nu), ilog2(pl->nv), planes);
         LAUNCH_CHECK();
-    } else {
-        // no visibilities in this channel: the planes are zero
-        zero_async<T>(reinterpret_cast<T *>(planes), (int64_t)pl->n_planes * pl->nu * pl->nv * 2, st);
     }
+    // a channel without visibilities has no active tile: its planes are never read
 }
 
 #define FR_W_DISPATCH(W_, CALL) \
@@ -699,12 +781,13 @@ void image_to_planes(const fr_plan *pl, const T *img_c, c2<T> *planes, hipStream
 
 // adjoint: planes -> image channel (inverse column FFT on the band, row kernel)
 template <typename T>
-void planes_to_image(const fr_plan *pl, const c2<T> *planes_c, T *img_c, hipStream_t st) {
+void planes_to_image(const fr_plan *pl, const c2<T> *planes_c, const uint8_t *active, T *img_c, hipStream_t st) {
     c2<T> *planes = const_cast<c2<T> *>(planes_c);
     const int l2u = ilog2(pl->nu), l2v = ilog2(pl->nv);
     {
         ProfScope prof("wplane_cols_inv", st);
-        launch_fft_cols<T>(*pl->ctx, FullColPro<T>{planes, l2u, l2v}, BandColEpi<T>{planes, (int)pl->nx, l2u, l2v},
+        launch_fft_cols<T>(*pl->ctx, ActiveColPro<T>{planes, active, l2u, l2v, pl->ntv},
+                           BandColEpi<T>{planes, (int)pl->nx, l2u, l2v},
                            pl->n_planes, (int)pl->nv, l2u, (int)pl->nu, (int)pl->nu, +1, st);
     }
     ProfScope prof("wplane_rows_inv", st);
@@ -756,7 +839,8 @@ void grid(const fr_plan *pl, const c2<T> *vis, const T *weight, T *img, hipStrea
 #define FR_CALL_GRID(WW) launch_grid_w<T, WW>(pl, c, planes.as<c2<T>>(), vis, weight, ybound.as<float>(), nbb, st)
         FR_W_DISPATCH(pl->W, FR_CALL_GRID)
 #undef FR_CALL_GRID
-        planes_to_image<T>(pl, planes.as<c2<T>>(), img + c * pl->nx * pl->ny, st);
+        planes_to_image<T>(pl, planes.as<c2<T>>(), pl->tile_active.as<uint8_t>() + c * pl->n_tiles,
+                           img + c * pl->nx * pl->ny, st);
     }
 }
 
@@ -873,7 +957,7 @@ static void build_records(fr_plan *pl, const DevBuf &d_uvw, const DevBuf &d_freq
             w.tv = tv * kTile;
             w.p0 = p0;
             w.chan = (int32_t)chan;
-            w.pad = 0;
+            w.rows = 0;
             for (int64_t s = 0; s < cnt; s += ch) {
                 w.start = run + s;
                 w.count = (int32_t)std::min<int64_t>(ch, cnt - s);
@@ -890,6 +974,30 @@ static void build_records(fr_plan *pl, const DevBuf &d_uvw, const DevBuf &d_freq
         run += cnt;
     }
     gfirst[n_keys] = (uint32_t)gwis.size();
+    {
+        std::vector<uint8_t> act((size_t)pl->n_chan * n_tiles, 0);
+        std::vector<int32_t> alist;
+        pl->atile_chan.assign(pl->n_chan + 1, 0);
+        for (int64_t c = 0; c < pl->n_chan; ++c) {
+            uint8_t *a = act.data() + c * n_tiles;
+            for (int p0 = 0; p0 < n_p0; ++p0)
+                for (int t = 0; t < n_tiles; ++t) {
+                    const int64_t k = (c * n_p0 + p0) * (int64_t)n_tiles + t;
+                    if (gfirst[k + 1] == gfirst[k]) continue;
+                    const int tu = t / ntv, tv = t - tu * ntv;
+                    for (int di = 0; di < 2; ++di)
+                        for (int dj = 0; dj < 2; ++dj) a[((tu + di) % ntu) * ntv + (tv + dj) % ntv] = 1;
+                }
+            for (int t = 0; t < n_tiles; ++t)
+                if (a[t]) alist.push_back(t);
+            pl->atile_chan[c + 1] = (int64_t)alist.size();
+        }
+        pl->atile = DevBuf(std::max<size_t>(1, alist.size()) * sizeof(int32_t));
+        if (!alist.empty())
+            HIP_CHECK(hipMemcpy(pl->atile.p, alist.data(), alist.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        pl->tile_active = DevBuf(act.size());
+        HIP_CHECK(hipMemcpy(pl->tile_active.p, act.data(), act.size(), hipMemcpyHostToDevice));
+    }
     for (int64_t c = 1; c <= pl->n_chan; ++c) {
         pl->wi_chan[c] = std::max(pl->wi_chan[c], pl->wi_chan[c - 1]);
         pl->gwi_chan[c] = std::max(pl->gwi_chan[c], pl->gwi_chan[c - 1]);
@@ -911,6 +1019,11 @@ static void build_records(fr_plan *pl, const DevBuf &d_uvw, const DevBuf &d_freq
         ph.as<T>(), pl->r_idx.as<uint32_t>(), pl->r_cell.as<uint32_t>(), pl->r_du.as<T>(), pl->r_dv.as<T>(),
         pl->r_dw.as<T>(), pl->r_ph.as<T>());
     LAUNCH_CHECK();
+    if (pl->n_gwi > 0) {
+        k_item_rows<<<dim3((unsigned)((pl->n_gwi + 255) / 256)), 256>>>(pl->gwi.as<WorkItem>(), pl->n_gwi,
+                                                                         pl->r_cell.as<uint32_t>(), pl->W);
+        LAUNCH_CHECK();
+    }
     pl->n_wi = (int64_t)wis.size();
     pl->wi = DevBuf(std::max<size_t>(1, wis.size()) * sizeof(WorkItem));
     if (!wis.empty()) HIP_CHECK(hipMemcpy(pl->wi.p, wis.data(), wis.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
@@ -1043,10 +1156,15 @@ void plan_build(fr_plan *pl, const double *uvw_m, const double *freq_hz) {
         pl->ntu = (int)(pl->nu / kTile);
         pl->ntv = (int)(pl->nv / kTile);
         pl->n_tiles = pl->ntu * pl->ntv;
+        // no active tile anywhere: gridding yields zero images without reading the planes
+        pl->atile_chan.assign(pl->n_chan + 1, 0);
+        pl->atile = DevBuf(sizeof(int32_t));
+        pl->tile_active = DevBuf((size_t)pl->n_chan * pl->n_tiles);
+        HIP_CHECK(hipMemset(pl->tile_active.p, 0, pl->tile_active.bytes));
     }
     pl->resident = pl->fac.bytes + pl->tpix.bytes + pl->nfac.bytes + pl->wplane.bytes + pl->r_idx.bytes +
                    pl->r_cell.bytes + pl->r_du.bytes + pl->r_dv.bytes + pl->r_dw.bytes + pl->r_ph.bytes +
-                   pl->wi.bytes;
+                   pl->wi.bytes + pl->gwi.bytes + pl->gkey_first.bytes + pl->atile.bytes + pl->tile_active.bytes;
 }
 
 }  // namespace frmi

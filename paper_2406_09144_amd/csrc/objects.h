@@ -29,7 +29,7 @@ struct WorkItem {
     int32_t chan;
     int64_t start;
     int32_t count;
-    int32_t pad;
+    int32_t rows;     // gridding items: tile rows touched (halo included), first | last << 16
 };
 
 }  // namespace frmi
@@ -67,6 +67,12 @@ struct fr_plan {
     int64_t n_gwi = 0;
     std::vector<int64_t> gwi_chan;
     frmi::DevBuf gkey_first;  // uint32 [n_keys + 1]
+    // tiles whose planes can be non-zero (an item of the tile, or of the tile one
+    // step back in u and/or v, whose halo reaches in): a list per channel and a
+    // per-channel map that lets the inverse column FFT skip the others
+    frmi::DevBuf atile;                 // int32 tile index [sum over channels]
+    std::vector<int64_t> atile_chan;    // [n_chan + 1] offsets into atile
+    frmi::DevBuf tile_active;           // uint8 [n_chan][n_tiles]
     int n_p0 = 1, n_tiles = 1, ntu = 1, ntv = 1;
     std::vector<double> freq;
     std::vector<double> uvw_host;  // [n_row][3] metres, kept to derive the PSF plan
