@@ -25,7 +25,7 @@
 namespace frmi {
 
 // ------------------------------------------------------------------ pass 1
-template <typename T, int NTHR, int BPT, class Pro>
+template <typename T, int NTHR, int BPT, bool TWL, class Pro>
 __global__ __launch_bounds__(NTHR) void k_rfft_rows(Pro pro, c2<T> *__restrict__ Y, int64_t nrows,
                                                      int log2M, int n_in, int lines_per_wg,
                                                      const c2<T> *__restrict__ tw,
@@ -35,17 +35,21 @@ __global__ __launch_bounds__(NTHR) void k_rfft_rows(Pro pro, c2<T> *__restrict__
     const int M = 1 << log2M;
     const int64_t row0 = (int64_t)blockIdx.x * lines_per_wg;
     const int nl = (int)min<int64_t>(lines_per_wg, nrows - row0);
-    for (int idx = threadIdx.x; idx < (nl << log2M); idx += NTHR) {
-        const int c = idx >> log2M, e = idx & (M - 1);
-        c2<T> z = mk<T>(T(0), T(0));
-        if (2 * e < n_in) {
-            z.x = pro(row0 + c, 2 * e);
-            z.y = pro(row0 + c, 2 * e + 1);
-        }
-        buf[idx] = z;
-    }
+    const c2<T> *twp = stage_twiddles<T, NTHR, TWL>(buf + ((int64_t)lines_per_wg << log2M), tw, M);
+    staged_copy<NTHR>(
+        nl << log2M,
+        [&](int idx) {
+            const int c = idx >> log2M, e = idx & (M - 1);
+            c2<T> z = mk<T>(T(0), T(0));
+            if (2 * e < n_in) {
+                z.x = pro(row0 + c, 2 * e);
+                z.y = pro(row0 + c, 2 * e + 1);
+            }
+            return z;
+        },
+        [&](int idx, c2<T> v) { buf[idx] = v; });
     __syncthreads();
-    lds_fft<T, NTHR, BPT>(buf, M, nl, log2M, -1, tw);
+    lds_fft<T, NTHR, BPT>(buf, M, nl, log2M, -1, twp);
     const int half = M / 2 + 1;
     for (int idx = threadIdx.x; idx < nl * half; idx += NTHR) {
         const int c = idx / half, k = idx - c * half;
@@ -68,7 +72,7 @@ __global__ __launch_bounds__(NTHR) void k_rfft_rows(Pro pro, c2<T> *__restrict__
 
 // ------------------------------------------------------------------ pass 2
 // K: [nk][Lc][M + 1] real, image g uses kernel g % nk.  mode 0: multiply, 1: divide.
-template <typename T, int NTHR, int BPT>
+template <typename T, int NTHR, int BPT, bool TWL>
 __global__ __launch_bounds__(NTHR) void k_conv_cols(c2<T> *__restrict__ Y, int log2M, int log2Lc,
                                                      int n_in, int n_out, int C,
                                                      const T *__restrict__ K, int nk, int mode,
@@ -82,12 +86,19 @@ __global__ __launch_bounds__(NTHR) void k_conv_cols(c2<T> *__restrict__ Y, int l
     const int64_t g = blockIdx.y;
     c2<T> *Yg = Y + ((g * n_in) << log2M);  // packed rows of image g (n_in rows stored)
     const T *Kg = K + (g % nk) * (int64_t)Lc * (M + 1);
-    for (int idx = threadIdx.x; idx < C * Lc; idx += NTHR) {
-        const int r = idx / C, c = idx - r * C;
-        buf[c * ld + r] = (r < n_in) ? Yg[((int64_t)r << log2M) + col0 + c] : mk<T>(T(0), T(0));
-    }
+    const c2<T> *twp = stage_twiddles<T, NTHR, TWL>(buf + C * ld, tw, Lc);
+    staged_copy<NTHR>(
+        C * Lc,
+        [&](int idx) {
+            const int r = idx / C, c = idx - r * C;
+            return (r < n_in) ? Yg[((int64_t)r << log2M) + col0 + c] : mk<T>(T(0), T(0));
+        },
+        [&](int idx, c2<T> v) {
+            const int r = idx / C, c = idx - r * C;
+            buf[c * ld + r] = v;
+        });
     __syncthreads();
-    lds_fft<T, NTHR, BPT>(buf, ld, C, log2Lc, -1, tw);
+    lds_fft<T, NTHR, BPT>(buf, ld, C, log2Lc, -1, twp);
     for (int idx = threadIdx.x; idx < C * Lc; idx += NTHR) {
         const int c = idx >> log2Lc, k = idx & (Lc - 1);
         const int col = col0 + c;
@@ -115,7 +126,7 @@ __global__ __launch_bounds__(NTHR) void k_conv_cols(c2<T> *__restrict__ Y, int l
         }
     }
     __syncthreads();
-    lds_fft<T, NTHR, BPT>(buf, ld, C, log2Lc, +1, tw);
+    lds_fft<T, NTHR, BPT>(buf, ld, C, log2Lc, +1, twp);
     for (int idx = threadIdx.x; idx < C * n_out; idx += NTHR) {
         const int r = idx / C, c = idx - r * C;
         Yg[((int64_t)r << log2M) + col0 + c] = buf[c * ld + r];
@@ -123,7 +134,7 @@ __global__ __launch_bounds__(NTHR) void k_conv_cols(c2<T> *__restrict__ Y, int l
 }
 
 // ------------------------------------------------------------------ pass 3
-template <typename T, int NTHR, int BPT, class Epi>
+template <typename T, int NTHR, int BPT, bool TWL, class Epi>
 __global__ __launch_bounds__(NTHR) void k_irfft_rows(Epi epi, const c2<T> *__restrict__ Y, int64_t nrows,
                                                       int log2M, int n_out_cols, int lines_per_wg,
                                                       const c2<T> *__restrict__ tw,
@@ -133,7 +144,9 @@ __global__ __launch_bounds__(NTHR) void k_irfft_rows(Epi epi, const c2<T> *__res
     const int M = 1 << log2M;
     const int64_t row0 = (int64_t)blockIdx.x * lines_per_wg;
     const int nl = (int)min<int64_t>(lines_per_wg, nrows - row0);
-    for (int idx = threadIdx.x; idx < (nl << log2M); idx += NTHR) buf[idx] = Y[(row0 << log2M) + idx];
+    const c2<T> *twp = stage_twiddles<T, NTHR, TWL>(buf + ((int64_t)lines_per_wg << log2M), tw, M);
+    staged_copy<NTHR>(
+        nl << log2M, [&](int idx) { return Y[(row0 << log2M) + idx]; }, [&](int idx, c2<T> v) { buf[idx] = v; });
     __syncthreads();
     const int half = M / 2 + 1;
     for (int idx = threadIdx.x; idx < nl * half; idx += NTHR) {
@@ -157,7 +170,7 @@ __global__ __launch_bounds__(NTHR) void k_irfft_rows(Epi epi, const c2<T> *__res
         }
     }
     __syncthreads();
-    lds_fft<T, NTHR, BPT>(buf, M, nl, log2M, +1, tw);
+    lds_fft<T, NTHR, BPT>(buf, M, nl, log2M, +1, twp);
     const int npair = n_out_cols / 2;
     for (int idx = threadIdx.x; idx < nl * npair; idx += NTHR) {
         const int c = idx / npair, e = idx - c * npair;
@@ -184,15 +197,20 @@ void launch_rfft_rows(const Ctx &ctx, const ConvGeom &g, Pro pro, c2<T> *Y, hipS
     const int M = 1 << g.log2M;
     const int64_t nrows = g.n_img * g.rows_in;
     FR_REQUIRE(M <= max_line_elems<T>() && M <= 16384, "row length too large for LDS");
+    const size_t line = (size_t)M * sizeof(c2<T>);
     if (M <= 4096) {
         const int lpw = rows_per_wg(M, nrows, ctx.n_cu);
         const int64_t nblk = (nrows + lpw - 1) / lpw;
-        allow_lds(k_rfft_rows<T, 256, 4, Pro>, lpw * M * sizeof(c2<T>));
-        k_rfft_rows<T, 256, 4, Pro><<<dim3((unsigned)nblk), 256, lpw * M * sizeof(c2<T>), st>>>(
+        allow_lds(k_rfft_rows<T, 256, 4, true, Pro>, (lpw + 1) * line);
+        k_rfft_rows<T, 256, 4, true, Pro><<<dim3((unsigned)nblk), 256, (lpw + 1) * line, st>>>(
             pro, Y, nrows, g.log2M, g.n_in_cols, lpw, ctx.tw<T>(g.log2M), ctx.tw<T>(g.log2M + 1));
+    } else if (2 * line <= (size_t)kLdsBytes) {
+        allow_lds(k_rfft_rows<T, 1024, 4, true, Pro>, 2 * line);
+        k_rfft_rows<T, 1024, 4, true, Pro><<<dim3((unsigned)nrows), 1024, 2 * line, st>>>(
+            pro, Y, nrows, g.log2M, g.n_in_cols, 1, ctx.tw<T>(g.log2M), ctx.tw<T>(g.log2M + 1));
     } else {
-        allow_lds(k_rfft_rows<T, 1024, 4, Pro>, M * sizeof(c2<T>));
-        k_rfft_rows<T, 1024, 4, Pro><<<dim3((unsigned)nrows), 1024, M * sizeof(c2<T>), st>>>(
+        allow_lds(k_rfft_rows<T, 1024, 4, false, Pro>, line);
+        k_rfft_rows<T, 1024, 4, false, Pro><<<dim3((unsigned)nrows), 1024, line, st>>>(
             pro, Y, nrows, g.log2M, g.n_in_cols, 1, ctx.tw<T>(g.log2M), ctx.tw<T>(g.log2M + 1));
     }
     LAUNCH_CHECK();
@@ -213,15 +231,22 @@ void launch_conv_cols(const Ctx &ctx, const ConvGeom &g, c2<T> *Y, const T *K, i
     const size_t lds = (size_t)C * (Lc + 1) * sizeof(c2<T>);
     dim3 grid((unsigned)(M / C), (unsigned)g.n_img);
     FR_REQUIRE(g.rows_in == g.rows_out, "column pass works in place");
+    const bool twl = lds + (size_t)Lc * sizeof(c2<T>) <= (size_t)kLdsBytes;
+    const size_t ldst = twl ? lds + (size_t)Lc * sizeof(c2<T>) : lds;
+#define FR_CONVCOLS(NT, TW)                                                                                 \
+    do {                                                                                                    \
+        allow_lds(k_conv_cols<T, NT, 4, TW>, ldst);                                                         \
+        k_conv_cols<T, NT, 4, TW><<<grid, NT, ldst, st>>>(Y, g.log2M, g.log2Lc, g.rows_in, g.rows_out, C, K, \
+                                                          nk, mode, scale, ctx.tw<T>(g.log2Lc));            \
+    } while (0)
     if (C * Lc <= 4096) {
-        allow_lds(k_conv_cols<T, 256, 4>, lds);
-        k_conv_cols<T, 256, 4><<<grid, 256, lds, st>>>(Y, g.log2M, g.log2Lc, g.rows_in, g.rows_out, C, K, nk, mode,
-                                                       scale, ctx.tw<T>(g.log2Lc));
+        if (twl) FR_CONVCOLS(256, true);
+        else FR_CONVCOLS(256, false);
     } else {
-        allow_lds(k_conv_cols<T, 1024, 4>, lds);
-        k_conv_cols<T, 1024, 4><<<grid, 1024, lds, st>>>(Y, g.log2M, g.log2Lc, g.rows_in, g.rows_out, C, K, nk,
-                                                         mode, scale, ctx.tw<T>(g.log2Lc));
+        if (twl) FR_CONVCOLS(1024, true);
+        else FR_CONVCOLS(1024, false);
     }
+#undef FR_CONVCOLS
     LAUNCH_CHECK();
 }
 
@@ -229,15 +254,20 @@ template <typename T, class Epi>
 void launch_irfft_rows(const Ctx &ctx, const ConvGeom &g, Epi epi, const c2<T> *Y, hipStream_t st) {
     const int M = 1 << g.log2M;
     const int64_t nrows = g.n_img * g.rows_out;
+    const size_t line = (size_t)M * sizeof(c2<T>);
     if (M <= 4096) {
         const int lpw = rows_per_wg(M, nrows, ctx.n_cu);
         const int64_t nblk = (nrows + lpw - 1) / lpw;
-        allow_lds(k_irfft_rows<T, 256, 4, Epi>, lpw * M * sizeof(c2<T>));
-        k_irfft_rows<T, 256, 4, Epi><<<dim3((unsigned)nblk), 256, lpw * M * sizeof(c2<T>), st>>>(
+        allow_lds(k_irfft_rows<T, 256, 4, true, Epi>, (lpw + 1) * line);
+        k_irfft_rows<T, 256, 4, true, Epi><<<dim3((unsigned)nblk), 256, (lpw + 1) * line, st>>>(
             epi, Y, nrows, g.log2M, g.n_out_cols, lpw, ctx.tw<T>(g.log2M), ctx.tw<T>(g.log2M + 1));
+    } else if (2 * line <= (size_t)kLdsBytes) {
+        allow_lds(k_irfft_rows<T, 1024, 4, true, Epi>, 2 * line);
+        k_irfft_rows<T, 1024, 4, true, Epi><<<dim3((unsigned)nrows), 1024, 2 * line, st>>>(
+            epi, Y, nrows, g.log2M, g.n_out_cols, 1, ctx.tw<T>(g.log2M), ctx.tw<T>(g.log2M + 1));
     } else {
-        allow_lds(k_irfft_rows<T, 1024, 4, Epi>, M * sizeof(c2<T>));
-        k_irfft_rows<T, 1024, 4, Epi><<<dim3((unsigned)nrows), 1024, M * sizeof(c2<T>), st>>>(
+        allow_lds(k_irfft_rows<T, 1024, 4, false, Epi>, line);
+        k_irfft_rows<T, 1024, 4, false, Epi><<<dim3((unsigned)nrows), 1024, line, st>>>(
             epi, Y, nrows, g.log2M, g.n_out_cols, 1, ctx.tw<T>(g.log2M), ctx.tw<T>(g.log2M + 1));
     }
     LAUNCH_CHECK();

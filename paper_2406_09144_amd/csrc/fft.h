@@ -111,6 +111,39 @@ __device__ __forceinline__ void lds_fft(c2<T> *buf, int ld, int nlines, int log2
     for (; log2Ns < log2L; log2Ns += 2) stockham_stage<T, 4, NTHR, BPT>(buf, ld, nlines, log2L, log2Ns, sign, tw);
 }
 
+// store(idx, load(idx)) for idx = threadIdx.x, threadIdx.x + NTHR, ... < n, with U
+// loads issued before their values are stored, so that U global loads per
+// thread are in flight instead of one.
+template <int NTHR, int U = 8, class Load, class Store>
+__device__ __forceinline__ void staged_copy(int n, Load load, Store store) {
+    for (int base = threadIdx.x; base < n; base += NTHR * U) {
+        decltype(load(0)) v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = base + u * NTHR;
+            if (idx < n) v[u] = load(idx);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int idx = base + u * NTHR;
+            if (idx < n) store(idx, v[u]);
+        }
+    }
+}
+
+// Twiddle table of a transform: copied into LDS (at twl) when the launcher
+// reserved room for it (TWL), read from global memory otherwise.  The copy is
+// complete at the caller's next barrier.
+template <typename T, int NTHR, bool TWL>
+__device__ __forceinline__ const c2<T> *stage_twiddles(c2<T> *twl, const c2<T> *__restrict__ tw, int L) {
+    if constexpr (TWL) {
+        staged_copy<NTHR>(L, [&](int i) { return tw[i]; }, [&](int i, c2<T> v) { twl[i] = v; });
+        return twl;
+    } else {
+        return tw;
+    }
+}
+
 // Rows per workgroup of the row transforms: about 2048 elements per workgroup,
 // fewer when there are too few rows to give every CU several workgroups.
 inline int rows_per_wg(int L, int64_t nrows, int n_cu) {

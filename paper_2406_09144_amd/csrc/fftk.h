@@ -14,7 +14,7 @@
 
 namespace frmi {
 
-template <typename T, int NTHR, int BPT, class Pro, class Epi>
+template <typename T, int NTHR, int BPT, bool TWL, class Pro, class Epi>
 __global__ __launch_bounds__(NTHR) void k_fft_rows(Pro pro, Epi epi, int64_t nrows, int log2L,
                                                     int lines_per_wg, int sign,
                                                     const c2<T> *__restrict__ tw) {
@@ -23,15 +23,17 @@ __global__ __launch_bounds__(NTHR) void k_fft_rows(Pro pro, Epi epi, int64_t nro
     const int L = 1 << log2L;
     const int64_t row0 = (int64_t)blockIdx.x * lines_per_wg;
     const int nl = (int)min<int64_t>(lines_per_wg, nrows - row0);
-    for (int idx = threadIdx.x; idx < (nl << log2L); idx += NTHR)
-        buf[idx] = pro(row0 + (idx >> log2L), idx & (L - 1));
+    const c2<T> *twp = stage_twiddles<T, NTHR, TWL>(buf + ((int64_t)lines_per_wg << log2L), tw, L);
+    staged_copy<NTHR>(
+        nl << log2L, [&](int idx) { return pro(row0 + (idx >> log2L), idx & (L - 1)); },
+        [&](int idx, c2<T> v) { buf[idx] = v; });
     __syncthreads();
-    lds_fft<T, NTHR, BPT>(buf, L, nl, log2L, sign, tw);
+    lds_fft<T, NTHR, BPT>(buf, L, nl, log2L, sign, twp);
     for (int idx = threadIdx.x; idx < (nl << log2L); idx += NTHR)
         epi(row0 + (idx >> log2L), idx & (L - 1), buf[idx]);
 }
 
-template <typename T, int NTHR, int BPT, class Pro, class Epi>
+template <typename T, int NTHR, int BPT, bool TWL, class Pro, class Epi>
 __global__ __launch_bounds__(NTHR) void k_fft_cols(Pro pro, Epi epi, int ncols, int log2L, int n_in,
                                                     int n_out, int C, int sign,
                                                     const c2<T> *__restrict__ tw) {
@@ -41,16 +43,28 @@ __global__ __launch_bounds__(NTHR) void k_fft_cols(Pro pro, Epi epi, int ncols, 
     const int ld = L + 1;
     const int col0 = blockIdx.x * C;
     const int64_t m = blockIdx.y;
-    for (int idx = threadIdx.x; idx < C * L; idx += NTHR) {
-        const int r = idx / C, c = idx - r * C;
-        buf[c * ld + r] = (r < n_in) ? pro(m, r, col0 + c) : mk<T>(T(0), T(0));
-    }
+    const c2<T> *twp = stage_twiddles<T, NTHR, TWL>(buf + C * ld, tw, L);
+    staged_copy<NTHR>(
+        C * L,
+        [&](int idx) {
+            const int r = idx / C, c = idx - r * C;
+            return (r < n_in) ? pro(m, r, col0 + c) : mk<T>(T(0), T(0));
+        },
+        [&](int idx, c2<T> v) {
+            const int r = idx / C, c = idx - r * C;
+            buf[c * ld + r] = v;
+        });
     __syncthreads();
-    lds_fft<T, NTHR, BPT>(buf, ld, C, log2L, sign, tw);
+    lds_fft<T, NTHR, BPT>(buf, ld, C, log2L, sign, twp);
     for (int idx = threadIdx.x; idx < C * n_out; idx += NTHR) {
         const int r = idx / C, c = idx - r * C;
         epi(m, r, col0 + c, buf[c * ld + r]);
     }
+}
+
+// dynamic LDS of a line transform: the lines, plus the twiddle table when it fits
+template <typename T> inline bool twl_fits(size_t data_bytes, int L) {
+    return data_bytes + (size_t)L * sizeof(c2<T>) <= (size_t)kLdsBytes;
 }
 
 template <typename T, class Pro, class Epi>
@@ -60,15 +74,20 @@ void launch_fft_rows(const Ctx &ctx, Pro pro, Epi epi, int64_t nrows, int log2L,
     if (nrows <= 0) return;
     if (L <= 4096) {
         const int lpw = rows_per_wg(L, nrows, ctx.n_cu);
-        const size_t lds = (size_t)lpw * L * sizeof(c2<T>);
-        allow_lds(k_fft_rows<T, 256, 4, Pro, Epi>, lds);
-        k_fft_rows<T, 256, 4, Pro, Epi><<<dim3((unsigned)((nrows + lpw - 1) / lpw)), 256, lds, st>>>(
+        const size_t lds = (size_t)lpw * L * sizeof(c2<T>) + (size_t)L * sizeof(c2<T>);
+        allow_lds(k_fft_rows<T, 256, 4, true, Pro, Epi>, lds);
+        k_fft_rows<T, 256, 4, true, Pro, Epi><<<dim3((unsigned)((nrows + lpw - 1) / lpw)), 256, lds, st>>>(
             pro, epi, nrows, log2L, lpw, sign, ctx.tw<T>(log2L));
+    } else if (twl_fits<T>((size_t)L * sizeof(c2<T>), L)) {
+        const size_t lds = (size_t)2 * L * sizeof(c2<T>);
+        allow_lds(k_fft_rows<T, 1024, 4, true, Pro, Epi>, lds);
+        k_fft_rows<T, 1024, 4, true, Pro, Epi><<<dim3((unsigned)nrows), 1024, lds, st>>>(pro, epi, nrows, log2L, 1,
+                                                                                      sign, ctx.tw<T>(log2L));
     } else {
         const size_t lds = (size_t)L * sizeof(c2<T>);
-        allow_lds(k_fft_rows<T, 1024, 4, Pro, Epi>, lds);
-        k_fft_rows<T, 1024, 4, Pro, Epi><<<dim3((unsigned)nrows), 1024, lds, st>>>(pro, epi, nrows, log2L, 1, sign,
-                                                                                ctx.tw<T>(log2L));
+        allow_lds(k_fft_rows<T, 1024, 4, false, Pro, Epi>, lds);
+        k_fft_rows<T, 1024, 4, false, Pro, Epi><<<dim3((unsigned)nrows), 1024, lds, st>>>(pro, epi, nrows, log2L, 1,
+                                                                                       sign, ctx.tw<T>(log2L));
     }
     LAUNCH_CHECK();
 }
@@ -90,15 +109,22 @@ void launch_fft_cols(const Ctx &ctx, Pro pro, Epi epi, int64_t nmat, int ncols, 
     FR_REQUIRE(lds <= (size_t)kLdsBytes && L <= 16384, "column FFT length too large");
     if (nmat <= 0) return;
     dim3 grid((unsigned)(ncols / C), (unsigned)nmat);
+    const bool twl = twl_fits<T>(lds, L);
+    const size_t ldst = twl ? lds + (size_t)L * sizeof(c2<T>) : lds;
+#define FR_COLS(NT, TW)                                                                                   \
+    do {                                                                                                  \
+        allow_lds(k_fft_cols<T, NT, 4, TW, Pro, Epi>, ldst);                                              \
+        k_fft_cols<T, NT, 4, TW, Pro, Epi><<<grid, NT, ldst, st>>>(pro, epi, ncols, log2L, n_in, n_out, C, \
+                                                                   sign, ctx.tw<T>(log2L));               \
+    } while (0)
     if (C * L <= 4096) {
-        allow_lds(k_fft_cols<T, 256, 4, Pro, Epi>, lds);
-        k_fft_cols<T, 256, 4, Pro, Epi><<<grid, 256, lds, st>>>(pro, epi, ncols, log2L, n_in, n_out, C, sign,
-                                                                ctx.tw<T>(log2L));
+        if (twl) FR_COLS(256, true);
+        else FR_COLS(256, false);
     } else {
-        allow_lds(k_fft_cols<T, 1024, 4, Pro, Epi>, lds);
-        k_fft_cols<T, 1024, 4, Pro, Epi><<<grid, 1024, lds, st>>>(pro, epi, ncols, log2L, n_in, n_out, C, sign,
-                                                                  ctx.tw<T>(log2L));
+        if (twl) FR_COLS(1024, true);
+        else FR_COLS(1024, false);
     }
+#undef FR_COLS
     LAUNCH_CHECK();
 }
 

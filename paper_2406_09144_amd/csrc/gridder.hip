@@ -627,7 +627,7 @@ template <typename T> struct BandColEpi {
 };
 
 // Gridding epilogue: image row i accumulates Re(exp(+2 pi i w_p t) G_p) over planes.
-template <typename T, int NTHR, int BPT, int ACC>
+template <typename T, int NTHR, int BPT, int ACC, bool TWL>
 __global__ __launch_bounds__(NTHR) void k_grid_rows(const c2<T> *__restrict__ planes, int n_planes, int log2nu,
                                                     int log2nv, int nx, int ny, const T *__restrict__ fac,
                                                     const T *__restrict__ tpix, const double *__restrict__ wplane,
@@ -641,11 +641,12 @@ __global__ __launch_bounds__(NTHR) void k_grid_rows(const c2<T> *__restrict__ pl
     T acc[ACC];
 #pragma unroll
     for (int k = 0; k < ACC; ++k) acc[k] = T(0);
+    const c2<T> *twp = stage_twiddles<T, NTHR, TWL>(buf + nv, tw, nv);
     for (int p = 0; p < n_planes; ++p) {
         const c2<T> *src = planes + ((((int64_t)p << log2nu) + a) << log2nv);
-        for (int e = threadIdx.x; e < nv; e += NTHR) buf[e] = src[e];
+        staged_copy<NTHR>(nv, [&](int e) { return src[e]; }, [&](int e, c2<T> v) { buf[e] = v; });
         __syncthreads();
-        lds_fft<T, NTHR, BPT>(buf, nv, 1, log2nv, +1, tw);
+        lds_fft<T, NTHR, BPT>(buf, nv, 1, log2nv, +1, twp);
         const T wp = (T)wplane[p];
 #pragma unroll
         for (int k = 0; k < ACC; ++k) {
@@ -793,15 +794,22 @@ void planes_to_image(const fr_plan *pl, const c2<T> *planes_c, const uint8_t *ac
     ProfScope prof("wplane_rows_inv", st);
     const int nv = (int)pl->nv;
     if (nv <= 4096) {
-        const size_t lds = (size_t)nv * sizeof(c2<T>);
-        auto kern = k_grid_rows<T, 256, 4, 8>;
+        const size_t lds = (size_t)2 * nv * sizeof(c2<T>);
+        auto kern = k_grid_rows<T, 256, 4, 8, true>;
         allow_lds(kern, lds);
         kern<<<dim3((unsigned)pl->nx), 256, lds, st>>>(planes, pl->n_planes, l2u, l2v, (int)pl->nx, (int)pl->ny,
                                                        pl->fac.as<T>(), pl->tpix.as<T>(), pl->wplane.as<double>(),
                                                        pl->coplanar ? 1 : 0, img_c, pl->ctx->tw<T>(l2v));
+    } else if ((size_t)2 * nv * sizeof(c2<T>) <= (size_t)kLdsBytes) {
+        const size_t lds = (size_t)2 * nv * sizeof(c2<T>);
+        auto kern = k_grid_rows<T, 1024, 4, 8, true>;
+        allow_lds(kern, lds);
+        kern<<<dim3((unsigned)pl->nx), 1024, lds, st>>>(planes, pl->n_planes, l2u, l2v, (int)pl->nx, (int)pl->ny,
+                                                        pl->fac.as<T>(), pl->tpix.as<T>(), pl->wplane.as<double>(),
+                                                        pl->coplanar ? 1 : 0, img_c, pl->ctx->tw<T>(l2v));
     } else {
         const size_t lds = (size_t)nv * sizeof(c2<T>);
-        auto kern = k_grid_rows<T, 1024, 4, 8>;
+        auto kern = k_grid_rows<T, 1024, 4, 8, false>;
         allow_lds(kern, lds);
         kern<<<dim3((unsigned)pl->nx), 1024, lds, st>>>(planes, pl->n_planes, l2u, l2v, (int)pl->nx, (int)pl->ny,
                                                         pl->fac.as<T>(), pl->tpix.as<T>(), pl->wplane.as<double>(),
