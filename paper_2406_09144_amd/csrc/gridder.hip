@@ -201,15 +201,42 @@ __global__ __launch_bounds__(NTHR) void k_degrid(const WorkItem *__restrict__ wi
             fw[k] = r_dw[pos];
         }
     }
+    // the tile of plane pw + 1 is fetched into registers while plane pw is used
+    constexpr int NLD = (TS * TS + NTHR - 1) / NTHR;
+    T pre_x[NLD], pre_y[NLD];
+    int64_t toff[NLD];  // tile element offsets inside a plane
+#pragma unroll
+    for (int u = 0; u < NLD; ++u) {
+        const int q = min(threadIdx.x + u * NTHR, TS * TS - 1);
+        const int i = q / TS, jj = q - i * TS;
+        toff[u] = ((int64_t)((it.tu + i) & (nu - 1)) << log2nv) + ((it.tv + jj) & (nv - 1));
+    }
+    {
+        const c2<T> *P = planes + ((int64_t)it.p0 << (log2nu + log2nv));
+#pragma unroll
+        for (int u = 0; u < NLD; ++u) {
+            const c2<T> g = P[toff[u]];
+            pre_x[u] = g.x;
+            pre_y[u] = g.y;
+        }
+    }
     for (int pw = 0; pw < Ww; ++pw) {
-        const c2<T> *P = planes + ((int64_t)(it.p0 + pw) << (log2nu + log2nv));
         __syncthreads();
-        for (int q = threadIdx.x; q < TS * TS; q += NTHR) {
-            const int i = q / TS, jj = q - i * TS;
-            const int a = (it.tu + i) & (nu - 1), b = (it.tv + jj) & (nv - 1);
-            tile[q] = P[((int64_t)a << log2nv) + b];
+#pragma unroll
+        for (int u = 0; u < NLD; ++u) {
+            const int q = threadIdx.x + u * NTHR;
+            if (q < TS * TS) tile[q] = mk<T>(pre_x[u], pre_y[u]);
         }
         __syncthreads();
+        if (pw + 1 < Ww) {
+            const c2<T> *P = planes + ((int64_t)(it.p0 + pw + 1) << (log2nu + log2nv));
+#pragma unroll
+            for (int u = 0; u < NLD; ++u) {
+                const c2<T> g = P[toff[u]];
+                pre_x[u] = g.x;
+                pre_y[u] = g.y;
+            }
+        }
 #pragma unroll
         for (int k = 0; k < VPT; ++k) {
             if (!ok[k]) continue;
@@ -418,18 +445,36 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial(const WorkItem *__restric
                 const T phu = es_eval<T>((xu_v - T(aa)) * two_over_W, beta);
                 const T phv = es_eval<T>((xv_v - T(aa)) * two_over_W, beta);
                 const int kend = min(k0 + VPB, nb);
+                // the permutes for visibility k + 1 are issued before the work on k
+                T nu_[NCELL], nv_[NCELL];
+#pragma unroll
+                for (int q = 0; q < NCELL; ++q) {
+                    nu_[q] = __shfl(phu, max(ca[q], 0), 64);
+                    nv_[q] = __shfl(phv, cb[q], 64);
+                }
                 for (int k = k0; k < kend; ++k) {
+                    T cu_[NCELL], cv_[NCELL];
+#pragma unroll
+                    for (int q = 0; q < NCELL; ++q) {
+                        cu_[q] = nu_[q];
+                        cv_[q] = nv_[q];
+                    }
+                    if (k + 1 < kend) {
+                        const int base1 = (k + 1 - k0) * W;
+#pragma unroll
+                        for (int q = 0; q < NCELL; ++q) {
+                            nu_[q] = __shfl(phu, base1 + max(ca[q], 0), 64);
+                            nv_[q] = __shfl(phv, base1 + cb[q], 64);
+                        }
+                    }
                     const int cell = __builtin_amdgcn_readlane(l_cell, k);
                     if (cell != run_cell) {
                         if (run_cell >= 0) flush();
                         run_cell = cell;
                     }
-                    const int base = (k - k0) * W;
 #pragma unroll
                     for (int q = 0; q < NCELL; ++q) {
-                        const T wu = __shfl(phu, base + max(ca[q], 0), 64);
-                        const T wv = __shfl(phv, base + cb[q], 64);
-                        const T w = ca[q] < 0 ? T(0) : wu * wv;
+                        const T w = ca[q] < 0 ? T(0) : cu_[q] * cv_[q];
 #pragma unroll
                         for (int p = 0; p < PR; ++p) {
                             acc_re[q][p] += w * wave_bcast(l_yr[p], k);
