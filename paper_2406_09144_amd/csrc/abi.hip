@@ -76,12 +76,6 @@ int fr_ctx_create(int device, fr_ctx **out) {
         ctx->tables.push_back(std::move(b64));
         ctx->tables.push_back(std::move(b32));
     }
-    // keep freed scratch cached in the stream-ordered pool
-    hipMemPool_t pool;
-    if (hipDeviceGetDefaultMemPool(&pool, device) == hipSuccess) {
-        uint64_t thr = UINT64_MAX;
-        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-    }
     *out = ctx.release();
     FR_API_END
 }
@@ -414,6 +408,18 @@ namespace frmi {
 Profiler &profiler() {
     static Profiler P;
     return P;
+}
+
+Arena &arena_for(hipStream_t st) {
+    static std::mutex mu;
+    // never destroyed: the runtime may be gone when static destructors run
+    static auto *arenas = new std::map<std::pair<int, hipStream_t>, std::unique_ptr<Arena>>();
+    int dev = 0;
+    HIP_CHECK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> g(mu);
+    auto &slot = (*arenas)[{dev, st}];
+    if (!slot) slot = std::make_unique<Arena>();
+    return *slot;
 }
 }  // namespace frmi
 
