@@ -35,7 +35,8 @@ __global__ __launch_bounds__(NTHR) void k_rfft_rows(Pro pro, c2<T> *__restrict__
     const int M = 1 << log2M;
     const int64_t row0 = (int64_t)blockIdx.x * lines_per_wg;
     const int nl = (int)min<int64_t>(lines_per_wg, nrows - row0);
-    const c2<T> *twp = stage_twiddles<T, NTHR, TWL>(buf + ((int64_t)lines_per_wg << log2M), tw, M);
+    const int ld = plen(M);
+    const c2<T> *twp = stage_twiddles<T, NTHR, TWL>(buf + lines_per_wg * ld, tw, M);
     staged_copy<NTHR>(
         nl << log2M,
         [&](int idx) {
@@ -47,27 +48,28 @@ __global__ __launch_bounds__(NTHR) void k_rfft_rows(Pro pro, c2<T> *__restrict__
             }
             return z;
         },
-        [&](int idx, c2<T> v) { buf[idx] = v; });
+        [&](int idx, c2<T> v) { buf[(idx >> log2M) * ld + padx(idx & (M - 1))] = v; });
     __syncthreads();
-    lds_fft<T, NTHR, BPT>(buf, M, nl, log2M, -1, twp);
+    lds_fft<T, NTHR, BPT>(buf, ld, nl, log2M, -1, twp);
     const int half = M / 2 + 1;
     for (int idx = threadIdx.x; idx < nl * half; idx += NTHR) {
         const int c = idx / half, k = idx - c * half;
-        c2<T> *line = buf + c * M;
+        c2<T> *line = buf + c * ld;
         if (k == 0) {
             c2<T> z = line[0];
             line[0] = mk<T>(z.x + z.y, z.x - z.y);
         } else {
             const int km = M - k;
-            c2<T> a = line[k], b = line[km];
+            c2<T> a = line[padx(k)], b = line[padx(km)];
             c2<T> E = mk<T>((a.x + b.x) * T(0.5), (a.y - b.y) * T(0.5));
             c2<T> O = mk<T>((a.y + b.y) * T(0.5), (b.x - a.x) * T(0.5));
-            line[k] = cadd<T>(E, cmul<T>(tw2[k], O));
-            if (km != k) line[km] = cadd<T>(cconj<T>(E), cmul<T>(tw2[km], cconj<T>(O)));
+            line[padx(k)] = cadd<T>(E, cmul<T>(tw2[k], O));
+            if (km != k) line[padx(km)] = cadd<T>(cconj<T>(E), cmul<T>(tw2[km], cconj<T>(O)));
         }
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < (nl << log2M); idx += NTHR) Y[(row0 << log2M) + idx] = buf[idx];
+    for (int idx = threadIdx.x; idx < (nl << log2M); idx += NTHR)
+        Y[(row0 << log2M) + idx] = buf[(idx >> log2M) * ld + padx(idx & (M - 1))];
 }
 
 // ------------------------------------------------------------------ pass 2
@@ -81,7 +83,7 @@ __global__ __launch_bounds__(NTHR) void k_conv_cols(c2<T> *__restrict__ Y, int l
     c2<T> *buf = reinterpret_cast<c2<T> *>(smem_raw);
     const int M = 1 << log2M;
     const int Lc = 1 << log2Lc;
-    const int ld = Lc + 1;
+    const int ld = plen(Lc) + 1;
     const int col0 = blockIdx.x * C;
     const int64_t g = blockIdx.y;
     c2<T> *Yg = Y + ((g * n_in) << log2M);  // packed rows of image g (n_in rows stored)
@@ -95,7 +97,7 @@ __global__ __launch_bounds__(NTHR) void k_conv_cols(c2<T> *__restrict__ Y, int l
         },
         [&](int idx, c2<T> v) {
             const int r = idx / C, c = idx - r * C;
-            buf[c * ld + r] = v;
+            buf[c * ld + padx(r)] = v;
         });
     __syncthreads();
     lds_fft<T, NTHR, BPT>(buf, ld, C, log2Lc, -1, twp);
@@ -106,7 +108,7 @@ __global__ __launch_bounds__(NTHR) void k_conv_cols(c2<T> *__restrict__ Y, int l
             // slot 0 = DC column + i * Nyquist column: split, scale each, recombine
             if (k <= Lc / 2) {
                 const int km = (Lc - k) & (Lc - 1);
-                c2<T> a = buf[k], b = buf[km];
+                c2<T> a = buf[padx(k)], b = buf[padx(km)];
                 // A = (F[k] + conj F[-k]) / 2,  Bn = (F[k] - conj F[-k]) / 2i
                 c2<T> A = mk<T>((a.x + b.x) * T(0.5), (a.y - b.y) * T(0.5));
                 c2<T> Bn = mk<T>((a.y + b.y) * T(0.5), (b.x - a.x) * T(0.5));
@@ -115,21 +117,21 @@ __global__ __launch_bounds__(NTHR) void k_conv_cols(c2<T> *__restrict__ Y, int l
                 if (mode) { k0 = T(1) / k0; k1 = T(1) / k1; k0m = T(1) / k0m; k1m = T(1) / k1m; }
                 k0 *= scale; k1 *= scale; k0m *= scale; k1m *= scale;
                 // F'[k] = A k0 + i Bn k1 ; F'[-k] = conj(A) k0m + i conj(Bn) k1m
-                buf[k] = mk<T>(A.x * k0 - Bn.y * k1, A.y * k0 + Bn.x * k1);
-                if (km != k) buf[km] = mk<T>(A.x * k0m + Bn.y * k1m, -A.y * k0m + Bn.x * k1m);
+                buf[padx(k)] = mk<T>(A.x * k0 - Bn.y * k1, A.y * k0 + Bn.x * k1);
+                if (km != k) buf[padx(km)] = mk<T>(A.x * k0m + Bn.y * k1m, -A.y * k0m + Bn.x * k1m);
             }
         } else {
             T kv = Kg[(int64_t)k * (M + 1) + col];
             kv = (mode ? T(1) / kv : kv) * scale;
-            c2<T> v = buf[c * ld + k];
-            buf[c * ld + k] = mk<T>(v.x * kv, v.y * kv);
+            c2<T> v = buf[c * ld + padx(k)];
+            buf[c * ld + padx(k)] = mk<T>(v.x * kv, v.y * kv);
         }
     }
     __syncthreads();
     lds_fft<T, NTHR, BPT>(buf, ld, C, log2Lc, +1, twp);
     for (int idx = threadIdx.x; idx < C * n_out; idx += NTHR) {
         const int r = idx / C, c = idx - r * C;
-        Yg[((int64_t)r << log2M) + col0 + c] = buf[c * ld + r];
+        Yg[((int64_t)r << log2M) + col0 + c] = buf[c * ld + padx(r)];
     }
 }
 
@@ -144,37 +146,39 @@ __global__ __launch_bounds__(NTHR) void k_irfft_rows(Epi epi, const c2<T> *__res
     const int M = 1 << log2M;
     const int64_t row0 = (int64_t)blockIdx.x * lines_per_wg;
     const int nl = (int)min<int64_t>(lines_per_wg, nrows - row0);
-    const c2<T> *twp = stage_twiddles<T, NTHR, TWL>(buf + ((int64_t)lines_per_wg << log2M), tw, M);
+    const int ld = plen(M);
+    const c2<T> *twp = stage_twiddles<T, NTHR, TWL>(buf + lines_per_wg * ld, tw, M);
     staged_copy<NTHR>(
-        nl << log2M, [&](int idx) { return Y[(row0 << log2M) + idx]; }, [&](int idx, c2<T> v) { buf[idx] = v; });
+        nl << log2M, [&](int idx) { return Y[(row0 << log2M) + idx]; },
+        [&](int idx, c2<T> v) { buf[(idx >> log2M) * ld + padx(idx & (M - 1))] = v; });
     __syncthreads();
     const int half = M / 2 + 1;
     for (int idx = threadIdx.x; idx < nl * half; idx += NTHR) {
         const int c = idx / half, k = idx - c * half;
-        c2<T> *line = buf + c * M;
+        c2<T> *line = buf + c * ld;
         if (k == 0) {
             c2<T> p = line[0];
             line[0] = mk<T>((p.x + p.y) * T(0.5), (p.x - p.y) * T(0.5));
         } else {
             const int km = M - k;
-            c2<T> a = line[k], b = line[km];
+            c2<T> a = line[padx(k)], b = line[padx(km)];
             c2<T> E = mk<T>((a.x + b.x) * T(0.5), (a.y - b.y) * T(0.5));
             c2<T> D = mk<T>((a.x - b.x) * T(0.5), (a.y + b.y) * T(0.5));
             c2<T> O = cmul<T>(D, cconj<T>(tw2[k]));
-            line[k] = mk<T>(E.x - O.y, E.y + O.x);
+            line[padx(k)] = mk<T>(E.x - O.y, E.y + O.x);
             if (km != k) {
                 c2<T> Ep = cconj<T>(E);
                 c2<T> Op = cmul<T>(mk<T>(-D.x, D.y), cconj<T>(tw2[km]));
-                line[km] = mk<T>(Ep.x - Op.y, Ep.y + Op.x);
+                line[padx(km)] = mk<T>(Ep.x - Op.y, Ep.y + Op.x);
             }
         }
     }
     __syncthreads();
-    lds_fft<T, NTHR, BPT>(buf, M, nl, log2M, +1, twp);
+    lds_fft<T, NTHR, BPT>(buf, ld, nl, log2M, +1, twp);
     const int npair = n_out_cols / 2;
     for (int idx = threadIdx.x; idx < nl * npair; idx += NTHR) {
         const int c = idx / npair, e = idx - c * npair;
-        c2<T> z = buf[c * M + e];
+        c2<T> z = buf[c * ld + padx(e)];
         epi(row0 + c, 2 * e, z.x, z.y);
     }
 }
@@ -196,17 +200,18 @@ template <typename T, class Pro>
 void launch_rfft_rows(const Ctx &ctx, const ConvGeom &g, Pro pro, c2<T> *Y, hipStream_t st) {
     const int M = 1 << g.log2M;
     const int64_t nrows = g.n_img * g.rows_in;
-    FR_REQUIRE(M <= max_line_elems<T>() && M <= 16384, "row length too large for LDS");
-    const size_t line = (size_t)M * sizeof(c2<T>);
+    FR_REQUIRE(plen(M) <= max_line_elems<T>() && M <= 16384, "row length too large for LDS");
+    const size_t line = (size_t)plen(M) * sizeof(c2<T>);
+    const size_t twb = (size_t)M * sizeof(c2<T>);
     if (M <= 4096) {
         const int lpw = rows_per_wg(M, nrows, ctx.n_cu);
         const int64_t nblk = (nrows + lpw - 1) / lpw;
-        allow_lds(k_rfft_rows<T, 256, 4, true, Pro>, (lpw + 1) * line);
-        k_rfft_rows<T, 256, 4, true, Pro><<<dim3((unsigned)nblk), 256, (lpw + 1) * line, st>>>(
+        allow_lds(k_rfft_rows<T, 256, 4, true, Pro>, lpw * line + twb);
+        k_rfft_rows<T, 256, 4, true, Pro><<<dim3((unsigned)nblk), 256, lpw * line + twb, st>>>(
             pro, Y, nrows, g.log2M, g.n_in_cols, lpw, ctx.tw<T>(g.log2M), ctx.tw<T>(g.log2M + 1));
-    } else if (2 * line <= (size_t)kLdsBytes) {
-        allow_lds(k_rfft_rows<T, 1024, 4, true, Pro>, 2 * line);
-        k_rfft_rows<T, 1024, 4, true, Pro><<<dim3((unsigned)nrows), 1024, 2 * line, st>>>(
+    } else if (line + twb <= (size_t)kLdsBytes) {
+        allow_lds(k_rfft_rows<T, 1024, 4, true, Pro>, line + twb);
+        k_rfft_rows<T, 1024, 4, true, Pro><<<dim3((unsigned)nrows), 1024, line + twb, st>>>(
             pro, Y, nrows, g.log2M, g.n_in_cols, 1, ctx.tw<T>(g.log2M), ctx.tw<T>(g.log2M + 1));
     } else {
         allow_lds(k_rfft_rows<T, 1024, 4, false, Pro>, line);
@@ -227,8 +232,8 @@ void launch_conv_cols(const Ctx &ctx, const ConvGeom &g, c2<T> *Y, const T *K, i
     C = std::min(C, M);
     // small batches: narrower strips so the grid still covers every CU a few times
     while (C > 2 && (int64_t)(M / C) * g.n_img < 4 * (int64_t)std::max(ctx.n_cu, 1)) C >>= 1;
-    FR_REQUIRE((int64_t)C * (Lc + 1) <= max_line_elems<T>(), "column length too large for LDS");
-    const size_t lds = (size_t)C * (Lc + 1) * sizeof(c2<T>);
+    FR_REQUIRE((int64_t)C * (plen(Lc) + 1) <= max_line_elems<T>(), "column length too large for LDS");
+    const size_t lds = (size_t)C * (plen(Lc) + 1) * sizeof(c2<T>);
     dim3 grid((unsigned)(M / C), (unsigned)g.n_img);
     FR_REQUIRE(g.rows_in == g.rows_out, "column pass works in place");
     const bool twl = lds + (size_t)Lc * sizeof(c2<T>) <= (size_t)kLdsBytes;
@@ -254,16 +259,17 @@ template <typename T, class Epi>
 void launch_irfft_rows(const Ctx &ctx, const ConvGeom &g, Epi epi, const c2<T> *Y, hipStream_t st) {
     const int M = 1 << g.log2M;
     const int64_t nrows = g.n_img * g.rows_out;
-    const size_t line = (size_t)M * sizeof(c2<T>);
+    const size_t line = (size_t)plen(M) * sizeof(c2<T>);
+    const size_t twb = (size_t)M * sizeof(c2<T>);
     if (M <= 4096) {
         const int lpw = rows_per_wg(M, nrows, ctx.n_cu);
         const int64_t nblk = (nrows + lpw - 1) / lpw;
-        allow_lds(k_irfft_rows<T, 256, 4, true, Epi>, (lpw + 1) * line);
-        k_irfft_rows<T, 256, 4, true, Epi><<<dim3((unsigned)nblk), 256, (lpw + 1) * line, st>>>(
+        allow_lds(k_irfft_rows<T, 256, 4, true, Epi>, lpw * line + twb);
+        k_irfft_rows<T, 256, 4, true, Epi><<<dim3((unsigned)nblk), 256, lpw * line + twb, st>>>(
             epi, Y, nrows, g.log2M, g.n_out_cols, lpw, ctx.tw<T>(g.log2M), ctx.tw<T>(g.log2M + 1));
-    } else if (2 * line <= (size_t)kLdsBytes) {
-        allow_lds(k_irfft_rows<T, 1024, 4, true, Epi>, 2 * line);
-        k_irfft_rows<T, 1024, 4, true, Epi><<<dim3((unsigned)nrows), 1024, 2 * line, st>>>(
+    } else if (line + twb <= (size_t)kLdsBytes) {
+        allow_lds(k_irfft_rows<T, 1024, 4, true, Epi>, line + twb);
+        k_irfft_rows<T, 1024, 4, true, Epi><<<dim3((unsigned)nrows), 1024, line + twb, st>>>(
             epi, Y, nrows, g.log2M, g.n_out_cols, 1, ctx.tw<T>(g.log2M), ctx.tw<T>(g.log2M + 1));
     } else {
         allow_lds(k_irfft_rows<T, 1024, 4, false, Epi>, line);

@@ -19,6 +19,12 @@
 
 namespace frmi {
 
+// LDS lines are padded by one element after every 32 (element e of a line at
+// padx(e)), so that the strided stores of the early Stockham stages and the
+// transposed strip accesses spread over the banks.
+__host__ __device__ constexpr int padx(int e) { return e + (e >> 5); }
+__host__ __device__ constexpr int plen(int L) { return L + (L >> 5); }
+
 template <typename T>
 __device__ __forceinline__ c2<T> mul_i_sign(c2<T> a, int sign) {
     // a * (sign * i)
@@ -73,7 +79,7 @@ __device__ __forceinline__ void stockham_stage(c2<T> *buf, int ld, int nlines, i
             const int k = j & (Ns - 1);
             const c2<T> *p = buf + line * ld;
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[b][r] = p[j + r * Q];
+            for (int r = 0; r < R; ++r) v[b][r] = p[padx(j + r * Q)];
             if (log2Ns > 0) {
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
@@ -83,21 +89,24 @@ __device__ __forceinline__ void stockham_stage(c2<T> *buf, int ld, int nlines, i
                 }
             }
             dftR<T, R>(v[b], sign);
-            obase[b] = line * ld + ((j >> log2Ns) << (log2Ns + LOG2R)) + k;
+            obase[b] = (line << 16) | (((j >> log2Ns) << (log2Ns + LOG2R)) + k);  // line, element
         }
     }
     __syncthreads();
 #pragma unroll
     for (int b = 0; b < BPT; ++b) {
         if (obase[b] >= 0) {
+            c2<T> *p = buf + (obase[b] >> 16) * ld;
+            const int e0 = obase[b] & 0xffff;
 #pragma unroll
-            for (int r = 0; r < R; ++r) buf[obase[b] + r * Ns] = v[b][r];
+            for (int r = 0; r < R; ++r) p[padx(e0 + r * Ns)] = v[b][r];
         }
     }
     __syncthreads();
 }
 
-// Full in-place FFT of `nlines` LDS lines (length 2^log2L, stride ld).  Caller
+// Full in-place FFT of `nlines` LDS lines (length 2^log2L <= 16384, stride ld >=
+// plen(2^log2L), element e at padx(e); nlines < 32768).  Caller
 // must __syncthreads() after filling the lines; returns after a barrier.
 // Requires nlines * 2^log2L <= 4 * BPT * NTHR.
 template <typename T, int NTHR, int BPT>

@@ -23,14 +23,15 @@ __global__ __launch_bounds__(NTHR) void k_fft_rows(Pro pro, Epi epi, int64_t nro
     const int L = 1 << log2L;
     const int64_t row0 = (int64_t)blockIdx.x * lines_per_wg;
     const int nl = (int)min<int64_t>(lines_per_wg, nrows - row0);
-    const c2<T> *twp = stage_twiddles<T, NTHR, TWL>(buf + ((int64_t)lines_per_wg << log2L), tw, L);
+    const int ld = plen(L);
+    const c2<T> *twp = stage_twiddles<T, NTHR, TWL>(buf + lines_per_wg * ld, tw, L);
     staged_copy<NTHR>(
         nl << log2L, [&](int idx) { return pro(row0 + (idx >> log2L), idx & (L - 1)); },
-        [&](int idx, c2<T> v) { buf[idx] = v; });
+        [&](int idx, c2<T> v) { buf[(idx >> log2L) * ld + padx(idx & (L - 1))] = v; });
     __syncthreads();
-    lds_fft<T, NTHR, BPT>(buf, L, nl, log2L, sign, twp);
+    lds_fft<T, NTHR, BPT>(buf, ld, nl, log2L, sign, twp);
     for (int idx = threadIdx.x; idx < (nl << log2L); idx += NTHR)
-        epi(row0 + (idx >> log2L), idx & (L - 1), buf[idx]);
+        epi(row0 + (idx >> log2L), idx & (L - 1), buf[(idx >> log2L) * ld + padx(idx & (L - 1))]);
 }
 
 template <typename T, int NTHR, int BPT, bool TWL, class Pro, class Epi>
@@ -40,7 +41,7 @@ __global__ __launch_bounds__(NTHR) void k_fft_cols(Pro pro, Epi epi, int ncols, 
     extern __shared__ __align__(16) unsigned char smem_raw[];
     c2<T> *buf = reinterpret_cast<c2<T> *>(smem_raw);
     const int L = 1 << log2L;
-    const int ld = L + 1;
+    const int ld = plen(L) + 1;
     const int col0 = blockIdx.x * C;
     const int64_t m = blockIdx.y;
     const c2<T> *twp = stage_twiddles<T, NTHR, TWL>(buf + C * ld, tw, L);
@@ -52,13 +53,13 @@ __global__ __launch_bounds__(NTHR) void k_fft_cols(Pro pro, Epi epi, int ncols, 
         },
         [&](int idx, c2<T> v) {
             const int r = idx / C, c = idx - r * C;
-            buf[c * ld + r] = v;
+            buf[c * ld + padx(r)] = v;
         });
     __syncthreads();
     lds_fft<T, NTHR, BPT>(buf, ld, C, log2L, sign, twp);
     for (int idx = threadIdx.x; idx < C * n_out; idx += NTHR) {
         const int r = idx / C, c = idx - r * C;
-        epi(m, r, col0 + c, buf[c * ld + r]);
+        epi(m, r, col0 + c, buf[c * ld + padx(r)]);
     }
 }
 
@@ -70,21 +71,22 @@ template <typename T> inline bool twl_fits(size_t data_bytes, int L) {
 template <typename T, class Pro, class Epi>
 void launch_fft_rows(const Ctx &ctx, Pro pro, Epi epi, int64_t nrows, int log2L, int sign, hipStream_t st) {
     const int L = 1 << log2L;
-    FR_REQUIRE((int64_t)L * (int64_t)sizeof(c2<T>) <= kLdsBytes && L <= 16384, "FFT length too large");
+    FR_REQUIRE((int64_t)plen(L) * (int64_t)sizeof(c2<T>) <= kLdsBytes && L <= 16384, "FFT length too large");
     if (nrows <= 0) return;
+    const size_t pline = (size_t)plen(L) * sizeof(c2<T>);
     if (L <= 4096) {
         const int lpw = rows_per_wg(L, nrows, ctx.n_cu);
-        const size_t lds = (size_t)lpw * L * sizeof(c2<T>) + (size_t)L * sizeof(c2<T>);
+        const size_t lds = (size_t)lpw * pline + (size_t)L * sizeof(c2<T>);
         allow_lds(k_fft_rows<T, 256, 4, true, Pro, Epi>, lds);
         k_fft_rows<T, 256, 4, true, Pro, Epi><<<dim3((unsigned)((nrows + lpw - 1) / lpw)), 256, lds, st>>>(
             pro, epi, nrows, log2L, lpw, sign, ctx.tw<T>(log2L));
-    } else if (twl_fits<T>((size_t)L * sizeof(c2<T>), L)) {
-        const size_t lds = (size_t)2 * L * sizeof(c2<T>);
+    } else if (twl_fits<T>(pline, L)) {
+        const size_t lds = pline + (size_t)L * sizeof(c2<T>);
         allow_lds(k_fft_rows<T, 1024, 4, true, Pro, Epi>, lds);
         k_fft_rows<T, 1024, 4, true, Pro, Epi><<<dim3((unsigned)nrows), 1024, lds, st>>>(pro, epi, nrows, log2L, 1,
                                                                                       sign, ctx.tw<T>(log2L));
     } else {
-        const size_t lds = (size_t)L * sizeof(c2<T>);
+        const size_t lds = pline;
         allow_lds(k_fft_rows<T, 1024, 4, false, Pro, Epi>, lds);
         k_fft_rows<T, 1024, 4, false, Pro, Epi><<<dim3((unsigned)nrows), 1024, lds, st>>>(pro, epi, nrows, log2L, 1,
                                                                                        sign, ctx.tw<T>(log2L));
@@ -105,7 +107,7 @@ void launch_fft_cols(const Ctx &ctx, Pro pro, Epi epi, int64_t nmat, int ncols, 
                      int sign, hipStream_t st) {
     const int L = 1 << log2L;
     const int C = col_strip<T>(L, ncols);
-    const size_t lds = (size_t)C * (L + 1) * sizeof(c2<T>);
+    const size_t lds = (size_t)C * (plen(L) + 1) * sizeof(c2<T>);
     FR_REQUIRE(lds <= (size_t)kLdsBytes && L <= 16384, "column FFT length too large");
     if (nmat <= 0) return;
     dim3 grid((unsigned)(ncols / C), (unsigned)nmat);

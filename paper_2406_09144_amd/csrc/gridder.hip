@@ -686,18 +686,18 @@ __global__ __launch_bounds__(NTHR) void k_grid_rows(const c2<T> *__restrict__ pl
     T acc[ACC];
 #pragma unroll
     for (int k = 0; k < ACC; ++k) acc[k] = T(0);
-    const c2<T> *twp = stage_twiddles<T, NTHR, TWL>(buf + nv, tw, nv);
+    const c2<T> *twp = stage_twiddles<T, NTHR, TWL>(buf + plen(nv), tw, nv);
     for (int p = 0; p < n_planes; ++p) {
         const c2<T> *src = planes + ((((int64_t)p << log2nu) + a) << log2nv);
-        staged_copy<NTHR>(nv, [&](int e) { return src[e]; }, [&](int e, c2<T> v) { buf[e] = v; });
+        staged_copy<NTHR>(nv, [&](int e) { return src[e]; }, [&](int e, c2<T> v) { buf[padx(e)] = v; });
         __syncthreads();
-        lds_fft<T, NTHR, BPT>(buf, nv, 1, log2nv, +1, twp);
+        lds_fft<T, NTHR, BPT>(buf, plen(nv), 1, log2nv, +1, twp);
         const T wp = (T)wplane[p];
 #pragma unroll
         for (int k = 0; k < ACC; ++k) {
             const int j = threadIdx.x + k * NTHR;
             if (j < ny) {
-                const c2<T> g = buf[(j - ny / 2) & (nv - 1)];
+                const c2<T> g = buf[padx((j - ny / 2) & (nv - 1))];
                 if (coplanar) {
                     acc[k] += g.x;
                 } else {
@@ -838,22 +838,23 @@ void planes_to_image(const fr_plan *pl, const c2<T> *planes_c, const uint8_t *ac
     }
     ProfScope prof("wplane_rows_inv", st);
     const int nv = (int)pl->nv;
+    const size_t pl_line = (size_t)plen(nv) * sizeof(c2<T>), twb = (size_t)nv * sizeof(c2<T>);
     if (nv <= 4096) {
-        const size_t lds = (size_t)2 * nv * sizeof(c2<T>);
+        const size_t lds = pl_line + twb;
         auto kern = k_grid_rows<T, 256, 4, 8, true>;
         allow_lds(kern, lds);
         kern<<<dim3((unsigned)pl->nx), 256, lds, st>>>(planes, pl->n_planes, l2u, l2v, (int)pl->nx, (int)pl->ny,
                                                        pl->fac.as<T>(), pl->tpix.as<T>(), pl->wplane.as<double>(),
                                                        pl->coplanar ? 1 : 0, img_c, pl->ctx->tw<T>(l2v));
-    } else if ((size_t)2 * nv * sizeof(c2<T>) <= (size_t)kLdsBytes) {
-        const size_t lds = (size_t)2 * nv * sizeof(c2<T>);
+    } else if (pl_line + twb <= (size_t)kLdsBytes) {
+        const size_t lds = pl_line + twb;
         auto kern = k_grid_rows<T, 1024, 4, 8, true>;
         allow_lds(kern, lds);
         kern<<<dim3((unsigned)pl->nx), 1024, lds, st>>>(planes, pl->n_planes, l2u, l2v, (int)pl->nx, (int)pl->ny,
                                                         pl->fac.as<T>(), pl->tpix.as<T>(), pl->wplane.as<double>(),
                                                         pl->coplanar ? 1 : 0, img_c, pl->ctx->tw<T>(l2v));
     } else {
-        const size_t lds = (size_t)nv * sizeof(c2<T>);
+        const size_t lds = pl_line;
         auto kern = k_grid_rows<T, 1024, 4, 8, false>;
         allow_lds(kern, lds);
         kern<<<dim3((unsigned)pl->nx), 1024, lds, st>>>(planes, pl->n_planes, l2u, l2v, (int)pl->nx, (int)pl->ny,
