@@ -231,7 +231,7 @@ void launch_conv_cols(const Ctx &ctx, const ConvGeom &g, c2<T> *Y, const T *K, i
     while (C > 1 && (M % C)) C >>= 1;
     C = std::min(C, M);
     // small batches: narrower strips so the grid still covers every CU a few times
-    while (C > 2 && (int64_t)(M / C) * g.n_img < 4 * (int64_t)std::max(ctx.n_cu, 1)) C >>= 1;
+    while (C > 2 && (int64_t)(M / C) * g.n_img < 2 * (int64_t)std::max(ctx.n_cu, 1)) C >>= 1;
     FR_REQUIRE((int64_t)C * (plen(Lc) + 1) <= max_line_elems<T>(), "column length too large for LDS");
     const size_t lds = (size_t)C * (plen(Lc) + 1) * sizeof(c2<T>);
     dim3 grid((unsigned)(M / C), (unsigned)g.n_img);
@@ -244,9 +244,13 @@ void launch_conv_cols(const Ctx &ctx, const ConvGeom &g, c2<T> *Y, const T *K, i
         k_conv_cols<T, NT, 4, TW><<<grid, NT, ldst, st>>>(Y, g.log2M, g.log2Lc, g.rows_in, g.rows_out, C, K, \
                                                           nk, mode, scale, ctx.tw<T>(g.log2Lc));            \
     } while (0)
+    // four radix-4 butterflies per thread
     if (C * Lc <= 4096) {
         if (twl) FR_CONVCOLS(256, true);
         else FR_CONVCOLS(256, false);
+    } else if (C * Lc <= 8192) {
+        if (twl) FR_CONVCOLS(512, true);
+        else FR_CONVCOLS(512, false);
     } else {
         if (twl) FR_CONVCOLS(1024, true);
         else FR_CONVCOLS(1024, false);

@@ -80,6 +80,11 @@ void launch_fft_rows(const Ctx &ctx, Pro pro, Epi epi, int64_t nrows, int log2L,
         allow_lds(k_fft_rows<T, 256, 4, true, Pro, Epi>, lds);
         k_fft_rows<T, 256, 4, true, Pro, Epi><<<dim3((unsigned)((nrows + lpw - 1) / lpw)), 256, lds, st>>>(
             pro, epi, nrows, log2L, lpw, sign, ctx.tw<T>(log2L));
+    } else if (L <= 8192 && twl_fits<T>(pline, L)) {
+        const size_t lds = pline + (size_t)L * sizeof(c2<T>);
+        allow_lds(k_fft_rows<T, 512, 4, true, Pro, Epi>, lds);
+        k_fft_rows<T, 512, 4, true, Pro, Epi><<<dim3((unsigned)nrows), 512, lds, st>>>(pro, epi, nrows, log2L, 1,
+                                                                                    sign, ctx.tw<T>(log2L));
     } else if (twl_fits<T>(pline, L)) {
         const size_t lds = pline + (size_t)L * sizeof(c2<T>);
         allow_lds(k_fft_rows<T, 1024, 4, true, Pro, Epi>, lds);
@@ -119,9 +124,13 @@ void launch_fft_cols(const Ctx &ctx, Pro pro, Epi epi, int64_t nmat, int ncols, 
         k_fft_cols<T, NT, 4, TW, Pro, Epi><<<grid, NT, ldst, st>>>(pro, epi, ncols, log2L, n_in, n_out, C, \
                                                                    sign, ctx.tw<T>(log2L));               \
     } while (0)
+    // four radix-4 butterflies per thread
     if (C * L <= 4096) {
         if (twl) FR_COLS(256, true);
         else FR_COLS(256, false);
+    } else if (C * L <= 8192) {
+        if (twl) FR_COLS(512, true);
+        else FR_COLS(512, false);
     } else {
         if (twl) FR_COLS(1024, true);
         else FR_COLS(1024, false);
