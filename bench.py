@@ -143,12 +143,17 @@ def served_workload(api, torch, seconds, rate, n_jobs, fp64_requests):
     st = latency_stats(out)
     st["launches"] = len(srv.launches)
     st["peak_scratch_GB"] = srv.peak_bytes / 2 ** 30
+    st["per_op"] = {op: {k: round(v, 3) for k, v in latency_stats([r for r in out if r.op == op]).items()
+                         if k in ("n", "p50_ms", "p99_ms")}
+                    for op in sorted({r.op for r in out})}
     log(f"[bench] served FP32: {json.dumps(st)}")
     res = {"fp32_batched": st, "rate_hz": rate, "seconds": seconds, "n_jobs": n_jobs}
     del ex, srv, jobs
-    if fp64_requests > 0:
+    if fp64_requests >= 0:
         jobs64 = build_served_jobs(api, torch, n_jobs, fp64=True)
-        trace64 = make_trace(len(jobs64), rate, seconds)[:fp64_requests]
+        trace64 = make_trace(len(jobs64), rate, seconds)
+        if fp64_requests > 0:
+            trace64 = trace64[:fp64_requests]
         ex64 = GpuExecutor(jobs64, n_slots=1)
         srv64 = Server(ex64, n_slots=1, hbm_budget=64 << 30, max_batch=1)
         out64 = srv64.run(trace64, realtime=True)
@@ -171,7 +176,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="served-mix trace length (0 disables)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-jobs", type=int, default=16)
-    ap.add_argument("--serve-fp64-requests", type=int, default=100)
+    ap.add_argument("--serve-fp64-requests", type=int, default=0,
+                    help="requests of the FP64 replay (0: the whole trace, -1: skip it)")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run 5 plain copies of this many bytes (counter calibration)")
     ap.add_argument("--n", type=int, default=512)

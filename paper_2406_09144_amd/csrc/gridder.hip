@@ -397,14 +397,15 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial(const WorkItem *__restric
         };
         for (int b0 = v_begin; b0 < v_end; b0 += 64) {
             // lane k loads visibility b0 + k (one memory round trip per 64) and
-            // forms its weighted value times the w-kernel weight of every plane of
-            // the pass; the walk below broadcasts them with readlane
+            // forms its weighted value y and the w-kernel weight of every plane
+            // of the pass; the walk below broadcasts them with readlane
             const int nb = min(64, v_end - b0);
             int l_cell = 0;
             T l_xu = T(0), l_xv = T(0);
-            T l_yr[PR], l_yi[PR];
+            c2<T> l_y = mk<T>(T(0), T(0));
+            T l_kw[PR];
 #pragma unroll
-            for (int p = 0; p < PR; ++p) l_yr[p] = l_yi[p] = T(0);
+            for (int p = 0; p < PR; ++p) l_kw[p] = T(p == 0 ? 1 : 0);
             if (lane < nb) {
                 const int64_t pos = it.start + b0 + lane;
                 l_cell = (int)r_cell[pos];
@@ -419,21 +420,16 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial(const WorkItem *__restric
                 if (id >> 31) y.y = -y.y;
                 l_xu = r_du[pos];
                 l_xv = r_dv[pos];
-                if (coplanar) {
-                    l_yr[0] = y.x;
-                    l_yi[0] = y.y;
-                } else {
+                if (!coplanar) {
                     T sn, cs;
                     sincos_cycles(r_ph[pos], &sn, &cs);
                     y = cmul<T>(y, mk<T>(cs, sn));
                     const T xw = r_dw[pos];
 #pragma unroll
-                    for (int p = 0; p < PR; ++p) {
-                        const T kw = p < np ? es_eval<T>((xw - T(g0 + p)) * (T(2) / T(Ww)), wbeta) : T(0);
-                        l_yr[p] = y.x * kw;
-                        l_yi[p] = y.y * kw;
-                    }
+                    for (int p = 0; p < PR; ++p)
+                        l_kw[p] = p < np ? es_eval<T>((xw - T(g0 + p)) * (T(2) / T(Ww)), wbeta) : T(0);
                 }
+                l_y = y;
             }
             // the separable kernel values: lane v W + a (v < VPB, a < W) evaluates
             // psi(du - a) and psi(dv - a) of visibility k0 + v, and lane (a, b) of
@@ -472,13 +468,18 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial(const WorkItem *__restric
                         if (run_cell >= 0) flush();
                         run_cell = cell;
                     }
+                    const T yx = wave_bcast(l_y.x, k), yy = wave_bcast(l_y.y, k);
+                    T kw[PR];
+#pragma unroll
+                    for (int p = 0; p < PR; ++p) kw[p] = wave_bcast(l_kw[p], k);
 #pragma unroll
                     for (int q = 0; q < NCELL; ++q) {
                         const T w = ca[q] < 0 ? T(0) : cu_[q] * cv_[q];
+                        const T wr = w * yx, wi = w * yy;
 #pragma unroll
                         for (int p = 0; p < PR; ++p) {
-                            acc_re[q][p] += w * wave_bcast(l_yr[p], k);
-                            acc_im[q][p] += w * wave_bcast(l_yi[p], k);
+                            acc_re[q][p] += wr * kw[p];
+                            acc_im[q][p] += wi * kw[p];
                         }
                     }
                 }
