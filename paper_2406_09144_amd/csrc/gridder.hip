@@ -354,7 +354,8 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial(const WorkItem *__restric
         kexp = 62 - e;
     }
     c2<T> *out = partial + (int64_t)blockIdx.x * Ww * TT;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar loop control
     const T two_over_W = T(2) / T(W);
     int ca[NCELL], cb[NCELL];
 #pragma unroll
