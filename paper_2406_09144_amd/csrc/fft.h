@@ -50,10 +50,46 @@ __device__ __forceinline__ void dft4(c2<T> (&v)[4], int sign) {
     v[3] = csub<T>(t1, t3);
 }
 
+// v * exp(sign 2 pi i m / 16), m < 16, from the exact values of cos and sin at
+// multiples of pi / 8
+template <typename T>
+__device__ __forceinline__ c2<T> rot16(c2<T> v, int m, int sign) {
+    constexpr double c1 = 0.92387953251128675613, s1 = 0.38268343236508977173, r2 = 0.70710678118654752440;
+    const double cs[5] = {1.0, c1, r2, s1, 0.0};  // cos(r pi / 8), r = 0..4
+    const int q = m >> 2, r = m & 3;              // m pi / 8 = q pi / 2 + r pi / 8
+    const T c = (T)cs[r], sn = (T)cs[4 - r];      // cos and sin of r pi / 8
+    // rotate by r pi / 8, then by q quarter turns
+    c2<T> w = mk<T>(v.x * c - (sign < 0 ? -1 : 1) * v.y * sn, v.y * c + (sign < 0 ? -1 : 1) * v.x * sn);
+    for (int t = 0; t < q; ++t) w = mul_i_sign<T>(w, sign);
+    return w;
+}
+
+// 16-point DFT as 4 x 4: n = 4 n1 + n2, k = k1 + 4 k2,
+//   X[k1 + 4 k2] = sum_n2 W16^(n2 k1) W4^(n2 k2) sum_n1 x[4 n1 + n2] W4^(n1 k1)
+template <typename T>
+__device__ __forceinline__ void dft16(c2<T> (&v)[16], int sign) {
+    c2<T> a[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+        c2<T> t[4] = {v[n2], v[4 + n2], v[8 + n2], v[12 + n2]};
+        dft4<T>(t, sign);
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) a[n2][k1] = (n2 * k1) ? rot16<T>(t[k1], n2 * k1, sign) : t[k1];
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        c2<T> t[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+        dft4<T>(t, sign);
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[k2];
+    }
+}
+
 template <typename T, int R>
 __device__ __forceinline__ void dftR(c2<T> (&v)[R], int sign) {
     if constexpr (R == 2) dft2<T>(v);
-    else dft4<T>(v, sign);
+    else if constexpr (R == 4) dft4<T>(v, sign);
+    else dft16<T>(v, sign);
 }
 
 // One Stockham stage over `nlines` lines of length 2^log2L spaced `ld` apart.
@@ -61,7 +97,7 @@ __device__ __forceinline__ void dftR(c2<T> (&v)[R], int sign) {
 template <typename T, int R, int NTHR, int BPT>
 __device__ __forceinline__ void stockham_stage(c2<T> *buf, int ld, int nlines, int log2L, int log2Ns,
                                                int sign, const c2<T> *__restrict__ tw) {
-    constexpr int LOG2R = (R == 2) ? 1 : 2;
+    constexpr int LOG2R = (R == 2) ? 1 : (R == 4) ? 2 : 4;
     const int log2Q = log2L - LOG2R;
     const int Q = 1 << log2Q;
     const int nb = nlines << log2Q;
@@ -112,12 +148,19 @@ __device__ __forceinline__ void stockham_stage(c2<T> *buf, int ld, int nlines, i
 template <typename T, int NTHR, int BPT>
 __device__ __forceinline__ void lds_fft(c2<T> *buf, int ld, int nlines, int log2L, int sign,
                                         const c2<T> *__restrict__ tw) {
+    // radix-16 stages (two radix-4 levels in registers, half the LDS passes),
+    // then radix 4 and 2 for the remaining factor
+    constexpr int BPT16 = BPT / 4 > 0 ? BPT / 4 : 1;
     int log2Ns = 0;
-    if (log2L & 1) {
-        stockham_stage<T, 2, NTHR, 2 * BPT>(buf, ld, nlines, log2L, 0, sign, tw);
-        log2Ns = 1;
+    while (log2L - log2Ns >= 4) {
+        stockham_stage<T, 16, NTHR, BPT16>(buf, ld, nlines, log2L, log2Ns, sign, tw);
+        log2Ns += 4;
     }
-    for (; log2Ns < log2L; log2Ns += 2) stockham_stage<T, 4, NTHR, BPT>(buf, ld, nlines, log2L, log2Ns, sign, tw);
+    if (log2L - log2Ns >= 2) {
+        stockham_stage<T, 4, NTHR, BPT>(buf, ld, nlines, log2L, log2Ns, sign, tw);
+        log2Ns += 2;
+    }
+    if (log2L - log2Ns == 1) stockham_stage<T, 2, NTHR, 2 * BPT>(buf, ld, nlines, log2L, log2Ns, sign, tw);
 }
 
 // store(idx, load(idx)) for idx = threadIdx.x, threadIdx.x + NTHR, ... < n, with U
