@@ -196,10 +196,11 @@ __device__ __forceinline__ const c2<T> *stage_twiddles(c2<T> *twl, const c2<T> *
     }
 }
 
-// Rows per workgroup of the row transforms: about 2048 elements per workgroup,
+// Rows per workgroup of the row transforms: about 4096 elements per workgroup
+// (every thread busy in the radix-16 stages),
 // fewer when there are too few rows to give every CU several workgroups.
 inline int rows_per_wg(int L, int64_t nrows, int n_cu) {
-    int lpw = std::max(1, 2048 / L);
+    int lpw = std::max(1, 4096 / L);
     while (lpw > 1 && nrows / lpw < 4 * (int64_t)std::max(n_cu, 1)) lpw >>= 1;
     return lpw;
 }

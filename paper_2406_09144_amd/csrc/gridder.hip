@@ -673,41 +673,52 @@ template <typename T> struct BandColEpi {
     }
 };
 
-// Gridding epilogue: image row i accumulates Re(exp(+2 pi i w_p t) G_p) over planes.
+// Gridding epilogue: image row i accumulates Re(exp(+2 pi i w_p t) G_p) over planes,
+// transforming `lines` plane rows at a time (all threads busy in every stage).
 template <typename T, int NTHR, int BPT, int ACC, bool TWL>
 __global__ __launch_bounds__(NTHR) void k_grid_rows(const c2<T> *__restrict__ planes, int n_planes, int log2nu,
                                                     int log2nv, int nx, int ny, const T *__restrict__ fac,
                                                     const T *__restrict__ tpix, const double *__restrict__ wplane,
-                                                    int coplanar, T *__restrict__ img,
+                                                    int coplanar, T *__restrict__ img, int lines,
                                                     const c2<T> *__restrict__ tw) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     c2<T> *buf = reinterpret_cast<c2<T> *>(smem_raw);
     const int i = blockIdx.x;
     const int nu = 1 << log2nu, nv = 1 << log2nv;
+    const int ld = plen(nv);
     const int a = (i - nx / 2) & (nu - 1);
     T acc[ACC];
 #pragma unroll
     for (int k = 0; k < ACC; ++k) acc[k] = T(0);
-    const c2<T> *twp = stage_twiddles<T, NTHR, TWL>(buf + plen(nv), tw, nv);
-    for (int p = 0; p < n_planes; ++p) {
-        const c2<T> *src = planes + ((((int64_t)p << log2nu) + a) << log2nv);
-        staged_copy<NTHR>(nv, [&](int e) { return src[e]; }, [&](int e, c2<T> v) { buf[padx(e)] = v; });
+    const c2<T> *twp = stage_twiddles<T, NTHR, TWL>(buf + lines * ld, tw, nv);
+    for (int p0 = 0; p0 < n_planes; p0 += lines) {
+        const int nl = min(lines, n_planes - p0);
+        staged_copy<NTHR>(
+            nl << log2nv,
+            [&](int idx) {
+                const int64_t row = ((int64_t)(p0 + (idx >> log2nv)) << log2nu) + a;
+                return planes[(row << log2nv) + (idx & (nv - 1))];
+            },
+            [&](int idx, c2<T> v) { buf[(idx >> log2nv) * ld + padx(idx & (nv - 1))] = v; });
         __syncthreads();
-        lds_fft<T, NTHR, BPT>(buf, plen(nv), 1, log2nv, +1, twp);
-        const T wp = (T)wplane[p];
+        lds_fft<T, NTHR, BPT>(buf, ld, nl, log2nv, +1, twp);
+        for (int l = 0; l < nl; ++l) {
+            const T wp = (T)wplane[p0 + l];
+            const c2<T> *line = buf + l * ld;
 #pragma unroll
-        for (int k = 0; k < ACC; ++k) {
-            const int j = threadIdx.x + k * NTHR;
-            if (j < ny) {
-                const c2<T> g = buf[padx((j - ny / 2) & (nv - 1))];
-                if (coplanar) {
-                    acc[k] += g.x;
-                } else {
-                    T ph = wp * tpix[(int64_t)i * ny + j];
-                    ph -= rint(ph);
-                    T s, c;
-                    sincos_cycles(ph, &s, &c);
-                    acc[k] += g.x * c - g.y * s;
+            for (int k = 0; k < ACC; ++k) {
+                const int j = threadIdx.x + k * NTHR;
+                if (j < ny) {
+                    const c2<T> g = line[padx((j - ny / 2) & (nv - 1))];
+                    if (coplanar) {
+                        acc[k] += g.x;
+                    } else {
+                        T ph = wp * tpix[(int64_t)i * ny + j];
+                        ph -= rint(ph);
+                        T s, c;
+                        sincos_cycles(ph, &s, &c);
+                        acc[k] += g.x * c - g.y * s;
+                    }
                 }
             }
         }
@@ -841,28 +852,20 @@ void planes_to_image(const fr_plan *pl, const c2<T> *planes_c, const uint8_t *ac
     ProfScope prof("wplane_rows_inv", st);
     const int nv = (int)pl->nv;
     const size_t pl_line = (size_t)plen(nv) * sizeof(c2<T>), twb = (size_t)nv * sizeof(c2<T>);
-    if (nv <= 4096) {
-        const size_t lds = pl_line + twb;
-        auto kern = k_grid_rows<T, 256, 4, 8, true>;
-        allow_lds(kern, lds);
-        kern<<<dim3((unsigned)pl->nx), 256, lds, st>>>(planes, pl->n_planes, l2u, l2v, (int)pl->nx, (int)pl->ny,
-                                                       pl->fac.as<T>(), pl->tpix.as<T>(), pl->wplane.as<double>(),
-                                                       pl->coplanar ? 1 : 0, img_c, pl->ctx->tw<T>(l2v));
-    } else if (pl_line + twb <= (size_t)kLdsBytes) {
-        const size_t lds = pl_line + twb;
-        auto kern = k_grid_rows<T, 1024, 4, 8, true>;
-        allow_lds(kern, lds);
-        kern<<<dim3((unsigned)pl->nx), 1024, lds, st>>>(planes, pl->n_planes, l2u, l2v, (int)pl->nx, (int)pl->ny,
-                                                        pl->fac.as<T>(), pl->tpix.as<T>(), pl->wplane.as<double>(),
-                                                        pl->coplanar ? 1 : 0, img_c, pl->ctx->tw<T>(l2v));
-    } else {
-        const size_t lds = pl_line;
-        auto kern = k_grid_rows<T, 1024, 4, 8, false>;
-        allow_lds(kern, lds);
-        kern<<<dim3((unsigned)pl->nx), 1024, lds, st>>>(planes, pl->n_planes, l2u, l2v, (int)pl->nx, (int)pl->ny,
-                                                        pl->fac.as<T>(), pl->tpix.as<T>(), pl->wplane.as<double>(),
-                                                        pl->coplanar ? 1 : 0, img_c, pl->ctx->tw<T>(l2v));
-    }
+    const int args_lines_small = std::max(1, std::min((int)pl->n_planes, 4096 / nv));
+#define FR_GRID_ROWS(NT, TW, LINES)                                                                             \
+    do {                                                                                                        \
+        const size_t lds = (size_t)(LINES) * pl_line + ((TW) ? twb : 0);                                         \
+        auto kern = k_grid_rows<T, NT, 4, 8, TW>;                                                               \
+        allow_lds(kern, lds);                                                                                   \
+        kern<<<dim3((unsigned)pl->nx), NT, lds, st>>>(planes, pl->n_planes, l2u, l2v, (int)pl->nx, (int)pl->ny, \
+                                                      pl->fac.as<T>(), pl->tpix.as<T>(), pl->wplane.as<double>(), \
+                                                      pl->coplanar ? 1 : 0, img_c, (LINES), pl->ctx->tw<T>(l2v)); \
+    } while (0)
+    if (nv <= 4096) FR_GRID_ROWS(256, true, args_lines_small);
+    else if (pl_line + twb <= (size_t)kLdsBytes) FR_GRID_ROWS(1024, true, 1);
+    else FR_GRID_ROWS(1024, false, 1);
+#undef FR_GRID_ROWS
     LAUNCH_CHECK();
 }
 
