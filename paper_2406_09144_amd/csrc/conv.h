@@ -86,17 +86,18 @@ __global__ __launch_bounds__(NTHR) void k_conv_cols(c2<T> *__restrict__ Y, int l
     const int ld = plen(Lc) + 1;
     const int col0 = blockIdx.x * C;
     const int64_t g = blockIdx.y;
+    const int log2C = 31 - __builtin_clz(C);  // strips are a power of two wide
     c2<T> *Yg = Y + ((g * n_in) << log2M);  // packed rows of image g (n_in rows stored)
     const T *Kg = K + (g % nk) * (int64_t)Lc * (M + 1);
     const c2<T> *twp = stage_twiddles<T, NTHR, TWL>(buf + C * ld, tw, Lc);
     staged_copy<NTHR>(
         C * Lc,
         [&](int idx) {
-            const int r = idx / C, c = idx - r * C;
+            const int r = idx >> log2C, c = idx & (C - 1);
             return (r < n_in) ? Yg[((int64_t)r << log2M) + col0 + c] : mk<T>(T(0), T(0));
         },
         [&](int idx, c2<T> v) {
-            const int r = idx / C, c = idx - r * C;
+            const int r = idx >> log2C, c = idx & (C - 1);
             buf[c * ld + padx(r)] = v;
         });
     __syncthreads();
@@ -130,7 +131,7 @@ __global__ __launch_bounds__(NTHR) void k_conv_cols(c2<T> *__restrict__ Y, int l
     __syncthreads();
     lds_fft<T, NTHR, BPT>(buf, ld, C, log2Lc, +1, twp);
     for (int idx = threadIdx.x; idx < C * n_out; idx += NTHR) {
-        const int r = idx / C, c = idx - r * C;
+        const int r = idx >> log2C, c = idx & (C - 1);
         Yg[((int64_t)r << log2M) + col0 + c] = buf[c * ld + padx(r)];
     }
 }
@@ -233,6 +234,7 @@ void launch_conv_cols(const Ctx &ctx, const ConvGeom &g, c2<T> *Y, const T *K, i
     // small batches: narrower strips so the grid still covers every CU a few times
     while (C > 2 && (int64_t)(M / C) * g.n_img < 2 * (int64_t)std::max(ctx.n_cu, 1)) C >>= 1;
     FR_REQUIRE((int64_t)C * (plen(Lc) + 1) <= max_line_elems<T>(), "column length too large for LDS");
+    FR_REQUIRE(is_pow2(C), "column strip width must be a power of two");
     const size_t lds = (size_t)C * (plen(Lc) + 1) * sizeof(c2<T>);
     dim3 grid((unsigned)(M / C), (unsigned)g.n_img);
     FR_REQUIRE(g.rows_in == g.rows_out, "column pass works in place");
@@ -284,6 +286,7 @@ void launch_irfft_rows(const Ctx &ctx, const ConvGeom &g, Epi epi, const c2<T> *
 }
 
 // ------------------------------------------------------------------ functors
+// (nx is a power of two: row % nx is row & (nx - 1); rows stay below 2^31)
 // x[row][col] (row-major, ny columns) times an optional per-pixel factor a[row % nx][col]
 template <typename T> struct ProScaled {
     const T *x;
@@ -291,7 +294,7 @@ template <typename T> struct ProScaled {
     int nx, ny;
     __device__ T operator()(int64_t row, int col) const {
         T v = x[row * ny + col];
-        return a ? v * a[(row % nx) * ny + col] : v;
+        return a ? v * a[((int)row & (nx - 1)) * ny + col] : v;
     }
 };
 
@@ -303,7 +306,7 @@ template <typename T> struct ProDiagScaled {
         const int64_t q = row * ny + col;
         T v = x[q];
         if (d) v *= d[q];
-        if (a) v *= a[(row % nx) * ny + col];
+        if (a) v *= a[((int)row & (nx - 1)) * ny + col];
         return v;
     }
 };
@@ -320,7 +323,7 @@ template <typename T> struct EpiDiagScaledAdd {
             v1 *= d[q + 1];
         }
         if (a) {
-            const T *pa = a + (row % nx) * ny + col;
+            const T *pa = a + ((int)row & (nx - 1)) * ny + col;
             v0 *= pa[0];
             v1 *= pa[1];
         }
@@ -343,7 +346,7 @@ template <typename T> struct EpiScaled {
     __device__ void operator()(int64_t row, int col, T v0, T v1) const {
         T *p = y + row * ny + col;
         if (a) {
-            const T *q = a + (row % nx) * ny + col;
+            const T *q = a + ((int)row & (nx - 1)) * ny + col;
             v0 *= q[0];
             v1 *= q[1];
         }

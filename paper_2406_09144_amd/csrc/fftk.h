@@ -44,21 +44,22 @@ __global__ __launch_bounds__(NTHR) void k_fft_cols(Pro pro, Epi epi, int ncols, 
     const int ld = plen(L) + 1;
     const int col0 = blockIdx.x * C;
     const int64_t m = blockIdx.y;
+    const int log2C = 31 - __builtin_clz(C);  // strips are a power of two wide
     const c2<T> *twp = stage_twiddles<T, NTHR, TWL>(buf + C * ld, tw, L);
     staged_copy<NTHR>(
         C * L,
         [&](int idx) {
-            const int r = idx / C, c = idx - r * C;
+            const int r = idx >> log2C, c = idx & (C - 1);
             return (r < n_in) ? pro(m, r, col0 + c) : mk<T>(T(0), T(0));
         },
         [&](int idx, c2<T> v) {
-            const int r = idx / C, c = idx - r * C;
+            const int r = idx >> log2C, c = idx & (C - 1);
             buf[c * ld + padx(r)] = v;
         });
     __syncthreads();
     lds_fft<T, NTHR, BPT>(buf, ld, C, log2L, sign, twp);
     for (int idx = threadIdx.x; idx < C * n_out; idx += NTHR) {
-        const int r = idx / C, c = idx - r * C;
+        const int r = idx >> log2C, c = idx & (C - 1);
         epi(m, r, col0 + c, buf[c * ld + padx(r)]);
     }
 }
@@ -112,6 +113,7 @@ void launch_fft_cols(const Ctx &ctx, Pro pro, Epi epi, int64_t nmat, int ncols, 
                      int sign, hipStream_t st) {
     const int L = 1 << log2L;
     const int C = col_strip<T>(L, ncols);
+    FR_REQUIRE(is_pow2(C), "column strip width must be a power of two");
     const size_t lds = (size_t)C * (plen(L) + 1) * sizeof(c2<T>);
     FR_REQUIRE(lds <= (size_t)kLdsBytes && L <= 16384, "column FFT length too large");
     if (nmat <= 0) return;

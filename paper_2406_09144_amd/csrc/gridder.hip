@@ -602,13 +602,14 @@ __global__ __launch_bounds__(kTile * kTile) void k_grid_assemble(const c2<T> *__
 
 // ------------------------------------------------------------------ FFT functors
 // row transform of degridding: line = p * nx + i
+// (image sides are powers of two: line = p nx + i splits with shifts)
 template <typename T> struct DegridRowPro {
     const T *img, *fac, *tpix;
     const double *wplane;
     int nx, ny, nv, coplanar;
     __device__ c2<T> operator()(int64_t line, int b) const {
-        const int p = (int)(line / nx);
-        const int i = (int)(line - (int64_t)p * nx);
+        const int p = (int)line >> (31 - __builtin_clz(nx));
+        const int i = (int)line & (nx - 1);
         const int j = (b + ny / 2) & (nv - 1);
         if (j >= ny) return mk<T>(T(0), T(0));
         const int64_t q = (int64_t)i * ny + j;
@@ -625,8 +626,8 @@ template <typename T> struct DegridRowEpi {
     c2<T> *planes;
     int nx, log2nu, log2nv;
     __device__ void operator()(int64_t line, int b, c2<T> v) const {
-        const int p = (int)(line / nx);
-        const int i = (int)(line - (int64_t)p * nx);
+        const int p = (int)line >> (31 - __builtin_clz(nx));
+        const int i = (int)line & (nx - 1);
         const int a = (i - nx / 2) & ((1 << log2nu) - 1);
         planes[((((int64_t)p << log2nu) + a) << log2nv) + b] = v;
     }
