@@ -52,8 +52,8 @@ __global__ __launch_bounds__(NTHR) void k_rfft_rows(Pro pro, c2<T> *__restrict__
     __syncthreads();
     lds_fft<T, NTHR, BPT>(buf, ld, nl, log2M, -1, twp);
     const int half = M / 2 + 1;
-    for (int idx = threadIdx.x; idx < nl * half; idx += NTHR) {
-        const int c = idx / half, k = idx - c * half;
+    for (int c = 0; c < nl; ++c)
+    for (int k = threadIdx.x; k < half; k += NTHR) {
         c2<T> *line = buf + c * ld;
         if (k == 0) {
             c2<T> z = line[0];
@@ -154,8 +154,8 @@ __global__ __launch_bounds__(NTHR) void k_irfft_rows(Epi epi, const c2<T> *__res
         [&](int idx, c2<T> v) { buf[(idx >> log2M) * ld + padx(idx & (M - 1))] = v; });
     __syncthreads();
     const int half = M / 2 + 1;
-    for (int idx = threadIdx.x; idx < nl * half; idx += NTHR) {
-        const int c = idx / half, k = idx - c * half;
+    for (int c = 0; c < nl; ++c)
+    for (int k = threadIdx.x; k < half; k += NTHR) {
         c2<T> *line = buf + c * ld;
         if (k == 0) {
             c2<T> p = line[0];
@@ -177,11 +177,11 @@ __global__ __launch_bounds__(NTHR) void k_irfft_rows(Epi epi, const c2<T> *__res
     __syncthreads();
     lds_fft<T, NTHR, BPT>(buf, ld, nl, log2M, +1, twp);
     const int npair = n_out_cols / 2;
-    for (int idx = threadIdx.x; idx < nl * npair; idx += NTHR) {
-        const int c = idx / npair, e = idx - c * npair;
-        c2<T> z = buf[c * ld + padx(e)];
-        epi(row0 + c, 2 * e, z.x, z.y);
-    }
+    for (int c = 0; c < nl; ++c)
+        for (int e = threadIdx.x; e < npair; e += NTHR) {
+            c2<T> z = buf[c * ld + padx(e)];
+            epi(row0 + c, 2 * e, z.x, z.y);
+        }
 }
 
 // ------------------------------------------------------------------ launchers

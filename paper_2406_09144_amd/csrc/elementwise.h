@@ -93,6 +93,17 @@ void batched_dot(const T *a, const T *b, int64_t n_per_img, int64_t n_img, doubl
     LAUNCH_CHECK();
 }
 
+// q mod n for 0 <= q < 2^52 without a 64-bit integer division (inv_n = 1 / n):
+// the quotient from the FP64 product is off by at most one, which the two
+// comparisons correct
+__device__ __forceinline__ int64_t mod_nonneg(int64_t q, int64_t n, double inv_n) {
+    const int64_t k = (int64_t)((double)q * inv_n);
+    int64_t r = q - k * n;
+    if (r < 0) r += n;
+    else if (r >= n) r -= n;
+    return r;
+}
+
 // generic grid-stride elementwise launcher
 template <class F> __global__ void k_map(F f, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)

@@ -23,9 +23,10 @@ template <typename T> struct SkyFromLog {
     const T *s, *ifix;
     T *I;
     int64_t n_img;
+    double inv_n;
     __device__ void operator()(int64_t q) const {
         T v = exp(s[q]);
-        if (ifix) v += ifix[q % n_img];
+        if (ifix) v += ifix[mod_nonneg(q, n_img, inv_n)];
         I[q] = v;
     }
 };
@@ -35,7 +36,8 @@ template <typename T> struct Residual {
     const T *d;
     T *t;
     int64_t n_img;
-    __device__ void operator()(int64_t q) const { t[q] = d[q % n_img] - t[q]; }
+    double inv_n;
+    __device__ void operator()(int64_t q) const { t[q] = d[mod_nonneg(q, n_img, inv_n)] - t[q]; }
 };
 
 // g = sign * exp(s) * u (+ prior)
@@ -78,13 +80,13 @@ void likelihood_grad(const fr_plan *pl, const fr_psf *psf, int mode, const T *s,
     Scratch partials((size_t)std::max<int64_t>(B, 1) * kRedMaxBlocks * sizeof(double), st);
     Scratch Ib((size_t)n_all * sizeof(T), st);
     Scratch ub((size_t)n_all * sizeof(T), st);
-    map_async(SkyFromLog<T>{s, i_fixed, Ib.as<T>(), n_img}, n_all, st);
+    map_async(SkyFromLog<T>{s, i_fixed, Ib.as<T>(), n_img, 1.0 / (double)n_img}, n_all, st);
     if (mode == FR_LIK_FAST) {
         FR_REQUIRE(psf->KN.p, "the PSF object has no noise kernel");
         Scratch tb((size_t)n_all * sizeof(T), st);
         // r = d - R' I
         apply_rnr_approx<T>(psf, Ib.as<T>(), tb.as<T>(), B, st);
-        map_async(Residual<T>{(const T *)data, tb.as<T>(), n_img}, n_all, st);
+        map_async(Residual<T>{(const T *)data, tb.as<T>(), n_img, 1.0 / (double)n_img}, n_all, st);
         // q = N'^-1 r  (into Ib, no longer needed)
         periodic_conv<T>(ctx, tb.as<T>(), Ib.as<T>(), B * nc, nx, ny, psf->KN.as<T>(), (int)nc, 1, st);
         // H = 1/2 <r, q>
