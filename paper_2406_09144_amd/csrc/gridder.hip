@@ -275,6 +275,17 @@ __global__ __launch_bounds__(NTHR) void k_degrid(const WorkItem *__restrict__ wi
     }
 }
 
+// value of lane (byte_addr / 4) in each lane (ds_bpermute)
+__device__ __forceinline__ float lane_permute(float v, int byte_addr) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(byte_addr, __float_as_int(v)));
+}
+__device__ __forceinline__ double lane_permute(double v, int byte_addr) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_ds_bpermute(byte_addr, (int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_ds_bpermute(byte_addr, (int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // value of lane k (wave-uniform k) in every lane
 __device__ __forceinline__ float wave_bcast(float v, int k) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
@@ -357,12 +368,14 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial(const WorkItem *__restric
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar loop control
     const T two_over_W = T(2) / T(W);
-    int ca[NCELL], cb[NCELL];
+    int ca[NCELL], cb[NCELL], au[NCELL], av[NCELL];
 #pragma unroll
     for (int q = 0; q < NCELL; ++q) {
         const int c = lane + 64 * q;
         ca[q] = c < W * W ? c / W : -1;
         cb[q] = c < W * W ? c - (c / W) * W : 0;
+        au[q] = 4 * max(ca[q], 0);
+        av[q] = 4 * cb[q];
     }
     // this wavefront's contiguous share of the item
     const int share = (it.count + NWAVE - 1) / NWAVE;
@@ -443,11 +456,12 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial(const WorkItem *__restric
                 const T phv = es_eval<T>((xv_v - T(aa)) * two_over_W, beta);
                 const int kend = min(k0 + VPB, nb);
                 // the permutes for visibility k + 1 are issued before the work on k
+                // (byte addresses: lane base + a of the value psi(d - a))
                 T nu_[NCELL], nv_[NCELL];
 #pragma unroll
                 for (int q = 0; q < NCELL; ++q) {
-                    nu_[q] = __shfl(phu, max(ca[q], 0), 64);
-                    nv_[q] = __shfl(phv, cb[q], 64);
+                    nu_[q] = lane_permute(phu, au[q]);
+                    nv_[q] = lane_permute(phv, av[q]);
                 }
                 for (int k = k0; k < kend; ++k) {
                     T cu_[NCELL], cv_[NCELL];
@@ -457,11 +471,11 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial(const WorkItem *__restric
                         cv_[q] = nv_[q];
                     }
                     if (k + 1 < kend) {
-                        const int base1 = (k + 1 - k0) * W;
+                        const int base1 = (k + 1 - k0) * W * 4;
 #pragma unroll
                         for (int q = 0; q < NCELL; ++q) {
-                            nu_[q] = __shfl(phu, base1 + max(ca[q], 0), 64);
-                            nv_[q] = __shfl(phv, base1 + cb[q], 64);
+                            nu_[q] = lane_permute(phu, base1 + au[q]);
+                            nv_[q] = lane_permute(phv, base1 + av[q]);
                         }
                     }
                     const int cell = __builtin_amdgcn_readlane(l_cell, k);
@@ -473,9 +487,11 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial(const WorkItem *__restric
                     T kw[PR];
 #pragma unroll
                     for (int p = 0; p < PR; ++p) kw[p] = wave_bcast(l_kw[p], k);
+                    // lanes beyond the footprint (ca < 0) accumulate values that
+                    // are never flushed
 #pragma unroll
                     for (int q = 0; q < NCELL; ++q) {
-                        const T w = ca[q] < 0 ? T(0) : cu_[q] * cv_[q];
+                        const T w = cu_[q] * cv_[q];
                         const T wr = w * yx, wi = w * yy;
 #pragma unroll
                         for (int p = 0; p < PR; ++p) {
