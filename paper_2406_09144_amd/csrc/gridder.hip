@@ -541,7 +541,8 @@ __global__ __launch_bounds__(256) void k_vis_bound(const c2<T> *__restrict__ vis
 // and v (their W - 1 halo reaches into this tile), for every first plane p0 with
 // p - Ww < p0 <= p.  The items of a tile are sorted by base cell, so those that
 // touch a given tile row form a contiguous run, found by binary search on their
-// first and last rows.  Every cell of an active tile is written exactly once;
+// first and last rows (once per workgroup, into LDS).  Every cell of an active
+// tile is written exactly once;
 // the inverse column transform reads zeros for the other tiles, so the planes
 // need no clearing and the result does not depend on scheduling.  Eight partial
 // loads are kept in flight per thread.
@@ -562,35 +563,46 @@ __global__ __launch_bounds__(kTile * kTile) void k_grid_assemble(const c2<T> *__
     const int n_tiles = ntu * ntv;
     const int pmin = max(0, p - Ww + 1), pmax = min(p, n_p0 - 1);
     const int64_t stride = (int64_t)Ww * TT;  // between consecutive items
+    // item ranges per (column step dj, first plane p0, tile row li), found once per
+    // workgroup by parallel binary searches: items of a key are sorted by rows, so
+    // those touching row li are [first whose last row reaches li, first whose
+    // first row passes li)
+    const int np = pmax - pmin + 1;
+    __shared__ uint2 range[2 * W * TS];
+    for (int q = threadIdx.x; q < 2 * np * TS; q += kTile * kTile) {
+        const int li = q % TS, r = q / TS;
+        const int dj = r / np, p0 = pmin + (r - dj * np);
+        const int di = li >= kTile ? 1 : 0;
+        const int t2 = ((tu - di + ntu) % ntu) * ntv + (tv - dj + ntv) % ntv;
+        const int64_t key = key0 + (int64_t)p0 * n_tiles + t2;
+        const uint32_t b = gkey_first[key], e = gkey_first[key + 1];
+        uint32_t lo = b, hi = e;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if ((items[mid].rows >> 16) < li) lo = mid + 1;
+            else hi = mid;
+        }
+        const uint32_t first = lo;
+        hi = e;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if ((items[mid].rows & 0xffff) <= li) lo = mid + 1;
+            else hi = mid;
+        }
+        range[q] = make_uint2(first, lo);
+    }
+    __syncthreads();
     const int i = threadIdx.x / kTile, j = threadIdx.x - (threadIdx.x / kTile) * kTile;
     T sx = 0, sy = 0;
     for (int di = 0; di < 2; ++di) {
         const int li = i + di * kTile;
         if (li >= TS) continue;
-        const int tu2 = (tu - di + ntu) % ntu;
         for (int dj = 0; dj < 2; ++dj) {
             const int lj = j + dj * kTile;
             if (lj >= TS) continue;
-            const int tv2 = (tv - dj + ntv) % ntv;
-            const int t2 = tu2 * ntv + tv2;
             for (int p0 = pmin; p0 <= pmax; ++p0) {
-                const int64_t key = key0 + (int64_t)p0 * n_tiles + t2;
-                uint32_t b = gkey_first[key], e = gkey_first[key + 1];
-                // first item whose last row reaches li, then first whose first row passes it
-                uint32_t lo = b, hi = e;
-                while (lo < hi) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if ((items[mid].rows >> 16) < li) lo = mid + 1;
-                    else hi = mid;
-                }
-                b = lo;
-                hi = e;
-                while (lo < hi) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if ((items[mid].rows & 0xffff) <= li) lo = mid + 1;
-                    else hi = mid;
-                }
-                e = lo;
+                const uint2 rg = range[(dj * np + (p0 - pmin)) * TS + li];
+                const uint32_t b = rg.x, e = rg.y;
                 const c2<T> *src = partial + ((int64_t)(b - item0) * Ww + (p - p0)) * TT + li * TS + lj;
                 const uint32_t n = e - b;
                 uint32_t k = 0;
