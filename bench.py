@@ -101,6 +101,47 @@ def algorithmic_bytes(name, info, n_vis, n_row, B_conv, nx, ny):
     return None
 
 
+def scale_workload(api, torch, steps=3):
+    """(De)gridding on the MeerKAT-like multi-channel workload (7,257,600 rows x 16
+    channels = 116,121,600 visibilities, 4096 x 4096 per channel, FP32, eps 1e-5):
+    the HBM-bound regime at the paper's data scale."""
+    import numpy as np
+    from synthetic import make_config
+    t0 = time.time()
+    obs = make_config(3, with_sky=False)
+    t_gen = time.time() - t0
+    t0 = time.time()
+    plan = api.Plan(obs.uvw, obs.freq, obs.nx, obs.ny, obs.dx, obs.dy, eps=1e-5)
+    torch.cuda.synchronize()
+    t_plan = time.time() - t0
+    info = plan.info
+    g = torch.Generator(device="cuda").manual_seed(11)
+    sky = torch.rand((obs.n_chan, obs.nx, obs.ny), device="cuda", generator=g)
+    w = torch.rand((obs.n_row, obs.n_chan), device="cuda", generator=g) + 0.5
+    vis = api.degrid(plan, sky)
+    img = api.grid(plan, vis, w)
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record()
+    for _ in range(steps):
+        api.degrid(plan, sky, out=vis)
+    e[1].record()
+    for _ in range(steps):
+        api.grid(plan, vis, w, out=img)
+    e[2].record()
+    torch.cuda.synchronize()
+    dg = e[0].elapsed_time(e[1]) / steps
+    gr = e[1].elapsed_time(e[2]) / steps
+    n_vis = obs.n_row * obs.n_chan
+    res = {"workload": f"MeerKAT-like: {obs.n_row} rows x {obs.n_chan} channels, {obs.nx}x{obs.ny} per channel, "
+                       f"eps=1e-5, FP32", "n_vis": n_vis, "support": info["support"], "n_planes": info["n_planes"],
+           "degrid_ms": dg, "grid_ms": gr, "vis_per_s": 2 * n_vis / ((dg + gr) * 1e-3),
+           "plan_create_s": t_plan, "inputs_generated_s": t_gen}
+    del plan, sky, w, vis, img
+    torch.cuda.empty_cache()
+    return res
+
+
 def build_served_jobs(api, torch, n_jobs, fp64):
     """Resident jobs of the served mix: plan, PSF kernels, data, input pools."""
     import numpy as np
@@ -180,6 +221,8 @@ def main():
                     help="requests of the FP64 replay (0: the whole trace, -1: skip it)")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only run 5 plain copies of this many bytes (counter calibration)")
+    ap.add_argument("--scale-steps", type=int, default=2,
+                    help="timed (de)grid passes of the MeerKAT-like workload (0 disables)")
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--n-int", type=int, default=2880)
     args = ap.parse_args()
@@ -368,6 +411,11 @@ def main():
                 "support": plan64.info["support"], "n_planes": plan64.info["n_planes"]}
         del plan64
 
+    scale = None
+    if args.scale_steps > 0:
+        scale = scale_workload(api, torch, args.scale_steps)
+        log(f"[bench] MeerKAT-like: {json.dumps(scale)}")
+
     served = None
     if args.serve_seconds > 0:
         served = served_workload(api, torch, args.serve_seconds, args.serve_rate, args.serve_jobs,
@@ -403,6 +451,7 @@ def main():
             "lik_fast_b8_ms": comp["lik_fast_b8"], "lik_exact_b1_ms": comp["lik_exact_b1"],
             "cg50_ms": comp["cg50"], "plan_create_s": t_plan, "make_psf_s": t_psf,
             "fp64_plain_form": fp64,
+            "meerkat_like": scale,
             "served": served,
         },
         "kernels_ms": {k: round(v["avg_ms"], 5) for k, v in kern.items()},
