@@ -215,6 +215,48 @@ def psf_conv_direct(x, psf, a=None, pix=None):
     return y * a.reshape(-1)[pix] if a is not None else y
 
 
+# ---------------------------------------------------------------- reduced PSF
+def psf_truncate(psf, hx, hy):
+    """The doubled-grid PSF with the sidelobes beyond offsets |dx| > hx, |dy| > hy
+    neglected (Sec. 3.3.2: a smaller PSF needs less zero padding, at the price of
+    a less accurate R').  0 <= hx < nx, 0 <= hy < ny."""
+    nx, ny = psf.shape[0] // 2, psf.shape[1] // 2
+    assert 0 <= hx < nx and 0 <= hy < ny
+    out = np.zeros_like(_f64(psf))
+    wx = slice(nx - hx, nx + hx + 1)
+    wy = slice(ny - hy, ny + hy + 1)
+    out[wx, wy] = psf[wx, wy]
+    return out
+
+
+def response_kernel_padded(psf, hx, hy, px, py):
+    """FFT[I_PSF] of the truncated PSF on a px x py periodic grid: offset (dx, dy)
+    sits at index (dx mod px, dy mod py).  Returns the real part of the r2c half,
+    [px, py // 2 + 1].  The convolution of an nx x ny image cropped back to
+    nx x ny is linear (no wrapped term reaches the window) iff px >= nx + hx and
+    py >= ny + hy."""
+    nx, ny = psf.shape[0] // 2, psf.shape[1] // 2
+    assert px >= 2 * hx + 1 and py >= 2 * hy + 1
+    ox = np.arange(-hx, hx + 1)
+    oy = np.arange(-hy, hy + 1)
+    z = np.zeros((px, py))
+    z[np.ix_(ox % px, oy % py)] = _f64(psf)[np.ix_(nx + ox, ny + oy)]
+    return np.real(np.fft.rfft2(z))
+
+
+def psf_conv_fft_padded(x, K, px, py, a=None):
+    """P^+ FFT^-1[K FFT[P I]] with P padding nx x ny into the top-left of
+    px x py (Sec. 3.3.2 with a reduced padding), D = diag(a) on both sides."""
+    x = _f64(x)
+    nx, ny = x.shape[-2:]
+    if a is not None:
+        x = x * a
+    xp = np.zeros(x.shape[:-2] + (px, py))
+    xp[..., :nx, :ny] = x
+    y = np.fft.irfft2(K * np.fft.rfft2(xp), s=(px, py))[..., :nx, :ny]
+    return y * a if a is not None else y
+
+
 def rnr_exact(uvw_m, freq_hz, nx, ny, dx, dy, x, weight, divide_by_n=True):
     """R' x = R^+ N^-1 R x evaluated exactly (Sec. 3.3.1; major cycle, Sec. 3.3.4)."""
     vis = degrid(uvw_m, freq_hz, nx, ny, dx, dy, x, divide_by_n)

@@ -192,6 +192,80 @@ def test_psf_conv_fft_equals_direct(oracle_lib):
     assert rel(O.psf_conv_direct(x, psf, a, pix=pix), O.psf_conv_direct(x, psf, a).ravel()[pix]) < 1e-14
 
 
+@pytest.mark.parametrize("h,p", [((3, 3), (19, 19)), ((3, 6), (20, 24)), ((8, 8), (24, 24)),
+                                 ((5, 2), (21, 40)), ((15, 15), (31, 31)), ((0, 0), (16, 16))])
+def test_reduced_psf_conv_equals_direct_truncated(oracle_lib, h, p):
+    """Sec. 3.3.2, reduced PSF: with the sidelobes beyond (hx, hy) dropped, padding
+    to px >= nx + hx, py >= ny + hy gives the linear convolution with the truncated
+    PSF, checked against the direct O(N^4) sum (which knows nothing of padding),
+    at odd, even, non-power-of-two and anisotropic sizes."""
+    obs, wt = _psf_setup(n=16)
+    n = obs.nx
+    psf = O.psf0(obs.uvw, obs.freq, n, n, obs.dx, obs.dy, wt)
+    (hx, hy), (px, py) = h, p
+    Kp = O.response_kernel_padded(psf, hx, hy, px, py)
+    assert Kp.shape == (px, py // 2 + 1)
+    rng = np.random.default_rng(21)
+    x = rng.standard_normal((n, n))
+    a = O.n_factor(n, n, obs.dx, obs.dy)
+    tr = O.psf_truncate(psf, hx, hy)
+    direct = O.psf_conv_direct(x, tr, a)
+    assert rel(O.psf_conv_fft_padded(x, Kp, px, py, a), direct) < 1e-12
+    # the truncated PSF keeps exactly the (2hx + 1)(2hy + 1) central offsets
+    assert np.count_nonzero(tr) == np.count_nonzero(psf[n - hx: n + hx + 1, n - hy: n + hy + 1])
+    assert np.all(tr[n - hx: n + hx + 1, n - hy: n + hy + 1] == psf[n - hx: n + hx + 1, n - hy: n + hy + 1])
+    # a single pixel at the centre picks out the truncated PSF itself
+    e = np.zeros((n, n))
+    e[n // 2, n // 2] = 1.0
+    y = O.psf_conv_fft_padded(e, Kp, px, py)
+    assert np.max(np.abs(y - tr[n - n // 2: n + n // 2, n - n // 2: n + n // 2])) < 1e-12 * psf.max()
+
+
+def test_reduced_psf_padding_bound_is_tight(oracle_lib):
+    """One row or column less than nx + hx (ny + hy) and the periodic wrap reaches
+    the cropped window."""
+    obs, wt = _psf_setup(n=16)
+    n = obs.nx
+    psf = O.psf0(obs.uvw, obs.freq, n, n, obs.dx, obs.dy, wt)
+    rng = np.random.default_rng(22)
+    x = rng.standard_normal((n, n))
+    hx, hy = 6, 4
+    direct = O.psf_conv_direct(x, O.psf_truncate(psf, hx, hy))
+    for px, py in ((n + hx - 1, n + hy), (n + hx, n + hy - 1)):
+        y = O.psf_conv_fft_padded(x, O.response_kernel_padded(psf, hx, hy, px, py), px, py)
+        assert rel(y, direct) > 1e-3
+
+
+def test_reduced_psf_full_support_is_the_doubled_grid(oracle_lib):
+    """hx = nx - 1, hy = ny - 1 on the 2nx x 2ny grid keeps every offset but the
+    zeroed -n row and column: the kernel is K_R itself."""
+    obs, wt = _psf_setup(n=16)
+    n = obs.nx
+    psf = O.psf0(obs.uvw, obs.freq, n, n, obs.dx, obs.dy, wt)
+    K = O.response_kernel(psf)
+    Kp = O.response_kernel_padded(psf, n - 1, n - 1, 2 * n, 2 * n)
+    assert np.max(np.abs(Kp - K)) < 1e-12 * np.max(np.abs(K))
+
+
+def test_reduced_psf_error_vanishes_with_support(oracle_lib):
+    """The neglected sidelobes are all that separates the reduced R' from the full
+    one: the error is the convolution with the dropped part, and it is zero once
+    nothing is dropped."""
+    obs, wt = _psf_setup(n=16)
+    n = obs.nx
+    psf = O.psf0(obs.uvw, obs.freq, n, n, obs.dx, obs.dy, wt)
+    rng = np.random.default_rng(23)
+    x = rng.standard_normal((n, n))
+    full = O.psf_conv_fft(x, O.response_kernel(psf))
+    for h in (2, 5, 9):
+        red = O.psf_conv_fft_padded(x, O.response_kernel_padded(psf, h, h, n + h, n + h), n + h, n + h)
+        dropped = O.psf_conv_direct(x, psf - O.psf_truncate(psf, h, h))
+        assert rel(full - red, dropped) < 1e-10
+    h = n - 1
+    red = O.psf_conv_fft_padded(x, O.response_kernel_padded(psf, h, h, n + h, n + h), n + h, n + h)
+    assert rel(red, full) < 1e-12
+
+
 @pytest.mark.parametrize("divide_by_n", [True, False])
 def test_psf_conv_exact_for_coplanar(oracle_lib, divide_by_n):
     """Sec. 3.3.2: the PSF convolution is exact for a coplanar array."""
