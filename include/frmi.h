@@ -166,12 +166,30 @@ int fr_make_psf_kernel(fr_plan *plan, const void *weight, double eps_noise, fr_p
 int fr_psf_create(fr_ctx *ctx, int64_t nx, int64_t ny, int64_t n_chan, const void *K_R,
                   const void *K_N, const void *nfac, int flags, fr_psf **out, void *stream);
 
-/* Copy the kernels out (either pointer may be NULL), same layouts as above. */
+/* Reduced PSF support (Sec. 3.3.2: neglecting the PSF sidelobes lets the zero
+ * padding shrink, at the price of a less accurate R'): a new PSF object whose
+ * response kernel keeps the PSF0 offsets |dx| <= hx, |dy| <= hy only, on a
+ * px x py periodic grid with px the smallest even 2^p, 3 2^p or 5 2^p >= nx + hx
+ * (py likewise), so that the cropped convolution stays linear:
+ *   K_R' = Re rfft2(PSF0 truncated, offset d at index d mod p) -> [n_chan][px][py/2 + 1]
+ * fr_apply_RNR_approx, the FAST likelihood and CG then convolve with the
+ * truncated PSF on the smaller grid.  K_N and the 1/n factors are copied.
+ *   psf     a PSF object with the full doubled-grid kernel (px = 2nx, py = 2ny),
+ *           not modified; 0 <= hx < nx, 0 <= hy < ny.
+ * The caller owns *out (fr_psf_destroy).  Synchronises `stream`. */
+int fr_psf_reduce(const fr_psf *psf, int64_t hx, int64_t hy, fr_psf **out, void *stream);
+
+/* Periodic grid px x py of the object's response kernel (2nx x 2ny unless reduced). */
+int fr_psf_get_padding(const fr_psf *psf, int64_t *px, int64_t *py);
+
+/* Copy the kernels out (either pointer may be NULL): K_R [n_chan][px][py/2 + 1],
+ * K_N as above. */
 int fr_psf_get_kernels(const fr_psf *psf, void *K_R, void *K_N, void *stream);
 void fr_psf_destroy(fr_psf *psf);
 
 /* R' x ~ D P^+ FFT^-1[K_R FFT[P D x]] (Sec. 3.3.2): zero-padded linear convolution
- * with the doubled-grid PSF.  x, y device [B][n_chan][nx][ny] real, y != x. */
+ * with the doubled-grid PSF (P pads to the object's px x py grid: 2nx x 2ny, or the
+ * reduced grid of fr_psf_reduce).  x, y device [B][n_chan][nx][ny] real, y != x. */
 int fr_apply_RNR_approx(fr_psf *psf, const void *x, void *y, int64_t B, void *stream);
 
 /* R' x = R^+ N^-1 R x evaluated exactly (major cycle, Sec. 3.3.4).
@@ -239,7 +257,8 @@ int fr_profile_reset(void);
 int fr_profile_query(const char *name, int64_t *launches, double *total_ms);
 
 /* Building block exposed for testing: in-place 2D complex FFT of a device array
- * [batch][n0][n1] (n0, n1 powers of two, 2 <= n <= 16384, FP64 up to 8192),
+ * [batch][n0][n1] (n0, n1 of the form 2^p, 3 2^p or 5 2^p, 2 <= n <= 16384, FP64 up
+ * to 8192),
  * sign -1 forward, +1 inverse, unnormalised.  fp64 selects complex128. */
 int fr_fft2(fr_ctx *ctx, void *data, int64_t batch, int64_t n0, int64_t n1, int sign, int fp64,
             void *stream);

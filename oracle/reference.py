@@ -329,16 +329,19 @@ def likelihood_exact(s, vis, weight, fwd, adj, i_fixed=None, inv_power=None):
     return H, g
 
 
-def likelihood_fast(s, d, K_R, K_N, a=None, i_fixed=None, inv_power=None):
+def likelihood_fast(s, d, K_R, K_N, a=None, i_fixed=None, inv_power=None, pad=None):
     """Eq. (ham_new) of Sec. 3.3.1 with R' replaced by the PSF convolution
     (Sec. 3.3.2) and N'^-1 by the inverse-kernel convolution (Sec. 3.3.3):
-        r = d - R' I,  q = N'^-1 r,  H = 1/2 <r, q>,  g = -exp(s) * R' q."""
+        r = d - R' I,  q = N'^-1 r,  H = 1/2 <r, q>,  g = -exp(s) * R' q.
+    pad = (px, py): K_R is a reduced-support kernel on that padded grid."""
+    def rconv(x):
+        return psf_conv_fft(x, K_R, a) if pad is None else psf_conv_fft_padded(x, K_R, pad[0], pad[1], a)
     s = _f64(s)
     I = np.exp(s) + (i_fixed if i_fixed is not None else 0.0)
-    r = _f64(d) - psf_conv_fft(I, K_R, a)
+    r = _f64(d) - rconv(I)
     q = noise_inv_apply(r, K_N)
     H = 0.5 * float(np.sum(r * q))
-    g = -np.exp(s) * psf_conv_fft(q, K_R, a)
+    g = -np.exp(s) * rconv(q)
     if inv_power is not None:
         Ss = prior_inv_apply(s, inv_power)
         H += 0.5 * float(np.sum(s * Ss))

@@ -63,6 +63,8 @@ SIGNATURES = {
     "fr_grid": ([_P, _P, _P, _P, _P], _I),
     "fr_make_psf_kernel": ([_P, _P, _D, _PP, _P], _I),
     "fr_psf_create": ([_P, _I64, _I64, _I64, _P, _P, _P, _I, _PP, _P], _I),
+    "fr_psf_reduce": ([_P, _I64, _I64, _PP, _P], _I),
+    "fr_psf_get_padding": ([_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64)], _I),
     "fr_psf_get_kernels": ([_P, _P, _P, _P], _I),
     "fr_psf_destroy": ([_P], None),
     "fr_apply_RNR_approx": ([_P, _P, _P, _I64, _P], _I),

@@ -72,12 +72,24 @@ class Context:
 
 
 class PSF:
-    """Response kernel K_R [n_chan, 2nx, ny+1] and noise kernel K_N [n_chan, nx, ny/2+1]."""
+    """Response kernel K_R [n_chan, px, py/2+1] on the px x py padded grid (2nx x 2ny,
+    smaller for a reduced support) and noise kernel K_N [n_chan, nx, ny/2+1]."""
 
     def __init__(self, handle, nx, ny, n_chan, fp64, ctx):
         self.handle = handle
         self.nx, self.ny, self.n_chan, self.fp64 = nx, ny, n_chan, fp64
         self.ctx = ctx
+        px, py = ctypes.c_int64(), ctypes.c_int64()
+        L.check(_lib().fr_psf_get_padding(handle, ctypes.byref(px), ctypes.byref(py)))
+        self.px, self.py = px.value, py.value
+
+    def reduce(self, hx, hy=None, stream=None):
+        """A new PSF object whose response kernel keeps the offsets |dx| <= hx,
+        |dy| <= hy of this one's PSF, on the smaller padded grid (Sec. 3.3.2)."""
+        hy = hx if hy is None else hy
+        h = ctypes.c_void_p()
+        L.check(_lib().fr_psf_reduce(self.handle, int(hx), int(hy), ctypes.byref(h), _stream(stream)))
+        return PSF(h, self.nx, self.ny, self.n_chan, self.fp64, self.ctx)
 
     @classmethod
     def from_kernels(cls, K_R, K_N=None, nfac=None, ctx=None, stream=None):
@@ -101,7 +113,7 @@ class PSF:
     def kernels(self, stream=None):
         rd = _real_dtype(self.fp64)
         dev = torch.device("cuda", self.ctx.device)
-        KR = torch.empty((self.n_chan, 2 * self.nx, self.ny + 1), dtype=rd, device=dev)
+        KR = torch.empty((self.n_chan, self.px, self.py // 2 + 1), dtype=rd, device=dev)
         KN = torch.empty((self.n_chan, self.nx, self.ny // 2 + 1), dtype=rd, device=dev)
         try:
             L.check(_lib().fr_psf_get_kernels(self.handle, _ptr(KR), _ptr(KN), _stream(stream)))

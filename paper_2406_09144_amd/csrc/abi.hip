@@ -56,8 +56,7 @@ int fr_ctx_create(int device, fr_ctx **out) {
     ctx->c.owner = ctx.get();
     HIP_CHECK(hipDeviceGetAttribute(&ctx->c.n_cu, hipDeviceAttributeMultiprocessorCount, device));
     // twiddle tables exp(-2 pi i m / L), computed in extended precision, rounded once
-    for (int l = 1; l <= kMaxLog2FFT + 1; ++l) {
-        const int64_t L = int64_t(1) << l;
+    auto make_table = [&](int64_t L, void **p64, void **p32) {
         std::vector<double> t64(2 * L);
         std::vector<float> t32(2 * L);
         for (int64_t m = 0; m < L; ++m) {
@@ -71,11 +70,15 @@ int fr_ctx_create(int device, fr_ctx **out) {
         DevBuf b64(t64.size() * sizeof(double)), b32(t32.size() * sizeof(float));
         HIP_CHECK(hipMemcpy(b64.p, t64.data(), b64.bytes, hipMemcpyHostToDevice));
         HIP_CHECK(hipMemcpy(b32.p, t32.data(), b32.bytes, hipMemcpyHostToDevice));
-        ctx->c.tw64[l] = b64.p;
-        ctx->c.tw32[l] = b32.p;
+        *p64 = b64.p;
+        *p32 = b32.p;
         ctx->tables.push_back(std::move(b64));
         ctx->tables.push_back(std::move(b32));
-    }
+    };
+    for (int l = 1; l <= kMaxLog2FFT + 1; ++l) make_table(int64_t(1) << l, &ctx->c.tw64[l], &ctx->c.tw32[l]);
+    for (int o = 0; o < 2; ++o)
+        for (int l = 0; l <= kMaxLog2Odd; ++l)
+            make_table(int64_t(o == 0 ? 3 : 5) << l, &ctx->c.tw64o[o][l], &ctx->c.tw32o[o][l]);
     *out = ctx.release();
     FR_API_END
 }
@@ -107,6 +110,8 @@ int fr_psf_create(fr_ctx *ctx, int64_t nx, int64_t ny, int64_t n_chan, const voi
     p->ny = ny;
     p->n_chan = n_chan;
     p->fp64 = fp64;
+    p->px = 2 * nx;
+    p->py = 2 * ny;
     const size_t rs = real_size(fp64);
     p->KR = DevBuf((size_t)n_chan * 2 * nx * (ny + 1) * rs);
     HIP_CHECK(hipMemcpyAsync(p->KR.p, K_R, p->KR.bytes, hipMemcpyDefault, st));
@@ -161,8 +166,9 @@ int fr_fft2(fr_ctx *ctx, void *data, int64_t batch, int64_t n0, int64_t n1, int 
     FR_API_BEGIN
     FR_REQUIRE(ctx && data, "ctx and data are required");
     FR_REQUIRE(batch >= 0, "batch must be >= 0");
-    FR_REQUIRE(is_pow2(n0) && is_pow2(n1) && n0 >= 2 && n1 >= 2 && n0 <= 16384 && n1 <= 16384,
-               "sizes must be powers of two in [2, 16384]");
+    int o = 1, l = 0;
+    FR_REQUIRE(split_len(n0, &o, &l) && split_len(n1, &o, &l) && n0 >= 2 && n1 >= 2 && n0 <= 16384 && n1 <= 16384,
+               "sizes must be 2^p, 3 2^p or 5 2^p in [2, 16384]");
     FR_REQUIRE(!fp64 || (n0 <= 8192 && n1 <= 8192), "FP64 sizes are limited to 8192");
     FR_REQUIRE(sign == -1 || sign == 1, "sign must be -1 or +1");
     DeviceGuard dg(ctx->c.device);
@@ -297,11 +303,44 @@ int fr_make_psf_kernel(fr_plan *pl, const void *weight, double eps_noise, fr_psf
     p->ny = pl->ny;
     p->n_chan = pl->n_chan;
     p->fp64 = pl->fp64;
+    p->px = 2 * pl->nx;
+    p->py = 2 * pl->ny;
     if (pl->fp64)
         make_psf<double>(pl, (const double *)weight, eps_noise, p.get(), as_stream(stream));
     else
         make_psf<float>(pl, (const float *)weight, eps_noise, p.get(), as_stream(stream));
     *out = p.release();
+    FR_API_END
+}
+
+int fr_psf_reduce(const fr_psf *psf, int64_t hx, int64_t hy, fr_psf **out, void *stream) {
+    FR_API_BEGIN
+    FR_REQUIRE(psf && out, "psf and out are required");
+    *out = nullptr;
+    FR_REQUIRE(psf->px == 2 * psf->nx && psf->py == 2 * psf->ny, "psf must carry the full doubled-grid kernel");
+    FR_REQUIRE(hx >= 0 && hx < psf->nx && hy >= 0 && hy < psf->ny, "support must satisfy 0 <= h < n per axis");
+    DeviceGuard dg(psf->ctx->device);
+    auto p = std::make_unique<fr_psf>();
+    p->ctx = psf->ctx;
+    p->nx = psf->nx;
+    p->ny = psf->ny;
+    p->n_chan = psf->n_chan;
+    p->fp64 = psf->fp64;
+    p->px = reduced_pad(psf->nx + hx);
+    p->py = reduced_pad(psf->ny + hy);
+    if (psf->fp64)
+        reduce_psf<double>(psf, hx, hy, p.get(), as_stream(stream));
+    else
+        reduce_psf<float>(psf, hx, hy, p.get(), as_stream(stream));
+    *out = p.release();
+    FR_API_END
+}
+
+int fr_psf_get_padding(const fr_psf *psf, int64_t *px, int64_t *py) {
+    FR_API_BEGIN
+    FR_REQUIRE(psf && px && py, "psf, px and py are required");
+    *px = psf->px;
+    *py = psf->py;
     FR_API_END
 }
 
@@ -377,7 +416,8 @@ int fr_query_footprint(const fr_plan *pl, const fr_psf *psf, int op, int64_t B, 
     const size_t rs = fp64 ? 8 : 4, cs = 2 * rs;
     const int64_t nx = pl ? pl->nx : psf->nx, ny = pl ? pl->ny : psf->ny, nc = pl ? pl->n_chan : psf->n_chan;
     const size_t img = (size_t)nc * nx * ny;
-    const size_t conv = img * cs;  // packed half-spectrum of one image (doubled grid: 2x rows, half width)
+    // packed half-spectrum rows of one image: nx rows of py/2 (at most ny) values
+    const size_t conv = (size_t)nc * nx * (psf ? psf->py / 2 : ny) * cs;
     const size_t red = (size_t)std::max<int64_t>(B, 1) * 64 * sizeof(double);
     size_t s = 0;
     switch (op) {

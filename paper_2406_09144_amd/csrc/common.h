@@ -68,15 +68,25 @@ __device__ __forceinline__ void sincos_cycles(double x, double *s, double *c) { 
 
 // ----------------------------------------------------------------- context
 constexpr int kMaxLog2FFT = 14;  // FFT lengths 2 .. 16384
+constexpr int kMaxLog2Odd = 13;  // tables of lengths 3 2^p and 5 2^p, p <= 13
 
 struct Ctx {
     void *owner = nullptr;  // the fr_ctx holding this context
     int device = 0;
     int n_cu = 0;
-    // twiddle tables tw[m] = exp(-2 pi i m / L), m < L, per log2 L, per precision
+    // twiddle tables tw[m] = exp(-2 pi i m / L), m < L, per log2 L, per precision;
+    // tw*o[0] for L = 3 2^p, tw*o[1] for L = 5 2^p
     void *tw32[kMaxLog2FFT + 2] = {};
     void *tw64[kMaxLog2FFT + 2] = {};
+    void *tw32o[2][kMaxLog2Odd + 1] = {};
+    void *tw64o[2][kMaxLog2Odd + 1] = {};
     template <typename T> const c2<T> *tw(int log2L) const;
+    // table of L = odd 2^log2P, odd in {1, 3, 5}
+    template <typename T> const c2<T> *tw(int odd, int log2P) const {
+        if (odd == 1) return tw<T>(log2P);
+        void *const(*t)[kMaxLog2Odd + 1] = sizeof(T) == 8 ? tw64o : tw32o;
+        return (const c2<T> *)t[odd == 3 ? 0 : 1][log2P];
+    }
 };
 template <> inline const float2 *Ctx::tw<float>(int l) const { return (const float2 *)tw32[l]; }
 template <> inline const double2 *Ctx::tw<double>(int l) const { return (const double2 *)tw64[l]; }
@@ -87,6 +97,31 @@ inline int ilog2(int64_t n) {
     return l;
 }
 inline bool is_pow2(int64_t n) { return n > 0 && (n & (n - 1)) == 0; }
+
+// Host side: n = odd 2^log2P with odd in {1, 3, 5}; false for other lengths.
+inline bool split_len(int64_t n, int *odd, int *log2P) {
+    if (n <= 0) return false;
+    int o = 1;
+    if (n % 3 == 0) o = 3;
+    else if (n % 5 == 0) o = 5;
+    const int64_t p = n / o;
+    if (p & (p - 1)) return false;
+    int l = 0;
+    while ((int64_t(1) << l) < p) ++l;
+    *odd = o;
+    *log2P = l;
+    return true;
+}
+
+// f(std::integral_constant<int, ODD>{}) for a runtime odd factor in {1, 3, 5}
+template <class F> inline void with_odd(int odd, F &&f) {
+    switch (odd) {
+        case 1: f(std::integral_constant<int, 1>{}); break;
+        case 3: f(std::integral_constant<int, 3>{}); break;
+        case 5: f(std::integral_constant<int, 5>{}); break;
+        default: throw Error(FR_EINVAL, "line lengths must be 2^p, 3 2^p or 5 2^p");
+    }
+}
 
 // Scratch memory of library calls on one stream, kept from call to call: a stack
 // of device chunks that only grows (a chunk is added when a request does not fit;

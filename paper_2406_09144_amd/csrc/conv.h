@@ -25,22 +25,22 @@
 namespace frmi {
 
 // ------------------------------------------------------------------ pass 1
-template <typename T, int NTHR, int BPT, bool TWL, class Pro>
+template <typename T, int NTHR, int BPT, bool TWL, class Pro, int ODD = 1>
 __global__ __launch_bounds__(NTHR) void k_rfft_rows(Pro pro, c2<T> *__restrict__ Y, int64_t nrows,
                                                      int log2M, int n_in, int lines_per_wg,
                                                      const c2<T> *__restrict__ tw,
                                                      const c2<T> *__restrict__ tw2) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     c2<T> *buf = reinterpret_cast<c2<T> *>(smem_raw);
-    const int M = 1 << log2M;
+    const int M = ODD << log2M;
     const int64_t row0 = (int64_t)blockIdx.x * lines_per_wg;
     const int nl = (int)min<int64_t>(lines_per_wg, nrows - row0);
     const int ld = plen(M);
     const c2<T> *twp = stage_twiddles<T, NTHR, TWL>(buf + lines_per_wg * ld, tw, M);
     staged_copy<NTHR>(
-        nl << log2M,
+        nl * M,
         [&](int idx) {
-            const int c = idx >> log2M, e = idx & (M - 1);
+            const int c = line_of<ODD>(idx, log2M), e = elem_of<ODD>(idx, c, M);
             c2<T> z = mk<T>(T(0), T(0));
             if (2 * e < n_in) {
                 z.x = pro(row0 + c, 2 * e);
@@ -48,9 +48,12 @@ __global__ __launch_bounds__(NTHR) void k_rfft_rows(Pro pro, c2<T> *__restrict__
             }
             return z;
         },
-        [&](int idx, c2<T> v) { buf[(idx >> log2M) * ld + padx(idx & (M - 1))] = v; });
+        [&](int idx, c2<T> v) {
+            const int c = line_of<ODD>(idx, log2M);
+            buf[c * ld + padx(elem_of<ODD>(idx, c, M))] = v;
+        });
     __syncthreads();
-    lds_fft<T, NTHR, BPT>(buf, ld, nl, log2M, -1, twp);
+    lds_fft<T, NTHR, BPT, ODD>(buf, ld, nl, log2M, -1, twp);
     const int half = M / 2 + 1;
     for (int c = 0; c < nl; ++c)
     for (int k = threadIdx.x; k < half; k += NTHR) {
@@ -68,47 +71,49 @@ __global__ __launch_bounds__(NTHR) void k_rfft_rows(Pro pro, c2<T> *__restrict__
         }
     }
     __syncthreads();
-    for (int idx = threadIdx.x; idx < (nl << log2M); idx += NTHR)
-        Y[(row0 << log2M) + idx] = buf[(idx >> log2M) * ld + padx(idx & (M - 1))];
+    for (int idx = threadIdx.x; idx < nl * M; idx += NTHR) {
+        const int c = line_of<ODD>(idx, log2M);
+        Y[row0 * M + idx] = buf[c * ld + padx(elem_of<ODD>(idx, c, M))];
+    }
 }
 
 // ------------------------------------------------------------------ pass 2
 // K: [nk][Lc][M + 1] real, image g uses kernel g % nk.  mode 0: multiply, 1: divide.
-template <typename T, int NTHR, int BPT, bool TWL>
-__global__ __launch_bounds__(NTHR) void k_conv_cols(c2<T> *__restrict__ Y, int log2M, int log2Lc,
+// M: packed row width; Lc = ODD 2^log2Lc.
+template <typename T, int NTHR, int BPT, bool TWL, int ODD = 1>
+__global__ __launch_bounds__(NTHR) void k_conv_cols(c2<T> *__restrict__ Y, int M, int log2Lc,
                                                      int n_in, int n_out, int C,
                                                      const T *__restrict__ K, int nk, int mode,
                                                      T scale, const c2<T> *__restrict__ tw) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     c2<T> *buf = reinterpret_cast<c2<T> *>(smem_raw);
-    const int M = 1 << log2M;
-    const int Lc = 1 << log2Lc;
+    const int Lc = ODD << log2Lc;
     const int ld = plen(Lc) + 1;
     const int col0 = blockIdx.x * C;
     const int64_t g = blockIdx.y;
     const int log2C = 31 - __builtin_clz(C);  // strips are a power of two wide
-    c2<T> *Yg = Y + ((g * n_in) << log2M);  // packed rows of image g (n_in rows stored)
+    c2<T> *Yg = Y + g * n_in * (int64_t)M;  // packed rows of image g (n_in rows stored)
     const T *Kg = K + (g % nk) * (int64_t)Lc * (M + 1);
     const c2<T> *twp = stage_twiddles<T, NTHR, TWL>(buf + C * ld, tw, Lc);
     staged_copy<NTHR>(
         C * Lc,
         [&](int idx) {
             const int r = idx >> log2C, c = idx & (C - 1);
-            return (r < n_in) ? Yg[((int64_t)r << log2M) + col0 + c] : mk<T>(T(0), T(0));
+            return (r < n_in) ? Yg[(int64_t)r * M + col0 + c] : mk<T>(T(0), T(0));
         },
         [&](int idx, c2<T> v) {
             const int r = idx >> log2C, c = idx & (C - 1);
             buf[c * ld + padx(r)] = v;
         });
     __syncthreads();
-    lds_fft<T, NTHR, BPT>(buf, ld, C, log2Lc, -1, twp);
+    lds_fft<T, NTHR, BPT, ODD>(buf, ld, C, log2Lc, -1, twp);
     for (int idx = threadIdx.x; idx < C * Lc; idx += NTHR) {
-        const int c = idx >> log2Lc, k = idx & (Lc - 1);
+        const int c = line_of<ODD>(idx, log2Lc), k = elem_of<ODD>(idx, c, Lc);
         const int col = col0 + c;
         if (col == 0) {
             // slot 0 = DC column + i * Nyquist column: split, scale each, recombine
             if (k <= Lc / 2) {
-                const int km = (Lc - k) & (Lc - 1);
+                const int km = k ? Lc - k : 0;
                 c2<T> a = buf[padx(k)], b = buf[padx(km)];
                 // A = (F[k] + conj F[-k]) / 2,  Bn = (F[k] - conj F[-k]) / 2i
                 c2<T> A = mk<T>((a.x + b.x) * T(0.5), (a.y - b.y) * T(0.5));
@@ -129,29 +134,32 @@ __global__ __launch_bounds__(NTHR) void k_conv_cols(c2<T> *__restrict__ Y, int l
         }
     }
     __syncthreads();
-    lds_fft<T, NTHR, BPT>(buf, ld, C, log2Lc, +1, twp);
+    lds_fft<T, NTHR, BPT, ODD>(buf, ld, C, log2Lc, +1, twp);
     for (int idx = threadIdx.x; idx < C * n_out; idx += NTHR) {
         const int r = idx >> log2C, c = idx & (C - 1);
-        Yg[((int64_t)r << log2M) + col0 + c] = buf[c * ld + padx(r)];
+        Yg[(int64_t)r * M + col0 + c] = buf[c * ld + padx(r)];
     }
 }
 
 // ------------------------------------------------------------------ pass 3
-template <typename T, int NTHR, int BPT, bool TWL, class Epi>
+template <typename T, int NTHR, int BPT, bool TWL, class Epi, int ODD = 1>
 __global__ __launch_bounds__(NTHR) void k_irfft_rows(Epi epi, const c2<T> *__restrict__ Y, int64_t nrows,
                                                       int log2M, int n_out_cols, int lines_per_wg,
                                                       const c2<T> *__restrict__ tw,
                                                       const c2<T> *__restrict__ tw2) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     c2<T> *buf = reinterpret_cast<c2<T> *>(smem_raw);
-    const int M = 1 << log2M;
+    const int M = ODD << log2M;
     const int64_t row0 = (int64_t)blockIdx.x * lines_per_wg;
     const int nl = (int)min<int64_t>(lines_per_wg, nrows - row0);
     const int ld = plen(M);
     const c2<T> *twp = stage_twiddles<T, NTHR, TWL>(buf + lines_per_wg * ld, tw, M);
     staged_copy<NTHR>(
-        nl << log2M, [&](int idx) { return Y[(row0 << log2M) + idx]; },
-        [&](int idx, c2<T> v) { buf[(idx >> log2M) * ld + padx(idx & (M - 1))] = v; });
+        nl * M, [&](int idx) { return Y[row0 * M + idx]; },
+        [&](int idx, c2<T> v) {
+            const int c = line_of<ODD>(idx, log2M);
+            buf[c * ld + padx(elem_of<ODD>(idx, c, M))] = v;
+        });
     __syncthreads();
     const int half = M / 2 + 1;
     for (int c = 0; c < nl; ++c)
@@ -175,7 +183,7 @@ __global__ __launch_bounds__(NTHR) void k_irfft_rows(Epi epi, const c2<T> *__res
         }
     }
     __syncthreads();
-    lds_fft<T, NTHR, BPT>(buf, ld, nl, log2M, +1, twp);
+    lds_fft<T, NTHR, BPT, ODD>(buf, ld, nl, log2M, +1, twp);
     const int npair = n_out_cols / 2;
     for (int c = 0; c < nl; ++c)
         for (int e = threadIdx.x; e < npair; e += NTHR) {
@@ -191,46 +199,55 @@ struct ConvGeom {
     int rows_out;    // rows kept after the column pass and written by pass 3
     int n_in_cols;   // non-zero real columns per row (<= 2M)
     int n_out_cols;  // real columns kept by pass 3
-    int log2M;       // packed width
-    int log2Lc;      // column FFT length
+    int log2M;       // packed width M = odd_M 2^log2M
+    int log2Lc;      // column FFT length Lc = odd_Lc 2^log2Lc
+    int odd_M = 1, odd_Lc = 1;  // odd factors (1, 3 or 5) of M and Lc
+    int M() const { return odd_M << log2M; }
+    int Lc() const { return odd_Lc << log2Lc; }
 };
 
 template <typename T> inline int max_line_elems() { return kLdsBytes / (int)sizeof(c2<T>); }
 
-template <typename T, class Pro>
+// ODD must equal g.odd_M
+template <typename T, int ODD = 1, class Pro>
 void launch_rfft_rows(const Ctx &ctx, const ConvGeom &g, Pro pro, c2<T> *Y, hipStream_t st) {
-    const int M = 1 << g.log2M;
+    FR_REQUIRE(g.odd_M == ODD, "row length and kernel variant disagree");
+    const int M = g.M();
     const int64_t nrows = g.n_img * g.rows_in;
     FR_REQUIRE(plen(M) <= max_line_elems<T>() && M <= 16384, "row length too large for LDS");
     const size_t line = (size_t)plen(M) * sizeof(c2<T>);
     const size_t twb = (size_t)M * sizeof(c2<T>);
+    const c2<T> *tw = ctx.tw<T>(ODD, g.log2M), *tw2 = ctx.tw<T>(ODD, g.log2M + 1);
     if (M <= 4096) {
         const int lpw = rows_per_wg(M, nrows, ctx.n_cu);
         const int64_t nblk = (nrows + lpw - 1) / lpw;
-        allow_lds(k_rfft_rows<T, 256, 4, true, Pro>, lpw * line + twb);
-        k_rfft_rows<T, 256, 4, true, Pro><<<dim3((unsigned)nblk), 256, lpw * line + twb, st>>>(
-            pro, Y, nrows, g.log2M, g.n_in_cols, lpw, ctx.tw<T>(g.log2M), ctx.tw<T>(g.log2M + 1));
+        allow_lds(k_rfft_rows<T, 256, 4, true, Pro, ODD>, lpw * line + twb);
+        k_rfft_rows<T, 256, 4, true, Pro, ODD><<<dim3((unsigned)nblk), 256, lpw * line + twb, st>>>(
+            pro, Y, nrows, g.log2M, g.n_in_cols, lpw, tw, tw2);
     } else if (line + twb <= (size_t)kLdsBytes) {
-        allow_lds(k_rfft_rows<T, 1024, 4, true, Pro>, line + twb);
-        k_rfft_rows<T, 1024, 4, true, Pro><<<dim3((unsigned)nrows), 1024, line + twb, st>>>(
-            pro, Y, nrows, g.log2M, g.n_in_cols, 1, ctx.tw<T>(g.log2M), ctx.tw<T>(g.log2M + 1));
+        allow_lds(k_rfft_rows<T, 1024, 4, true, Pro, ODD>, line + twb);
+        k_rfft_rows<T, 1024, 4, true, Pro, ODD><<<dim3((unsigned)nrows), 1024, line + twb, st>>>(
+            pro, Y, nrows, g.log2M, g.n_in_cols, 1, tw, tw2);
     } else {
-        allow_lds(k_rfft_rows<T, 1024, 4, false, Pro>, line);
-        k_rfft_rows<T, 1024, 4, false, Pro><<<dim3((unsigned)nrows), 1024, line, st>>>(
-            pro, Y, nrows, g.log2M, g.n_in_cols, 1, ctx.tw<T>(g.log2M), ctx.tw<T>(g.log2M + 1));
+        allow_lds(k_rfft_rows<T, 1024, 4, false, Pro, ODD>, line);
+        k_rfft_rows<T, 1024, 4, false, Pro, ODD><<<dim3((unsigned)nrows), 1024, line, st>>>(
+            pro, Y, nrows, g.log2M, g.n_in_cols, 1, tw, tw2);
     }
     LAUNCH_CHECK();
 }
 
-template <typename T>
+// ODD must equal g.odd_Lc
+template <typename T, int ODD = 1>
 void launch_conv_cols(const Ctx &ctx, const ConvGeom &g, c2<T> *Y, const T *K, int nk, int mode, T scale,
                       hipStream_t st) {
-    const int M = 1 << g.log2M;
-    const int Lc = 1 << g.log2Lc;
+    FR_REQUIRE(g.odd_Lc == ODD, "column length and kernel variant disagree");
+    const int M = g.M();
+    const int Lc = g.Lc();
     const int budget = 65536 / (int)sizeof(c2<T>);  // <= 64 KiB: two workgroups per CU
-    int C = std::max(1, std::min(16, budget / Lc));
+    const int cap = std::max(1, std::min(16, budget / Lc));
+    int C = 1;
+    while (2 * C <= cap) C *= 2;
     while (C > 1 && (M % C)) C >>= 1;
-    C = std::min(C, M);
     // small batches: narrower strips so the grid still covers every CU a few times
     while (C > 2 && (int64_t)(M / C) * g.n_img < 2 * (int64_t)std::max(ctx.n_cu, 1)) C >>= 1;
     FR_REQUIRE((int64_t)C * (plen(Lc) + 1) <= max_line_elems<T>(), "column length too large for LDS");
@@ -240,11 +257,11 @@ void launch_conv_cols(const Ctx &ctx, const ConvGeom &g, c2<T> *Y, const T *K, i
     FR_REQUIRE(g.rows_in == g.rows_out, "column pass works in place");
     const bool twl = lds + (size_t)Lc * sizeof(c2<T>) <= (size_t)kLdsBytes;
     const size_t ldst = twl ? lds + (size_t)Lc * sizeof(c2<T>) : lds;
-#define FR_CONVCOLS(NT, TW)                                                                                 \
-    do {                                                                                                    \
-        allow_lds(k_conv_cols<T, NT, 4, TW>, ldst);                                                         \
-        k_conv_cols<T, NT, 4, TW><<<grid, NT, ldst, st>>>(Y, g.log2M, g.log2Lc, g.rows_in, g.rows_out, C, K, \
-                                                          nk, mode, scale, ctx.tw<T>(g.log2Lc));            \
+#define FR_CONVCOLS(NT, TW)                                                                              \
+    do {                                                                                                 \
+        allow_lds(k_conv_cols<T, NT, 4, TW, ODD>, ldst);                                                 \
+        k_conv_cols<T, NT, 4, TW, ODD><<<grid, NT, ldst, st>>>(Y, M, g.log2Lc, g.rows_in, g.rows_out, C, \
+                                                               K, nk, mode, scale, ctx.tw<T>(ODD, g.log2Lc)); \
     } while (0)
     // four radix-4 butterflies per thread
     if (C * Lc <= 4096) {
@@ -261,26 +278,29 @@ void launch_conv_cols(const Ctx &ctx, const ConvGeom &g, c2<T> *Y, const T *K, i
     LAUNCH_CHECK();
 }
 
-template <typename T, class Epi>
+// ODD must equal g.odd_M
+template <typename T, int ODD = 1, class Epi>
 void launch_irfft_rows(const Ctx &ctx, const ConvGeom &g, Epi epi, const c2<T> *Y, hipStream_t st) {
-    const int M = 1 << g.log2M;
+    FR_REQUIRE(g.odd_M == ODD, "row length and kernel variant disagree");
+    const int M = g.M();
     const int64_t nrows = g.n_img * g.rows_out;
     const size_t line = (size_t)plen(M) * sizeof(c2<T>);
     const size_t twb = (size_t)M * sizeof(c2<T>);
+    const c2<T> *tw = ctx.tw<T>(ODD, g.log2M), *tw2 = ctx.tw<T>(ODD, g.log2M + 1);
     if (M <= 4096) {
         const int lpw = rows_per_wg(M, nrows, ctx.n_cu);
         const int64_t nblk = (nrows + lpw - 1) / lpw;
-        allow_lds(k_irfft_rows<T, 256, 4, true, Epi>, lpw * line + twb);
-        k_irfft_rows<T, 256, 4, true, Epi><<<dim3((unsigned)nblk), 256, lpw * line + twb, st>>>(
-            epi, Y, nrows, g.log2M, g.n_out_cols, lpw, ctx.tw<T>(g.log2M), ctx.tw<T>(g.log2M + 1));
+        allow_lds(k_irfft_rows<T, 256, 4, true, Epi, ODD>, lpw * line + twb);
+        k_irfft_rows<T, 256, 4, true, Epi, ODD><<<dim3((unsigned)nblk), 256, lpw * line + twb, st>>>(
+            epi, Y, nrows, g.log2M, g.n_out_cols, lpw, tw, tw2);
     } else if (line + twb <= (size_t)kLdsBytes) {
-        allow_lds(k_irfft_rows<T, 1024, 4, true, Epi>, line + twb);
-        k_irfft_rows<T, 1024, 4, true, Epi><<<dim3((unsigned)nrows), 1024, line + twb, st>>>(
-            epi, Y, nrows, g.log2M, g.n_out_cols, 1, ctx.tw<T>(g.log2M), ctx.tw<T>(g.log2M + 1));
+        allow_lds(k_irfft_rows<T, 1024, 4, true, Epi, ODD>, line + twb);
+        k_irfft_rows<T, 1024, 4, true, Epi, ODD><<<dim3((unsigned)nrows), 1024, line + twb, st>>>(
+            epi, Y, nrows, g.log2M, g.n_out_cols, 1, tw, tw2);
     } else {
-        allow_lds(k_irfft_rows<T, 1024, 4, false, Epi>, line);
-        k_irfft_rows<T, 1024, 4, false, Epi><<<dim3((unsigned)nrows), 1024, line, st>>>(
-            epi, Y, nrows, g.log2M, g.n_out_cols, 1, ctx.tw<T>(g.log2M), ctx.tw<T>(g.log2M + 1));
+        allow_lds(k_irfft_rows<T, 1024, 4, false, Epi, ODD>, line);
+        k_irfft_rows<T, 1024, 4, false, Epi, ODD><<<dim3((unsigned)nrows), 1024, line, st>>>(
+            epi, Y, nrows, g.log2M, g.n_out_cols, 1, tw, tw2);
     }
     LAUNCH_CHECK();
 }

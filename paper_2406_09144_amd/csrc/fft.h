@@ -1,6 +1,6 @@
-// Radix-4/2 Stockham FFT on LDS-resident lines, shared by every transform in the
-// library (uv-grid FFTs of the gridder, the zero-padded PSF convolution, the
-// periodic noise and prior convolutions).
+// Stockham FFT on LDS-resident lines, shared by every transform in the library
+// (uv-grid FFTs of the gridder, the zero-padded PSF convolution, the periodic
+// noise and prior convolutions).
 //
 // Method: the self-sorting Stockham formulation (natural-order output without a
 // bit-reversal pass) of Govindaraju et al., "High performance discrete Fourier
@@ -10,6 +10,12 @@
 // applies the R-point DFT, and writes y[(j / Ns) Ns R + k + r Ns] = v_r.
 // Lines live in LDS; each butterfly keeps its R values in registers between the
 // read and the write barrier, so a stage is in place.
+//
+// Lengths are L = ODD 2^p with ODD in {1, 3, 5}: radix-16, 4 and 2 stages take
+// the power of two, then one radix-ODD stage (Ns = 2^p) the odd factor, so Ns
+// stays a power of two throughout and only the butterfly-to-line split divides
+// by ODD.  The odd lengths serve the reduced zero padding of the PSF
+// convolution (n + h instead of 2n).
 //
 // Twiddles come from a per-length table tw[m] = exp(-2 pi i m / L) built in FP64
 // on the host and rounded once to the working precision.
@@ -85,24 +91,72 @@ __device__ __forceinline__ void dft16(c2<T> (&v)[16], int sign) {
     }
 }
 
+// 3-point DFT: w = exp(sign 2 pi i / 3) = -1/2 + sign i sqrt(3)/2, so
+//   X1, X2 = a - (b + c)/2 +- sign i (sqrt(3)/2)(b - c)
+template <typename T>
+__device__ __forceinline__ void dft3(c2<T> (&v)[3], int sign) {
+    constexpr double h3 = 0.86602540378443864676;  // sqrt(3) / 2
+    const c2<T> s = cadd<T>(v[1], v[2]);
+    const c2<T> m = mk<T>(v[0].x - T(0.5) * s.x, v[0].y - T(0.5) * s.y);
+    const c2<T> d = mul_i_sign<T>(cscale<T>(csub<T>(v[1], v[2]), T(h3)), sign);
+    v[0] = cadd<T>(v[0], s);
+    v[1] = cadd<T>(m, d);
+    v[2] = csub<T>(m, d);
+}
+
+// 5-point DFT from the pairs A_r = x_r + x_{5-r}, B_r = x_r - x_{5-r} (r = 1, 2):
+//   X1, X4 = x0 + c1 A1 + c2 A2 +- sign i (s1 B1 + s2 B2)
+//   X2, X3 = x0 + c2 A1 + c1 A2 +- sign i (s2 B1 - s1 B2)
+// with c_r = cos(2 pi r / 5), s_r = sin(2 pi r / 5).
+template <typename T>
+__device__ __forceinline__ void dft5(c2<T> (&v)[5], int sign) {
+    constexpr double c1 = 0.30901699437494742410, c2_ = -0.80901699437494742410;
+    constexpr double s1 = 0.95105651629515357212, s2 = 0.58778525229247312917;
+    const c2<T> A1 = cadd<T>(v[1], v[4]), B1 = csub<T>(v[1], v[4]);
+    const c2<T> A2 = cadd<T>(v[2], v[3]), B2 = csub<T>(v[2], v[3]);
+    const c2<T> e1 = mk<T>(v[0].x + T(c1) * A1.x + T(c2_) * A2.x, v[0].y + T(c1) * A1.y + T(c2_) * A2.y);
+    const c2<T> e2 = mk<T>(v[0].x + T(c2_) * A1.x + T(c1) * A2.x, v[0].y + T(c2_) * A1.y + T(c1) * A2.y);
+    const c2<T> o1 = mul_i_sign<T>(mk<T>(T(s1) * B1.x + T(s2) * B2.x, T(s1) * B1.y + T(s2) * B2.y), sign);
+    const c2<T> o2 = mul_i_sign<T>(mk<T>(T(s2) * B1.x - T(s1) * B2.x, T(s2) * B1.y - T(s1) * B2.y), sign);
+    v[0] = cadd<T>(v[0], cadd<T>(A1, A2));
+    v[1] = cadd<T>(e1, o1);
+    v[4] = csub<T>(e1, o1);
+    v[2] = cadd<T>(e2, o2);
+    v[3] = csub<T>(e2, o2);
+}
+
 template <typename T, int R>
 __device__ __forceinline__ void dftR(c2<T> (&v)[R], int sign) {
     if constexpr (R == 2) dft2<T>(v);
+    else if constexpr (R == 3) dft3<T>(v, sign);
     else if constexpr (R == 4) dft4<T>(v, sign);
+    else if constexpr (R == 5) dft5<T>(v, sign);
     else dft16<T>(v, sign);
 }
 
-// One Stockham stage over `nlines` lines of length 2^log2L spaced `ld` apart.
+// x / ODD for x >= 0 (a multiply-high for ODD = 3, 5; nothing for ODD = 1)
+template <int ODD> __device__ __forceinline__ int div_odd(int x) {
+    if constexpr (ODD == 1) return x;
+    else return (int)((unsigned)x / (unsigned)ODD);
+}
+
+// One Stockham stage over `nlines` lines of length L = ODD 2^log2P spaced `ld`
+// apart.  R is 16, 4 or 2 (a power-of-two stage, Ns = 2^log2Ns) or R = ODD (the
+// final odd stage, Ns = 2^log2P).
 // BPT: butterflies per thread this launch can need (host-checked).
-template <typename T, int R, int NTHR, int BPT>
-__device__ __forceinline__ void stockham_stage(c2<T> *buf, int ld, int nlines, int log2L, int log2Ns,
+template <typename T, int R, int NTHR, int BPT, int ODD>
+__device__ __forceinline__ void stockham_stage(c2<T> *buf, int ld, int nlines, int log2P, int log2Ns,
                                                int sign, const c2<T> *__restrict__ tw) {
-    constexpr int LOG2R = (R == 2) ? 1 : (R == 4) ? 2 : 4;
-    const int log2Q = log2L - LOG2R;
-    const int Q = 1 << log2Q;
-    const int nb = nlines << log2Q;
+    constexpr bool kOddStage = (R == 3 || R == 5);
+    static_assert(!kOddStage || R == ODD, "the odd stage takes the odd factor of the length");
+    constexpr int LOG2R = kOddStage ? 0 : (R == 2) ? 1 : (R == 4) ? 2 : 4;
+    // Q = L / R butterflies per line: QODD 2^log2Qp; twiddle stride L / (Ns R) = QODD 2^twshift
+    constexpr int QODD = kOddStage ? 1 : ODD;
+    const int log2Qp = log2P - LOG2R;
+    const int Q = QODD << log2Qp;
+    const int nb = nlines * Q;
     const int Ns = 1 << log2Ns;
-    const int twshift = log2L - log2Ns - LOG2R;
+    const int twshift = log2P - log2Ns - LOG2R;
     c2<T> v[BPT][R];
     int obase[BPT];
 #pragma unroll
@@ -110,8 +164,8 @@ __device__ __forceinline__ void stockham_stage(c2<T> *buf, int ld, int nlines, i
         const int f = threadIdx.x + b * NTHR;
         obase[b] = -1;
         if (f < nb) {
-            const int line = f >> log2Q;
-            const int j = f & (Q - 1);
+            const int line = div_odd<QODD>(f >> log2Qp);
+            const int j = (QODD == 1) ? (f & (Q - 1)) : f - line * Q;
             const int k = j & (Ns - 1);
             const c2<T> *p = buf + line * ld;
 #pragma unroll
@@ -119,7 +173,7 @@ __device__ __forceinline__ void stockham_stage(c2<T> *buf, int ld, int nlines, i
             if (log2Ns > 0) {
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
-                    c2<T> w = tw[(r * k) << twshift];
+                    c2<T> w = tw[(r * k * QODD) << twshift];
                     if (sign > 0) w.y = -w.y;
                     v[b][r] = cmul<T>(v[b][r], w);
                 }
@@ -141,26 +195,35 @@ __device__ __forceinline__ void stockham_stage(c2<T> *buf, int ld, int nlines, i
     __syncthreads();
 }
 
-// Full in-place FFT of `nlines` LDS lines (length 2^log2L <= 16384, stride ld >=
-// plen(2^log2L), element e at padx(e); nlines < 32768).  Caller
-// must __syncthreads() after filling the lines; returns after a barrier.
-// Requires nlines * 2^log2L <= 4 * BPT * NTHR.
-template <typename T, int NTHR, int BPT>
-__device__ __forceinline__ void lds_fft(c2<T> *buf, int ld, int nlines, int log2L, int sign,
+// Full in-place FFT of `nlines` LDS lines (length L = ODD 2^log2P <= 16384,
+// stride ld >= plen(L), element e at padx(e); nlines < 32768).  Caller must
+// __syncthreads() after filling the lines; returns after a barrier.
+// Requires nlines * L <= 4 * BPT * NTHR.
+template <typename T, int NTHR, int BPT, int ODD = 1>
+__device__ __forceinline__ void lds_fft(c2<T> *buf, int ld, int nlines, int log2P, int sign,
                                         const c2<T> *__restrict__ tw) {
+    static_assert(ODD == 1 || ODD == 3 || ODD == 5, "line lengths are 2^p, 3 2^p or 5 2^p");
     // radix-16 stages (two radix-4 levels in registers, half the LDS passes),
-    // then radix 4 and 2 for the remaining factor
+    // then radix 4 and 2 for the remaining power of two, then the odd factor
     constexpr int BPT16 = BPT / 4 > 0 ? BPT / 4 : 1;
     int log2Ns = 0;
-    while (log2L - log2Ns >= 4) {
-        stockham_stage<T, 16, NTHR, BPT16>(buf, ld, nlines, log2L, log2Ns, sign, tw);
+    while (log2P - log2Ns >= 4) {
+        stockham_stage<T, 16, NTHR, BPT16, ODD>(buf, ld, nlines, log2P, log2Ns, sign, tw);
         log2Ns += 4;
     }
-    if (log2L - log2Ns >= 2) {
-        stockham_stage<T, 4, NTHR, BPT>(buf, ld, nlines, log2L, log2Ns, sign, tw);
+    if (log2P - log2Ns >= 2) {
+        stockham_stage<T, 4, NTHR, BPT, ODD>(buf, ld, nlines, log2P, log2Ns, sign, tw);
         log2Ns += 2;
     }
-    if (log2L - log2Ns == 1) stockham_stage<T, 2, NTHR, 2 * BPT>(buf, ld, nlines, log2L, log2Ns, sign, tw);
+    if (log2P - log2Ns == 1) stockham_stage<T, 2, NTHR, 2 * BPT, ODD>(buf, ld, nlines, log2P, log2Ns, sign, tw);
+    if constexpr (ODD > 1)
+        stockham_stage<T, ODD, NTHR, (4 * BPT + ODD - 1) / ODD, ODD>(buf, ld, nlines, log2P, log2P, sign, tw);
+}
+
+// Element idx of a batch of lines of length L = ODD 2^log2P: line idx / L, element idx % L.
+template <int ODD> __device__ __forceinline__ int line_of(int idx, int log2P) { return div_odd<ODD>(idx >> log2P); }
+template <int ODD> __device__ __forceinline__ int elem_of(int idx, int line, int L) {
+    return (ODD == 1) ? (idx & (L - 1)) : idx - line * L;
 }
 
 // store(idx, load(idx)) for idx = threadIdx.x, threadIdx.x + NTHR, ... < n, with U

@@ -14,33 +14,42 @@
 
 namespace frmi {
 
-template <typename T, int NTHR, int BPT, bool TWL, class Pro, class Epi>
-__global__ __launch_bounds__(NTHR) void k_fft_rows(Pro pro, Epi epi, int64_t nrows, int log2L,
+template <typename T, int NTHR, int BPT, bool TWL, class Pro, class Epi, int ODD = 1>
+__global__ __launch_bounds__(NTHR) void k_fft_rows(Pro pro, Epi epi, int64_t nrows, int log2P,
                                                     int lines_per_wg, int sign,
                                                     const c2<T> *__restrict__ tw) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     c2<T> *buf = reinterpret_cast<c2<T> *>(smem_raw);
-    const int L = 1 << log2L;
+    const int L = ODD << log2P;
     const int64_t row0 = (int64_t)blockIdx.x * lines_per_wg;
     const int nl = (int)min<int64_t>(lines_per_wg, nrows - row0);
     const int ld = plen(L);
     const c2<T> *twp = stage_twiddles<T, NTHR, TWL>(buf + lines_per_wg * ld, tw, L);
     staged_copy<NTHR>(
-        nl << log2L, [&](int idx) { return pro(row0 + (idx >> log2L), idx & (L - 1)); },
-        [&](int idx, c2<T> v) { buf[(idx >> log2L) * ld + padx(idx & (L - 1))] = v; });
+        nl * L,
+        [&](int idx) {
+            const int c = line_of<ODD>(idx, log2P);
+            return pro(row0 + c, elem_of<ODD>(idx, c, L));
+        },
+        [&](int idx, c2<T> v) {
+            const int c = line_of<ODD>(idx, log2P);
+            buf[c * ld + padx(elem_of<ODD>(idx, c, L))] = v;
+        });
     __syncthreads();
-    lds_fft<T, NTHR, BPT>(buf, ld, nl, log2L, sign, twp);
-    for (int idx = threadIdx.x; idx < (nl << log2L); idx += NTHR)
-        epi(row0 + (idx >> log2L), idx & (L - 1), buf[(idx >> log2L) * ld + padx(idx & (L - 1))]);
+    lds_fft<T, NTHR, BPT, ODD>(buf, ld, nl, log2P, sign, twp);
+    for (int idx = threadIdx.x; idx < nl * L; idx += NTHR) {
+        const int c = line_of<ODD>(idx, log2P), e = elem_of<ODD>(idx, c, L);
+        epi(row0 + c, e, buf[c * ld + padx(e)]);
+    }
 }
 
-template <typename T, int NTHR, int BPT, bool TWL, class Pro, class Epi>
-__global__ __launch_bounds__(NTHR) void k_fft_cols(Pro pro, Epi epi, int ncols, int log2L, int n_in,
+template <typename T, int NTHR, int BPT, bool TWL, class Pro, class Epi, int ODD = 1>
+__global__ __launch_bounds__(NTHR) void k_fft_cols(Pro pro, Epi epi, int ncols, int log2P, int n_in,
                                                     int n_out, int C, int sign,
                                                     const c2<T> *__restrict__ tw) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     c2<T> *buf = reinterpret_cast<c2<T> *>(smem_raw);
-    const int L = 1 << log2L;
+    const int L = ODD << log2P;
     const int ld = plen(L) + 1;
     const int col0 = blockIdx.x * C;
     const int64_t m = blockIdx.y;
@@ -57,7 +66,7 @@ __global__ __launch_bounds__(NTHR) void k_fft_cols(Pro pro, Epi epi, int ncols, 
             buf[c * ld + padx(r)] = v;
         });
     __syncthreads();
-    lds_fft<T, NTHR, BPT>(buf, ld, C, log2L, sign, twp);
+    lds_fft<T, NTHR, BPT, ODD>(buf, ld, C, log2P, sign, twp);
     for (int idx = threadIdx.x; idx < C * n_out; idx += NTHR) {
         const int r = idx >> log2C, c = idx & (C - 1);
         epi(m, r, col0 + c, buf[c * ld + padx(r)]);
@@ -69,33 +78,35 @@ template <typename T> inline bool twl_fits(size_t data_bytes, int L) {
     return data_bytes + (size_t)L * sizeof(c2<T>) <= (size_t)kLdsBytes;
 }
 
-template <typename T, class Pro, class Epi>
-void launch_fft_rows(const Ctx &ctx, Pro pro, Epi epi, int64_t nrows, int log2L, int sign, hipStream_t st) {
-    const int L = 1 << log2L;
+// Row transforms of length L = ODD 2^log2P.
+template <typename T, class Pro, class Epi, int ODD = 1>
+void launch_fft_rows(const Ctx &ctx, Pro pro, Epi epi, int64_t nrows, int log2P, int sign, hipStream_t st) {
+    const int L = ODD << log2P;
     FR_REQUIRE((int64_t)plen(L) * (int64_t)sizeof(c2<T>) <= kLdsBytes && L <= 16384, "FFT length too large");
     if (nrows <= 0) return;
+    const c2<T> *tw = ctx.tw<T>(ODD, log2P);
     const size_t pline = (size_t)plen(L) * sizeof(c2<T>);
     if (L <= 4096) {
         const int lpw = rows_per_wg(L, nrows, ctx.n_cu);
         const size_t lds = (size_t)lpw * pline + (size_t)L * sizeof(c2<T>);
-        allow_lds(k_fft_rows<T, 256, 4, true, Pro, Epi>, lds);
-        k_fft_rows<T, 256, 4, true, Pro, Epi><<<dim3((unsigned)((nrows + lpw - 1) / lpw)), 256, lds, st>>>(
-            pro, epi, nrows, log2L, lpw, sign, ctx.tw<T>(log2L));
+        allow_lds(k_fft_rows<T, 256, 4, true, Pro, Epi, ODD>, lds);
+        k_fft_rows<T, 256, 4, true, Pro, Epi, ODD><<<dim3((unsigned)((nrows + lpw - 1) / lpw)), 256, lds, st>>>(
+            pro, epi, nrows, log2P, lpw, sign, tw);
     } else if (L <= 8192 && twl_fits<T>(pline, L)) {
         const size_t lds = pline + (size_t)L * sizeof(c2<T>);
-        allow_lds(k_fft_rows<T, 512, 4, true, Pro, Epi>, lds);
-        k_fft_rows<T, 512, 4, true, Pro, Epi><<<dim3((unsigned)nrows), 512, lds, st>>>(pro, epi, nrows, log2L, 1,
-                                                                                    sign, ctx.tw<T>(log2L));
+        allow_lds(k_fft_rows<T, 512, 4, true, Pro, Epi, ODD>, lds);
+        k_fft_rows<T, 512, 4, true, Pro, Epi, ODD><<<dim3((unsigned)nrows), 512, lds, st>>>(pro, epi, nrows, log2P,
+                                                                                         1, sign, tw);
     } else if (twl_fits<T>(pline, L)) {
         const size_t lds = pline + (size_t)L * sizeof(c2<T>);
-        allow_lds(k_fft_rows<T, 1024, 4, true, Pro, Epi>, lds);
-        k_fft_rows<T, 1024, 4, true, Pro, Epi><<<dim3((unsigned)nrows), 1024, lds, st>>>(pro, epi, nrows, log2L, 1,
-                                                                                      sign, ctx.tw<T>(log2L));
+        allow_lds(k_fft_rows<T, 1024, 4, true, Pro, Epi, ODD>, lds);
+        k_fft_rows<T, 1024, 4, true, Pro, Epi, ODD><<<dim3((unsigned)nrows), 1024, lds, st>>>(pro, epi, nrows, log2P,
+                                                                                           1, sign, tw);
     } else {
         const size_t lds = pline;
-        allow_lds(k_fft_rows<T, 1024, 4, false, Pro, Epi>, lds);
-        k_fft_rows<T, 1024, 4, false, Pro, Epi><<<dim3((unsigned)nrows), 1024, lds, st>>>(pro, epi, nrows, log2L, 1,
-                                                                                       sign, ctx.tw<T>(log2L));
+        allow_lds(k_fft_rows<T, 1024, 4, false, Pro, Epi, ODD>, lds);
+        k_fft_rows<T, 1024, 4, false, Pro, Epi, ODD><<<dim3((unsigned)nrows), 1024, lds, st>>>(pro, epi, nrows,
+                                                                                            log2P, 1, sign, tw);
     }
     LAUNCH_CHECK();
 }
@@ -103,15 +114,18 @@ void launch_fft_rows(const Ctx &ctx, Pro pro, Epi epi, int64_t nrows, int log2L,
 // Column strip width: as many columns as keep the LDS lines within 64 KiB (two
 // workgroups per CU), at most 16, a divisor of ncols.
 template <typename T> inline int col_strip(int L, int ncols) {
-    int C = std::max(1, std::min(16, (int)(65536 / sizeof(c2<T>)) / L));
+    const int cap = std::max(1, std::min(16, (int)(65536 / sizeof(c2<T>)) / L));
+    int C = 1;
+    while (2 * C <= cap) C *= 2;
     while (C > 1 && (ncols % C)) C >>= 1;
     return C;
 }
 
-template <typename T, class Pro, class Epi>
-void launch_fft_cols(const Ctx &ctx, Pro pro, Epi epi, int64_t nmat, int ncols, int log2L, int n_in, int n_out,
+// Column transforms of length L = ODD 2^log2P.
+template <typename T, class Pro, class Epi, int ODD = 1>
+void launch_fft_cols(const Ctx &ctx, Pro pro, Epi epi, int64_t nmat, int ncols, int log2P, int n_in, int n_out,
                      int sign, hipStream_t st) {
-    const int L = 1 << log2L;
+    const int L = ODD << log2P;
     const int C = col_strip<T>(L, ncols);
     FR_REQUIRE(is_pow2(C), "column strip width must be a power of two");
     const size_t lds = (size_t)C * (plen(L) + 1) * sizeof(c2<T>);
@@ -122,9 +136,9 @@ void launch_fft_cols(const Ctx &ctx, Pro pro, Epi epi, int64_t nmat, int ncols, 
     const size_t ldst = twl ? lds + (size_t)L * sizeof(c2<T>) : lds;
 #define FR_COLS(NT, TW)                                                                                   \
     do {                                                                                                  \
-        allow_lds(k_fft_cols<T, NT, 4, TW, Pro, Epi>, ldst);                                              \
-        k_fft_cols<T, NT, 4, TW, Pro, Epi><<<grid, NT, ldst, st>>>(pro, epi, ncols, log2L, n_in, n_out, C, \
-                                                                   sign, ctx.tw<T>(log2L));               \
+        allow_lds(k_fft_cols<T, NT, 4, TW, Pro, Epi, ODD>, ldst);                                              \
+        k_fft_cols<T, NT, 4, TW, Pro, Epi, ODD><<<grid, NT, ldst, st>>>(pro, epi, ncols, log2P, n_in, n_out, C, \
+                                                                   sign, ctx.tw<T>(ODD, log2P));               \
     } while (0)
     // four radix-4 butterflies per thread
     if (C * L <= 4096) {
@@ -156,13 +170,13 @@ template <typename T> struct MatStore {
 };
 template <typename T> struct RowLoad {
     const c2<T> *base;
-    int log2L;
-    __device__ c2<T> operator()(int64_t r, int e) const { return base[(r << log2L) + e]; }
+    int64_t L;
+    __device__ c2<T> operator()(int64_t r, int e) const { return base[r * L + e]; }
 };
 template <typename T> struct RowStore {
     c2<T> *base;
-    int log2L;
-    __device__ void operator()(int64_t r, int e, c2<T> v) const { base[(r << log2L) + e] = v; }
+    int64_t L;
+    __device__ void operator()(int64_t r, int e, c2<T> v) const { base[r * L + e] = v; }
 };
 
 }  // namespace frmi

@@ -14,7 +14,8 @@ struct fr_psf {
     frmi::Ctx *ctx = nullptr;
     int64_t nx = 0, ny = 0, n_chan = 0;
     bool fp64 = false;
-    frmi::DevBuf KR;    // [n_chan][2nx][ny + 1] real
+    int64_t px = 0, py = 0;  // periodic grid of the response kernel: 2nx x 2ny, smaller when reduced
+    frmi::DevBuf KR;    // [n_chan][px][py/2 + 1] real
     frmi::DevBuf KN;    // [n_chan][nx][ny/2 + 1] real (empty if absent)
     frmi::DevBuf nfac;  // [nx][ny] real diagonal D (empty = identity)
 };
@@ -116,5 +117,8 @@ void periodic_conv(const Ctx &ctx, const T *x, T *y, int64_t n_img, int64_t nx, 
                    int mode, hipStream_t st);
 template <typename T>
 void fft2_inplace(const Ctx &ctx, c2<T> *data, int64_t batch, int64_t n0, int64_t n1, int sign, hipStream_t st);
+template <typename T>
+void reduce_psf(const fr_psf *in, int64_t hx, int64_t hy, fr_psf *out, hipStream_t st);
+int64_t reduced_pad(int64_t n);
 
 }  // namespace frmi

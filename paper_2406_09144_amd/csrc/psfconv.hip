@@ -8,7 +8,8 @@
 namespace frmi {
 
 // y = D P^+ irfft2(K_R rfft2(P D x)): x padded into the top-left nx x ny block of
-// the 2nx x 2ny grid.  Only the nx non-zero rows are transformed along y and only
+// the px x py grid of the response kernel (2nx x 2ny, or n + h per axis for a
+// reduced support).  Only the nx non-zero rows are transformed along y and only
 // the nx wanted rows are kept after the column pass.
 // y = d_out D P^+ irfft2(K_R rfft2(P D d_in x)) + add, every extra factor optional:
 // the diagonal metric factors and the prior term of CG fused into the first and
@@ -25,21 +26,27 @@ void apply_rnr_approx_ex(const fr_psf *psf, const T *x, const T *d_in, T *y, con
     g.rows_out = (int)nx;
     g.n_in_cols = (int)ny;
     g.n_out_cols = (int)ny;
-    g.log2M = ilog2(ny);
-    g.log2Lc = ilog2(2 * nx);
-    Scratch Y((size_t)n_img * nx * ny * sizeof(c2<T>), st);
+    FR_REQUIRE(split_len(psf->py / 2, &g.odd_M, &g.log2M) && split_len(psf->px, &g.odd_Lc, &g.log2Lc),
+               "padded kernel sizes must be 2^p, 3 2^p or 5 2^p");
+    const int64_t M = g.M();
+    Scratch Y((size_t)n_img * nx * M * sizeof(c2<T>), st);
     const T *a = psf->nfac.as<T>();
-    {
+    with_odd(g.odd_M, [&](auto odd) {
         ProfScope prof("psfconv_rows_r2c", st);
-        launch_rfft_rows<T>(*psf->ctx, g, ProDiagScaled<T>{x, d_in, a, (int)nx, (int)ny}, Y.as<c2<T>>(), st);
-    }
-    const T scale = T(1) / (T(2 * nx) * T(ny));
-    {
+        launch_rfft_rows<T, decltype(odd)::value>(*psf->ctx, g, ProDiagScaled<T>{x, d_in, a, (int)nx, (int)ny},
+                                                  Y.as<c2<T>>(), st);
+    });
+    const T scale = T(1) / (T(g.Lc()) * T(M));
+    with_odd(g.odd_Lc, [&](auto odd) {
         ProfScope prof("psfconv_cols", st);
-        launch_conv_cols<T>(*psf->ctx, g, Y.as<c2<T>>(), psf->KR.as<T>(), (int)nc, 0, scale, st);
-    }
-    ProfScope prof("psfconv_rows_c2r", st);
-    launch_irfft_rows<T>(*psf->ctx, g, EpiDiagScaledAdd<T>{y, d_out, a, add, (int)nx, (int)ny}, Y.as<c2<T>>(), st);
+        launch_conv_cols<T, decltype(odd)::value>(*psf->ctx, g, Y.as<c2<T>>(), psf->KR.as<T>(), (int)nc, 0, scale,
+                                                  st);
+    });
+    with_odd(g.odd_M, [&](auto odd) {
+        ProfScope prof("psfconv_rows_c2r", st);
+        launch_irfft_rows<T, decltype(odd)::value>(*psf->ctx, g, EpiDiagScaledAdd<T>{y, d_out, a, add, (int)nx, (int)ny},
+                                                   Y.as<c2<T>>(), st);
+    });
 }
 
 template <typename T>
@@ -75,12 +82,21 @@ void periodic_conv(const Ctx &ctx, const T *x, T *y, int64_t n_img, int64_t nx, 
     launch_irfft_rows<T>(ctx, g, EpiScaled<T>{y, nullptr, (int)nx, (int)ny, T(1), 0}, Y.as<c2<T>>(), st);
 }
 
+// n0 and n1 are 2^p, 3 2^p or 5 2^p
 template <typename T>
 void fft2_inplace(const Ctx &ctx, c2<T> *data, int64_t batch, int64_t n0, int64_t n1, int sign, hipStream_t st) {
-    const int l0 = ilog2(n0), l1 = ilog2(n1);
-    launch_fft_rows<T>(ctx, RowLoad<T>{data, l1}, RowStore<T>{data, l1}, batch * n0, l1, sign, st);
-    launch_fft_cols<T>(ctx, MatLoad<T>{data, n0 * n1, (int)n1}, MatStore<T>{data, n0 * n1, (int)n1}, batch, (int)n1,
-                       l0, (int)n0, (int)n0, sign, st);
+    int o0 = 1, l0 = 0, o1 = 1, l1 = 0;
+    FR_REQUIRE(split_len(n0, &o0, &l0) && split_len(n1, &o1, &l1), "FFT sizes must be 2^p, 3 2^p or 5 2^p");
+    with_odd(o1, [&](auto odd) {
+        launch_fft_rows<T, RowLoad<T>, RowStore<T>, decltype(odd)::value>(ctx, RowLoad<T>{data, n1},
+                                                                          RowStore<T>{data, n1}, batch * n0, l1, sign,
+                                                                          st);
+    });
+    with_odd(o0, [&](auto odd) {
+        launch_fft_cols<T, MatLoad<T>, MatStore<T>, decltype(odd)::value>(
+            ctx, MatLoad<T>{data, n0 * n1, (int)n1}, MatStore<T>{data, n0 * n1, (int)n1}, batch, (int)n1, l0, (int)n0,
+            (int)n0, sign, st);
+    });
 }
 
 template void apply_rnr_approx_ex<float>(const fr_psf *, const float *, const float *, float *, const float *,

@@ -11,7 +11,10 @@ def rel(a, b):
 
 
 @pytest.mark.parametrize("shape", [(2, 2), (16, 32), (64, 64), (3, 256, 128), (1024, 1024), (8, 2048),
-                                   (2, 4096, 8), (2, 8192), (16384, 2), (2, 16384)])
+                                   (2, 4096, 8), (2, 8192), (16384, 2), (2, 16384),
+                                   # mixed radix: 3 2^p and 5 2^p (reduced PSF padding)
+                                   (3, 5), (6, 10), (2, 12, 40), (48, 80), (3, 96, 160), (640, 768),
+                                   (1280, 24), (2, 12288), (10240, 2), (2, 6144), (5120, 4)])
 @pytest.mark.parametrize("fp64", [False, True])
 @pytest.mark.parametrize("sign", [-1, 1])
 def test_fft2_matches_numpy(shape, fp64, sign):
@@ -28,3 +31,12 @@ def test_fft2_matches_numpy(shape, fp64, sign):
     ref = np.fft.fft2(x) if sign < 0 else np.fft.ifft2(x) * (shape[-1] * shape[-2])
     err = rel(t.cpu().numpy(), ref)
     assert err < (1e-13 if fp64 else 2e-6), err
+
+
+@pytest.mark.parametrize("shape", [(9, 16), (15, 16), (16, 7), (16, 24576)])
+def test_fft2_rejects_unsupported_lengths(shape):
+    import torch
+    from paper_2406_09144_amd import api, FrError
+    t = torch.zeros(shape, dtype=torch.complex64, device="cuda")
+    with pytest.raises(FrError):
+        api.fft2(t)

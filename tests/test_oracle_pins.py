@@ -433,6 +433,29 @@ def test_fast_likelihood_dense_brute_force(oracle_lib):
     assert rel(g.ravel(), g2) < 1e-12
 
 
+def test_fast_likelihood_reduced_psf_dense_brute_force(oracle_lib):
+    """The FAST likelihood with a reduced-support kernel on a smaller padded grid
+    equals the dense form with the direct convolution by the truncated PSF."""
+    obs, wt, V, s, fwd, adj, rng = _lik_setup(n=16)
+    n = obs.nx
+    psf = O.psf0(obs.uvw, obs.freq, n, n, obs.dx, obs.dy, wt[:, 0])
+    hx, hy, px, py = 5, 3, 21, 20
+    Kp = O.response_kernel_padded(psf, hx, hy, px, py)
+    KN = O.noise_kernel(psf, 1e-2 * psf.max())
+    a = O.n_factor(n, n, obs.dx, obs.dy)
+    tr = O.psf_truncate(psf, hx, hy)
+    Rm = _dense(lambda x: O.psf_conv_direct(x, tr, a), n)
+    Nm = _dense(lambda x: O.noise_inv_apply(x, KN), n)
+    d = rng.standard_normal((n, n))
+    H, g = O.likelihood_fast(s, d, Kp, KN, a, pad=(px, py))
+    I = np.exp(s).ravel()
+    r = d.ravel() - Rm @ I
+    H2 = 0.5 * r @ Nm @ r
+    g2 = -np.exp(s).ravel() * (Rm.T @ (Nm @ r))
+    assert abs(H - H2) < 1e-12 * abs(H2)
+    assert rel(g.ravel(), g2) < 1e-12
+
+
 def test_fast_likelihood_gradient_fd(oracle_lib):
     obs, wt, V, s, fwd, adj, rng = _lik_setup(n=16)
     n = obs.nx
