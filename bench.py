@@ -21,6 +21,9 @@ from the library's per-kernel hipEvent timing over a second pass of the same
 steps (per-launch event brackets are kept out of the step timings);
 "roofline_hbm" lists the memory-bound kernels of the same path against HBM.
 PSF applies/s is the sustained rate of back-to-back batch-8 applies.
+"reduced_psf" measures the PSF cut to |offset| <= h on the n + h padded grid:
+applies/s, accuracy against the exact R^+ N^-1 R, and the major cycles of the
+major/minor scheme it needs.
 """
 
 import argparse
@@ -142,6 +145,63 @@ def scale_workload(api, torch, steps=3):
     return res
 
 
+def reduced_psf_tradeoff(api, torch, plan, w, V, x8, inv_power, s0, supports=(128, 256, 384, 511),
+                         cycle_supports=(384, 256, 128), n_major=6, reps=20):
+    """Reduced PSF support (Sec. 3.3.2): speed and accuracy of R' with the PSF cut
+    to |offset| <= h on the n + h padded grid, and the effect on the major cycles
+    of Algorithm 1 (exact likelihood after each cycle; the count is the number of
+    major cycles to reach the value the full PSF reaches after two)."""
+    from paper_2406_09144_amd import major_minor
+    from paper_2406_09144_amd._lib import FR_LIK_EXACT
+    psf = api.make_psf_kernel(plan, w, eps_noise=-1e-1)
+    full_y = api.apply_RNR_approx(psf, x8)
+    exact = api.apply_RNR_exact(plan, x8[0].contiguous(), w)[0]
+
+    def nrm(t):
+        return float(torch.linalg.vector_norm(t.double()))
+
+    rows = []
+    for h in (None,) + tuple(supports):
+        p = psf if h is None else psf.reduce(h)
+        y = api.apply_RNR_approx(p, x8)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            api.apply_RNR_approx(p, x8, out=y)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        rows.append({"support": h if h is not None else "full", "padded": [p.px, p.py], "b8_ms": round(ms, 5),
+                     "applies_per_s": round(x8.shape[0] / (ms * 1e-3)),
+                     "rel_err_vs_exact": nrm(y[0, 0] - exact) / nrm(exact),
+                     "rel_err_vs_full_psf": nrm(y - full_y) / nrm(full_y)})
+
+    def H_exact(s):
+        return float(api.likelihood_grad(FR_LIK_EXACT, s[None].contiguous(), V, plan=plan, weight=w,
+                                         inv_power=inv_power)[0])
+
+    I_D = api.grid(plan, V, w)
+    lam0 = 1e-2 * float(psf.kernels()[0].abs().max())
+    cycles = {}
+    for h in (None,) + tuple(cycle_supports):
+        p = psf if h is None else psf.reduce(h)
+        d, s, lam, I_prev = I_D, s0, lam0, None
+        Hs = [H_exact(s0)]
+        for _ in range(n_major):
+            s, _, lam = major_minor.minor_cycle(p, d, s, I_prev, inv_power, lam, n_steps=8, cg_iters=20)
+            I_prev = torch.exp(s)
+            d = (I_D - api.apply_RNR_exact(plan, I_prev, w)).contiguous()
+            Hs.append(H_exact(s))
+        cycles["full" if h is None else h] = Hs
+    target = cycles["full"][2]
+    counts = {str(k): next((i for i, v in enumerate(Hs) if v <= target * (1 + 1e-6)), None)
+              for k, Hs in cycles.items()}
+    return {"workload": "VLA-like 512x512, 1,010,880 visibilities, batch 8, eps_noise 0.1 of the PSF peak",
+            "apply": rows, "major_cycles_to_full_psf_H_after_2": counts, "n_major": n_major,
+            "exact_H_per_major_cycle": {str(k): [round(v, 1) for v in Hs] for k, Hs in cycles.items()}}
+
+
 def build_served_jobs(api, torch, n_jobs, fp64):
     """Resident jobs of the served mix: plan, PSF kernels, data, input pools."""
     import numpy as np
@@ -223,6 +283,8 @@ def main():
                     help="only run 5 plain copies of this many bytes (counter calibration)")
     ap.add_argument("--scale-steps", type=int, default=2,
                     help="timed (de)grid passes of the MeerKAT-like workload (0 disables)")
+    ap.add_argument("--reduced-psf", type=int, default=1,
+                    help="measure the reduced-PSF-support trade-off (0 disables)")
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--n-int", type=int, default=2880)
     args = ap.parse_args()
@@ -416,6 +478,12 @@ def main():
         scale = scale_workload(api, torch, args.scale_steps)
         log(f"[bench] MeerKAT-like: {json.dumps(scale)}")
 
+    reduced = None
+    if args.reduced_psf:
+        s0 = torch.full((1, n, n), float(np.log(max(float(obs.sky.mean()), 1e-12))), device=dev)
+        reduced = reduced_psf_tradeoff(api, torch, plan, w, V, x8, ip, s0)
+        log(f"[bench] reduced PSF: {json.dumps(reduced)}")
+
     served = None
     if args.serve_seconds > 0:
         served = served_workload(api, torch, args.serve_seconds, args.serve_rate, args.serve_jobs,
@@ -452,6 +520,7 @@ def main():
             "cg50_ms": comp["cg50"], "plan_create_s": t_plan, "make_psf_s": t_psf,
             "fp64_plain_form": fp64,
             "meerkat_like": scale,
+            "reduced_psf": reduced,
             "served": served,
         },
         "kernels_ms": {k: round(v["avg_ms"], 5) for k, v in kern.items()},

@@ -64,3 +64,43 @@ def test_major_minor_reduces_residual():
     # the packaged driver runs the same loop
     s2, I2, norms2 = major_minor.reconstruct(pl, psf, V, w, ip, n_major=1, n_minor=2, s0=s0)
     assert len(norms2) == 2 and norms2[1] < norms2[0]
+
+
+def test_major_minor_with_reduced_psf():
+    """Algorithm 1 with the reduced-support PSF of Sec. 3.3.2: at h = n - 1 the
+    minor cycles see the full-PSF operator (same result to FP32 rounding); with
+    the PSF cut to h = n / 4 (80 x 80 padding) the first major cycle still lowers
+    ||d||."""
+    import torch
+    from paper_2406_09144_amd import api, major_minor
+    from paper_2406_09144_amd._lib import FR_LIK_EXACT
+    n = 64
+    obs = make_config(1, n=n, n_int=240, with_sky=False)
+    pl = api.Plan(obs.uvw, obs.freq, n, n, obs.dx, obs.dy, eps=1e-5)
+    sky_np = np.exp(correlated_field(np.random.default_rng(5), n, n))
+    sky = torch.from_numpy(sky_np[None]).float().cuda()
+    model = api.degrid(pl, sky).cpu().numpy().astype(np.complex128)
+    noise, wt = noise_from_model(config_rng(1, "noise"), model, rel=0.05)
+    V = torch.from_numpy(model + noise).to(torch.complex64).cuda()
+    w = torch.from_numpy(wt).float().cuda()
+    psf = api.make_psf_kernel(pl, w, eps_noise=-1e-1)
+    ip = torch.from_numpy(inv_power_half(n, n)).float().cuda()
+    s0 = torch.full((1, n, n), float(np.log(sky_np.mean())), device="cuda")
+
+    def run(p):
+        s, I, norms = major_minor.reconstruct(pl, p, V, w, ip, n_major=2, n_minor=4, s0=s0)
+        H = float(api.likelihood_grad(FR_LIK_EXACT, s[None].contiguous(), V, plan=pl, weight=w,
+                                      inv_power=ip)[0])
+        return s, norms, H
+
+    s_full, n_full, H_full = run(psf)
+    same = psf.reduce(n - 1)
+    assert (same.px, same.py) == (2 * n, 2 * n)
+    s_same, n_same, H_same = run(same)
+    assert abs(H_same - H_full) < 1e-3 * abs(H_full)
+    assert np.allclose(n_same, n_full, rtol=1e-3)
+    cut = psf.reduce(n // 4)
+    assert (cut.px, cut.py) == (80, 80)
+    _, n_cut, H_cut = run(cut)
+    print("||d_i|| full", n_full, "cut", n_cut, "H", H_full, H_cut)
+    assert n_cut[1] < n_cut[0]
