@@ -375,6 +375,61 @@ def cg(apply_A, b, maxiter, rtol=0.0):
     return x, np.array(hist)
 
 
+# ---------------------------------------------------------------- MGVI (standardised coordinates)
+def gp_apply(x, power, inverse=False):
+    """Standardised excitations -> log-sky: A x = F^-1 diag(sqrt P) F x on the
+    periodic grid, the Gaussian process of the diffuse-emission prior (Sec. 3.1.1:
+    correlated pixels, exponentiated for positivity), so s = A xi has covariance
+    S = F^-1 diag(P) F for white xi.  power: full [nx, ny] array P(k) > 0.
+    inverse: apply A^-1 instead."""
+    f = np.sqrt(power)
+    if inverse:
+        f = 1.0 / f
+    return np.real(np.fft.ifft2(np.fft.fft2(_f64(x)) * f))
+
+
+def noise_inv_sqrt_apply(x, K_N):
+    """N'^-1/2 x = F^-1 diag(K^-1/2) F x (square root of the Sec. 3.3.3 kernel)."""
+    return np.real(np.fft.ifft2(np.fft.fft2(_f64(x)) / np.sqrt(K_N)))
+
+
+def mgvi_hamiltonian(xi, d, K_R, K_N, power, a=None):
+    """Eq. (ham_new) in standardised coordinates with the Gaussian-process prior
+    (the minor-cycle posterior of Sec. 3.3.5): s = A xi, I = exp(s),
+        r = d - R' I,  H = 1/2 r^T N'^-1 r + 1/2 xi^T xi,
+        dH/dxi = -A D R' N'^-1 r + xi,  D = diag(I)."""
+    xi = _f64(xi)
+    I = np.exp(gp_apply(xi, power))
+    r = _f64(d) - psf_conv_fft(I, K_R, a)
+    q = noise_inv_apply(r, K_N)
+    H = 0.5 * float(np.sum(r * q)) + 0.5 * float(np.sum(xi * xi))
+    g = -gp_apply(I * psf_conv_fft(q, K_R, a), power) + xi
+    return H, g
+
+
+def mgvi_metric_apply(x, K_R, K_N, power, diag, a=None):
+    """M x = x + A D R' N'^-1 R' D A x: the Fisher metric of mgvi_hamiltonian
+    (J^T N'^-1 J + 1 with J = dr/dxi = -R' D A), which MGVI inverts to draw its
+    samples (Sec. 3.3.5).  diag = exp(s) at the expansion point."""
+    u = psf_conv_fft(diag * gp_apply(x, power), K_R, a)
+    u = diag * psf_conv_fft(noise_inv_apply(u, K_N), K_R, a)
+    return _f64(x) + gp_apply(u, power)
+
+
+def mgvi_draw(eta0, eta1, K_R, K_N, power, diag, a=None):
+    """A vector with covariance M from two white ones: eta0 + A D R' N'^-1/2 eta1
+    (covariance 1 + A D R' N'^-1 R' D A, every factor symmetric)."""
+    u = diag * psf_conv_fft(noise_inv_sqrt_apply(eta1, K_N), K_R, a)
+    return _f64(eta0) + gp_apply(u, power)
+
+
+def mgvi_sample(eta0, eta1, K_R, K_N, power, diag, maxiter, a=None, rtol=0.0):
+    """An MGVI sample offset x = M^-1 (draw with covariance M), so x ~ N(0, M^-1),
+    by CG; returns x and the residual history."""
+    xi = mgvi_draw(eta0, eta1, K_R, K_N, power, diag, a)
+    return cg(lambda p: mgvi_metric_apply(p, K_R, K_N, power, diag, a), xi, maxiter, rtol)
+
+
 def metric_apply(x, K_R, inv_power, a=None, diag=None):
     """A x = D_s R' D_s x + S^-1 x with R' the PSF convolution and D_s = diag(diag)."""
     y = x if diag is None else diag * x
