@@ -66,6 +66,9 @@ enum fr_plan_flags {
 
 enum fr_lik_mode { FR_LIK_EXACT = 0, FR_LIK_FAST = 1 };
 
+/* kernel factor of fr_periodic_conv */
+enum fr_conv_mode { FR_CONV_MUL = 0, FR_CONV_DIV = 1, FR_CONV_MUL_SQRT = 2, FR_CONV_DIV_SQRT = 3 };
+
 enum fr_op {
     FR_OP_DEGRID = 0,
     FR_OP_GRID = 1,
@@ -237,6 +240,45 @@ int fr_likelihood_grad(fr_plan *plan, fr_psf *psf, int mode, const void *s, cons
 int fr_cg_solve(fr_plan *plan, fr_psf *psf, const void *weight, const void *inv_power,
                 const void *diag, const void *b, void *x, int maxiter, double rtol,
                 double *resid_hist, int *iters_done, void *stream);
+
+/*
+ * Periodic convolution with a real even kernel given by its r2c half spectrum on
+ * the nx x ny grid (noise kernel of Sec. 3.3.3, Gaussian-process prior):
+ *   y = F^-1 diag(f(K)) F x,  f = K, 1/K, sqrt K or 1/sqrt K for mode
+ *   FR_CONV_MUL, FR_CONV_DIV, FR_CONV_MUL_SQRT, FR_CONV_DIV_SQRT.
+ * With K = P(k) and FR_CONV_MUL_SQRT this maps standardised excitations xi to the
+ * log-sky s = A xi of covariance S (the exponentiated Gaussian process of the
+ * diffuse prior, Sec. 3.1.1); FR_CONV_DIV_SQRT is A^-1.
+ *   K      device [nk][nx][ny/2 + 1] real (> 0 for the DIV and SQRT modes);
+ *          image g uses K[g % nk]
+ *   x, y   device [n_img][nx][ny] real, y != x; fp64 selects double.
+ * nx, ny powers of two in [4, 8192]. */
+int fr_periodic_conv(fr_ctx *ctx, const void *K, int64_t nk, int mode, const void *x, void *y,
+                     int64_t n_img, int64_t nx, int64_t ny, int fp64, void *stream);
+
+/*
+ * MGVI pieces for the minor cycle (Sec. 3.3.5) in standardised coordinates: the
+ * log-sky is s = A xi (A as fr_periodic_conv with power P, FR_CONV_MUL_SQRT) and
+ * the FAST likelihood (eq. ham_new) has the Fisher metric
+ *   M = 1 + A D R' N'^-1 R' D A,   D = diag(diag) = diag(exp s) at the expansion point,
+ * with R' the PSF convolution of `psf` (any padding) and N'^-1 its noise kernel.
+ *   power  device [nx][ny/2 + 1] real P(k) > 0 (shared by the channels)
+ *   diag   device [n_chan][nx][ny] or NULL (= 1)
+ *   vectors device [n_chan][nx][ny]: one system over all channels.
+ * fr_mgvi_metric_apply: y = M x (y != x).
+ * fr_mgvi_draw: xi = eta0 + A D R' N'^-1/2 eta1, which has covariance M for white
+ *   eta0, eta1 (the random numbers come from the caller); xi aliases neither.
+ * fr_mgvi_solve: M x = b by conjugate gradients (Hestenes-Stiefel, x0 = 0, FP64
+ *   scalars on the device, no host synchronisation; arguments as fr_cg_solve).
+ *   With b from fr_mgvi_draw, x ~ N(0, M^-1) is an MGVI sample offset; with b a
+ *   gradient, x is the natural-gradient step.
+ * The PSF object must carry a noise kernel. */
+int fr_mgvi_metric_apply(fr_psf *psf, const void *power, const void *diag, const void *x, void *y,
+                         void *stream);
+int fr_mgvi_draw(fr_psf *psf, const void *power, const void *diag, const void *eta0,
+                 const void *eta1, void *xi, void *stream);
+int fr_mgvi_solve(fr_psf *psf, const void *power, const void *diag, const void *b, void *x,
+                  int maxiter, double rtol, double *resid_hist, int *iters_done, void *stream);
 
 /* Device bytes a call of `op` with batch B needs beyond its inputs and outputs
  * (per-call scratch), plus the resident plan/psf bytes.  Host-only, no GPU work. */

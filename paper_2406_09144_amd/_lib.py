@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libfrmi.so")
 FR_OK, FR_EINVAL, FR_ENOMEM, FR_EHIP, FR_EUNSUPPORTED, FR_EBUSY = 0, -1, -2, -3, -4, -5
 FR_FP64, FR_DIVIDE_BY_N, FR_COPLANAR = 1, 2, 4
 FR_LIK_EXACT, FR_LIK_FAST = 0, 1
+FR_CONV_MUL, FR_CONV_DIV, FR_CONV_MUL_SQRT, FR_CONV_DIV_SQRT = 0, 1, 2, 3
 (FR_OP_DEGRID, FR_OP_GRID, FR_OP_RNR_APPROX, FR_OP_RNR_EXACT, FR_OP_LIK_EXACT,
  FR_OP_LIK_FAST, FR_OP_CG, FR_OP_MAKE_PSF) = range(8)
 
@@ -71,6 +72,10 @@ SIGNATURES = {
     "fr_apply_RNR_exact": ([_P, _P, _P, _P, _I64, _P], _I),
     "fr_likelihood_grad": ([_P, _P, _I, _P, _P, _P, _P, _P, _I64, _P, _P, _P], _I),
     "fr_cg_solve": ([_P, _P, _P, _P, _P, _P, _P, _I, _D, _P, _P, _P], _I),
+    "fr_periodic_conv": ([_P, _P, _I64, _I, _P, _P, _I64, _I64, _I64, _I, _P], _I),
+    "fr_mgvi_metric_apply": ([_P, _P, _P, _P, _P, _P], _I),
+    "fr_mgvi_draw": ([_P, _P, _P, _P, _P, _P, _P], _I),
+    "fr_mgvi_solve": ([_P, _P, _P, _P, _P, _I, _D, _P, _P, _P], _I),
     "fr_query_footprint": ([_P, _P, _I, _I64, ctypes.POINTER(ctypes.c_size_t),
                             ctypes.POINTER(ctypes.c_size_t)], _I),
     "fr_fft2": ([_P, _P, _I64, _I64, _I64, _I, _I, _P], _I),

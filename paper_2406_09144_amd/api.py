@@ -341,6 +341,65 @@ def cg_solve(b, psf=None, plan=None, weight=None, inv_power=None, diag=None, max
     return x, hist, iters
 
 
+def periodic_conv(K, x, mode=L.FR_CONV_MUL, out=None, ctx=None, stream=None):
+    """y = F^-1 diag(f(K)) F x on the periodic grid, f = K, 1/K, sqrt K, 1/sqrt K
+    (FR_CONV_MUL / _DIV / _MUL_SQRT / _DIV_SQRT); K [nk, nx, ny/2+1] or [nx, ny/2+1]
+    (image g uses K[g % nk]), x [..., nx, ny]."""
+    ctx = ctx or Context.get(x.device.index)
+    nx, ny = x.shape[-2:]
+    fp64 = x.dtype == torch.float64
+    rd = _real_dtype(fp64)
+    Kb = K if K.dim() == 3 else K[None]
+    Kb = _need(Kb.contiguous(), rd, (Kb.shape[0], nx, ny // 2 + 1), "K")
+    xc = _need(x.contiguous(), rd, tuple(x.shape), "x")
+    y = out if out is not None else torch.empty_like(xc)
+    n_img = xc.numel() // (nx * ny)
+    L.check(_lib().fr_periodic_conv(ctx.handle, _ptr(Kb), Kb.shape[0], int(mode), _ptr(xc), _ptr(y), n_img, nx, ny,
+                                    int(fp64), _stream(stream)))
+    return y
+
+
+def _mgvi_args(psf, power, diag):
+    rd = _real_dtype(psf.fp64)
+    shape = (psf.n_chan, psf.nx, psf.ny)
+    power = _need(power, rd, (psf.nx, psf.ny // 2 + 1), "power")
+    if diag is not None:
+        diag = _need(diag.reshape(shape), rd, shape, "diag")
+    return rd, shape, power, diag
+
+
+def mgvi_metric_apply(psf, power, diag, x, stream=None):
+    """M x = x + A D R' N'^-1 R' D A x (MGVI metric in standardised coordinates)."""
+    rd, shape, power, diag = _mgvi_args(psf, power, diag)
+    x = _need(x.reshape(shape), rd, shape, "x")
+    y = torch.empty_like(x)
+    L.check(_lib().fr_mgvi_metric_apply(psf.handle, _ptr(power), _ptr(diag), _ptr(x), _ptr(y), _stream(stream)))
+    return y
+
+
+def mgvi_draw(psf, power, diag, eta0, eta1, stream=None):
+    """eta0 + A D R' N'^-1/2 eta1: covariance M for white eta0, eta1."""
+    rd, shape, power, diag = _mgvi_args(psf, power, diag)
+    eta0 = _need(eta0.reshape(shape), rd, shape, "eta0")
+    eta1 = _need(eta1.reshape(shape), rd, shape, "eta1")
+    xi = torch.empty_like(eta0)
+    L.check(_lib().fr_mgvi_draw(psf.handle, _ptr(power), _ptr(diag), _ptr(eta0), _ptr(eta1), _ptr(xi),
+                                _stream(stream)))
+    return xi
+
+
+def mgvi_solve(psf, power, diag, b, maxiter=20, rtol=0.0, stream=None):
+    """M x = b by CG; returns x, the residual history and the iteration count."""
+    rd, shape, power, diag = _mgvi_args(psf, power, diag)
+    b = _need(b.reshape(shape), rd, shape, "b")
+    x = torch.empty_like(b)
+    hist = torch.zeros(maxiter + 1, dtype=torch.float64, device=b.device)
+    iters = torch.zeros((), dtype=torch.int32, device=b.device)
+    L.check(_lib().fr_mgvi_solve(psf.handle, _ptr(power), _ptr(diag), _ptr(b), _ptr(x), int(maxiter), float(rtol),
+                                 _ptr(hist), _ptr(iters), _stream(stream)))
+    return x, hist, iters
+
+
 def query_footprint(op, B=1, plan=None, psf=None):
     """(scratch_bytes, resident_bytes) of one call of `op` (host-only)."""
     s, r = ctypes.c_size_t(), ctypes.c_size_t()

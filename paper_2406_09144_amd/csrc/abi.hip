@@ -401,6 +401,79 @@ int fr_cg_solve(fr_plan *pl, fr_psf *psf, const void *weight, const void *inv_po
     FR_API_END
 }
 
+int fr_periodic_conv(fr_ctx *ctx, const void *K, int64_t nk, int mode, const void *x, void *y, int64_t n_img,
+                     int64_t nx, int64_t ny, int fp64, void *stream) {
+    FR_API_BEGIN
+    FR_REQUIRE(ctx && K, "ctx and K are required");
+    FR_REQUIRE(n_img >= 0 && nk >= 1, "n_img >= 0 and nk >= 1 required");
+    FR_REQUIRE(mode >= FR_CONV_MUL && mode <= FR_CONV_DIV_SQRT, "unknown mode");
+    FR_REQUIRE(is_pow2(nx) && is_pow2(ny) && nx >= 4 && ny >= 4 && nx <= 8192 && ny <= 8192,
+               "nx, ny must be powers of two in [4, 8192]");
+    FR_REQUIRE(!fp64 || (nx <= 4096 && ny <= 8192), "FP64 periodic convolutions need nx <= 4096");
+    if (n_img == 0) return FR_OK;
+    FR_REQUIRE(x && y && x != y, "x and y are required and must differ");
+    DeviceGuard dg(ctx->c.device);
+    if (fp64)
+        periodic_conv_ex<double>(ctx->c, (const double *)x, nullptr, (double *)y, nullptr, nullptr, n_img, nx, ny,
+                                 (const double *)K, (int)nk, mode, as_stream(stream));
+    else
+        periodic_conv_ex<float>(ctx->c, (const float *)x, nullptr, (float *)y, nullptr, nullptr, n_img, nx, ny,
+                                (const float *)K, (int)nk, mode, as_stream(stream));
+    FR_API_END
+}
+
+static void mgvi_check(const fr_psf *psf, const void *power) {
+    FR_REQUIRE(psf && power, "psf and power are required");
+    FR_REQUIRE(psf->KN.p, "the PSF object has no noise kernel (N'^-1 is part of the metric)");
+}
+
+int fr_mgvi_metric_apply(fr_psf *psf, const void *power, const void *diag, const void *x, void *y, void *stream) {
+    FR_API_BEGIN
+    mgvi_check(psf, power);
+    FR_REQUIRE(x && y && x != y, "x and y are required and must differ");
+    DeviceGuard dg(psf->ctx->device);
+    if (psf->fp64)
+        mgvi_metric_apply<double>(psf, (const double *)power, (const double *)diag, (const double *)x, (double *)y,
+                                  as_stream(stream));
+    else
+        mgvi_metric_apply<float>(psf, (const float *)power, (const float *)diag, (const float *)x, (float *)y,
+                                 as_stream(stream));
+    FR_API_END
+}
+
+int fr_mgvi_draw(fr_psf *psf, const void *power, const void *diag, const void *eta0, const void *eta1, void *xi,
+                 void *stream) {
+    FR_API_BEGIN
+    mgvi_check(psf, power);
+    FR_REQUIRE(eta0 && eta1 && xi, "eta0, eta1 and xi are required");
+    FR_REQUIRE(xi != eta0 && xi != eta1, "xi must not alias eta0 or eta1");
+    DeviceGuard dg(psf->ctx->device);
+    if (psf->fp64)
+        mgvi_draw<double>(psf, (const double *)power, (const double *)diag, (const double *)eta0,
+                          (const double *)eta1, (double *)xi, as_stream(stream));
+    else
+        mgvi_draw<float>(psf, (const float *)power, (const float *)diag, (const float *)eta0, (const float *)eta1,
+                         (float *)xi, as_stream(stream));
+    FR_API_END
+}
+
+int fr_mgvi_solve(fr_psf *psf, const void *power, const void *diag, const void *b, void *x, int maxiter, double rtol,
+                  double *resid_hist, int *iters_done, void *stream) {
+    FR_API_BEGIN
+    mgvi_check(psf, power);
+    FR_REQUIRE(b && x && resid_hist && iters_done, "b, x, resid_hist and iters_done are required");
+    FR_REQUIRE(b != x, "x must not alias b");
+    FR_REQUIRE(maxiter >= 0 && rtol >= 0 && std::isfinite(rtol), "maxiter >= 0 and rtol >= 0 required");
+    DeviceGuard dg(psf->ctx->device);
+    if (psf->fp64)
+        mgvi_solve<double>(psf, (const double *)power, (const double *)diag, (const double *)b, (double *)x, maxiter,
+                           rtol, resid_hist, iters_done, as_stream(stream));
+    else
+        mgvi_solve<float>(psf, (const float *)power, (const float *)diag, (const float *)b, (float *)x, maxiter, rtol,
+                          resid_hist, iters_done, as_stream(stream));
+    FR_API_END
+}
+
 int fr_query_footprint(const fr_plan *pl, const fr_psf *psf, int op, int64_t B, size_t *scratch_bytes,
                        size_t *resident_bytes) {
     FR_API_BEGIN

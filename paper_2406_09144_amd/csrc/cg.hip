@@ -1,6 +1,6 @@
-// Conjugate gradients on A x = D_s R' D_s x + S^-1 x = b: the solve MGVI uses to
-// apply the inverse metric in the minor cycle (Sec. 3.3.5).  Hestenes-Stiefel
-// recurrences with x0 = 0 and no preconditioner.
+// Conjugate gradients on A x = D_s R' D_s x + S^-1 x = b and on the MGVI metric:
+// the solves MGVI uses to apply the inverse metric in the minor cycle (Sec. 3.3.5).
+// Hestenes-Stiefel recurrences with x0 = 0 and no preconditioner.
 //
 // Vectors are in the plan/PSF precision; <r, r>, <p, A p>, alpha and beta are
 // double precision scalars that live on the device.  Every kernel reads them
@@ -133,22 +133,16 @@ __global__ void k_cg_report(const CGState *st, int *iters_done) {
     if (threadIdx.x == 0) *iters_done = st->iters;
 }
 
-template <typename T>
-void cg_solve(const fr_plan *pl, const fr_psf *psf, const T *weight, const T *inv_power, const T *diag, const T *b,
-              T *x, int maxiter, double rtol, double *hist, int *iters_done, hipStream_t st) {
-    const int64_t nx = psf ? psf->nx : pl->nx, ny = psf ? psf->ny : pl->ny;
-    const int64_t nc = psf ? psf->n_chan : pl->n_chan;
-    const int64_t n = nc * nx * ny;
-    const Ctx &ctx = psf ? *psf->ctx : *pl->ctx;
+// The Hestenes-Stiefel loop around an operator apply(p, Ap) on n values.
+template <typename T, class Apply>
+void cg_run(int64_t n, const T *b, T *x, int maxiter, double rtol, double *hist, int *iters_done, hipStream_t st,
+            Apply apply) {
     Scratch state(sizeof(CGState), st);
     const int nb = red_blocks(n);
     Scratch partials((size_t)2 * nb * sizeof(double), st);
     Scratch rr((size_t)(maxiter + 1) * sizeof(double), st);
     double *pAp_part = partials.as<double>(), *rr_part = partials.as<double>() + nb;
-    Scratch r(n * sizeof(T), st), p(n * sizeof(T), st), Ap(n * sizeof(T), st), t(n * sizeof(T), st),
-        u(n * sizeof(T), st);
-    Scratch pr;
-    if (inv_power) pr = Scratch(n * sizeof(T), st);
+    Scratch r(n * sizeof(T), st), p(n * sizeof(T), st), Ap(n * sizeof(T), st);
     CGState *S = state.as<CGState>();
     map_async(CGInit<T>{b, x, r.as<T>(), p.as<T>()}, n, st);
     k_dot_partials<T><<<dim3((unsigned)nb, 1), kRedThreads, 0, st>>>(r.as<T>(), nullptr, n, rr_part);
@@ -156,20 +150,7 @@ void cg_solve(const fr_plan *pl, const fr_psf *psf, const T *weight, const T *in
     k_cg_start<<<1, kRedThreads, 0, st>>>(S, rr_part, nb, rtol, maxiter, rr.as<double>(), hist);
     LAUNCH_CHECK();
     for (int k = 0; k < maxiter; ++k) {
-        // A p = D R' D p + S^-1 p
-        if (inv_power) periodic_conv<T>(ctx, p.as<T>(), pr.as<T>(), nc, nx, ny, inv_power, 1, 0, st);
-        const T *prior = inv_power ? pr.as<T>() : nullptr;
-        if (psf) {
-            apply_rnr_approx_ex<T>(psf, p.as<T>(), diag, Ap.as<T>(), diag, prior, 1, st);
-        } else {
-            const T *src = p.as<T>();
-            if (diag) {
-                map_async(DiagMul<T>{diag, p.as<T>(), t.as<T>()}, n, st);
-                src = t.as<T>();
-            }
-            apply_rnr_exact<T>(pl, weight, src, u.as<T>(), 1, st);
-            map_async(DiagMulAdd<T>{diag, u.as<T>(), prior, Ap.as<T>()}, n, st);
-        }
+        apply(p.as<T>(), Ap.as<T>());
         k_cg_dot_pAp<T><<<dim3((unsigned)nb), kRedThreads, 0, st>>>(S, p.as<T>(), Ap.as<T>(), n, pAp_part);
         LAUNCH_CHECK();
         k_cg_step<T><<<dim3((unsigned)nb), kRedThreads, 0, st>>>(S, x, r.as<T>(), p.as<T>(), Ap.as<T>(), n, pAp_part,
@@ -183,9 +164,103 @@ void cg_solve(const fr_plan *pl, const fr_psf *psf, const T *weight, const T *in
     LAUNCH_CHECK();
 }
 
+template <typename T>
+void cg_solve(const fr_plan *pl, const fr_psf *psf, const T *weight, const T *inv_power, const T *diag, const T *b,
+              T *x, int maxiter, double rtol, double *hist, int *iters_done, hipStream_t st) {
+    const int64_t nx = psf ? psf->nx : pl->nx, ny = psf ? psf->ny : pl->ny;
+    const int64_t nc = psf ? psf->n_chan : pl->n_chan;
+    const int64_t n = nc * nx * ny;
+    const Ctx &ctx = psf ? *psf->ctx : *pl->ctx;
+    Scratch t(n * sizeof(T), st), u(n * sizeof(T), st);
+    Scratch pr;
+    if (inv_power) pr = Scratch(n * sizeof(T), st);
+    cg_run<T>(n, b, x, maxiter, rtol, hist, iters_done, st, [&](const T *p, T *Ap) {
+        // A p = D R' D p + S^-1 p
+        if (inv_power) periodic_conv<T>(ctx, p, pr.as<T>(), nc, nx, ny, inv_power, 1, 0, st);
+        const T *prior = inv_power ? pr.as<T>() : nullptr;
+        if (psf) {
+            apply_rnr_approx_ex<T>(psf, p, diag, Ap, diag, prior, 1, st);
+        } else {
+            const T *src = p;
+            if (diag) {
+                map_async(DiagMul<T>{diag, p, t.as<T>()}, n, st);
+                src = t.as<T>();
+            }
+            apply_rnr_exact<T>(pl, weight, src, u.as<T>(), 1, st);
+            map_async(DiagMulAdd<T>{diag, u.as<T>(), prior, Ap}, n, st);
+        }
+    });
+}
+
+// ------------------------------------------------------------------ MGVI
+// Minor-cycle posterior in standardised coordinates xi (log-sky s = A xi, A =
+// F^-1 sqrt(P) F, the exponentiated Gaussian process of the prior), FAST
+// likelihood: Fisher metric M = 1 + A D R' N'^-1 R' D A with D = diag(exp s).
+enum { kConvMul = 0, kConvDiv = 1, kConvMulSqrt = 2, kConvDivSqrt = 3 };
+
+template <typename T> struct MgviOp {
+    const fr_psf *psf;
+    const T *power, *diag;
+    int64_t nx, ny, nc, n;
+    // y = x + A D R' N'^-1 R' D A x  (u1, u2 scratch of n values)
+    void metric(const T *x, T *y, T *u1, T *u2, hipStream_t st) const {
+        const Ctx &ctx = *psf->ctx;
+        periodic_conv_ex<T>(ctx, x, nullptr, u1, nullptr, nullptr, nc, nx, ny, power, 1, kConvMulSqrt, st);
+        apply_rnr_approx_ex<T>(psf, u1, diag, u2, nullptr, nullptr, 1, st);
+        periodic_conv_ex<T>(ctx, u2, nullptr, u1, nullptr, nullptr, nc, nx, ny, psf->KN.as<T>(), (int)nc, kConvDiv,
+                            st);
+        apply_rnr_approx_ex<T>(psf, u1, nullptr, u2, diag, nullptr, 1, st);
+        periodic_conv_ex<T>(ctx, u2, nullptr, y, nullptr, x, nc, nx, ny, power, 1, kConvMulSqrt, st);
+    }
+};
+
+template <typename T>
+void mgvi_metric_apply(const fr_psf *psf, const T *power, const T *diag, const T *x, T *y, hipStream_t st) {
+    const int64_t n = psf->n_chan * psf->nx * psf->ny;
+    MgviOp<T> op{psf, power, diag, psf->nx, psf->ny, psf->n_chan, n};
+    Scratch u1(n * sizeof(T), st), u2(n * sizeof(T), st);
+    op.metric(x, y, u1.as<T>(), u2.as<T>(), st);
+}
+
+// xi = eta0 + A D R' N'^-1/2 eta1: covariance M for white eta0, eta1
+template <typename T>
+void mgvi_draw(const fr_psf *psf, const T *power, const T *diag, const T *eta0, const T *eta1, T *xi,
+               hipStream_t st) {
+    const int64_t nx = psf->nx, ny = psf->ny, nc = psf->n_chan, n = nc * nx * ny;
+    const Ctx &ctx = *psf->ctx;
+    Scratch u1(n * sizeof(T), st), u2(n * sizeof(T), st);
+    periodic_conv_ex<T>(ctx, eta1, nullptr, u1.as<T>(), nullptr, nullptr, nc, nx, ny, psf->KN.as<T>(), (int)nc,
+                        kConvDivSqrt, st);
+    apply_rnr_approx_ex<T>(psf, u1.as<T>(), nullptr, u2.as<T>(), diag, nullptr, 1, st);
+    periodic_conv_ex<T>(ctx, u2.as<T>(), nullptr, xi, nullptr, eta0, nc, nx, ny, power, 1, kConvMulSqrt, st);
+}
+
+// M x = b by CG (b = an mgvi_draw gives the sample offset x ~ N(0, M^-1))
+template <typename T>
+void mgvi_solve(const fr_psf *psf, const T *power, const T *diag, const T *b, T *x, int maxiter, double rtol,
+                double *hist, int *iters_done, hipStream_t st) {
+    const int64_t n = psf->n_chan * psf->nx * psf->ny;
+    MgviOp<T> op{psf, power, diag, psf->nx, psf->ny, psf->n_chan, n};
+    Scratch u1(n * sizeof(T), st), u2(n * sizeof(T), st);
+    cg_run<T>(n, b, x, maxiter, rtol, hist, iters_done, st,
+              [&](const T *p, T *Ap) { op.metric(p, Ap, u1.as<T>(), u2.as<T>(), st); });
+}
+
 template void cg_solve<float>(const fr_plan *, const fr_psf *, const float *, const float *, const float *,
                               const float *, float *, int, double, double *, int *, hipStream_t);
 template void cg_solve<double>(const fr_plan *, const fr_psf *, const double *, const double *, const double *,
                                const double *, double *, int, double, double *, int *, hipStream_t);
+template void mgvi_metric_apply<float>(const fr_psf *, const float *, const float *, const float *, float *,
+                                       hipStream_t);
+template void mgvi_metric_apply<double>(const fr_psf *, const double *, const double *, const double *, double *,
+                                        hipStream_t);
+template void mgvi_draw<float>(const fr_psf *, const float *, const float *, const float *, const float *, float *,
+                               hipStream_t);
+template void mgvi_draw<double>(const fr_psf *, const double *, const double *, const double *, const double *,
+                                double *, hipStream_t);
+template void mgvi_solve<float>(const fr_psf *, const float *, const float *, const float *, float *, int, double,
+                                double *, int *, hipStream_t);
+template void mgvi_solve<double>(const fr_psf *, const double *, const double *, const double *, double *, int,
+                                 double, double *, int *, hipStream_t);
 
 }  // namespace frmi

@@ -78,7 +78,15 @@ __global__ __launch_bounds__(NTHR) void k_rfft_rows(Pro pro, c2<T> *__restrict__
 }
 
 // ------------------------------------------------------------------ pass 2
-// K: [nk][Lc][M + 1] real, image g uses kernel g % nk.  mode 0: multiply, 1: divide.
+// Factor applied per frequency: mode 0: K, 1: 1/K, 2: sqrt K, 3: 1/sqrt K.
+template <typename T> __device__ __forceinline__ T kernel_factor(T k, int mode) {
+    if (mode == 0) return k;
+    if (mode == 1) return T(1) / k;
+    const T r = sqrt(k);
+    return mode == 2 ? r : T(1) / r;
+}
+
+// K: [nk][Lc][M + 1] real, image g uses kernel g % nk; `mode` as kernel_factor.
 // M: packed row width; Lc = ODD 2^log2Lc.
 template <typename T, int NTHR, int BPT, bool TWL, int ODD = 1>
 __global__ __launch_bounds__(NTHR) void k_conv_cols(c2<T> *__restrict__ Y, int M, int log2Lc,
@@ -122,15 +130,17 @@ __global__ __launch_bounds__(NTHR) void k_conv_cols(c2<T> *__restrict__ Y, int M
                 c2<T> Bn = mk<T>((a.y + b.y) * T(0.5), (b.x - a.x) * T(0.5));
                 T k0 = Kg[(int64_t)k * (M + 1)], k1 = Kg[(int64_t)k * (M + 1) + M];
                 T k0m = Kg[(int64_t)km * (M + 1)], k1m = Kg[(int64_t)km * (M + 1) + M];
-                if (mode) { k0 = T(1) / k0; k1 = T(1) / k1; k0m = T(1) / k0m; k1m = T(1) / k1m; }
-                k0 *= scale; k1 *= scale; k0m *= scale; k1m *= scale;
+                k0 = kernel_factor(k0, mode) * scale;
+                k1 = kernel_factor(k1, mode) * scale;
+                k0m = kernel_factor(k0m, mode) * scale;
+                k1m = kernel_factor(k1m, mode) * scale;
                 // F'[k] = A k0 + i Bn k1 ; F'[-k] = conj(A) k0m + i conj(Bn) k1m
                 buf[padx(k)] = mk<T>(A.x * k0 - Bn.y * k1, A.y * k0 + Bn.x * k1);
                 if (km != k) buf[padx(km)] = mk<T>(A.x * k0m + Bn.y * k1m, -A.y * k0m + Bn.x * k1m);
             }
         } else {
             T kv = Kg[(int64_t)k * (M + 1) + col];
-            kv = (mode ? T(1) / kv : kv) * scale;
+            kv = kernel_factor(kv, mode) * scale;
             c2<T> v = buf[c * ld + padx(k)];
             buf[c * ld + padx(k)] = mk<T>(v.x * kv, v.y * kv);
         }

@@ -106,6 +106,15 @@ template <typename T>
 void cg_solve(const fr_plan *pl, const fr_psf *psf, const T *weight, const T *inv_power, const T *diag, const T *b,
               T *x, int maxiter, double rtol, double *hist, int *iters_done, hipStream_t st);
 
+template <typename T>
+void mgvi_metric_apply(const fr_psf *psf, const T *power, const T *diag, const T *x, T *y, hipStream_t st);
+template <typename T>
+void mgvi_draw(const fr_psf *psf, const T *power, const T *diag, const T *eta0, const T *eta1, T *xi,
+               hipStream_t st);
+template <typename T>
+void mgvi_solve(const fr_psf *psf, const T *power, const T *diag, const T *b, T *x, int maxiter, double rtol,
+                double *hist, int *iters_done, hipStream_t st);
+
 // psfconv.hip
 template <typename T>
 void apply_rnr_approx(const fr_psf *psf, const T *x, T *y, int64_t B, hipStream_t st);
@@ -115,6 +124,9 @@ void apply_rnr_approx_ex(const fr_psf *psf, const T *x, const T *d_in, T *y, con
 template <typename T>
 void periodic_conv(const Ctx &ctx, const T *x, T *y, int64_t n_img, int64_t nx, int64_t ny, const T *K, int nk,
                    int mode, hipStream_t st);
+template <typename T>
+void periodic_conv_ex(const Ctx &ctx, const T *x, const T *d_in, T *y, const T *d_out, const T *add,
+                      int64_t n_img, int64_t nx, int64_t ny, const T *K, int nk, int mode, hipStream_t st);
 template <typename T>
 void fft2_inplace(const Ctx &ctx, c2<T> *data, int64_t batch, int64_t n0, int64_t n1, int sign, hipStream_t st);
 template <typename T>

@@ -83,6 +83,34 @@ void periodic_conv(const Ctx &ctx, const T *x, T *y, int64_t n_img, int64_t nx, 
 }
 
 // n0 and n1 are 2^p, 3 2^p or 5 2^p
+// y = d_out * irfft2(f(K) rfft2(d_in * x)) + add on the periodic nx x ny grid,
+// f(K) as kernel_factor(mode); every extra factor optional (NULL).
+template <typename T>
+void periodic_conv_ex(const Ctx &ctx, const T *x, const T *d_in, T *y, const T *d_out, const T *add,
+                      int64_t n_img, int64_t nx, int64_t ny, const T *K, int nk, int mode, hipStream_t st) {
+    if (n_img == 0) return;
+    ConvGeom g;
+    g.n_img = n_img;
+    g.rows_in = (int)nx;
+    g.rows_out = (int)nx;
+    g.n_in_cols = (int)ny;
+    g.n_out_cols = (int)ny;
+    g.log2M = ilog2(ny / 2);
+    g.log2Lc = ilog2(nx);
+    Scratch Y((size_t)n_img * nx * (ny / 2) * sizeof(c2<T>), st);
+    {
+        ProfScope prof("pconv_rows_r2c", st);
+        launch_rfft_rows<T>(ctx, g, ProDiagScaled<T>{x, d_in, nullptr, (int)nx, (int)ny}, Y.as<c2<T>>(), st);
+    }
+    const T scale = T(1) / (T(nx) * T(ny / 2));
+    {
+        ProfScope prof("pconv_cols", st);
+        launch_conv_cols<T>(ctx, g, Y.as<c2<T>>(), K, nk, mode, scale, st);
+    }
+    ProfScope prof("pconv_rows_c2r", st);
+    launch_irfft_rows<T>(ctx, g, EpiDiagScaledAdd<T>{y, d_out, nullptr, add, (int)nx, (int)ny}, Y.as<c2<T>>(), st);
+}
+
 template <typename T>
 void fft2_inplace(const Ctx &ctx, c2<T> *data, int64_t batch, int64_t n0, int64_t n1, int sign, hipStream_t st) {
     int o0 = 1, l0 = 0, o1 = 1, l1 = 0;
@@ -109,6 +137,11 @@ template void periodic_conv<float>(const Ctx &, const float *, float *, int64_t,
                                    int, hipStream_t);
 template void periodic_conv<double>(const Ctx &, const double *, double *, int64_t, int64_t, int64_t, const double *,
                                     int, int, hipStream_t);
+template void periodic_conv_ex<float>(const Ctx &, const float *, const float *, float *, const float *,
+                                      const float *, int64_t, int64_t, int64_t, const float *, int, int, hipStream_t);
+template void periodic_conv_ex<double>(const Ctx &, const double *, const double *, double *, const double *,
+                                       const double *, int64_t, int64_t, int64_t, const double *, int, int,
+                                       hipStream_t);
 template void fft2_inplace<float>(const Ctx &, float2 *, int64_t, int64_t, int64_t, int, hipStream_t);
 template void fft2_inplace<double>(const Ctx &, double2 *, int64_t, int64_t, int64_t, int, hipStream_t);
 

@@ -80,3 +80,53 @@ def reconstruct(plan, psf, vis, weight, inv_power, n_major=3, n_minor=8, cg_iter
             log(f"major {i}: H_fast {H:.6e}, ||d|| {norms[-2]:.6e} -> {norms[-1]:.6e}")
         I_prev = I
     return s, torch.exp(s), norms
+
+
+def mgvi_minor_cycle(psf, d, xi, power, s0=None, i_fixed=None, n_samples=2, n_iter=4, cg_iters=20, seed=0,
+                     log=None):
+    """MGVI (Sec. 3.3.5) on the FAST posterior in standardised coordinates: the
+    log-sky is s = s0 + A xi (A = F^-1 sqrt(P) F, the Gaussian process of the
+    prior; xi has the white prior 1/2 xi^T xi).  Each iteration draws n_samples
+    antithetic pairs +-x_j, x_j = M^-1 (a draw with covariance M) at the current
+    mean, estimates the KL and its gradient by the sample average of H and dH/dxi,
+    and takes the natural-gradient step -M^-1 g, halved until the estimate drops.
+    power: [nx, ny/2+1] P(k); d: [n_chan, nx, ny].  Returns xi, the last KL
+    estimate and the samples of the last iteration (offsets of xi)."""
+    from ._lib import FR_CONV_MUL_SQRT
+    gen = torch.Generator(device=d.device).manual_seed(seed)
+    shape = tuple(d.shape)
+
+    def logsky(z):
+        s = api.periodic_conv(power, z.contiguous(), FR_CONV_MUL_SQRT)
+        return s if s0 is None else s + s0
+
+    def kl(z, samples):
+        X = torch.stack([z + x for x in samples]).contiguous()  # [2S, n_chan, nx, ny]
+        H, g_s = api.likelihood_grad(FR_LIK_FAST, logsky(X), d, psf=psf, i_fixed=i_fixed)
+        g = api.periodic_conv(power, g_s.contiguous(), FR_CONV_MUL_SQRT) + X
+        prior = 0.5 * (X.double() ** 2).sum(dim=(1, 2, 3))
+        return float((H + prior).mean()), g.mean(dim=0).contiguous()
+
+    H = None
+    samples = []
+    for it in range(n_iter):
+        D = torch.exp(logsky(xi)).contiguous()
+        samples = []
+        for _ in range(n_samples):
+            eta0 = torch.randn(shape, generator=gen, device=d.device, dtype=d.dtype)
+            eta1 = torch.randn(shape, generator=gen, device=d.device, dtype=d.dtype)
+            x, _, _ = api.mgvi_solve(psf, power, D, api.mgvi_draw(psf, power, D, eta0, eta1), maxiter=cg_iters)
+            samples += [x, -x]
+        H, g = kl(xi, samples)
+        step, _, _ = api.mgvi_solve(psf, power, D, (-g).contiguous(), maxiter=cg_iters)
+        t, accepted = 1.0, False
+        while t >= 1.0 / 64:
+            cand = (xi + t * step).contiguous()
+            Hc, _ = kl(cand, samples)
+            if Hc < H:
+                xi, H, accepted = cand, Hc, True
+                break
+            t *= 0.5
+        if log is not None:
+            log(f"  MGVI iteration {it}: KL estimate {H:.6e} ({'step ' + format(t, '.3g') if accepted else 'no step'})")
+    return xi, H, samples
