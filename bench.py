@@ -23,7 +23,8 @@ steps (per-launch event brackets are kept out of the step timings);
 PSF applies/s is the sustained rate of back-to-back batch-8 applies.
 "reduced_psf" measures the PSF cut to |offset| <= h on the n + h padded grid:
 applies/s, accuracy against the exact R^+ N^-1 R, and the major cycles of the
-major/minor scheme it needs.
+major/minor scheme it needs.  "mgvi" times the MGVI metric apply, a draw and a
+sample (draw + 20-iteration metric CG) of the minor cycle.
 """
 
 import argparse
@@ -200,6 +201,39 @@ def reduced_psf_tradeoff(api, torch, plan, w, V, x8, inv_power, s0, supports=(12
     return {"workload": "VLA-like 512x512, 1,010,880 visibilities, batch 8, eps_noise 0.1 of the PSF peak",
             "apply": rows, "major_cycles_to_full_psf_H_after_2": counts, "n_major": n_major,
             "exact_H_per_major_cycle": {str(k): [round(v, 1) for v in Hs] for k, Hs in cycles.items()}}
+
+
+def mgvi_timing(api, torch, plan, w, n, reps=5, cg_iters=20):
+    """MGVI pieces at the VLA-like 512 x 512 shape (Sec. 3.3.5, standardised
+    coordinates): one metric apply M x, one draw, and one sample (draw + a
+    20-iteration CG solve of M x = draw), device time per call."""
+    import numpy as np
+    from synthetic.skies import power_spectrum
+    psf = api.make_psf_kernel(plan, w, eps_noise=-1e-1)
+    power = torch.from_numpy(power_spectrum(n, n)[:, : n // 2 + 1]).float().cuda().contiguous()
+    g = torch.Generator(device="cuda").manual_seed(5)
+    D = torch.exp(0.1 * torch.randn((1, n, n), device="cuda", generator=g)).contiguous()
+    e0 = torch.randn((1, n, n), device="cuda", generator=g)
+    e1 = torch.randn((1, n, n), device="cuda", generator=g)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    metric_ms = timed(lambda: api.mgvi_metric_apply(psf, power, D, e0))
+    draw_ms = timed(lambda: api.mgvi_draw(psf, power, D, e0, e1))
+    sample_ms = timed(lambda: api.mgvi_solve(psf, power, D, api.mgvi_draw(psf, power, D, e0, e1),
+                                             maxiter=cg_iters))
+    return {"workload": f"VLA-like {n}x{n}, PSF-convolution metric, FP32", "metric_apply_ms": round(metric_ms, 5),
+            "draw_ms": round(draw_ms, 5), "sample_ms": round(sample_ms, 4), "cg_iters": cg_iters,
+            "samples_per_s": round(1e3 / sample_ms, 1)}
 
 
 def build_served_jobs(api, torch, n_jobs, fp64):
@@ -484,6 +518,9 @@ def main():
         reduced = reduced_psf_tradeoff(api, torch, plan, w, V, x8, ip, s0)
         log(f"[bench] reduced PSF: {json.dumps(reduced)}")
 
+    mgvi = mgvi_timing(api, torch, plan, w, n)
+    log(f"[bench] MGVI: {json.dumps(mgvi)}")
+
     served = None
     if args.serve_seconds > 0:
         served = served_workload(api, torch, args.serve_seconds, args.serve_rate, args.serve_jobs,
@@ -521,6 +558,7 @@ def main():
             "fp64_plain_form": fp64,
             "meerkat_like": scale,
             "reduced_psf": reduced,
+            "mgvi": mgvi,
             "served": served,
         },
         "kernels_ms": {k: round(v["avg_ms"], 5) for k, v in kern.items()},
