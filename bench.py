@@ -58,7 +58,7 @@ def grid_flops(info, n_vis):
 def gridder_source_digest():
     import hashlib
     h = hashlib.sha256()
-    for f in ("gridder.hip", "eskernel.h", "objects.h"):
+    for f in ("gridder.hip", "eskernel.h", "workitem.h"):
         with open(os.path.join(ROOT, "paper_2406_09144_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

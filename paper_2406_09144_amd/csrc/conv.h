@@ -97,8 +97,9 @@ __global__ __launch_bounds__(NTHR) void k_conv_cols(c2<T> *__restrict__ Y, int M
     c2<T> *buf = reinterpret_cast<c2<T> *>(smem_raw);
     const int Lc = ODD << log2Lc;
     const int ld = plen(Lc) + 1;
-    const int col0 = blockIdx.x * C;
-    const int64_t g = blockIdx.y;
+    const unsigned w = xcd_contiguous(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+    const int col0 = (int)(w % gridDim.x) * C;
+    const int64_t g = w / gridDim.x;
     const int log2C = 31 - __builtin_clz(C);  // strips are a power of two wide
     c2<T> *Yg = Y + g * n_in * (int64_t)M;  // packed rows of image g (n_in rows stored)
     const T *Kg = K + (g % nk) * (int64_t)Lc * (M + 1);

@@ -226,6 +226,15 @@ template <int ODD> __device__ __forceinline__ int elem_of(int idx, int line, int
     return (ODD == 1) ? (idx & (L - 1)) : idx - line * L;
 }
 
+// Workgroups go to the 8 XCDs round robin (linear id mod 8) and each XCD has its
+// own L2.  Column-strip kernels, whose neighbouring strips share cache lines,
+// renumber their work so that each XCD walks one contiguous range of strips:
+// work = (lin mod 8) (n / 8) + lin / 8 when 8 divides the workgroup count n
+// (a permutation of 0 .. n - 1; the identity otherwise).
+__device__ __forceinline__ unsigned xcd_contiguous(unsigned lin, unsigned n) {
+    return (n & 7u) ? lin : (lin & 7u) * (n >> 3) + (lin >> 3);
+}
+
 // store(idx, load(idx)) for idx = threadIdx.x, threadIdx.x + NTHR, ... < n, with U
 // loads issued before their values are stored, so that U global loads per
 // thread are in flight instead of one.

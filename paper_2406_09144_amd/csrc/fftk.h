@@ -3,7 +3,7 @@
 //   k_fft_rows: each workgroup transforms `lines_per_wg` rows; element e of row r
 //               is read with pro(r, e) and written with epi(r, e, value).
 //   k_fft_cols: each workgroup transforms a strip of C adjacent columns of one
-//               [rows][cols] matrix (matrix index = blockIdx.y); only the first
+//               [rows][cols] matrix (strips of all matrices in XCD-contiguous order); only the first
 //               n_in rows are read (the rest are known zeros) and the first n_out
 //               rows are written.  Row-segment reads of C consecutive elements keep
 //               the global accesses coalesced; columns are transposed into padded
@@ -51,8 +51,9 @@ __global__ __launch_bounds__(NTHR) void k_fft_cols(Pro pro, Epi epi, int ncols, 
     c2<T> *buf = reinterpret_cast<c2<T> *>(smem_raw);
     const int L = ODD << log2P;
     const int ld = plen(L) + 1;
-    const int col0 = blockIdx.x * C;
-    const int64_t m = blockIdx.y;
+    const unsigned w = xcd_contiguous(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+    const int col0 = (int)(w % gridDim.x) * C;
+    const int64_t m = w / gridDim.x;
     const int log2C = 31 - __builtin_clz(C);  // strips are a power of two wide
     const c2<T> *twp = stage_twiddles<T, NTHR, TWL>(buf + C * ld, tw, L);
     staged_copy<NTHR>(
