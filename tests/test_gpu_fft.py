@@ -14,7 +14,9 @@ def rel(a, b):
                                    (2, 4096, 8), (2, 8192), (16384, 2), (2, 16384),
                                    # mixed radix: 3 2^p and 5 2^p (reduced PSF padding)
                                    (3, 5), (6, 10), (2, 12, 40), (48, 80), (3, 96, 160), (640, 768),
-                                   (1280, 24), (2, 12288), (10240, 2), (2, 6144), (5120, 4)])
+                                   (1280, 24), (2, 12288), (10240, 2), (2, 6144), (5120, 4),
+                                   # 8192-long columns in strips of two
+                                   (8192, 4), (2, 8192, 6)])
 @pytest.mark.parametrize("fp64", [False, True])
 @pytest.mark.parametrize("sign", [-1, 1])
 def test_fft2_matches_numpy(shape, fp64, sign):
