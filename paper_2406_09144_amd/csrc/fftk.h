@@ -93,17 +93,14 @@ void launch_fft_rows(const Ctx &ctx, Pro pro, Epi epi, int64_t nrows, int log2P,
         allow_lds(k_fft_rows<T, 256, 4, true, Pro, Epi, ODD>, lds);
         k_fft_rows<T, 256, 4, true, Pro, Epi, ODD><<<dim3((unsigned)((nrows + lpw - 1) / lpw)), 256, lds, st>>>(
             pro, epi, nrows, log2P, lpw, sign, tw);
-    } else if (L <= 8192 && twl_fits<T>(pline, L)) {
+    } else if (L < 8192 && twl_fits<T>(pline, L)) {
         const size_t lds = pline + (size_t)L * sizeof(c2<T>);
         allow_lds(k_fft_rows<T, 512, 4, true, Pro, Epi, ODD>, lds);
         k_fft_rows<T, 512, 4, true, Pro, Epi, ODD><<<dim3((unsigned)nrows), 512, lds, st>>>(pro, epi, nrows, log2P,
                                                                                          1, sign, tw);
-    } else if (twl_fits<T>(pline, L)) {
-        const size_t lds = pline + (size_t)L * sizeof(c2<T>);
-        allow_lds(k_fft_rows<T, 1024, 4, true, Pro, Epi, ODD>, lds);
-        k_fft_rows<T, 1024, 4, true, Pro, Epi, ODD><<<dim3((unsigned)nrows), 1024, lds, st>>>(pro, epi, nrows, log2P,
-                                                                                           1, sign, tw);
     } else {
+        // lines of 8192 and more: no LDS twiddle table, so that two workgroups fit
+        // per CU (8192^2 planes: 33% faster than one workgroup with the table)
         const size_t lds = pline;
         allow_lds(k_fft_rows<T, 1024, 4, false, Pro, Epi, ODD>, lds);
         k_fft_rows<T, 1024, 4, false, Pro, Epi, ODD><<<dim3((unsigned)nrows), 1024, lds, st>>>(pro, epi, nrows,
