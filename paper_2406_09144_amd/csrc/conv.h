@@ -276,13 +276,14 @@ void launch_conv_cols(const Ctx &ctx, const ConvGeom &g, c2<T> *Y, const T *K, i
         k_conv_cols<T, NT, 4, TW, ODD><<<grid, NT, ldst, st>>>(Y, M, g.log2Lc, g.rows_in, g.rows_out, C, \
                                                                K, nk, mode, scale, ctx.tw<T>(ODD, g.log2Lc)); \
     } while (0)
-    // up to two radix-4 butterflies per thread (measured at 512 x 512, batch 8: a
-    // 1024-thread strip of 8 columns beats 512 threads by 15%; the strip's
-    // load -> FFT -> multiply -> FFT -> store chain is latency-bound)
-    if (C * Lc <= 2048) {
+    // one radix-4 butterfly per thread where the strip allows (the strip's load ->
+    // FFT -> multiply -> FFT -> store chain is latency-bound; measured at
+    // 512 x 512: batch 8, 8 columns: 1024 threads 15% faster than 512; batch 1,
+    // 2 columns: 512 threads 16% faster than 256)
+    if (C * Lc <= 1024) {
         if (twl) FR_CONVCOLS(256, true);
         else FR_CONVCOLS(256, false);
-    } else if (C * Lc <= 4096) {
+    } else if (C * Lc <= 2048) {
         if (twl) FR_CONVCOLS(512, true);
         else FR_CONVCOLS(512, false);
     } else {

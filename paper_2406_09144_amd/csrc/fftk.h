@@ -146,11 +146,12 @@ void launch_fft_cols(const Ctx &ctx, Pro pro, Epi epi, int64_t nmat, int ncols, 
         k_fft_cols<T, NT, 4, TW, Pro, Epi, ODD><<<grid, NT, ldst, st>>>(pro, epi, ncols, log2P, n_in, n_out, C, \
                                                                    sign, ctx.tw<T>(ODD, log2P));               \
     } while (0)
-    // four radix-4 butterflies per thread
-    if (C * L <= 4096) {
+    // one radix-4 butterfly per thread where the strip allows (as the convolution
+    // column pass)
+    if (C * L <= 1024) {
         if (twl) FR_COLS(256, true);
         else FR_COLS(256, false);
-    } else if (C * L <= 8192) {
+    } else if (C * L <= 2048) {
         if (twl) FR_COLS(512, true);
         else FR_COLS(512, false);
     } else {
