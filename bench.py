@@ -24,7 +24,9 @@ PSF applies/s is the sustained rate of back-to-back batch-8 applies.
 "reduced_psf" measures the PSF cut to |offset| <= h on the n + h padded grid:
 applies/s, accuracy against the exact R^+ N^-1 R, and the major cycles of the
 major/minor scheme it needs.  "mgvi" times the MGVI metric apply, a draw and a
-sample (draw + 20-iteration metric CG) of the minor cycle.
+sample (draw + 20-iteration metric CG) of the minor cycle.  "taylor_w" is the
+same (de)gridding with the w-term as a Taylor series instead of w-stacking (the
+plan option for small w-phases; `value` stays on improved w-stacking).
 """
 
 import argparse
@@ -234,6 +236,29 @@ def mgvi_timing(api, torch, plan, w, n, reps=5, cg_iters=20):
     return {"workload": f"VLA-like {n}x{n}, PSF-convolution metric, FP32", "metric_apply_ms": round(metric_ms, 5),
             "draw_ms": round(draw_ms, 5), "sample_ms": round(sample_ms, 4), "cg_iters": cg_iters,
             "samples_per_s": round(1e3 / sample_ms, 1)}
+
+
+def taylor_timing(api, torch, obs, sky, V, w, n, steps=5):
+    """The same (de)gridding with the w-term as a Taylor series (FR_W_TAYLOR:
+    3 terms instead of 7 w-planes at eps 1e-5 on this array), device time per
+    call and the rate."""
+    pl = api.Plan(obs.uvw, obs.freq, n, n, obs.dx, obs.dy, eps=1e-5, w_taylor=True)
+    vis = api.degrid(pl, sky)
+    img = api.grid(pl, V, w)
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record()
+    for _ in range(steps):
+        api.degrid(pl, sky, out=vis)
+    e[1].record()
+    for _ in range(steps):
+        api.grid(pl, V, w, out=img)
+    e[2].record()
+    torch.cuda.synchronize()
+    dg, gr = e[0].elapsed_time(e[1]) / steps, e[1].elapsed_time(e[2]) / steps
+    info = pl.info
+    return {"w_taylor": info["w_taylor"], "n_planes": info["n_planes"], "support": info["support"],
+            "degrid_ms": round(dg, 5), "grid_ms": round(gr, 5), "vis_per_s": 2 * obs.n_vis / ((dg + gr) * 1e-3)}
 
 
 def build_served_jobs(api, torch, n_jobs, fp64):
@@ -518,6 +543,8 @@ def main():
         reduced = reduced_psf_tradeoff(api, torch, plan, w, V, x8, ip, s0)
         log(f"[bench] reduced PSF: {json.dumps(reduced)}")
 
+    taylor = taylor_timing(api, torch, obs, sky, V, w, n)
+    log(f"[bench] Taylor in w: {json.dumps(taylor)}")
     mgvi = mgvi_timing(api, torch, plan, w, n)
     log(f"[bench] MGVI: {json.dumps(mgvi)}")
 
@@ -559,6 +586,7 @@ def main():
             "meerkat_like": scale,
             "reduced_psf": reduced,
             "mgvi": mgvi,
+            "taylor_w": taylor,
             "served": served,
         },
         "kernels_ms": {k: round(v["avg_ms"], 5) for k, v in kern.items()},

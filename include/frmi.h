@@ -61,7 +61,9 @@ enum fr_status {
 enum fr_plan_flags {
     FR_FP64 = 1,        /* double precision buffers and arithmetic */
     FR_DIVIDE_BY_N = 2, /* include the 1/n factor of the w-term C(l, w) (Sec. 2) */
-    FR_COPLANAR = 4     /* treat every w as 0 (the paper's coplanar case, Sec. 3.3.2) */
+    FR_COPLANAR = 4,    /* treat every w as 0 (the paper's coplanar case, Sec. 3.3.2) */
+    FR_W_TAYLOR = 8     /* expand the w-term in a Taylor series when that needs fewer
+                           planes than improved w-stacking at this epsilon */
 };
 
 enum fr_lik_mode { FR_LIK_EXACT = 0, FR_LIK_FAST = 1 };
@@ -97,6 +99,7 @@ typedef struct fr_plan_info {
     int tile;               /* uv tile side in cells */
     int64_t n_workitems;
     size_t resident_bytes;  /* device memory the plan holds */
+    int w_taylor;           /* 1: the planes are Taylor terms in w, not w-planes */
 } fr_plan_info;
 
 /* Library version string. */
@@ -118,7 +121,15 @@ void fr_ctx_destroy(fr_ctx *ctx);
  *   dx, dy   pixel sizes (radians, > 0); the field must satisfy l^2 + m^2 < 1
  *   epsilon  requested relative L2 accuracy of R and R^+ against the direct
  *            sums, in [1e-14, 1e-1]; FP32 plans accept epsilon >= 1e-6
- *   flags    FR_FP64 | FR_DIVIDE_BY_N | FR_COPLANAR
+ *   flags    FR_FP64 | FR_DIVIDE_BY_N | FR_COPLANAR | FR_W_TAYLOR
+ *            FR_W_TAYLOR: with t = (n - 1) - yc in [-h, h] over the image, write
+ *            exp(-2 pi i w t) = sum_j (2 pi w h)^j / j! (-i t / h)^j and keep the
+ *            J + 1 terms whose truncation, (2 pi w_max h)^(J+1) / (J+1)!, is below
+ *            epsilon / 8: term j is a 2-D plane of the image times (-i t/h)^j,
+ *            weighted per visibility by (2 pi w h)^j / j!.  Used only when
+ *            2 pi w_max h <= 1 (no term above 1) and J + 1 is below the plane count
+ *            of improved w-stacking (small w: short arrays, narrow fields);
+ *            otherwise the plan stays w-stacked.
  *   n_wplanes 0 = derive from epsilon; otherwise the number of w-planes to use
  *            (must be >= the derived minimum)
  * The method itself is exact (Sec. 2); the gridder reaches it up to epsilon with

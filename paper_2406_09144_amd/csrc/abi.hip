@@ -85,8 +85,12 @@ int fr_ctx_create(int device, fr_ctx **out) {
 
 void fr_ctx_destroy(fr_ctx *ctx) {
     if (!ctx) return;
-    DeviceGuard dg(ctx->c.device);
-    delete ctx;
+    try {
+        DeviceGuard dg(ctx->c.device);
+        delete ctx;
+    } catch (...) {
+        // the HIP runtime is already gone (process teardown): its memory goes with it
+    }
 }
 
 static size_t real_size(bool fp64) { return fp64 ? 8 : 4; }
@@ -143,8 +147,12 @@ int fr_psf_get_kernels(const fr_psf *psf, void *K_R, void *K_N, void *stream) {
 
 void fr_psf_destroy(fr_psf *psf) {
     if (!psf) return;
-    DeviceGuard dg(psf->ctx->device);
-    delete psf;
+    try {
+        DeviceGuard dg(psf->ctx->device);
+        delete psf;
+    } catch (...) {
+        // the HIP runtime is already gone (process teardown): its memory goes with it
+    }
 }
 
 int fr_apply_RNR_approx(fr_psf *psf, const void *x, void *y, int64_t B, void *stream) {
@@ -191,7 +199,7 @@ int fr_plan_create(fr_ctx *ctx, const double *uvw_m, int64_t n_row, const double
     FR_REQUIRE(freq_hz, "freq_hz is NULL");
     FR_REQUIRE(is_pow2(nx) && is_pow2(ny) && nx >= 16 && ny >= 16 && nx <= 8192 && ny <= 8192,
                "nx, ny must be powers of two in [16, 8192]");
-    FR_REQUIRE((flags & ~(FR_FP64 | FR_DIVIDE_BY_N | FR_COPLANAR)) == 0, "unknown flag");
+    FR_REQUIRE((flags & ~(FR_FP64 | FR_DIVIDE_BY_N | FR_COPLANAR | FR_W_TAYLOR)) == 0, "unknown flag");
     const bool fp64 = flags & FR_FP64;
     FR_REQUIRE(!fp64 || (nx <= 4096 && ny <= 4096), "FP64 plans support nx, ny <= 4096");
     FR_REQUIRE(dx > 0 && dy > 0 && std::isfinite(dx) && std::isfinite(dy), "pixel sizes must be > 0");
@@ -219,6 +227,7 @@ int fr_plan_create(fr_ctx *ctx, const double *uvw_m, int64_t n_row, const double
     pl->fp64 = fp64;
     pl->divide_by_n = flags & FR_DIVIDE_BY_N;
     pl->coplanar = flags & FR_COPLANAR;
+    pl->want_taylor = flags & FR_W_TAYLOR;
     pl->eps = epsilon;
     pl->dx_ = dx;
     pl->dy_ = dy;
@@ -233,8 +242,12 @@ int fr_plan_create(fr_ctx *ctx, const double *uvw_m, int64_t n_row, const double
 
 void fr_plan_destroy(fr_plan *plan) {
     if (!plan) return;
-    DeviceGuard dg(plan->ctx->device);
-    delete plan;
+    try {
+        DeviceGuard dg(plan->ctx->device);
+        delete plan;
+    } catch (...) {
+        // the HIP runtime is already gone (process teardown): its memory goes with it
+    }
 }
 
 int fr_plan_get_info(const fr_plan *pl, fr_plan_info *info) {
@@ -260,6 +273,7 @@ int fr_plan_get_info(const fr_plan *pl, fr_plan_info *info) {
     info->tile = pl->tile;
     info->n_workitems = pl->n_wi;
     info->resident_bytes = pl->resident;
+    info->w_taylor = pl->taylor ? 1 : 0;
     FR_API_END
 }
 

@@ -133,6 +133,9 @@ void launch_fft_cols(const Ctx &ctx, Pro pro, Epi epi, int64_t nmat, int ncols, 
         C = 2;
         allow_twl = false;
     }
+    // few matrices (e.g. three Taylor planes): narrower strips so the grid still
+    // covers every CU a couple of times
+    while (C > 2 && (int64_t)(ncols / C) * nmat < 2 * (int64_t)std::max(ctx.n_cu, 1)) C >>= 1;
     FR_REQUIRE(is_pow2(C), "column strip width must be a power of two");
     const size_t lds = (size_t)C * (plen(L) + 1) * sizeof(c2<T>);
     FR_REQUIRE(lds <= (size_t)kLdsBytes && L <= 16384, "column FFT length too large");

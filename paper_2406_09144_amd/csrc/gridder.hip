@@ -40,7 +40,8 @@ constexpr int kTile = 32;
 template <typename T>
 __global__ void k_vis_coords(const double *__restrict__ uvw, const double *__restrict__ freq, int64_t n_vis,
                              int n_chan, int log2nu, int log2nv, double dx, double dy, int W, int Ww, int coplanar,
-                             double w0, double dw, double yc, int ntv, int n_tiles, int n_p0,
+                             double w0, double dw, double yc, double two_pi_h, int taylor, int ntv, int n_tiles,
+                             int n_p0,
                              uint32_t *__restrict__ key, uint32_t *__restrict__ idx, uint32_t *__restrict__ cell,
                              T *__restrict__ du, T *__restrict__ dv, T *__restrict__ dwf, T *__restrict__ ph) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -72,7 +73,11 @@ __global__ void k_vis_coords(const double *__restrict__ uvw, const double *__res
     const int tu = a0 / kTile, tv = b0 / kTile;
     int p0 = 0;
     double fw = 0, phc = 0;
-    if (!coplanar) {
+    if (taylor) {
+        fw = two_pi_h * w;  // the Taylor variable x = 2 pi w h; every term is a plane
+        phc = w * yc;
+        phc -= rint(phc);
+    } else if (!coplanar) {
         const double kw = (w - w0) / dw;
         p0 = (int)ceil(kw - 0.5 * Ww);
         fw = kw - p0;
@@ -161,11 +166,23 @@ template <> __device__ __forceinline__ float es_eval<float>(float z, float beta)
     return q >= 0.0f ? __builtin_amdgcn_exp2f(beta * kLog2e * (__builtin_amdgcn_sqrtf(q) - 1.0f)) : 0.0f;
 }
 
+// Weight of plane p for a visibility with w coordinate x: the ES w-kernel at
+// x - p (improved w-stacking, x in planes) or the Taylor coefficient x^p / p!
+// (x = 2 pi w h).
+template <typename T> __device__ __forceinline__ T plane_weight(T x, int p, int Ww, T wbeta, int taylor) {
+    if (taylor) {
+        T c = T(1);
+        for (int j = 1; j <= p; ++j) c *= x / T(j);
+        return c;
+    }
+    return es_eval<T>((x - T(p)) * (T(2) / T(Ww)), wbeta);
+}
+
 // ------------------------------------------------------------------ degrid
 template <typename T, int W, int NTHR, int VPT>
 __global__ __launch_bounds__(NTHR) void k_degrid(const WorkItem *__restrict__ wis, const c2<T> *__restrict__ planes,
                                                  int log2nu, int log2nv, int Ww, T beta, T wbeta, int coplanar,
-                                                 const uint32_t *__restrict__ r_idx,
+                                                 int taylor, const uint32_t *__restrict__ r_idx,
                                                  const uint32_t *__restrict__ r_cell, const T *__restrict__ r_du,
                                                  const T *__restrict__ r_dv, const T *__restrict__ r_dw,
                                                  const T *__restrict__ r_ph, c2<T> *__restrict__ vis) {
@@ -240,7 +257,7 @@ __global__ __launch_bounds__(NTHR) void k_degrid(const WorkItem *__restrict__ wi
 #pragma unroll
         for (int k = 0; k < VPT; ++k) {
             if (!ok[k]) continue;
-            const T kw = coplanar ? T(1) : es_eval<T>((fw[k] - T(pw)) * (T(2) / T(Ww)), wbeta);
+            const T kw = coplanar ? T(1) : plane_weight<T>(fw[k], pw, Ww, wbeta, taylor);
             T sx = 0, sy = 0;
 #pragma unroll
             for (int a = 0; a < W; ++a) {
@@ -331,7 +348,7 @@ template <typename T, int W> constexpr int grid_reg_planes() {
 template <typename T, int W, int NTHR>
 __global__ __launch_bounds__(NTHR) void k_grid_partial(const WorkItem *__restrict__ wis, c2<T> *__restrict__ partial,
                                                        int Ww, int ppass, T beta, T wbeta, int coplanar,
-                                                       const uint32_t *__restrict__ r_idx,
+                                                       int taylor, const uint32_t *__restrict__ r_idx,
                                                        const uint32_t *__restrict__ r_cell,
                                                        const T *__restrict__ r_du, const T *__restrict__ r_dv,
                                                        const T *__restrict__ r_dw, const T *__restrict__ r_ph,
@@ -441,7 +458,7 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial(const WorkItem *__restric
                     const T xw = r_dw[pos];
 #pragma unroll
                     for (int p = 0; p < PR; ++p)
-                        l_kw[p] = p < np ? es_eval<T>((xw - T(g0 + p)) * (T(2) / T(Ww)), wbeta) : T(0);
+                        l_kw[p] = p < np ? plane_weight<T>(xw, g0 + p, Ww, wbeta, taylor) : T(0);
                 }
                 l_y = y;
             }
@@ -634,7 +651,7 @@ __global__ __launch_bounds__(kTile * kTile) void k_grid_assemble(const c2<T> *__
 template <typename T> struct DegridRowPro {
     const T *img, *fac, *tpix;
     const double *wplane;
-    int nx, ny, nv, coplanar;
+    int nx, ny, nv, coplanar, taylor;
     __device__ c2<T> operator()(int64_t line, int b) const {
         const int p = (int)line >> (31 - __builtin_clz(nx));
         const int i = (int)line & (nx - 1);
@@ -643,6 +660,17 @@ template <typename T> struct DegridRowPro {
         const int64_t q = (int64_t)i * ny + j;
         const T f = img[q] * fac[q];
         if (coplanar) return mk<T>(f, T(0));
+        if (taylor) {
+            // Taylor term p: f (-i tau)^p with tau = ((n - 1) - yc) / h
+            T g = f;
+            for (int k = 0; k < p; ++k) g *= tpix[q];
+            switch (p & 3) {
+                case 0: return mk<T>(g, T(0));
+                case 1: return mk<T>(T(0), -g);
+                case 2: return mk<T>(-g, T(0));
+                default: return mk<T>(T(0), g);
+            }
+        }
         T ph = (T)wplane[p] * tpix[q];
         ph -= rint(ph);
         T s, c;
@@ -708,7 +736,7 @@ template <typename T, int NTHR, int BPT, int ACC, bool TWL>
 __global__ __launch_bounds__(NTHR) void k_grid_rows(const c2<T> *__restrict__ planes, int n_planes, int log2nu,
                                                     int log2nv, int nx, int ny, const T *__restrict__ fac,
                                                     const T *__restrict__ tpix, const double *__restrict__ wplane,
-                                                    int coplanar, T *__restrict__ img, int lines,
+                                                    int coplanar, int taylor, T *__restrict__ img, int lines,
                                                     const c2<T> *__restrict__ tw) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     c2<T> *buf = reinterpret_cast<c2<T> *>(smem_raw);
@@ -741,6 +769,13 @@ __global__ __launch_bounds__(NTHR) void k_grid_rows(const c2<T> *__restrict__ pl
                     const c2<T> g = line[padx((j - ny / 2) & (nv - 1))];
                     if (coplanar) {
                         acc[k] += g.x;
+                    } else if (taylor) {
+                        // adjoint of term p: tau^p Re(i^p G)
+                        const int p = p0 + l;
+                        T tp = T(1);
+                        for (int e = 0; e < p; ++e) tp *= tpix[(int64_t)i * ny + j];
+                        const T re = (p & 1) ? ((p & 2) ? g.y : -g.y) : ((p & 2) ? -g.x : g.x);
+                        acc[k] += tp * re;
                     } else {
                         T ph = wp * tpix[(int64_t)i * ny + j];
                         ph -= rint(ph);
@@ -788,7 +823,7 @@ void launch_degrid_w(const fr_plan *pl, const WorkItem *wis, int64_t nwi, const 
     ProfScope prof("degrid", st);
     kern<<<dim3((unsigned)nwi), kGridThreads, lds, st>>>(
         wis, planes, ilog2(pl->nu), ilog2(pl->nv), pl->Ww, (T)pl->beta, (T)pl->wbeta, pl->coplanar ? 1 : 0,
-        pl->r_idx.as<uint32_t>(), pl->r_cell.as<uint32_t>(), pl->r_du.as<T>(), pl->r_dv.as<T>(), pl->r_dw.as<T>(),
+        pl->taylor ? 1 : 0, pl->r_idx.as<uint32_t>(), pl->r_cell.as<uint32_t>(), pl->r_du.as<T>(), pl->r_dv.as<T>(), pl->r_dw.as<T>(),
         pl->r_ph.as<T>(), vis);
     LAUNCH_CHECK();
 }
@@ -814,7 +849,8 @@ void launch_grid_w(const fr_plan *pl, int64_t chan, c2<T> *planes, const c2<T> *
             ProfScope prof("grid", st);
             kern<<<dim3((unsigned)(i1 - i0)), NTHR, lds, st>>>(
                 pl->gwi.as<WorkItem>() + i0, partial.as<c2<T>>(), pl->Ww, ppass, (T)pl->beta, (T)pl->wbeta,
-                pl->coplanar ? 1 : 0, pl->r_idx.as<uint32_t>(), pl->r_cell.as<uint32_t>(), pl->r_du.as<T>(),
+                pl->coplanar ? 1 : 0, pl->taylor ? 1 : 0, pl->r_idx.as<uint32_t>(), pl->r_cell.as<uint32_t>(),
+                pl->r_du.as<T>(),
                 pl->r_dv.as<T>(), pl->r_dw.as<T>(), pl->r_ph.as<T>(), vis, weight, ybound, nbb);
             LAUNCH_CHECK();
         }
@@ -856,7 +892,7 @@ template <typename T>
 void image_to_planes(const fr_plan *pl, const T *img_c, c2<T> *planes, hipStream_t st) {
     const int l2u = ilog2(pl->nu), l2v = ilog2(pl->nv);
     DegridRowPro<T> pro{img_c, pl->fac.as<T>(), pl->tpix.as<T>(), pl->wplane.as<double>(),
-                        (int)pl->nx, (int)pl->ny, (int)pl->nv, pl->coplanar ? 1 : 0};
+                        (int)pl->nx, (int)pl->ny, (int)pl->nv, pl->coplanar ? 1 : 0, pl->taylor ? 1 : 0};
     DegridRowEpi<T> epi{planes, (int)pl->nx, l2u, l2v};
     {
         ProfScope prof("wplane_rows_fwd", st);
@@ -889,7 +925,8 @@ void planes_to_image(const fr_plan *pl, const c2<T> *planes_c, const uint8_t *ac
         allow_lds(kern, lds);                                                                                   \
         kern<<<dim3((unsigned)pl->nx), NT, lds, st>>>(planes, pl->n_planes, l2u, l2v, (int)pl->nx, (int)pl->ny, \
                                                       pl->fac.as<T>(), pl->tpix.as<T>(), pl->wplane.as<double>(), \
-                                                      pl->coplanar ? 1 : 0, img_c, (LINES), pl->ctx->tw<T>(l2v)); \
+                                                      pl->coplanar ? 1 : 0, pl->taylor ? 1 : 0, img_c, (LINES),       \
+                                                      pl->ctx->tw<T>(l2v));                                           \
     } while (0)
     if (nv <= 4096) FR_GRID_ROWS(256, true, args_lines_small);
     else if (pl_line + twb <= (size_t)kLdsBytes) FR_GRID_ROWS(1024, true, 1);
@@ -1001,7 +1038,8 @@ static void build_records(fr_plan *pl, const DevBuf &d_uvw, const DevBuf &d_freq
     const int64_t blocks = (n + 255) / 256;
     k_vis_coords<T><<<dim3((unsigned)blocks), 256>>>(
         d_uvw.as<double>(), d_freq.as<double>(), n, (int)pl->n_chan, ilog2(pl->nu), ilog2(pl->nv),
-        pl->dx_, pl->dy_, pl->W, pl->Ww, pl->coplanar ? 1 : 0, pl->w0, pl->dw, pl->yc, ntv, n_tiles, n_p0,
+        pl->dx_, pl->dy_, pl->W, pl->Ww, pl->coplanar ? 1 : 0, pl->w0, pl->dw, pl->yc,
+        2.0 * 3.14159265358979323846 * pl->taylor_h, pl->taylor ? 1 : 0, ntv, n_tiles, n_p0,
         key.as<uint32_t>(), idx.as<uint32_t>(), cell.as<uint32_t>(), du.as<T>(), dv.as<T>(), dwf.as<T>(), ph.as<T>());
     LAUNCH_CHECK();
     // stable radix sort of (bucket, cell in tile) keys; the permutation gathers the records
@@ -1192,8 +1230,34 @@ void plan_build(fr_plan *pl, const double *uvw_m, const double *freq_hz) {
         pl->dw = dw;
         pl->n_planes = npl;
         pl->w0 = wmin - (0.5 * pl->Ww - 1.0 + delta) * dw;
+        // Taylor expansion in w: exp(-2 pi i w t) = sum_j x^j / j! (-i t / h)^j with
+        // x = 2 pi w h <= x_max; J + 1 terms leave x_max^(J+1) / (J+1)! of it, kept
+        // below epsilon / 8 (the uv kernel keeps 2 dimensions of the rest).  Only
+        // for x_max <= 1, where no term exceeds 1 (no cancellation between terms).
+        const double x_max = 2.0 * 3.14159265358979323846 * wmax * h;
+        if (pl->want_taylor && pl->n_wplanes_req == 0 && x_max <= 1.0) {
+            int J = 0;
+            double rem = x_max;  // x_max^(J+1) / (J+1)!
+            while (rem > pl->eps / 8 && J < 15) {
+                ++J;
+                rem *= x_max / (J + 1);
+            }
+            if (J + 1 < npl) {
+                pl->taylor = true;
+                pl->taylor_h = h;
+                pl->W = es_support(pl->eps * 7.0 / 8.0, 2, 4);
+                pl->beta = es_beta(pl->W);
+                pl->eps_bound = 2 * kESAliasBound[pl->W] + rem;
+                kuv = ESKernel(pl->W, pl->beta);
+                pl->Ww = J + 1;
+                pl->wbeta = 0;
+                pl->n_planes = J + 1;
+                pl->w0 = 0;
+                pl->dw = 1;
+            }
+        }
     }
-    ESKernel kw(pl->Ww > 1 ? pl->Ww : 4, pl->Ww > 1 ? pl->wbeta : 9.2);
+    ESKernel kw(pl->Ww > 1 && !pl->taylor ? pl->Ww : 4, pl->Ww > 1 && !pl->taylor ? pl->wbeta : 9.2);
     // --- per-pixel factors
     std::vector<double> cu(nx), cv(ny);
     for (int64_t i = 0; i < nx; ++i) cu[i] = 1.0 / kuv.psi_hat((double)(i - nx / 2) / (double)pl->nu);
@@ -1207,7 +1271,9 @@ void plan_build(fr_plan *pl, const double *uvw_m, const double *freq_hz) {
             const double y = n_minus_1(l, m);
             const double a = pl->divide_by_n ? 1.0 / (1.0 + y) : 1.0;
             double f = a * cu[i] * cv[j];
-            if (!coplanar) {
+            if (pl->taylor) {
+                tpix[i * ny + j] = (y - pl->yc) / pl->taylor_h;
+            } else if (!coplanar) {
                 const double t = y - pl->yc;
                 tpix[i * ny + j] = t;
                 f /= psiw(pl->dw * t);
@@ -1217,7 +1283,7 @@ void plan_build(fr_plan *pl, const double *uvw_m, const double *freq_hz) {
         }
     }
     std::vector<double> wpl(pl->n_planes);
-    for (int p = 0; p < pl->n_planes; ++p) wpl[p] = coplanar ? 0.0 : pl->w0 + p * pl->dw;
+    for (int p = 0; p < pl->n_planes; ++p) wpl[p] = coplanar || pl->taylor ? 0.0 : pl->w0 + p * pl->dw;
     if (pl->fp64) {
         pl->fac = upload<double>(fac);
         pl->tpix = upload<double>(tpix);

@@ -32,6 +32,9 @@ struct fr_plan {
     double wbeta = 0;
     int n_planes = 1;
     double w0 = 0, dw = 1, yc = 0;  // plane p at w0 + p dw; n - 1 measured from yc
+    bool want_taylor = false;       // FR_W_TAYLOR requested
+    bool taylor = false;            // planes are the Taylor terms of exp(-2 pi i w t)
+    double taylor_h = 0;            // |t| <= h over the image
     int tile = 32;
     double eps = 0, eps_bound = 0;
     double dx_ = 0, dy_ = 0;  // pixel sizes (radians)
@@ -40,7 +43,7 @@ struct fr_plan {
     int64_t max_wi_count = 0;
     // per-pixel factors (precision of the plan)
     frmi::DevBuf fac;   // [nx][ny] a / (Psi_u Psi_v Psi_w)
-    frmi::DevBuf tpix;  // [nx][ny] (n - 1) - yc, w-stacking only
+    frmi::DevBuf tpix;  // [nx][ny] (n - 1) - yc (w-stacking) or ((n - 1) - yc) / h (Taylor)
     frmi::DevBuf nfac;  // [nx][ny] a (1/n or 1)
     frmi::DevBuf wplane;  // [n_planes] double: w of each plane
     // sorted visibility records (structure of arrays)
