@@ -533,6 +533,188 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial(const WorkItem *__restric
     }
 }
 
+// The same spread on the matrix cores (FP32, W <= 8, at most 8 planes per pass).
+// Within a run of equal base cells the register sums are a dense contraction,
+//   S[cell][n] = sum_k A[cell][k] B[k][n],
+//   A[cell][k] = psi(du_k - a) psi(dv_k - b)   (cell = a W + b, 64 rows in 4 blocks of 16),
+//   B[k][n]    = y_k times the plane-(n/2) weight of visibility k, real part for even
+//                n and imaginary for odd (n < 16),
+// taken four visibilities at a time with v_mfma_f32_16x16x4_f32 per block of 16
+// cells.  Operand layout of that instruction (checked on the hardware): lane l
+// supplies A[l % 16][l / 16] and B[l / 16][l % 16] and holds D[4 (l / 16) + r][l % 16],
+// r < 4.  The 1-D kernel values of 8 visibilities are evaluated at a time (lane
+// 8 v + a holds psi(d_v - a)) and A is gathered from them with lane permutes;
+// visibilities outside the current run get A = 0.  Runs, flushes to the 64-bit
+// fixed-point LDS tiles and the band output are as in k_grid_partial.
+template <int W, int NTHR>
+__global__ __launch_bounds__(NTHR) void k_grid_partial_mfma(
+    const WorkItem *__restrict__ wis, c2<float> *__restrict__ partial, int Ww, int ppass, float beta, float wbeta,
+    int coplanar, int taylor, const uint32_t *__restrict__ r_idx, const uint32_t *__restrict__ r_cell,
+    const float *__restrict__ r_du, const float *__restrict__ r_dv, const float *__restrict__ r_dw,
+    const float *__restrict__ r_ph, const c2<float> *__restrict__ vis, const float *__restrict__ weight,
+    const float *__restrict__ ybound_partials, int n_ybound) {
+    static_assert(W <= 8, "one lane per 1-D kernel value of 8 visibilities");
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    long long *tile = reinterpret_cast<long long *>(smem_raw);  // [ppass][2][TS * TS]
+    constexpr int TS = kTile + W - 1;
+    constexpr int TT = TS * TS;
+    constexpr int NWAVE = NTHR / 64;
+    constexpr int NBLK = (W * W + 15) / 16;  // blocks of 16 cells
+    const WorkItem it = wis[blockIdx.x];
+    __shared__ float wmax[NWAVE];
+    {
+        float m = 0.0f;
+        for (int q = threadIdx.x; q < n_ybound; q += NTHR) m = fmaxf(m, ybound_partials[q]);
+        for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+        if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+    }
+    __syncthreads();
+    float ymax = 0.0f;
+#pragma unroll
+    for (int q = 0; q < NWAVE; ++q) ymax = fmaxf(ymax, wmax[q]);
+    int kexp = 0;
+    if (ymax > 0.0f && ymax <= 3.0e38f) {
+        int e;
+        frexp(2.0 * (double)ymax * (double)it.count, &e);  // bound < 2^(e-1)
+        kexp = 62 - e;
+    }
+    c2<float> *out = partial + (int64_t)blockIdx.x * Ww * TT;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const float two_over_W = 2.0f / (float)W;
+    // A operand: row (cell) lane % 16 of each block, column (visibility) lane / 16
+    const int kk = lane >> 4;
+    int a_addr[NBLK], b_addr[NBLK];
+    bool a_ok[NBLK];
+#pragma unroll
+    for (int blk = 0; blk < NBLK; ++blk) {
+        const int c = 16 * blk + (lane & 15);
+        a_ok[blk] = c < W * W;
+        const int ca = a_ok[blk] ? c / W : 0, cb = a_ok[blk] ? c - (c / W) * W : 0;
+        a_addr[blk] = 4 * ca;  // byte offset of psi(du - a) inside a visibility's 8 lanes
+        b_addr[blk] = 4 * cb;
+    }
+    // B operand: column n = lane % 16 -> plane n / 2, real or imaginary part
+    const int n_col = lane & 15, p_col = n_col >> 1, im_col = n_col & 1;
+    // D: lane holds cells 16 blk + 4 (lane / 16) + r of column n_col
+    const int share = (it.count + NWAVE - 1) / NWAVE;
+    const int v_begin = min(it.count, wave * share), v_end = min(it.count, v_begin + share);
+    const int pp = min(ppass, 8);
+    for (int g0 = 0; g0 < Ww; g0 += pp) {
+        const int np = min(pp, Ww - g0);
+        for (int q = threadIdx.x; q < np * 2 * TT; q += NTHR) tile[q] = 0;
+        __syncthreads();
+        v4f acc[NBLK];
+#pragma unroll
+        for (int blk = 0; blk < NBLK; ++blk) acc[blk] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+        int run_cell = -1;
+        auto flush = [&]() {
+            const int ru = run_cell & 0xffff, rv = run_cell >> 16;
+            if (p_col < np) {
+                long long *tp = tile + (2 * p_col + im_col) * TT;
+#pragma unroll
+                for (int blk = 0; blk < NBLK; ++blk)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int c = 16 * blk + 4 * kk + r;
+                        if (c < W * W) {
+                            const int ca = c / W, cb = c - (c / W) * W;
+                            const long long v = (long long)rint(ldexp((double)acc[blk][r], kexp));
+                            atomicAdd(reinterpret_cast<unsigned long long *>(tp + (ru + ca) * TS + rv + cb),
+                                      (unsigned long long)v);
+                        }
+                    }
+            }
+#pragma unroll
+            for (int blk = 0; blk < NBLK; ++blk) acc[blk] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+        };
+        for (int b0 = v_begin; b0 < v_end; b0 += 64) {
+            const int nb = min(64, v_end - b0);
+            int l_cell = 0;
+            float l_xu = 0.0f, l_xv = 0.0f, l_xw = 0.0f;
+            c2<float> l_y = mk<float>(0.0f, 0.0f);
+            if (lane < nb) {
+                const int64_t pos = it.start + b0 + lane;
+                l_cell = (int)r_cell[pos];
+                const uint32_t id = r_idx[pos];
+                const uint32_t vi = id & 0x7fffffffu;
+                c2<float> y = vis ? vis[vi] : mk<float>(1.0f, 0.0f);
+                if (weight) {
+                    const float wt = weight[vi];
+                    y.x *= wt;
+                    y.y *= wt;
+                }
+                if (id >> 31) y.y = -y.y;
+                l_xu = r_du[pos];
+                l_xv = r_dv[pos];
+                if (!coplanar) {
+                    float sn, cs;
+                    sincos_cycles(r_ph[pos], &sn, &cs);
+                    y = cmul<float>(y, mk<float>(cs, sn));
+                    l_xw = r_dw[pos];
+                }
+                l_y = y;
+            }
+            for (int k0 = 0; k0 < nb; k0 += 8) {
+                // 1-D kernel values of visibilities k0 .. k0 + 7: lane 8 v + a
+                const int src = min(k0 + (lane >> 3), 63), ta = lane & 7;
+                const float xu_v = __shfl(l_xu, src, 64), xv_v = __shfl(l_xv, src, 64);
+                const float phu = ta < W ? es_eval<float>((xu_v - (float)ta) * two_over_W, beta) : 0.0f;
+                const float phv = ta < W ? es_eval<float>((xv_v - (float)ta) * two_over_W, beta) : 0.0f;
+                const int kend = min(k0 + 8, nb);
+                int k = k0;
+                while (k < kend) {
+                    // the run segment [k, ke) of equal base cells inside this group
+                    const int cell = __builtin_amdgcn_readlane(l_cell, k);
+                    if (cell != run_cell) {
+                        if (run_cell >= 0) flush();
+                        run_cell = cell;
+                    }
+                    int ke = k + 1;
+                    while (ke < kend && __builtin_amdgcn_readlane(l_cell, ke) == cell) ++ke;
+#pragma unroll
+                    for (int s = 0; s < 2; ++s) {
+                        const int q0 = k0 + 4 * s;  // visibilities q0 .. q0 + 3
+                        if (q0 + 4 <= k || q0 >= ke) continue;
+                        const int q = q0 + kk;       // this lane's visibility in A and B
+                        const bool in_run = q >= k && q < ke;
+                        // B: y_q times its weight for plane g0 + p_col
+                        const int sq = min(q, 63);
+                        const float yx = __shfl(l_y.x, sq, 64), yy = __shfl(l_y.y, sq, 64);
+                        const float xw = __shfl(l_xw, sq, 64);
+                        float bval = 0.0f;
+                        if (in_run && p_col < np) {
+                            const float kw = coplanar ? 1.0f : plane_weight<float>(xw, g0 + p_col, Ww, wbeta, taylor);
+                            bval = kw * (im_col ? yy : yx);
+                        }
+                        // A: psi(du_q - a) psi(dv_q - b) of the lane's cell in each block
+                        const int vbase = 32 * (q - k0);  // byte offset of visibility q's 8 lanes
+#pragma unroll
+                        for (int blk = 0; blk < NBLK; ++blk) {
+                            const float u = lane_permute(phu, vbase + a_addr[blk]);
+                            const float v = lane_permute(phv, vbase + b_addr[blk]);
+                            const float aval = (in_run && a_ok[blk]) ? u * v : 0.0f;
+                            acc[blk] = __builtin_amdgcn_mfma_f32_16x16x4f32(aval, bval, acc[blk], 0, 0, 0);
+                        }
+                    }
+                    k = ke;
+                }
+            }
+        }
+        if (run_cell >= 0) flush();
+        __syncthreads();
+        const int r0 = it.rows & 0xffff, r1 = it.rows >> 16;
+        const int band = (r1 - r0 + 1) * TS;
+        for (int q = threadIdx.x; q < np * band; q += NTHR) {
+            const int p = q / band, r = r0 * TS + (q - p * band);
+            out[(int64_t)(g0 + p) * TT + r] = mk<float>((float)ldexp((double)tile[2 * p * TT + r], -kexp),
+                                                        (float)ldexp((double)tile[2 * p * TT + TT + r], -kexp));
+        }
+        __syncthreads();
+    }
+}
+
 // partials[b] = block b's maximum over visibilities of (|Re v| + |Im v|) |w|
 // (v = 1 without visibilities, w = 1 without weights), rounded up to FP32
 template <typename T>
@@ -843,15 +1025,24 @@ void launch_grid_w(const fr_plan *pl, int64_t chan, c2<T> *planes, const c2<T> *
         const size_t lds_dyn = (size_t)kLdsBytes - (NTHR / 64) * sizeof(float);
         const int ppass = (int)std::max<size_t>(1, std::min<size_t>(pl->Ww, lds_dyn / per_plane_lds));
         const size_t lds = per_plane_lds * ppass;
-        auto kern = k_grid_partial<T, W, NTHR>;
-        allow_lds(kern, lds);
         {
             ProfScope prof("grid", st);
-            kern<<<dim3((unsigned)(i1 - i0)), NTHR, lds, st>>>(
-                pl->gwi.as<WorkItem>() + i0, partial.as<c2<T>>(), pl->Ww, ppass, (T)pl->beta, (T)pl->wbeta,
-                pl->coplanar ? 1 : 0, pl->taylor ? 1 : 0, pl->r_idx.as<uint32_t>(), pl->r_cell.as<uint32_t>(),
-                pl->r_du.as<T>(),
-                pl->r_dv.as<T>(), pl->r_dw.as<T>(), pl->r_ph.as<T>(), vis, weight, ybound, nbb);
+            if constexpr (std::is_same<T, float>::value && W <= 8) {
+                // FP32, footprint <= 64 cells: the run sums on the matrix cores
+                auto kern = k_grid_partial_mfma<W, NTHR>;
+                allow_lds(kern, lds);
+                kern<<<dim3((unsigned)(i1 - i0)), NTHR, lds, st>>>(
+                    pl->gwi.as<WorkItem>() + i0, partial.as<c2<T>>(), pl->Ww, ppass, (T)pl->beta, (T)pl->wbeta,
+                    pl->coplanar ? 1 : 0, pl->taylor ? 1 : 0, pl->r_idx.as<uint32_t>(), pl->r_cell.as<uint32_t>(),
+                    pl->r_du.as<T>(), pl->r_dv.as<T>(), pl->r_dw.as<T>(), pl->r_ph.as<T>(), vis, weight, ybound, nbb);
+            } else {
+                auto kern = k_grid_partial<T, W, NTHR>;
+                allow_lds(kern, lds);
+                kern<<<dim3((unsigned)(i1 - i0)), NTHR, lds, st>>>(
+                    pl->gwi.as<WorkItem>() + i0, partial.as<c2<T>>(), pl->Ww, ppass, (T)pl->beta, (T)pl->wbeta,
+                    pl->coplanar ? 1 : 0, pl->taylor ? 1 : 0, pl->r_idx.as<uint32_t>(), pl->r_cell.as<uint32_t>(),
+                    pl->r_du.as<T>(), pl->r_dv.as<T>(), pl->r_dw.as<T>(), pl->r_ph.as<T>(), vis, weight, ybound, nbb);
+            }
             LAUNCH_CHECK();
         }
         ProfScope prof("grid_assemble", st);
