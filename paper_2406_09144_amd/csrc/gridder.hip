@@ -656,6 +656,9 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial_mfma(
                 }
                 l_y = y;
             }
+            // records that start a run (base cell differs from the previous record's)
+            const int prev_cell = __shfl(l_cell, lane > 0 ? lane - 1 : 0, 64);
+            const unsigned long long starts = __ballot(lane < nb && (lane == 0 || l_cell != prev_cell));
             for (int k0 = 0; k0 < nb; k0 += 8) {
                 // 1-D kernel values of visibilities k0 .. k0 + 7: lane 8 v + a
                 const int src = min(k0 + (lane >> 3), 63), ta = lane & 7;
@@ -671,12 +674,18 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial_mfma(
                         if (run_cell >= 0) flush();
                         run_cell = cell;
                     }
-                    int ke = k + 1;
-                    while (ke < kend && __builtin_amdgcn_readlane(l_cell, ke) == cell) ++ke;
+                    // the segment ends at the next run start inside the group
+                    // (shift counts stay below 64: k < kend <= 64)
+                    const unsigned long long above = (k >= 63) ? 0ull : (~0ull << (k + 1));
+                    const unsigned long long below = (kend >= 64) ? ~0ull : ((1ull << kend) - 1ull);
+                    const unsigned long long later = starts & above & below;
+                    const int ke = later ? __builtin_ctzll(later) : kend;  // k < ke <= kend
+                    // both halves of the group, whether or not the segment reaches
+                    // them (lanes outside it contribute zero): no branch between the
+                    // two, so their permutes and products overlap
 #pragma unroll
                     for (int s = 0; s < 2; ++s) {
                         const int q0 = k0 + 4 * s;  // visibilities q0 .. q0 + 3
-                        if (q0 + 4 <= k || q0 >= ke) continue;
                         const int q = q0 + kk;       // this lane's visibility in A and B
                         const bool in_run = q >= k && q < ke;
                         // B: y_q times its weight for plane g0 + p_col
