@@ -323,17 +323,6 @@ void launch_irfft_rows(const Ctx &ctx, const ConvGeom &g, Epi epi, const c2<T> *
 
 // ------------------------------------------------------------------ functors
 // (nx is a power of two: row % nx is row & (nx - 1); rows stay below 2^31)
-// x[row][col] (row-major, ny columns) times an optional per-pixel factor a[row % nx][col]
-template <typename T> struct ProScaled {
-    const T *x;
-    const T *a;
-    int nx, ny;
-    __device__ T operator()(int64_t row, int col) const {
-        T v = x[row * ny + col];
-        return a ? v * a[((int)row & (nx - 1)) * ny + col] : v;
-    }
-};
-
 // x[q] * d[q] * a[row % nx][col] with optional full-size d and per-pixel a (q = row * ny + col)
 template <typename T> struct ProDiagScaled {
     const T *x, *d, *a;
@@ -369,31 +358,6 @@ template <typename T> struct EpiDiagScaledAdd {
         }
         y[q] = v0;
         y[q + 1] = v1;
-    }
-};
-
-// y[row][col] = (accumulate ? y : 0) + alpha * a[row % nx][col] * value
-template <typename T> struct EpiScaled {
-    T *y;
-    const T *a;
-    int nx, ny;
-    T alpha;
-    int accumulate;
-    __device__ void operator()(int64_t row, int col, T v0, T v1) const {
-        T *p = y + row * ny + col;
-        if (a) {
-            const T *q = a + ((int)row & (nx - 1)) * ny + col;
-            v0 *= q[0];
-            v1 *= q[1];
-        }
-        v0 *= alpha;
-        v1 *= alpha;
-        if (accumulate) {
-            v0 += p[0];
-            v1 += p[1];
-        }
-        p[0] = v0;
-        p[1] = v1;
     }
 };
 

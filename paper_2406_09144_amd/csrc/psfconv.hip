@@ -54,35 +54,6 @@ void apply_rnr_approx(const fr_psf *psf, const T *x, T *y, int64_t B, hipStream_
     apply_rnr_approx_ex<T>(psf, x, nullptr, y, nullptr, nullptr, B, st);
 }
 
-// y = irfft2(K rfft2(x)) (mode 0) or irfft2(rfft2(x) / K) (mode 1) on the periodic
-// nx x ny grid; K is [nk][nx][ny/2 + 1], image g uses K[g % nk].
-template <typename T>
-void periodic_conv(const Ctx &ctx, const T *x, T *y, int64_t n_img, int64_t nx, int64_t ny, const T *K, int nk,
-                   int mode, hipStream_t st) {
-    if (n_img == 0) return;
-    ConvGeom g;
-    g.n_img = n_img;
-    g.rows_in = (int)nx;
-    g.rows_out = (int)nx;
-    g.n_in_cols = (int)ny;
-    g.n_out_cols = (int)ny;
-    g.log2M = ilog2(ny / 2);
-    g.log2Lc = ilog2(nx);
-    Scratch Y((size_t)n_img * nx * (ny / 2) * sizeof(c2<T>), st);
-    {
-        ProfScope prof("pconv_rows_r2c", st);
-        launch_rfft_rows<T>(ctx, g, ProScaled<T>{x, nullptr, (int)nx, (int)ny}, Y.as<c2<T>>(), st);
-    }
-    const T scale = T(1) / (T(nx) * T(ny / 2));
-    {
-        ProfScope prof("pconv_cols", st);
-        launch_conv_cols<T>(ctx, g, Y.as<c2<T>>(), K, nk, mode, scale, st);
-    }
-    ProfScope prof("pconv_rows_c2r", st);
-    launch_irfft_rows<T>(ctx, g, EpiScaled<T>{y, nullptr, (int)nx, (int)ny, T(1), 0}, Y.as<c2<T>>(), st);
-}
-
-// n0 and n1 are 2^p, 3 2^p or 5 2^p
 // y = d_out * irfft2(f(K) rfft2(d_in * x)) + add on the periodic nx x ny grid,
 // f(K) as kernel_factor(mode); every extra factor optional (NULL).
 template <typename T>
@@ -109,6 +80,14 @@ void periodic_conv_ex(const Ctx &ctx, const T *x, const T *d_in, T *y, const T *
     }
     ProfScope prof("pconv_rows_c2r", st);
     launch_irfft_rows<T>(ctx, g, EpiDiagScaledAdd<T>{y, d_out, nullptr, add, (int)nx, (int)ny}, Y.as<c2<T>>(), st);
+}
+
+// y = irfft2(f(K) rfft2(x)) on the periodic nx x ny grid (f as kernel_factor:
+// mode 0 K, 1 1/K); K is [nk][nx][ny/2 + 1], image g uses K[g % nk].
+template <typename T>
+void periodic_conv(const Ctx &ctx, const T *x, T *y, int64_t n_img, int64_t nx, int64_t ny, const T *K, int nk,
+                   int mode, hipStream_t st) {
+    periodic_conv_ex<T>(ctx, x, nullptr, y, nullptr, nullptr, n_img, nx, ny, K, nk, mode, st);
 }
 
 template <typename T>
