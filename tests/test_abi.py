@@ -14,7 +14,7 @@ def declared_functions():
     return sorted(set(re.findall(r"\b(fr_[a-zA-Z0-9_]+)\s*\(", src)))
 
 
-def test_header_declares_the_north_star_calls():
+def test_header_declares_the_hot_path_calls():
     names = declared_functions()
     for n in ["fr_degrid", "fr_grid", "fr_make_psf_kernel", "fr_apply_RNR_approx",
               "fr_apply_RNR_exact", "fr_likelihood_grad", "fr_cg_solve"]:
