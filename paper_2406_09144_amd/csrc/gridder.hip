@@ -346,7 +346,8 @@ template <typename T, int W> constexpr int grid_reg_planes() {
 // k_grid_assemble adds them up.  Tiles are stored in LDS as separate real and
 // imaginary arrays.
 template <typename T, int W, int NTHR>
-__global__ __launch_bounds__(NTHR) void k_grid_partial(const WorkItem *__restrict__ wis, c2<T> *__restrict__ partial,
+__global__ __launch_bounds__(NTHR) void k_grid_partial(const WorkItem *__restrict__ wis,
+                                                       const int32_t *__restrict__ order, c2<T> *__restrict__ partial,
                                                        int Ww, int ppass, T beta, T wbeta, int coplanar,
                                                        int taylor, const uint32_t *__restrict__ r_idx,
                                                        const uint32_t *__restrict__ r_cell,
@@ -362,7 +363,9 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial(const WorkItem *__restric
     constexpr int NWAVE = NTHR / 64;
     constexpr int PR = grid_reg_planes<T, W>() < W ? grid_reg_planes<T, W>() : W;
     constexpr int VPB = 64 / W;  // visibilities per kernel-evaluation step
-    const WorkItem it = wis[blockIdx.x];
+    // items run largest first (order), each writing its own slot of the partials
+    const int item = order[blockIdx.x];
+    const WorkItem it = wis[item];
     // fixed-point exponent from the bound on every contribution
     __shared__ float wmax[NWAVE];
     {
@@ -381,7 +384,7 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial(const WorkItem *__restric
         frexp(2.0 * (double)ymax * (double)it.count, &e);  // bound < 2^(e-1)
         kexp = 62 - e;
     }
-    c2<T> *out = partial + (int64_t)blockIdx.x * Ww * TT;
+    c2<T> *out = partial + (int64_t)item * Ww * TT;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar loop control
     const T two_over_W = T(2) / T(W);
@@ -548,7 +551,8 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial(const WorkItem *__restric
 // fixed-point LDS tiles and the band output are as in k_grid_partial.
 template <int W, int NTHR>
 __global__ __launch_bounds__(NTHR) void k_grid_partial_mfma(
-    const WorkItem *__restrict__ wis, c2<float> *__restrict__ partial, int Ww, int ppass, float beta, float wbeta,
+    const WorkItem *__restrict__ wis, const int32_t *__restrict__ order, c2<float> *__restrict__ partial, int Ww,
+    int ppass, float beta, float wbeta,
     int coplanar, int taylor, const uint32_t *__restrict__ r_idx, const uint32_t *__restrict__ r_cell,
     const float *__restrict__ r_du, const float *__restrict__ r_dv, const float *__restrict__ r_dw,
     const float *__restrict__ r_ph, const c2<float> *__restrict__ vis, const float *__restrict__ weight,
@@ -561,7 +565,8 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial_mfma(
     constexpr int TT = TS * TS;
     constexpr int NWAVE = NTHR / 64;
     constexpr int NBLK = (W * W + 15) / 16;  // blocks of 16 cells
-    const WorkItem it = wis[blockIdx.x];
+    const int item = order[blockIdx.x];  // items run largest first
+    const WorkItem it = wis[item];
     __shared__ float wmax[NWAVE];
     {
         float m = 0.0f;
@@ -579,7 +584,7 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial_mfma(
         frexp(2.0 * (double)ymax * (double)it.count, &e);  // bound < 2^(e-1)
         kexp = 62 - e;
     }
-    c2<float> *out = partial + (int64_t)blockIdx.x * Ww * TT;
+    c2<float> *out = partial + (int64_t)item * Ww * TT;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const float two_over_W = 2.0f / (float)W;
@@ -1041,14 +1046,16 @@ void launch_grid_w(const fr_plan *pl, int64_t chan, c2<T> *planes, const c2<T> *
                 auto kern = k_grid_partial_mfma<W, NTHR>;
                 allow_lds(kern, lds);
                 kern<<<dim3((unsigned)(i1 - i0)), NTHR, lds, st>>>(
-                    pl->gwi.as<WorkItem>() + i0, partial.as<c2<T>>(), pl->Ww, ppass, (T)pl->beta, (T)pl->wbeta,
+                    pl->gwi.as<WorkItem>() + i0, pl->gorder.as<int32_t>() + i0, partial.as<c2<T>>(), pl->Ww, ppass,
+                    (T)pl->beta, (T)pl->wbeta,
                     pl->coplanar ? 1 : 0, pl->taylor ? 1 : 0, pl->r_idx.as<uint32_t>(), pl->r_cell.as<uint32_t>(),
                     pl->r_du.as<T>(), pl->r_dv.as<T>(), pl->r_dw.as<T>(), pl->r_ph.as<T>(), vis, weight, ybound, nbb);
             } else {
                 auto kern = k_grid_partial<T, W, NTHR>;
                 allow_lds(kern, lds);
                 kern<<<dim3((unsigned)(i1 - i0)), NTHR, lds, st>>>(
-                    pl->gwi.as<WorkItem>() + i0, partial.as<c2<T>>(), pl->Ww, ppass, (T)pl->beta, (T)pl->wbeta,
+                    pl->gwi.as<WorkItem>() + i0, pl->gorder.as<int32_t>() + i0, partial.as<c2<T>>(), pl->Ww, ppass,
+                    (T)pl->beta, (T)pl->wbeta,
                     pl->coplanar ? 1 : 0, pl->taylor ? 1 : 0, pl->r_idx.as<uint32_t>(), pl->r_cell.as<uint32_t>(),
                     pl->r_du.as<T>(), pl->r_dv.as<T>(), pl->r_dw.as<T>(), pl->r_ph.as<T>(), vis, weight, ybound, nbb);
             }
@@ -1329,6 +1336,20 @@ static void build_records(fr_plan *pl, const DevBuf &d_uvw, const DevBuf &d_freq
         pl->gwi_chan[c] = std::max(pl->gwi_chan[c], pl->gwi_chan[c - 1]);
     }
     pl->n_gwi = (int64_t)gwis.size();
+    // launch order of the gridding items of each channel: largest first, so that
+    // the hardware's in-order dispatch fills the CUs like a longest-first schedule
+    {
+        std::vector<int32_t> order(gwis.size());
+        for (int64_t c = 0; c < pl->n_chan; ++c) {
+            const int64_t a = pl->gwi_chan[c], b = pl->gwi_chan[c + 1];
+            for (int64_t i = a; i < b; ++i) order[i] = (int32_t)(i - a);
+            std::stable_sort(order.begin() + a, order.begin() + b,
+                             [&](int32_t x, int32_t y) { return gwis[a + x].count > gwis[a + y].count; });
+        }
+        pl->gorder = DevBuf(std::max<size_t>(1, order.size()) * sizeof(int32_t));
+        if (!order.empty())
+            HIP_CHECK(hipMemcpy(pl->gorder.p, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
     pl->gwi = DevBuf(std::max<size_t>(1, gwis.size()) * sizeof(WorkItem));
     if (!gwis.empty())
         HIP_CHECK(hipMemcpy(pl->gwi.p, gwis.data(), gwis.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
@@ -1518,7 +1539,8 @@ void plan_build(fr_plan *pl, const double *uvw_m, const double *freq_hz) {
     }
     pl->resident = pl->fac.bytes + pl->tpix.bytes + pl->nfac.bytes + pl->wplane.bytes + pl->r_idx.bytes +
                    pl->r_cell.bytes + pl->r_du.bytes + pl->r_dv.bytes + pl->r_dw.bytes + pl->r_ph.bytes +
-                   pl->wi.bytes + pl->gwi.bytes + pl->gkey_first.bytes + pl->atile.bytes + pl->tile_active.bytes;
+                   pl->wi.bytes + pl->gwi.bytes + pl->gorder.bytes + pl->gkey_first.bytes + pl->atile.bytes +
+                   pl->tile_active.bytes;
 }
 
 }  // namespace frmi

@@ -55,6 +55,7 @@ struct fr_plan {
     std::vector<int64_t> wi_chan;  // work-item range per channel, [n_chan + 1]
     // gridding items: larger chunks of one key each, and per key the first item
     frmi::DevBuf gwi;        // WorkItem [n_gwi]
+    frmi::DevBuf gorder;     // int32 [n_gwi]: per channel, item indices largest first
     int64_t n_gwi = 0;
     std::vector<int64_t> gwi_chan;
     frmi::DevBuf gkey_first;  // uint32 [n_keys + 1]
