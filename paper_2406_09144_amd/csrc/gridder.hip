@@ -122,6 +122,15 @@ __global__ void k_bucket_bounds(const uint64_t *__restrict__ k64, int64_t n, int
     offs[k] = lo;
 }
 
+// number of sorted records whose (bucket, base cell) differs from the previous
+// record's: the runs the gridding spread accumulates, less one
+__global__ void k_count_runs(const uint64_t *__restrict__ k64, int64_t n, unsigned long long *__restrict__ count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool step = i > 0 && i < n && k64[i] != k64[i - 1];
+    const unsigned long long b = __ballot(step);
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd(count, (unsigned long long)__popcll(b));
+}
+
 // rows of the tile (halo included) that gridding item i touches: its records are
 // sorted by base cell, so the first and last hold the smallest and largest
 // base row
@@ -1041,23 +1050,33 @@ void launch_grid_w(const fr_plan *pl, int64_t chan, c2<T> *planes, const c2<T> *
         const size_t lds = per_plane_lds * ppass;
         {
             ProfScope prof("grid", st);
-            if constexpr (std::is_same<T, float>::value && W <= 8) {
-                // FP32, footprint <= 64 cells: the run sums on the matrix cores
-                auto kern = k_grid_partial_mfma<W, NTHR>;
-                allow_lds(kern, lds);
-                kern<<<dim3((unsigned)(i1 - i0)), NTHR, lds, st>>>(
-                    pl->gwi.as<WorkItem>() + i0, pl->gorder.as<int32_t>() + i0, partial.as<c2<T>>(), pl->Ww, ppass,
-                    (T)pl->beta, (T)pl->wbeta,
-                    pl->coplanar ? 1 : 0, pl->taylor ? 1 : 0, pl->r_idx.as<uint32_t>(), pl->r_cell.as<uint32_t>(),
-                    pl->r_du.as<T>(), pl->r_dv.as<T>(), pl->r_dw.as<T>(), pl->r_ph.as<T>(), vis, weight, ybound, nbb);
-            } else {
+            auto launch_vector = [&]() {
                 auto kern = k_grid_partial<T, W, NTHR>;
                 allow_lds(kern, lds);
                 kern<<<dim3((unsigned)(i1 - i0)), NTHR, lds, st>>>(
                     pl->gwi.as<WorkItem>() + i0, pl->gorder.as<int32_t>() + i0, partial.as<c2<T>>(), pl->Ww, ppass,
-                    (T)pl->beta, (T)pl->wbeta,
-                    pl->coplanar ? 1 : 0, pl->taylor ? 1 : 0, pl->r_idx.as<uint32_t>(), pl->r_cell.as<uint32_t>(),
-                    pl->r_du.as<T>(), pl->r_dv.as<T>(), pl->r_dw.as<T>(), pl->r_ph.as<T>(), vis, weight, ybound, nbb);
+                    (T)pl->beta, (T)pl->wbeta, pl->coplanar ? 1 : 0, pl->taylor ? 1 : 0, pl->r_idx.as<uint32_t>(),
+                    pl->r_cell.as<uint32_t>(), pl->r_du.as<T>(), pl->r_dv.as<T>(), pl->r_dw.as<T>(), pl->r_ph.as<T>(),
+                    vis, weight, ybound, nbb);
+            };
+            if constexpr (std::is_same<T, float>::value && W <= 8) {
+                // FP32, footprint <= 64 cells and runs of several records (an MFMA
+                // step takes 4 records of one run; measured 1.4x faster than the
+                // vector kernel at 62 records per run, 1.5x slower at ~1): the run
+                // sums on the matrix cores
+                if (pl->vis_per_run >= 4.0) {
+                    auto kern = k_grid_partial_mfma<W, NTHR>;
+                    allow_lds(kern, lds);
+                    kern<<<dim3((unsigned)(i1 - i0)), NTHR, lds, st>>>(
+                        pl->gwi.as<WorkItem>() + i0, pl->gorder.as<int32_t>() + i0, partial.as<c2<T>>(), pl->Ww,
+                        ppass, (T)pl->beta, (T)pl->wbeta, pl->coplanar ? 1 : 0, pl->taylor ? 1 : 0,
+                        pl->r_idx.as<uint32_t>(), pl->r_cell.as<uint32_t>(), pl->r_du.as<T>(), pl->r_dv.as<T>(),
+                        pl->r_dw.as<T>(), pl->r_ph.as<T>(), vis, weight, ybound, nbb);
+                } else {
+                    launch_vector();
+                }
+            } else {
+                launch_vector();
             }
             LAUNCH_CHECK();
         }
@@ -1269,6 +1288,16 @@ static void build_records(fr_plan *pl, const DevBuf &d_uvw, const DevBuf &d_freq
     LAUNCH_CHECK();
     std::vector<int64_t> bounds(n_keys + 1);
     HIP_CHECK(hipMemcpy(bounds.data(), d_bounds.p, d_bounds.bytes, hipMemcpyDeviceToHost));
+    {
+        DevBuf d_steps(sizeof(unsigned long long));
+        HIP_CHECK(hipMemset(d_steps.p, 0, d_steps.bytes));
+        k_count_runs<<<dim3((unsigned)((n + 255) / 256)), 256>>>(k64s.as<uint64_t>(), n,
+                                                                  d_steps.as<unsigned long long>());
+        LAUNCH_CHECK();
+        unsigned long long steps = 0;
+        HIP_CHECK(hipMemcpy(&steps, d_steps.p, sizeof(steps), hipMemcpyDeviceToHost));
+        pl->vis_per_run = (double)n / (double)(steps + 1);
+    }
     int64_t run = 0;
     std::vector<WorkItem> wis, gwis;
     std::vector<uint32_t> gfirst(n_keys + 1, 0);
