@@ -555,9 +555,10 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial(const WorkItem *__restric
 // cells.  Operand layout of that instruction (checked on the hardware): lane l
 // supplies A[l % 16][l / 16] and B[l / 16][l % 16] and holds D[4 (l / 16) + r][l % 16],
 // r < 4.  The 1-D kernel values of 8 visibilities are evaluated at a time (lane
-// 8 v + a holds psi(d_v - a)) and A is gathered from them with lane permutes;
-// visibilities outside the current run get A = 0.  Runs, flushes to the 64-bit
-// fixed-point LDS tiles and the band output are as in k_grid_partial.
+// 8 v + a holds psi(d_v - a)), as are the plane weights, and A and B are gathered
+// from them with lane permutes once per group; visibilities outside the current
+// run segment get B = 0.  Runs, flushes to the 64-bit fixed-point LDS tiles and
+// the band output are as in k_grid_partial.
 template <int W, int NTHR>
 __global__ __launch_bounds__(NTHR) void k_grid_partial_mfma(
     const WorkItem *__restrict__ wis, const int32_t *__restrict__ order, c2<float> *__restrict__ partial, int Ww,
@@ -600,12 +601,11 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial_mfma(
     // A operand: row (cell) lane % 16 of each block, column (visibility) lane / 16
     const int kk = lane >> 4;
     int a_addr[NBLK], b_addr[NBLK];
-    bool a_ok[NBLK];
 #pragma unroll
     for (int blk = 0; blk < NBLK; ++blk) {
         const int c = 16 * blk + (lane & 15);
-        a_ok[blk] = c < W * W;
-        const int ca = a_ok[blk] ? c / W : 0, cb = a_ok[blk] ? c - (c / W) * W : 0;
+        const bool ok = c < W * W;
+        const int ca = ok ? c / W : 0, cb = ok ? c - (c / W) * W : 0;
         a_addr[blk] = 4 * ca;  // byte offset of psi(du - a) inside a visibility's 8 lanes
         b_addr[blk] = 4 * cb;
     }
@@ -679,6 +679,41 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial_mfma(
                 const float xu_v = __shfl(l_xu, src, 64), xv_v = __shfl(l_xv, src, 64);
                 const float phu = ta < W ? es_eval<float>((xu_v - (float)ta) * two_over_W, beta) : 0.0f;
                 const float phv = ta < W ? es_eval<float>((xv_v - (float)ta) * two_over_W, beta) : 0.0f;
+                // plane weights of the same visibilities: lane 8 v + a holds plane g0 + a
+                float phw = 1.0f;
+                if (!coplanar) {
+                    const float xw_v = __shfl(l_xw, src, 64);
+                    phw = ta < np ? plane_weight<float>(xw_v, g0 + ta, Ww, wbeta, taylor) : 0.0f;
+                }
+                // operands of both halves of the group, gathered once for all its
+                // run segments (lanes outside a segment get B = 0).  All lane
+                // permutes are issued before the first product, so their latency
+                // is paid once per group rather than once per block.
+                float ua[2][NBLK], va[2][NBLK], kwa[2], yxa[2], yya[2];
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+                    const int q = k0 + 4 * s + kk;  // this lane's visibility in A and B
+                    const int sq = min(q, 63);
+                    const int vbase = 32 * (4 * s + kk);  // byte offset of visibility q's 8 lanes
+                    yxa[s] = __shfl(l_y.x, sq, 64);
+                    yya[s] = __shfl(l_y.y, sq, 64);
+                    kwa[s] = lane_permute(phw, vbase + 4 * p_col);
+#pragma unroll
+                    for (int blk = 0; blk < NBLK; ++blk) {
+                        ua[s][blk] = lane_permute(phu, vbase + a_addr[blk]);
+                        va[s][blk] = lane_permute(phv, vbase + b_addr[blk]);
+                    }
+                }
+                // A: psi(du_q - a) psi(dv_q - b) of the lane's cell in each block
+                // (finite everywhere; rows of cells beyond W^2 are never flushed);
+                // B before the segment mask: y_q times its plane-(g0 + p_col) weight
+                float aop[2][NBLK], bop[2];
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+                    bop[s] = kwa[s] * (im_col ? yya[s] : yxa[s]);
+#pragma unroll
+                    for (int blk = 0; blk < NBLK; ++blk) aop[s][blk] = ua[s][blk] * va[s][blk];
+                }
                 const int kend = min(k0 + 8, nb);
                 int k = k0;
                 while (k < kend) {
@@ -694,32 +729,15 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial_mfma(
                     const unsigned long long below = (kend >= 64) ? ~0ull : ((1ull << kend) - 1ull);
                     const unsigned long long later = starts & above & below;
                     const int ke = later ? __builtin_ctzll(later) : kend;  // k < ke <= kend
-                    // both halves of the group, whether or not the segment reaches
-                    // them (lanes outside it contribute zero): no branch between the
-                    // two, so their permutes and products overlap
 #pragma unroll
                     for (int s = 0; s < 2; ++s) {
-                        const int q0 = k0 + 4 * s;  // visibilities q0 .. q0 + 3
-                        const int q = q0 + kk;       // this lane's visibility in A and B
-                        const bool in_run = q >= k && q < ke;
-                        // B: y_q times its weight for plane g0 + p_col
-                        const int sq = min(q, 63);
-                        const float yx = __shfl(l_y.x, sq, 64), yy = __shfl(l_y.y, sq, 64);
-                        const float xw = __shfl(l_xw, sq, 64);
-                        float bval = 0.0f;
-                        if (in_run && p_col < np) {
-                            const float kw = coplanar ? 1.0f : plane_weight<float>(xw, g0 + p_col, Ww, wbeta, taylor);
-                            bval = kw * (im_col ? yy : yx);
-                        }
-                        // A: psi(du_q - a) psi(dv_q - b) of the lane's cell in each block
-                        const int vbase = 32 * (q - k0);  // byte offset of visibility q's 8 lanes
+                        // B is zero outside the segment, which also cancels A there
+                        const int q = k0 + 4 * s + kk;
+                        const bool use = q >= k && q < ke && p_col < np;
+                        const float bval = use ? bop[s] : 0.0f;
 #pragma unroll
-                        for (int blk = 0; blk < NBLK; ++blk) {
-                            const float u = lane_permute(phu, vbase + a_addr[blk]);
-                            const float v = lane_permute(phv, vbase + b_addr[blk]);
-                            const float aval = (in_run && a_ok[blk]) ? u * v : 0.0f;
-                            acc[blk] = __builtin_amdgcn_mfma_f32_16x16x4f32(aval, bval, acc[blk], 0, 0, 0);
-                        }
+                        for (int blk = 0; blk < NBLK; ++blk)
+                            acc[blk] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop[s][blk], bval, acc[blk], 0, 0, 0);
                     }
                     k = ke;
                 }
