@@ -1032,19 +1032,20 @@ template <typename T> void zero_async(T *p, int64_t n, hipStream_t st) {
 }
 
 // ------------------------------------------------------------------ launch helpers
-template <typename T> constexpr int vpt() { return std::is_same<T, float>::value ? 2 : 1; }
-constexpr int kGridThreads = 256;
-template <typename T> constexpr int chunk() { return kGridThreads * vpt<T>(); }
+// Records per degridding item, one thread each (FP32: 512 threads measured 6%
+// faster than 256 threads with two records each, the registers per thread
+// dropping enough for more resident waves).
+template <typename T> constexpr int chunk() { return std::is_same<T, float>::value ? 512 : 256; }
 
 template <typename T, int W>
 void launch_degrid_w(const fr_plan *pl, const WorkItem *wis, int64_t nwi, const c2<T> *planes, c2<T> *vis,
                      hipStream_t st) {
     constexpr int TS = kTile + W - 1;
     const size_t lds = (size_t)TS * TS * sizeof(c2<T>);
-    auto kern = k_degrid<T, W, kGridThreads, vpt<T>()>;
+    auto kern = k_degrid<T, W, chunk<T>(), 1>;
     allow_lds(kern, lds);
     ProfScope prof("degrid", st);
-    kern<<<dim3((unsigned)nwi), kGridThreads, lds, st>>>(
+    kern<<<dim3((unsigned)nwi), chunk<T>(), lds, st>>>(
         wis, planes, ilog2(pl->nu), ilog2(pl->nv), pl->Ww, (T)pl->beta, (T)pl->wbeta, pl->coplanar ? 1 : 0,
         pl->taylor ? 1 : 0, pl->r_idx.as<uint32_t>(), pl->r_cell.as<uint32_t>(), pl->r_du.as<T>(), pl->r_dv.as<T>(), pl->r_dw.as<T>(),
         pl->r_ph.as<T>(), vis);
