@@ -100,6 +100,9 @@ typedef struct fr_plan_info {
     int64_t n_workitems;
     size_t resident_bytes;  /* device memory the plan holds */
     int w_taylor;           /* 1: the planes are Taylor terms in w, not w-planes */
+    double records_per_run; /* sorted records per run of equal (bucket, base cell) */
+    int matrix_spread;      /* 1: fr_grid spreads on the matrix cores (FP32, support <= 8,
+                               >= 4 records per run); 0: on the vector units */
 } fr_plan_info;
 
 /* Library version string. */

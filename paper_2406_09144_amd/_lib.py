@@ -41,6 +41,7 @@ class fr_plan_info(ctypes.Structure):
         ("eps_bound", ctypes.c_double), ("tile", ctypes.c_int),
         ("n_workitems", ctypes.c_int64), ("resident_bytes", ctypes.c_size_t),
         ("w_taylor", ctypes.c_int),
+        ("records_per_run", ctypes.c_double), ("matrix_spread", ctypes.c_int),
     ]
 
     def as_dict(self):

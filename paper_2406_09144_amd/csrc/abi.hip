@@ -274,6 +274,8 @@ int fr_plan_get_info(const fr_plan *pl, fr_plan_info *info) {
     info->n_workitems = pl->n_wi;
     info->resident_bytes = pl->resident;
     info->w_taylor = pl->taylor ? 1 : 0;
+    info->records_per_run = pl->vis_per_run;
+    info->matrix_spread = frmi::matrix_spread(pl) ? 1 : 0;
     FR_API_END
 }
 

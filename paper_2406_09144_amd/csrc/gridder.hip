@@ -1083,7 +1083,7 @@ void launch_grid_w(const fr_plan *pl, int64_t chan, c2<T> *planes, const c2<T> *
                 // step takes 4 records of one run; measured 1.4x faster than the
                 // vector kernel at 62 records per run, 1.5x slower at ~1): the run
                 // sums on the matrix cores
-                if (pl->vis_per_run >= 4.0) {
+                if (matrix_spread(pl)) {
                     auto kern = k_grid_partial_mfma<W, NTHR>;
                     allow_lds(kern, lds);
                     kern<<<dim3((unsigned)(i1 - i0)), NTHR, lds, st>>>(

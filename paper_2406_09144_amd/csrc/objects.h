@@ -74,6 +74,11 @@ struct fr_plan {
 
 namespace frmi {
 
+// FP32 gridding of plans with W <= 8 runs the spread on the matrix cores when the
+// sorted records average at least 4 per run of equal base cell (one MFMA step
+// takes four records of a run); otherwise it stays on the vector units.
+inline bool matrix_spread(const fr_plan *pl) { return !pl->fp64 && pl->W <= 8 && pl->vis_per_run >= 4.0; }
+
 // gridder.hip
 void plan_build(fr_plan *pl, const double *uvw_m, const double *freq_hz);
 size_t planes_bytes(const fr_plan *pl);

@@ -256,3 +256,38 @@ def test_taylor_w_falls_back_to_w_stacking_for_large_w():
     assert pl.info["w_taylor"] == 0
     assert pl.info["n_planes"] == api.Plan(c["uvw"], c["freq"], c["nx"], c["ny"], c["dx"], c["dy"],
                                            eps=1e-5).info["n_planes"]
+
+
+def dense_tracks(n=64, n_bl=12):
+    """VLA-like tracks sampled every 10 s on a few baselines: consecutive records of
+    a baseline stay in one uv cell, so the sorted records come in long runs."""
+    o = make_config(1, n=n, n_int=2880, with_sky=False)
+    nbl = 27 * 26 // 2  # rows are time-major over the 351 baselines
+    assert o.uvw.shape[0] % nbl == 0
+    sel = (np.arange(o.uvw.shape[0]) % nbl) < n_bl
+    return dict(uvw=o.uvw[sel], freq=o.freq, nx=n, ny=n, dx=o.dx, dy=o.dy)
+
+
+@pytest.mark.parametrize("kind", ["dense_tracks", "random_uv"])
+def test_both_spread_kernels_vs_oracle(kind):
+    """Long runs take the matrix-core spread and single-record runs the vector one
+    (the plan reports which); both grid to the FP32 bound against the oracle."""
+    import torch
+    from paper_2406_09144_amd import api
+    c = dense_tracks() if kind == "dense_tracks" else wide_field()
+    pl = _plan(c, False)
+    info = pl.info
+    long_runs = kind == "dense_tracks"
+    assert (info["records_per_run"] >= 4.0) == long_runs, info
+    assert info["matrix_spread"] == (1 if long_runs else 0), info
+    assert _plan(c, True).info["matrix_spread"] == 0  # FP64 always on the vector units
+    rng = np.random.default_rng(21)
+    nrow = c["uvw"].shape[0]
+    vis = rng.standard_normal((nrow, 1)) + 1j * rng.standard_normal((nrow, 1))
+    wt = rng.uniform(0.2, 3.0, (nrow, 1))
+    img = api.grid(pl, torch.from_numpy(vis).to(torch.complex64).cuda(),
+                   torch.from_numpy(wt).to(torch.float32).cuda()).cpu().numpy()
+    ref = O.grid(c["uvw"], c["freq"], c["nx"], c["ny"], c["dx"], c["dy"], vis, wt)
+    err = rel(img, ref)
+    print(kind, info["records_per_run"], info["matrix_spread"], err)
+    assert err < 1e-5, (err, info)
