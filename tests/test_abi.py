@@ -35,3 +35,23 @@ def test_version_and_error_string_without_gpu():
     lib = _lib.load(import_torch=False)
     assert lib.fr_version().startswith(b"frmi")
     assert lib.fr_last_error() is not None
+
+
+def test_plan_info_binding_matches_header():
+    """The ctypes fr_plan_info lists the header's fields, in order, with C types of
+    the same size (a drifted layout would misread every field after the change)."""
+    from paper_2406_09144_amd import _lib
+    src = open(os.path.join(ROOT, "include", "frmi.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    body = re.search(r"typedef struct(?:\s+fr_plan_info)?\s*\{(.*?)\}\s*fr_plan_info\s*;", src, flags=re.S).group(1)
+    sizes = {"int64_t": 8, "int": 4, "double": 8, "size_t": 8}
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        ctype, names = decl.split(None, 1)
+        for name in names.split(","):
+            fields.append((name.strip(), sizes[ctype]))
+    binding = [(name, ctypes.sizeof(t)) for name, t in _lib.fr_plan_info._fields_]
+    assert binding == fields
