@@ -55,3 +55,14 @@ def test_plan_info_binding_matches_header():
             fields.append((name.strip(), sizes[ctype]))
     binding = [(name, ctypes.sizeof(t)) for name, t in _lib.fr_plan_info._fields_]
     assert binding == fields
+
+
+def test_binding_constants_match_header():
+    """Status codes, plan flags and mode enums of the binding equal the header's."""
+    from paper_2406_09144_amd import _lib
+    src = open(os.path.join(ROOT, "include", "frmi.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    consts = {m.group(1): int(m.group(2)) for m in re.finditer(r"\b(FR_[A-Z0-9_]+)\s*=\s*(-?\d+)", src)}
+    assert len(consts) >= 20
+    for name, value in consts.items():
+        assert getattr(_lib, name) == value, name
