@@ -4,6 +4,7 @@ times, on outputs the oracle computes one by one:
   * VLA-like 512^2, 1,010,880 visibilities with w (FP32, eps = 1e-5): degridding
     on a random sample of visibilities, gridding on a random sample of pixels,
     the PSF-convolution response on a sample of output pixels (brute force);
+  * the same VLA-like workload with an FP64 plan at eps = 1e-11 (bound 1e-10);
   * MeerKAT-like 4096^2 x 16 channels, 7,257,600 rows (116 M visibilities): the
     same samples on three channels.
 
@@ -24,17 +25,18 @@ def rel(a, b):
     return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
 
 
-def _check_plan(obs, chans, n_vis_sample=2048, n_pix_sample=96, seed=0):
+def _check_plan(obs, chans, n_vis_sample=2048, n_pix_sample=96, seed=0, fp64=False, eps=1e-5, bound=1e-5):
     import torch
     from paper_2406_09144_amd import api
     rng = np.random.default_rng(seed)
     n = obs.nx
-    print(f"[fullsize] {obs.n_vis} visibilities, {n}x{n}, {obs.n_chan} channel(s)", flush=True)
-    pl = api.Plan(obs.uvw, obs.freq, n, n, obs.dx, obs.dy, eps=1e-5)
+    rd, cd = (torch.float64, torch.complex128) if fp64 else (torch.float32, torch.complex64)
+    print(f"[fullsize] {obs.n_vis} visibilities, {n}x{n}, {obs.n_chan} channel(s), fp64={fp64}", flush=True)
+    pl = api.Plan(obs.uvw, obs.freq, n, n, obs.dx, obs.dy, eps=eps, fp64=fp64)
     info = pl.info
     print(f"[fullsize] plan: W={info['support']} planes={info['n_planes']} items={info['n_workitems']}", flush=True)
-    sky = torch.from_numpy(obs.sky).float().cuda() if obs.sky is not None else \
-        torch.from_numpy(rng.standard_normal((obs.n_chan, n, n))).float().cuda()
+    sky = torch.from_numpy(obs.sky).to(rd).cuda() if obs.sky is not None else \
+        torch.from_numpy(rng.standard_normal((obs.n_chan, n, n))).to(rd).cuda()
     vis = api.degrid(pl, sky)
     torch.cuda.synchronize()
     rows = rng.choice(obs.n_row, n_vis_sample, replace=False)
@@ -44,10 +46,10 @@ def _check_plan(obs, chans, n_vis_sample=2048, n_pix_sample=96, seed=0):
     ref = O.degrid_rows(obs.uvw, obs.freq, n, n, obs.dx, obs.dy, skyh, rows, ch)
     e_deg = rel(got, ref)
     print(f"[fullsize] degrid sampled rel err {e_deg:.2e}", flush=True)
-    assert e_deg < 1e-5
+    assert e_deg < bound
     # gridding: random data and weights, sampled pixels per channel
-    y = torch.randn((obs.n_row, obs.n_chan), dtype=torch.complex64, device="cuda")
-    w = torch.rand((obs.n_row, obs.n_chan), device="cuda") + 0.5
+    y = torch.randn((obs.n_row, obs.n_chan), dtype=cd, device="cuda")
+    w = torch.rand((obs.n_row, obs.n_chan), dtype=rd, device="cuda") + 0.5
     img = api.grid(pl, y, w).cpu().numpy()
     yh = y.cpu().numpy().astype(np.complex128)
     wh = w.cpu().numpy().astype(np.float64)
@@ -56,7 +58,7 @@ def _check_plan(obs, chans, n_vis_sample=2048, n_pix_sample=96, seed=0):
         refp = O.grid_pixels(obs.uvw, obs.freq, n, n, obs.dx, obs.dy, yh, pix, chan=c, weight=wh)
         e_grid = rel(img[c].ravel()[pix], refp)
         print(f"[fullsize] grid channel {c} sampled rel err {e_grid:.2e}", flush=True)
-        assert e_grid < 1e-5
+        assert e_grid < bound
     return pl
 
 
@@ -64,6 +66,12 @@ def test_vla_like_full_size():
     obs = make_config(1)
     assert obs.n_vis == 1_010_880
     _check_plan(obs, chans=[0])
+
+
+def test_vla_like_full_size_fp64():
+    """The FP64 plain form at full size: FP64 plan at eps = 1e-11, bound 1e-10."""
+    obs = make_config(1)
+    _check_plan(obs, chans=[0], n_vis_sample=1024, n_pix_sample=64, fp64=True, eps=1e-11, bound=1e-10)
 
 
 def test_meerkat_like_full_size():
