@@ -26,8 +26,12 @@
  *   - stream is a hipStream_t (NULL = the null stream).  Operator calls are
  *     asynchronous: they return after enqueueing; outputs are valid once the
  *     stream reaches that point.  Plan and PSF objects are read-only after
- *     creation and may be used from several streams at once; per-call scratch
- *     comes from the device's stream-ordered pool and is never shared.
+ *     creation and may be used from several streams at once.  Per-call scratch
+ *     comes from an arena owned by the library for each (device, stream) pair:
+ *     device memory that grows on demand (hipMalloc, outside the stream) and is
+ *     reused by later calls on the same stream, which run in order; calls on
+ *     different streams never share it.  fr_scratch_stats reports its use and
+ *     fr_scratch_trim returns it to the device.
  *   - The caller owns every input/output buffer and the stream; the library
  *     owns ctx, plan and psf objects until the matching *_destroy.
  *   - Errors are returned as status codes (never exceptions, never abort);
@@ -146,9 +150,31 @@ int fr_plan_create(fr_ctx *ctx, const double *uvw_m, int64_t n_row, const double
 void fr_plan_destroy(fr_plan *plan);
 int fr_plan_get_info(const fr_plan *plan, fr_plan_info *info);
 
+/* Inspection of a plan's bucketing (for tests and tools; synchronous, host arrays,
+ * any output may be NULL).  Visibility v = row * n_chan + chan has the 64-bit
+ * sort key  bucket << 10 | (a * 32 + b),  bucket = (chan * n_first_planes +
+ * first w-plane) * n_tiles + tile, (a, b) its base cell inside the 32 x 32 uv tile:
+ *   keys          [n_vis]: the key of every visibility, in input order;
+ *   perm          [n_vis]: perm[k] = v of the k-th record in the plan's order (a
+ *                 stable sort of the keys);
+ *   bucket_start  [n_keys + 1]: first record position of every bucket (and n_vis),
+ *                 read back from the plan's degridding work items after checking
+ *                 that they, and the gridding items, tile each bucket exactly;
+ *   n_keys        number of buckets.
+ * Errors: FR_EHIP if the work items are inconsistent. */
+int fr_plan_export_order(const fr_plan *plan, uint64_t *keys, uint32_t *perm, int64_t *bucket_start,
+                         int64_t *n_keys);
+
 /* R (Sec. 2, Eq. 1): img device [n_chan][nx][ny] real -> vis device [n_row][n_chan]
  * complex.  Overwrites vis. */
 int fr_degrid(fr_plan *plan, const void *img, void *vis, void *stream);
+
+/* N^-1 R (Sec. 3.1.2 with Sec. 2): vis = weight * (R img), the weights applied as
+ * the visibilities are stored.  The adjoint of fr_grid with the same weights in
+ * the real inner product (the gradient of gridding with respect to its input
+ * visibilities).  img device [n_chan][nx][ny] real, weight device [n_row][n_chan]
+ * real (required), vis device [n_row][n_chan] complex, overwritten. */
+int fr_degrid_weighted(fr_plan *plan, const void *img, const void *weight, void *vis, void *stream);
 
 /* R^+ N^-1 (Sec. 3.2): vis device [n_row][n_chan] complex, weight device
  * [n_row][n_chan] real or NULL (= 1) -> img device [n_chan][nx][ny] real, the dirty
@@ -294,10 +320,29 @@ int fr_mgvi_draw(fr_psf *psf, const void *power, const void *diag, const void *e
 int fr_mgvi_solve(fr_psf *psf, const void *power, const void *diag, const void *b, void *x,
                   int maxiter, double rtol, double *resid_hist, int *iters_done, void *stream);
 
-/* Device bytes a call of `op` with batch B needs beyond its inputs and outputs
- * (per-call scratch), plus the resident plan/psf bytes.  Host-only, no GPU work. */
+/* Device bytes a call of `op` with batch B needs beyond its inputs and outputs,
+ * plus the resident plan/psf bytes.  Host-only, no GPU work.  scratch_bytes bounds
+ * the per-call scratch the call takes from its stream's arena (regions rounded to
+ * 256 bytes, prior-term scratch included for the ops that take one); for
+ * FR_OP_MAKE_PSF it adds a bound on the doubled-field plan the call builds and
+ * frees.  Admission control can sum it over calls in flight. */
 int fr_query_footprint(const fr_plan *plan, const fr_psf *psf, int op, int64_t B,
                        size_t *scratch_bytes, size_t *resident_bytes);
+
+/* Scratch arena of (ctx's device, stream): `held` = device bytes it owns,
+ * `peak_in_use` = the largest sum of regions live at once since the last reset
+ * (reset != 0 restarts the count after reading).  Host-only. */
+int fr_scratch_stats(fr_ctx *ctx, void *stream, int reset, size_t *peak_in_use, size_t *held);
+
+/* Synchronise `stream`, then free the device memory of its arena (the next call on
+ * the stream allocates again).  FR_EBUSY if a call is using it. */
+int fr_scratch_trim(fr_ctx *ctx, void *stream);
+
+/* Failure injection for tests of the error paths: after `after` more successful
+ * device allocations by the library, the next one fails as out of memory (the
+ * call returns FR_ENOMEM and releases what it had taken).  One failure per
+ * injection; -1 cancels a pending one. */
+int fr_inject_alloc_failure(int64_t after);
 
 /* Per-kernel timing for measurement (off by default, process-wide).  While
  * enabled, each instrumented kernel launch is bracketed by two hipEvents

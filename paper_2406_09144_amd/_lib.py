@@ -63,6 +63,8 @@ SIGNATURES = {
     "fr_plan_destroy": ([_P], None),
     "fr_plan_get_info": ([_P, ctypes.POINTER(fr_plan_info)], _I),
     "fr_degrid": ([_P, _P, _P, _P], _I),
+    "fr_degrid_weighted": ([_P, _P, _P, _P, _P], _I),
+    "fr_plan_export_order": ([_P, _P, _P, _P, ctypes.POINTER(_I64)], _I),
     "fr_grid": ([_P, _P, _P, _P, _P], _I),
     "fr_make_psf_kernel": ([_P, _P, _D, _PP, _P], _I),
     "fr_psf_create": ([_P, _I64, _I64, _I64, _P, _P, _P, _I, _PP, _P], _I),
@@ -80,6 +82,9 @@ SIGNATURES = {
     "fr_mgvi_solve": ([_P, _P, _P, _P, _P, _I, _D, _P, _P, _P], _I),
     "fr_query_footprint": ([_P, _P, _I, _I64, ctypes.POINTER(ctypes.c_size_t),
                             ctypes.POINTER(ctypes.c_size_t)], _I),
+    "fr_scratch_stats": ([_P, _P, _I, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)], _I),
+    "fr_scratch_trim": ([_P, _P], _I),
+    "fr_inject_alloc_failure": ([_I64], _I),
     "fr_fft2": ([_P, _P, _I64, _I64, _I64, _I, _I, _P], _I),
     "fr_profile_enable": ([_I], _I),
     "fr_profile_reset": ([], _I),

@@ -189,6 +189,22 @@ class Plan:
     def device(self):
         return torch.device("cuda", self.ctx.device)
 
+    def export_order(self):
+        """The plan's bucketing as host numpy arrays: the sort key of every
+        visibility (input order), the record order perm (perm[k] = visibility of
+        record k) and the first record of every bucket (n_keys + 1 entries)."""
+        import numpy as np
+        nk = ctypes.c_int64()
+        L.check(_lib().fr_plan_export_order(self.handle, None, None, None, ctypes.byref(nk)))
+        n = self.n_row * self.n_chan
+        keys = np.empty(n, np.uint64)
+        perm = np.empty(n, np.uint32)
+        bs = np.empty(nk.value + 1, np.int64)
+        L.check(_lib().fr_plan_export_order(self.handle, keys.ctypes.data_as(ctypes.c_void_p),
+                                            perm.ctypes.data_as(ctypes.c_void_p),
+                                            bs.ctypes.data_as(ctypes.c_void_p), ctypes.byref(nk)))
+        return keys, perm, bs
+
     def img_shape(self, B=None):
         s = (self.n_chan, self.nx, self.ny)
         return s if B is None else (B,) + s
@@ -207,13 +223,19 @@ def _img3(plan, img, name):
     return _need(img, _real_dtype(plan.fp64), plan.img_shape(), name)
 
 
-def degrid(plan, img, out=None, stream=None):
-    """R: image [n_chan, nx, ny] (or [nx, ny]) -> visibilities [n_row, n_chan] complex."""
+def degrid(plan, img, out=None, stream=None, weight=None):
+    """R: image [n_chan, nx, ny] (or [nx, ny]) -> visibilities [n_row, n_chan] complex;
+    with weight [n_row, n_chan], N^-1 R (weights applied by the library as it stores)."""
     img = _img3(plan, img, "img")
     vis = out if out is not None else torch.empty((plan.n_row, plan.n_chan), dtype=_cplx_dtype(plan.fp64),
                                                   device=img.device)
     _need(vis, _cplx_dtype(plan.fp64), (plan.n_row, plan.n_chan), "vis")
-    L.check(_lib().fr_degrid(plan.handle, _ptr(img), _ptr(vis), _stream(stream)))
+    if weight is None:
+        L.check(_lib().fr_degrid(plan.handle, _ptr(img), _ptr(vis), _stream(stream)))
+    else:
+        weight = _need(weight.reshape(plan.n_row, plan.n_chan), _real_dtype(plan.fp64),
+                       (plan.n_row, plan.n_chan), "weight")
+        L.check(_lib().fr_degrid_weighted(plan.handle, _ptr(img), _ptr(weight), _ptr(vis), _stream(stream)))
     return vis
 
 
@@ -246,7 +268,7 @@ class Degrid(torch.autograd.Function):
 
 class Grid(torch.autograd.Function):
     """I = R^+ (w V).  The gradient with respect to V in torch's convention is
-    w (R g), i.e. fr_degrid followed by the weights."""
+    w (R g): fr_degrid_weighted (fr_degrid without weights)."""
 
     @staticmethod
     def forward(ctx, vis, plan, weight=None):
@@ -256,10 +278,8 @@ class Grid(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, g):
-        gv = degrid(ctx.plan, g.contiguous())
-        if ctx.weight is not None:
-            gv = gv * ctx.weight.reshape(gv.shape)
-        return gv, None, None
+        w = None if ctx.weight is None else ctx.weight.contiguous()
+        return degrid(ctx.plan, g.contiguous(), weight=w), None, None
 
 
 def make_psf_kernel(plan, weight=None, eps_noise=-1e-6, stream=None):
@@ -409,6 +429,27 @@ def query_footprint(op, B=1, plan=None, psf=None):
                                       psf.handle if psf is not None else None, int(op), int(B),
                                       ctypes.byref(s), ctypes.byref(r)))
     return s.value, r.value
+
+
+def scratch_stats(stream=None, reset=False, ctx=None):
+    """(peak bytes in use since the last reset, bytes held) of the library's scratch
+    arena for `stream` (default: torch's current stream) on ctx's device."""
+    ctx = ctx or Context.get()
+    peak, held = ctypes.c_size_t(), ctypes.c_size_t()
+    L.check(_lib().fr_scratch_stats(ctx.handle, _stream(stream), int(bool(reset)), ctypes.byref(peak),
+                                    ctypes.byref(held)))
+    return peak.value, held.value
+
+
+def scratch_trim(stream=None, ctx=None):
+    """Synchronise `stream` and return its arena's device memory."""
+    ctx = ctx or Context.get()
+    L.check(_lib().fr_scratch_trim(ctx.handle, _stream(stream)))
+
+
+def inject_alloc_failure(after):
+    """Make the library's device allocation after the next `after` fail (tests)."""
+    L.check(_lib().fr_inject_alloc_failure(int(after)))
 
 
 def profile_enable(on=True):

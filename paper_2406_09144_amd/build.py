@@ -2,7 +2,7 @@
 
 Every translation unit under csrc/ is compiled with hipcc in parallel and linked
 into paper_2406_09144_amd/libfrmi.so.  Packed-FP32 instructions are disabled
-(-packed-fp32-ops); hardware float atomics are enabled (-munsafe-fp-atomics).
+(-packed-fp32-ops).
 """
 
 import concurrent.futures as cf
@@ -22,7 +22,7 @@ ARCH = "gfx950"
 CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function",
+    "-Wall", "-Wno-unused-function",
     "-I", os.path.join(ROOT, "include"),
 ]
 

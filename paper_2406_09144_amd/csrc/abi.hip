@@ -7,11 +7,29 @@
 #include "objects.h"
 #include "profiler.h"
 
+#include <atomic>
+
 namespace frmi {
 
 static thread_local std::string g_last_error;
 
 void set_last_error(const std::string &m) { g_last_error = m; }
+
+// allocations left before an injected failure (< 0: none injected)
+static std::atomic<long long> g_alloc_budget{-1};
+
+hipError_t device_alloc(void **p, size_t bytes) {
+    long long b = g_alloc_budget.load();
+    while (b >= 0) {
+        if (b == 0) {
+            *p = nullptr;
+            g_alloc_budget.store(-1);  // one failure per injection
+            return hipErrorOutOfMemory;
+        }
+        if (g_alloc_budget.compare_exchange_weak(b, b - 1)) break;
+    }
+    return hipMalloc(p, bytes);
+}
 
 }  // namespace frmi
 
@@ -279,6 +297,16 @@ int fr_plan_get_info(const fr_plan *pl, fr_plan_info *info) {
     FR_API_END
 }
 
+int fr_plan_export_order(const fr_plan *pl, uint64_t *keys, uint32_t *perm, int64_t *bucket_start,
+                         int64_t *n_keys) {
+    FR_API_BEGIN
+    FR_REQUIRE(pl, "plan is NULL");
+    DeviceGuard dg(pl->ctx->device);
+    if (n_keys) *n_keys = plan_n_keys(pl);
+    plan_export_order(pl, keys, perm, bucket_start);
+    FR_API_END
+}
+
 int fr_degrid(fr_plan *pl, const void *img, void *vis, void *stream) {
     FR_API_BEGIN
     FR_REQUIRE(pl, "plan is NULL");
@@ -289,6 +317,19 @@ int fr_degrid(fr_plan *pl, const void *img, void *vis, void *stream) {
         degrid<double>(pl, (const double *)img, (double2 *)vis, as_stream(stream));
     else
         degrid<float>(pl, (const float *)img, (float2 *)vis, as_stream(stream));
+    FR_API_END
+}
+
+int fr_degrid_weighted(fr_plan *pl, const void *img, const void *weight, void *vis, void *stream) {
+    FR_API_BEGIN
+    FR_REQUIRE(pl, "plan is NULL");
+    if (pl->n_vis == 0) return FR_OK;
+    FR_REQUIRE(img && vis && weight, "img, weight and vis are required");
+    DeviceGuard dg(pl->ctx->device);
+    if (pl->fp64)
+        degrid<double>(pl, (const double *)img, (double2 *)vis, as_stream(stream), (const double *)weight);
+    else
+        degrid<float>(pl, (const float *)img, (float2 *)vis, as_stream(stream), (const float *)weight);
     FR_API_END
 }
 
@@ -501,33 +542,49 @@ int fr_query_footprint(const fr_plan *pl, const fr_psf *psf, int op, int64_t B, 
     FR_REQUIRE(!need_plan || pl, "this op needs a plan");
     FR_REQUIRE(need_plan || op == FR_OP_CG || psf, "this op needs a PSF object");
     FR_REQUIRE(op != FR_OP_CG || pl || psf, "CG needs a plan or a PSF object");
-    const bool fp64 = pl ? pl->fp64 : psf->fp64;
-    const size_t rs = fp64 ? 8 : 4, cs = 2 * rs;
-    const int64_t nx = pl ? pl->nx : psf->nx, ny = pl ? pl->ny : psf->ny, nc = pl ? pl->n_chan : psf->n_chan;
-    const size_t img = (size_t)nc * nx * ny;
-    // packed half-spectrum rows of one image: nx rows of py/2 (at most ny) values
-    const size_t conv = (size_t)nc * nx * (psf ? psf->py / 2 : ny) * cs;
-    const size_t red = (size_t)std::max<int64_t>(B, 1) * 64 * sizeof(double);
+    const bool prior = true;  // the prior term's scratch is counted whenever an op can take one
     size_t s = 0;
     switch (op) {
-    case FR_OP_DEGRID:
-    case FR_OP_GRID: s = planes_bytes(pl); break;
-    case FR_OP_RNR_APPROX: s = B * conv; break;
-    case FR_OP_RNR_EXACT: s = planes_bytes(pl) + pl->n_vis * cs; break;
-    case FR_OP_LIK_FAST: s = 3 * B * img * rs + B * conv + red; break;
-    case FR_OP_LIK_EXACT: s = 3 * B * img * rs + planes_bytes(pl) + pl->n_vis * cs + B * conv + red; break;
-    case FR_OP_CG:
-        s = 6 * img * rs + conv + red + (psf ? 0 : planes_bytes(pl) + pl->n_vis * cs);
-        break;
-    case FR_OP_MAKE_PSF:
-        s = (size_t)nc * 16 * nx * ny * cs + (size_t)nc * 4 * nx * ny * (rs + cs) + pl->n_vis * 28;
-        break;
+    case FR_OP_DEGRID: s = pl->n_vis ? degrid_scratch(pl) : 0; break;
+    case FR_OP_GRID: s = grid_scratch(pl); break;
+    case FR_OP_RNR_APPROX: s = rnr_approx_scratch(psf, B); break;
+    case FR_OP_RNR_EXACT: s = B ? rnr_exact_scratch(pl) : 0; break;
+    case FR_OP_LIK_FAST: s = B ? lik_scratch(pl, psf, FR_LIK_FAST, B, prior) : 0; break;
+    case FR_OP_LIK_EXACT: s = B ? lik_scratch(pl, psf, FR_LIK_EXACT, B, prior) : 0; break;
+    case FR_OP_CG: s = cg_scratch(pl, psf, prior); break;
+    case FR_OP_MAKE_PSF: s = psf_build_scratch(pl) + psf_plan_device_bound(pl); break;
     }
     *scratch_bytes = s;
     size_t r = 0;
     if (pl) r += pl->resident;
     if (psf) r += psf->KR.bytes + psf->KN.bytes + psf->nfac.bytes;
     *resident_bytes = r;
+    FR_API_END
+}
+
+int fr_scratch_stats(fr_ctx *ctx, void *stream, int reset, size_t *peak_in_use, size_t *held) {
+    FR_API_BEGIN
+    FR_REQUIRE(ctx && peak_in_use && held, "ctx, peak_in_use and held are required");
+    DeviceGuard dg(ctx->c.device);
+    Arena &a = arena_for(as_stream(stream));
+    *held = a.held();
+    *peak_in_use = a.peak(reset != 0);
+    FR_API_END
+}
+
+int fr_scratch_trim(fr_ctx *ctx, void *stream) {
+    FR_API_BEGIN
+    FR_REQUIRE(ctx, "ctx is NULL");
+    DeviceGuard dg(ctx->c.device);
+    HIP_CHECK(hipStreamSynchronize(as_stream(stream)));
+    if (!arena_for(as_stream(stream)).trim()) throw Error(FR_EBUSY, "scratch of this stream is in use");
+    FR_API_END
+}
+
+int fr_inject_alloc_failure(int64_t after) {
+    FR_API_BEGIN
+    FR_REQUIRE(after >= -1, "after must be >= -1");
+    g_alloc_budget.store(after);
     FR_API_END
 }
 

@@ -77,7 +77,8 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_dot_pAp(const CGState *__res
     if (threadIdx.x == 0) pAp_partials[blockIdx.x] = s;
 }
 
-// alpha = rr[k] / <p, A p>; x += alpha p, r -= alpha A p; partials of <r, r>
+// alpha = <r_k, r_k> / <p, A p>; x += alpha p, r -= alpha A p; partials of <r, r>.
+// <r_k, r_k> lives in rr[k & 1] (two slots: iteration k reads one, writes the other)
 template <typename T>
 __global__ __launch_bounds__(kRedThreads) void k_cg_step(const CGState *__restrict__ st, T *__restrict__ x,
                                                          T *__restrict__ r, const T *__restrict__ p,
@@ -88,7 +89,7 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_step(const CGState *__restri
     if (cg_done(st)) return;
     __shared__ double alpha_sh;
     const double pAp = block_sum_partials(pAp_partials, n_pAp);
-    if (threadIdx.x == 0) alpha_sh = rr[k] / pAp;
+    if (threadIdx.x == 0) alpha_sh = rr[k & 1] / pAp;
     __syncthreads();
     const T a = (T)alpha_sh;
     double s = grid_stride_sum(n, [&](int64_t i) {
@@ -102,7 +103,7 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_step(const CGState *__restri
     if (threadIdx.x == 0) rr_partials[blockIdx.x] = s;
 }
 
-// rr[k+1] = <r, r>, beta = rr[k+1] / rr[k], p = r + beta p; block 0 records the
+// <r_k+1, r_k+1> -> rr[(k + 1) & 1], beta = its ratio to rr[k & 1], p = r + beta p; block 0 records the
 // history and the stopping flag (blocks that already see the flag skip the
 // update of p, which is no longer used)
 template <typename T>
@@ -115,9 +116,9 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_update_p(CGState *__restrict
     __shared__ double beta_sh;
     const double rn = block_sum_partials(rr_partials, n_rr);
     if (threadIdx.x == 0) {
-        beta_sh = rn / rr[k];
+        beta_sh = rn / rr[k & 1];
         if (blockIdx.x == 0) {
-            rr[k + 1] = rn;
+            rr[(k + 1) & 1] = rn;
             hist[k + 1] = sqrt(rn);
             st->iters = k + 1;
             if (sqrt(rn) <= st->stop) __hip_atomic_store(&st->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -140,7 +141,7 @@ void cg_run(int64_t n, const T *b, T *x, int maxiter, double rtol, double *hist,
     Scratch state(sizeof(CGState), st);
     const int nb = red_blocks(n);
     Scratch partials((size_t)2 * nb * sizeof(double), st);
-    Scratch rr((size_t)(maxiter + 1) * sizeof(double), st);
+    Scratch rr(2 * sizeof(double), st);
     double *pAp_part = partials.as<double>(), *rr_part = partials.as<double>() + nb;
     Scratch r(n * sizeof(T), st), p(n * sizeof(T), st), Ap(n * sizeof(T), st);
     CGState *S = state.as<CGState>();
@@ -162,6 +163,18 @@ void cg_run(int64_t n, const T *b, T *x, int maxiter, double rtol, double *hist,
     }
     k_cg_report<<<1, 64, 0, st>>>(S, iters_done);
     LAUNCH_CHECK();
+}
+
+size_t cg_scratch(const fr_plan *pl, const fr_psf *psf, bool prior) {
+    const bool fp64 = psf ? psf->fp64 : pl->fp64;
+    const size_t rs = fp64 ? 8 : 4;
+    const int64_t nx = psf ? psf->nx : pl->nx, ny = psf ? psf->ny : pl->ny, nc = psf ? psf->n_chan : pl->n_chan;
+    const size_t vec = scratch_round((size_t)nc * nx * ny * rs);
+    const size_t loop = scratch_round(sizeof(CGState)) + scratch_round(2 * (size_t)red_blocks(nc * nx * ny) * 8) +
+                        scratch_round(2 * sizeof(double)) + 3 * vec;
+    const size_t apply = std::max(prior ? periodic_conv_scratch(nc, nx, ny, fp64) : size_t(0),
+                                  psf ? rnr_approx_scratch(psf, 1) : rnr_exact_scratch(pl));
+    return 2 * vec + (prior ? vec : 0) + loop + apply;
 }
 
 template <typename T>

@@ -123,6 +123,14 @@ template <class F> inline void with_odd(int odd, F &&f) {
     }
 }
 
+// Device allocations of the library (hipMalloc).  A test hook can make the
+// allocation after the next `n` succeed fail as if the device were out of memory
+// (fr_inject_alloc_failure), to exercise the error paths.
+hipError_t device_alloc(void **p, size_t bytes);
+
+// Bytes a Scratch of `bytes` takes from its arena (regions are 256-byte aligned).
+constexpr size_t scratch_round(size_t bytes) { return (bytes + 255) & ~size_t(255); }
+
 // Scratch memory of library calls on one stream, kept from call to call: a stack
 // of device chunks that only grows (a chunk is added when a request does not fit;
 // the first calls on a stream pay for it).  Work on a stream runs in order, so a
@@ -136,28 +144,60 @@ class Arena {
     struct Mark {
         int chunk = 0;
         size_t top = 0;
+        size_t live = 0;
     };
     void *push(size_t bytes, Mark &m) {
         std::lock_guard<std::mutex> g(mu_);
-        const size_t b = (bytes + 255) & ~size_t(255);
+        const size_t b = scratch_round(bytes);
+        if (chunks_.empty()) add_chunk(std::max<size_t>(b, size_t(64) << 20));
+        // on failure below nothing has moved: the caller's regions stay as they were
+        int cur = cur_;
+        size_t top = top_;
+        while (top + b > chunks_[cur].cap) {
+            if (cur + 1 == (int)chunks_.size()) add_chunk(std::max(b, 2 * chunks_[cur].cap));
+            ++cur;
+            top = 0;
+        }
         m.chunk = cur_;
         m.top = top_;
-        if (chunks_.empty()) add_chunk(std::max<size_t>(b, size_t(64) << 20));
-        while (top_ + b > chunks_[cur_].cap) {
-            if (cur_ + 1 == (int)chunks_.size()) add_chunk(std::max(b, 2 * chunks_[cur_].cap));
-            ++cur_;
-            top_ = 0;
-        }
-        void *p = chunks_[cur_].p + top_;
-        top_ += b;
+        m.live = live_;
+        cur_ = cur;
+        void *p = chunks_[cur].p + top;
+        top_ = top + b;
+        live_ += b;
+        peak_ = std::max(peak_, live_);
         return p;
     }
     void pop(const Mark &m) {
         std::lock_guard<std::mutex> g(mu_);
         cur_ = m.chunk;
         top_ = m.top;
+        live_ = m.live;
     }
-    size_t held() const { size_t t = 0; for (auto &c : chunks_) t += c.cap; return t; }
+    size_t held() {
+        std::lock_guard<std::mutex> g(mu_);
+        size_t t = 0;
+        for (auto &c : chunks_) t += c.cap;
+        return t;
+    }
+    // highest sum of live region sizes since the last reset
+    size_t peak(bool reset) {
+        std::lock_guard<std::mutex> g(mu_);
+        const size_t v = peak_;
+        if (reset) peak_ = live_;
+        return v;
+    }
+    // Free every chunk; false (nothing freed) while a region is live.  The caller
+    // has synchronised the stream, so no enqueued work still uses the memory.
+    bool trim() {
+        std::lock_guard<std::mutex> g(mu_);
+        if (live_ != 0) return false;
+        for (auto &c : chunks_) (void)hipFree(c.p);
+        chunks_.clear();
+        cur_ = 0;
+        top_ = 0;
+        return true;
+    }
 
   private:
     struct Chunk {
@@ -166,7 +206,7 @@ class Arena {
     };
     void add_chunk(size_t cap) {
         void *p = nullptr;
-        const hipError_t e = hipMalloc(&p, cap);
+        const hipError_t e = device_alloc(&p, cap);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             throw Error(FR_ENOMEM, "scratch allocation of " + std::to_string(cap) + " bytes failed");
@@ -177,6 +217,7 @@ class Arena {
     std::vector<Chunk> chunks_;
     int cur_ = 0;
     size_t top_ = 0;
+    size_t live_ = 0, peak_ = 0;
 };
 
 // the arena of (current device, stream)
@@ -231,7 +272,7 @@ struct DevBuf {
     size_t bytes = 0;
     DevBuf() = default;
     explicit DevBuf(size_t n) : bytes(n) {
-        if (n) HIP_CHECK(hipMalloc(&p, n));
+        if (n) HIP_CHECK(device_alloc(&p, n));
     }
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;

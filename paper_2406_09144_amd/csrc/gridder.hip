@@ -24,12 +24,11 @@
 #include <cmath>
 #include <numeric>
 
-#include <rocprim/device/device_radix_sort.hpp>
-
 #include "eskernel.h"
 #include "fftk.h"
 #include "objects.h"
 #include "profiler.h"
+#include "radix_sort.h"
 
 namespace frmi {
 
@@ -194,7 +193,8 @@ __global__ __launch_bounds__(NTHR) void k_degrid(const WorkItem *__restrict__ wi
                                                  int taylor, const uint32_t *__restrict__ r_idx,
                                                  const uint32_t *__restrict__ r_cell, const T *__restrict__ r_du,
                                                  const T *__restrict__ r_dv, const T *__restrict__ r_dw,
-                                                 const T *__restrict__ r_ph, c2<T> *__restrict__ vis) {
+                                                 const T *__restrict__ r_ph, const T *__restrict__ weight,
+                                                 c2<T> *__restrict__ vis) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     c2<T> *tile = reinterpret_cast<c2<T> *>(smem_raw);
     constexpr int TS = kTile + W - 1;
@@ -297,7 +297,13 @@ __global__ __launch_bounds__(NTHR) void k_degrid(const WorkItem *__restrict__ wi
         }
         const uint32_t id = r_idx[pos];
         if (id >> 31) v.y = -v.y;
-        vis[id & 0x7fffffffu] = v;
+        const uint32_t vi = id & 0x7fffffffu;
+        if (weight) {  // N^-1 R: the diagonal noise weights applied in the store
+            const T wt = weight[vi];
+            v.x *= wt;
+            v.y *= wt;
+        }
+        vis[vi] = v;
     }
 }
 
@@ -1038,8 +1044,8 @@ template <typename T> void zero_async(T *p, int64_t n, hipStream_t st) {
 template <typename T> constexpr int chunk() { return std::is_same<T, float>::value ? 512 : 256; }
 
 template <typename T, int W>
-void launch_degrid_w(const fr_plan *pl, const WorkItem *wis, int64_t nwi, const c2<T> *planes, c2<T> *vis,
-                     hipStream_t st) {
+void launch_degrid_w(const fr_plan *pl, const WorkItem *wis, int64_t nwi, const c2<T> *planes, const T *weight,
+                     c2<T> *vis, hipStream_t st) {
     constexpr int TS = kTile + W - 1;
     const size_t lds = (size_t)TS * TS * sizeof(c2<T>);
     auto kern = k_degrid<T, W, chunk<T>(), 1>;
@@ -1048,7 +1054,7 @@ void launch_degrid_w(const fr_plan *pl, const WorkItem *wis, int64_t nwi, const 
     kern<<<dim3((unsigned)nwi), chunk<T>(), lds, st>>>(
         wis, planes, ilog2(pl->nu), ilog2(pl->nv), pl->Ww, (T)pl->beta, (T)pl->wbeta, pl->coplanar ? 1 : 0,
         pl->taylor ? 1 : 0, pl->r_idx.as<uint32_t>(), pl->r_cell.as<uint32_t>(), pl->r_du.as<T>(), pl->r_dv.as<T>(), pl->r_dw.as<T>(),
-        pl->r_ph.as<T>(), vis);
+        pl->r_ph.as<T>(), weight, vis);
     LAUNCH_CHECK();
 }
 
@@ -1132,6 +1138,62 @@ size_t planes_bytes(const fr_plan *pl) {
     return (size_t)pl->n_planes * pl->nu * pl->nv * (pl->fp64 ? sizeof(double2) : sizeof(float2));
 }
 
+// Blocks of k_vis_bound (one partial maximum each).
+static int vis_bound_blocks(int64_t n_vis) {
+    return (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n_vis + 1023) / 1024));
+}
+
+// Partial tiles of the largest channel: [items][Ww][TS * TS] complex.
+static size_t grid_partial_bytes(int64_t items, int Ww, int W, bool fp64) {
+    const size_t TS = kTile + W - 1;
+    return (size_t)items * Ww * TS * TS * (fp64 ? sizeof(double2) : sizeof(float2));
+}
+
+size_t degrid_scratch(const fr_plan *pl) { return scratch_round(planes_bytes(pl)); }
+
+size_t grid_scratch(const fr_plan *pl) {
+    int64_t items = 0;
+    for (int64_t c = 0; c < pl->n_chan; ++c) items = std::max(items, pl->gwi_chan[c + 1] - pl->gwi_chan[c]);
+    return scratch_round(planes_bytes(pl)) + scratch_round((size_t)vis_bound_blocks(pl->n_vis) * sizeof(float)) +
+           scratch_round(grid_partial_bytes(items, pl->Ww, pl->W, pl->fp64));
+}
+
+static int grid_chunk(int64_t n_vis_per_chan, int n_cu);
+
+// Bound on the arena scratch of gridding with the coplanar plan of the doubled
+// field that fr_make_psf_kernel derives (built inside the call): one plane of
+// 4 nx x 4 ny cells, and at most one gridding item per non-empty tile plus one per
+// chunk of records in each channel.
+// Device memory a plan build takes per visibility at its peak: the coordinate
+// and key arrays of k_vis_coords (idx, cell, key, du, dv, dw, ph), the two key and
+// permutation buffers of the sort and its tables (12 bytes per 16 keys), and the
+// sorted records the plan keeps (idx, cell, du, dv, dw, ph); per bucket, its
+// first record and first gridding item, and the tile maps.
+static size_t plan_bytes_per_vis(size_t rs) { return 12 + 4 * rs + 24 + 1 + 8 + 4 * rs; }
+static size_t plan_bytes_per_key() { return 8 + 4 + 4 + 1; }
+
+// Bound on the device memory of building the coplanar doubled-field plan inside
+// fr_make_psf_kernel: the records it keeps and its construction temporaries
+// (per visibility: coordinates, keys, sort buffers), plus the per-bucket offsets.
+size_t psf_plan_device_bound(const fr_plan *pl) {
+    const size_t rs = pl->fp64 ? 8 : 4;
+    const int64_t n_tiles = (4 * pl->nx / kTile) * (4 * pl->ny / kTile);
+    const size_t n_keys = (size_t)pl->n_chan * n_tiles;
+    return (size_t)pl->n_vis * (plan_bytes_per_vis(rs)) + (n_keys + 1) * plan_bytes_per_key();
+}
+
+size_t psf_grid_scratch_bound(const fr_plan *pl) {
+    const bool fp64 = pl->fp64;
+    const int W = es_support(pl->eps, 2, 4);
+    const int64_t nu = 4 * pl->nx, nv = 4 * pl->ny;
+    const int64_t n_tiles = (nu / kTile) * (nv / kTile);
+    const int64_t items = std::min<int64_t>(n_tiles, pl->n_row) +
+                          (pl->n_row + grid_chunk(pl->n_row, pl->ctx->n_cu) - 1) / grid_chunk(pl->n_row, pl->ctx->n_cu);
+    const size_t planes = (size_t)nu * nv * (fp64 ? sizeof(double2) : sizeof(float2));
+    return scratch_round(planes) + scratch_round((size_t)vis_bound_blocks(pl->n_vis) * sizeof(float)) +
+           scratch_round(grid_partial_bytes(items, 1, W, fp64));
+}
+
 // forward: image channel -> planes (prep, row FFT, column FFT)
 template <typename T>
 void image_to_planes(const fr_plan *pl, const T *img_c, c2<T> *planes, hipStream_t st) {
@@ -1181,14 +1243,14 @@ void planes_to_image(const fr_plan *pl, const c2<T> *planes_c, const uint8_t *ac
 }
 
 template <typename T>
-void degrid(const fr_plan *pl, const T *img, c2<T> *vis, hipStream_t st) {
+void degrid(const fr_plan *pl, const T *img, c2<T> *vis, hipStream_t st, const T *weight) {
     Scratch planes(planes_bytes(pl), st);
     const WorkItem *wis = pl->wi.as<WorkItem>();
     for (int64_t c = 0; c < pl->n_chan; ++c) {
         image_to_planes<T>(pl, img + c * pl->nx * pl->ny, planes.as<c2<T>>(), st);
         const int64_t w0 = pl->wi_chan[c], w1 = pl->wi_chan[c + 1];
         if (w1 > w0) {
-#define FR_CALL_DEGRID(WW) launch_degrid_w<T, WW>(pl, wis + w0, w1 - w0, planes.as<c2<T>>(), vis, st)
+#define FR_CALL_DEGRID(WW) launch_degrid_w<T, WW>(pl, wis + w0, w1 - w0, planes.as<c2<T>>(), weight, vis, st)
             FR_W_DISPATCH(pl->W, FR_CALL_DEGRID)
 #undef FR_CALL_DEGRID
         }
@@ -1199,7 +1261,7 @@ template <typename T>
 void grid(const fr_plan *pl, const c2<T> *vis, const T *weight, T *img, hipStream_t st) {
     Scratch planes(planes_bytes(pl), st);
     // bound on every gridded contribution (sets the fixed-point scale of the tiles)
-    const int nbb = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (pl->n_vis + 1023) / 1024));
+    const int nbb = vis_bound_blocks(pl->n_vis);
     Scratch ybound((size_t)nbb * sizeof(float), st);
     if (pl->n_vis > 0) {
         k_vis_bound<T><<<dim3((unsigned)nbb), 256, 0, st>>>(vis, weight, pl->n_vis, ybound.as<float>());
@@ -1214,8 +1276,8 @@ void grid(const fr_plan *pl, const c2<T> *vis, const T *weight, T *img, hipStrea
     }
 }
 
-template void degrid<float>(const fr_plan *, const float *, float2 *, hipStream_t);
-template void degrid<double>(const fr_plan *, const double *, double2 *, hipStream_t);
+template void degrid<float>(const fr_plan *, const float *, float2 *, hipStream_t, const float *);
+template void degrid<double>(const fr_plan *, const double *, double2 *, hipStream_t, const double *);
 template void grid<float>(const fr_plan *, const float2 *, const float *, float *, hipStream_t);
 template void grid<double>(const fr_plan *, const double2 *, const double *, double *, hipStream_t);
 
@@ -1290,22 +1352,22 @@ static void build_records(fr_plan *pl, const DevBuf &d_uvw, const DevBuf &d_freq
         2.0 * 3.14159265358979323846 * pl->taylor_h, pl->taylor ? 1 : 0, ntv, n_tiles, n_p0,
         key.as<uint32_t>(), idx.as<uint32_t>(), cell.as<uint32_t>(), du.as<T>(), dv.as<T>(), dwf.as<T>(), ph.as<T>());
     LAUNCH_CHECK();
-    // stable radix sort of (bucket, cell in tile) keys; the permutation gathers the records
+    // stable radix sort of (bucket, cell in tile) keys (hand-written LSD sort, 8-bit
+    // digits over the key's used bits); the permutation gathers the records
     DevBuf k64(n * 8), k64s(n * 8), perm(n * 4), perms(n * 4);
     k_sort_keys<<<dim3((unsigned)blocks), 256>>>(key.as<uint32_t>(), cell.as<uint32_t>(), n, k64.as<uint64_t>(),
                                                  perm.as<uint32_t>());
     LAUNCH_CHECK();
     int key_bits = 1;
     while ((int64_t(1) << key_bits) < n_keys) ++key_bits;
-    const unsigned end_bit = (unsigned)(10 + key_bits);
-    size_t tmp_bytes = 0;
-    HIP_CHECK(rocprim::radix_sort_pairs(nullptr, tmp_bytes, k64.as<uint64_t>(), k64s.as<uint64_t>(),
-                                        perm.as<uint32_t>(), perms.as<uint32_t>(), (size_t)n, 0u, end_bit));
-    DevBuf tmp(std::max<size_t>(tmp_bytes, 1));
-    HIP_CHECK(rocprim::radix_sort_pairs(tmp.p, tmp_bytes, k64.as<uint64_t>(), k64s.as<uint64_t>(),
-                                        perm.as<uint32_t>(), perms.as<uint32_t>(), (size_t)n, 0u, end_bit));
+    const int end_bit = 10 + key_bits;
+    DevBuf tmp(std::max<size_t>(RadixSortBuffers().bytes(n), 1));
+    const bool in_second = radix_sort_pairs(k64.as<uint64_t>(), perm.as<uint32_t>(), k64s.as<uint64_t>(),
+                                            perms.as<uint32_t>(), n, end_bit, tmp.p, nullptr);
+    const uint64_t *keys_sorted = in_second ? k64s.as<uint64_t>() : k64.as<uint64_t>();
+    const uint32_t *perm_sorted = in_second ? perms.as<uint32_t>() : perm.as<uint32_t>();
     DevBuf d_bounds((n_keys + 1) * 8);
-    k_bucket_bounds<<<dim3((unsigned)((n_keys + 1 + 255) / 256)), 256>>>(k64s.as<uint64_t>(), n, n_keys,
+    k_bucket_bounds<<<dim3((unsigned)((n_keys + 1 + 255) / 256)), 256>>>(keys_sorted, n, n_keys,
                                                                           d_bounds.as<int64_t>());
     LAUNCH_CHECK();
     std::vector<int64_t> bounds(n_keys + 1);
@@ -1313,8 +1375,7 @@ static void build_records(fr_plan *pl, const DevBuf &d_uvw, const DevBuf &d_freq
     {
         DevBuf d_steps(sizeof(unsigned long long));
         HIP_CHECK(hipMemset(d_steps.p, 0, d_steps.bytes));
-        k_count_runs<<<dim3((unsigned)((n + 255) / 256)), 256>>>(k64s.as<uint64_t>(), n,
-                                                                  d_steps.as<unsigned long long>());
+        k_count_runs<<<dim3((unsigned)((n + 255) / 256)), 256>>>(keys_sorted, n, d_steps.as<unsigned long long>());
         LAUNCH_CHECK();
         unsigned long long steps = 0;
         HIP_CHECK(hipMemcpy(&steps, d_steps.p, sizeof(steps), hipMemcpyDeviceToHost));
@@ -1413,7 +1474,7 @@ static void build_records(fr_plan *pl, const DevBuf &d_uvw, const DevBuf &d_freq
     pl->r_dw = DevBuf(n * sizeof(T));
     pl->r_ph = DevBuf(n * sizeof(T));
     k_gather_records<T><<<dim3((unsigned)blocks), 256>>>(
-        n, perms.as<uint32_t>(), idx.as<uint32_t>(), cell.as<uint32_t>(), du.as<T>(), dv.as<T>(), dwf.as<T>(),
+        n, perm_sorted, idx.as<uint32_t>(), cell.as<uint32_t>(), du.as<T>(), dv.as<T>(), dwf.as<T>(),
         ph.as<T>(), pl->r_idx.as<uint32_t>(), pl->r_cell.as<uint32_t>(), pl->r_du.as<T>(), pl->r_dv.as<T>(),
         pl->r_dw.as<T>(), pl->r_ph.as<T>());
     LAUNCH_CHECK();
@@ -1426,6 +1487,71 @@ static void build_records(fr_plan *pl, const DevBuf &d_uvw, const DevBuf &d_freq
     pl->wi = DevBuf(std::max<size_t>(1, wis.size()) * sizeof(WorkItem));
     if (!wis.empty()) HIP_CHECK(hipMemcpy(pl->wi.p, wis.data(), wis.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
     HIP_CHECK(hipDeviceSynchronize());
+}
+
+// ------------------------------------------------------------------ inspection
+int64_t plan_n_keys(const fr_plan *pl) { return pl->n_chan * (int64_t)pl->n_p0 * pl->n_tiles; }
+
+template <typename T> static void export_keys(const fr_plan *pl, uint64_t *keys_host) {
+    const int64_t n = pl->n_vis;
+    DevBuf d_uvw(pl->n_row * 3 * sizeof(double)), d_freq(pl->n_chan * sizeof(double));
+    HIP_CHECK(hipMemcpy(d_uvw.p, pl->uvw_host.data(), d_uvw.bytes, hipMemcpyHostToDevice));
+    HIP_CHECK(hipMemcpy(d_freq.p, pl->freq.data(), d_freq.bytes, hipMemcpyHostToDevice));
+    DevBuf key(n * 4), idx(n * 4), cell(n * 4), du(n * sizeof(T)), dv(n * sizeof(T)), dwf(n * sizeof(T)),
+        ph(n * sizeof(T)), k64(n * 8), perm(n * 4);
+    const int64_t blocks = (n + 255) / 256;
+    k_vis_coords<T><<<dim3((unsigned)blocks), 256>>>(
+        d_uvw.as<double>(), d_freq.as<double>(), n, (int)pl->n_chan, ilog2(pl->nu), ilog2(pl->nv), pl->dx_, pl->dy_,
+        pl->W, pl->Ww, pl->coplanar ? 1 : 0, pl->w0, pl->dw, pl->yc, 2.0 * 3.14159265358979323846 * pl->taylor_h,
+        pl->taylor ? 1 : 0, pl->ntv, pl->n_tiles, pl->n_p0, key.as<uint32_t>(), idx.as<uint32_t>(),
+        cell.as<uint32_t>(), du.as<T>(), dv.as<T>(), dwf.as<T>(), ph.as<T>());
+    LAUNCH_CHECK();
+    k_sort_keys<<<dim3((unsigned)blocks), 256>>>(key.as<uint32_t>(), cell.as<uint32_t>(), n, k64.as<uint64_t>(),
+                                                 perm.as<uint32_t>());
+    LAUNCH_CHECK();
+    HIP_CHECK(hipMemcpy(keys_host, k64.p, n * 8, hipMemcpyDeviceToHost));
+}
+
+// Bucket boundaries from a list of work items (chunks of one bucket each, in bucket
+// order), checking that the items of every bucket tile its range exactly.
+static void bounds_from_items(const fr_plan *pl, const DevBuf &items, int64_t n_items, int64_t *bs) {
+    const int64_t n_keys = plan_n_keys(pl);
+    std::vector<WorkItem> it(n_items);
+    if (n_items) HIP_CHECK(hipMemcpy(it.data(), items.p, n_items * sizeof(WorkItem), hipMemcpyDeviceToHost));
+    int64_t end = 0, k_next = 0;
+    for (int64_t j = 0; j < n_items; ++j) {
+        const WorkItem &w = it[j];
+        const int64_t k = ((int64_t)w.chan * pl->n_p0 + w.p0) * pl->n_tiles + (int64_t)(w.tu / kTile) * pl->ntv +
+                          w.tv / kTile;
+        if (k >= k_next) {  // first item of bucket k: the buckets in between are empty
+            if (w.start != end) throw Error(FR_EHIP, "work items leave a gap in the sorted records");
+            for (; k_next <= k; ++k_next) bs[k_next] = end;
+        } else if (k != k_next - 1 || w.start != end) {
+            throw Error(FR_EHIP, "work items out of bucket order");
+        }
+        end = w.start + w.count;
+    }
+    if (end != pl->n_vis) throw Error(FR_EHIP, "work items do not cover every record");
+    for (; k_next <= n_keys; ++k_next) bs[k_next] = end;
+}
+
+void plan_export_order(const fr_plan *pl, uint64_t *keys, uint32_t *perm, int64_t *bucket_start) {
+    const int64_t n = pl->n_vis;
+    if (keys && n) {
+        if (pl->fp64) export_keys<double>(pl, keys);
+        else export_keys<float>(pl, keys);
+    }
+    if (perm && n) {
+        HIP_CHECK(hipMemcpy(perm, pl->r_idx.p, n * 4, hipMemcpyDeviceToHost));
+        for (int64_t k = 0; k < n; ++k) perm[k] &= 0x7fffffffu;
+    }
+    if (bucket_start) {
+        bounds_from_items(pl, pl->wi, pl->n_wi, bucket_start);
+        std::vector<int64_t> g(plan_n_keys(pl) + 1);
+        bounds_from_items(pl, pl->gwi, pl->n_gwi, g.data());
+        for (size_t k = 0; k < g.size(); ++k)
+            if (g[k] != bucket_start[k]) throw Error(FR_EHIP, "degridding and gridding items disagree");
+    }
 }
 
 void plan_build(fr_plan *pl, const double *uvw_m, const double *freq_hz) {

@@ -8,6 +8,26 @@
 
 namespace frmi {
 
+size_t rnr_exact_scratch(const fr_plan *pl) {
+    const size_t cs = pl->fp64 ? sizeof(double2) : sizeof(float2);
+    return scratch_round((size_t)pl->n_vis * cs) + std::max(degrid_scratch(pl), grid_scratch(pl));
+}
+
+size_t lik_scratch(const fr_plan *pl, const fr_psf *psf, int mode, int64_t B, bool prior) {
+    const bool fp64 = mode == FR_LIK_FAST ? psf->fp64 : pl->fp64;
+    const size_t rs = fp64 ? 8 : 4;
+    const int64_t nx = mode == FR_LIK_FAST ? psf->nx : pl->nx, ny = mode == FR_LIK_FAST ? psf->ny : pl->ny;
+    const int64_t nc = mode == FR_LIK_FAST ? psf->n_chan : pl->n_chan;
+    const size_t n_all = (size_t)B * nc * nx * ny;
+    const size_t per = scratch_round((size_t)std::max<int64_t>(B, 1) * kRedMaxBlocks * sizeof(double)) +
+                       2 * scratch_round(n_all * rs);
+    const size_t yper = periodic_conv_scratch(B * nc, nx, ny, fp64);
+    const size_t body = mode == FR_LIK_FAST
+                            ? scratch_round(n_all * rs) + std::max(rnr_approx_scratch(psf, B), yper)
+                            : rnr_exact_scratch(pl);
+    return per + std::max(body, prior ? scratch_round(n_all * rs) + yper : size_t(0));
+}
+
 template <typename T>
 void apply_rnr_exact(const fr_plan *pl, const T *weight, const T *x, T *y, int64_t B, hipStream_t st) {
     const int64_t n_img = pl->n_chan * pl->nx * pl->ny;

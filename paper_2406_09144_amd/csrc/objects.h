@@ -81,9 +81,23 @@ inline bool matrix_spread(const fr_plan *pl) { return !pl->fp64 && pl->W <= 8 &&
 
 // gridder.hip
 void plan_build(fr_plan *pl, const double *uvw_m, const double *freq_hz);
+int64_t plan_n_keys(const fr_plan *pl);
+void plan_export_order(const fr_plan *pl, uint64_t *keys, uint32_t *perm, int64_t *bucket_start);
 size_t planes_bytes(const fr_plan *pl);
+// arena scratch (bytes, regions rounded) that one call takes at most
+size_t degrid_scratch(const fr_plan *pl);
+size_t grid_scratch(const fr_plan *pl);
+size_t psf_grid_scratch_bound(const fr_plan *pl);
+size_t psf_build_scratch(const fr_plan *pl);
+size_t psf_plan_device_bound(const fr_plan *pl);
+size_t rnr_approx_scratch(const fr_psf *psf, int64_t B);
+size_t periodic_conv_scratch(int64_t n_img, int64_t nx, int64_t ny, bool fp64);
+size_t rnr_exact_scratch(const fr_plan *pl);
+size_t lik_scratch(const fr_plan *pl, const fr_psf *psf, int mode, int64_t B, bool prior);
+size_t cg_scratch(const fr_plan *pl, const fr_psf *psf, bool prior);
+// vis = R img, or diag(weight) R img when weight is given
 template <typename T>
-void degrid(const fr_plan *pl, const T *img, c2<T> *vis, hipStream_t st);
+void degrid(const fr_plan *pl, const T *img, c2<T> *vis, hipStream_t st, const T *weight = nullptr);
 template <typename T>
 void grid(const fr_plan *pl, const c2<T> *vis, const T *weight, T *img, hipStream_t st);
 

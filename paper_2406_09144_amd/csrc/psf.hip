@@ -75,6 +75,12 @@ template <typename T> struct ExtractKN {
     }
 };
 
+size_t psf_build_scratch(const fr_plan *pl) {
+    const size_t rs = pl->fp64 ? 8 : 4;
+    const size_t n_psf = (size_t)pl->n_chan * 4 * pl->nx * pl->ny;
+    return scratch_round(n_psf * rs) + std::max(psf_grid_scratch_bound(pl), scratch_round(n_psf * 2 * rs));
+}
+
 template <typename T>
 void make_psf(fr_plan *pl, const T *weight, double eps_noise, fr_psf *out, hipStream_t st) {
     const int64_t nx = pl->nx, ny = pl->ny, nc = pl->n_chan;

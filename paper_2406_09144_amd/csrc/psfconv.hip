@@ -49,6 +49,15 @@ void apply_rnr_approx_ex(const fr_psf *psf, const T *x, const T *d_in, T *y, con
     });
 }
 
+size_t rnr_approx_scratch(const fr_psf *psf, int64_t B) {
+    const size_t cs = psf->fp64 ? sizeof(double2) : sizeof(float2);
+    return scratch_round((size_t)B * psf->n_chan * psf->nx * (psf->py / 2) * cs);
+}
+
+size_t periodic_conv_scratch(int64_t n_img, int64_t nx, int64_t ny, bool fp64) {
+    return scratch_round((size_t)n_img * nx * (ny / 2) * (fp64 ? sizeof(double2) : sizeof(float2)));
+}
+
 template <typename T>
 void apply_rnr_approx(const fr_psf *psf, const T *x, T *y, int64_t B, hipStream_t st) {
     apply_rnr_approx_ex<T>(psf, x, nullptr, y, nullptr, nullptr, B, st);

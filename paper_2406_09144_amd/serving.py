@@ -11,7 +11,12 @@ Requests (PSF-convolution applies, degrid, grid, FAST likelihood gradients and
   * runs launches of different jobs concurrently on a pool of streams (default
     priority) and detects completion with events, so new arrivals are admitted as
     soon as slots and memory free up;
-  * records arrival -> completion latency per request.
+  * records arrival -> completion latency per request;
+  * drops cancelled requests: one cancelled while pending (its t_cancel has
+    passed, or Server.cancel was called from another thread) is never launched;
+    one cancelled while on the device keeps its slot and memory until the launch
+    finishes (device work is not preempted), then frees both and its result is
+    discarded.
 
 The scheduling logic is independent of the GPU: an executor object launches a
 batch and reports whether it has finished.  `GpuExecutor` drives libfrmi through
@@ -19,6 +24,7 @@ batch and reports whether it has finished.  `GpuExecutor` drives libfrmi through
 """
 
 import collections
+import threading
 import time
 from dataclasses import dataclass, field
 
@@ -40,6 +46,8 @@ class Request:
     t_start: float = None
     t_done: float = None
     batch: int = 0         # number of requests it was launched with
+    t_cancel: float = None  # the client gives up at this trace time (None: never)
+    cancelled: bool = False
 
 
 @dataclass
@@ -81,6 +89,21 @@ class Server:
         self.clock = clock
         self.peak_bytes = 0
         self.launches = []
+        self.free_slots = list(range(n_slots))
+        self.bytes_in_flight = 0
+        self._cancel_lock = threading.Lock()
+        self._cancel_ids = set()
+
+    def cancel(self, rid):
+        """Cancel request `rid` (thread-safe; takes effect at the loop's next turn)."""
+        with self._cancel_lock:
+            self._cancel_ids.add(rid)
+
+    def _is_cancelled(self, r, now):
+        if r.t_cancel is not None and r.t_cancel <= now:
+            return True
+        with self._cancel_lock:
+            return r.rid in self._cancel_ids
 
     def _form_batches(self, pending):
         """Group pending requests by (job, op), oldest group first."""
@@ -112,7 +135,7 @@ class Server:
         nxt = 0
         pending = []
         inflight = []
-        free_slots = list(range(self.n_slots))
+        free_slots = self.free_slots = list(range(self.n_slots))
         used = 0
         done = 0
         while done < len(trace):
@@ -121,6 +144,16 @@ class Server:
                 trace[nxt].t_release = now
                 pending.append(trace[nxt])
                 nxt += 1
+            # cancelled while waiting: never launched
+            keep = []
+            for r in pending:
+                if self._is_cancelled(r, now):
+                    r.cancelled = True
+                    r.t_done = now
+                    done += 1
+                else:
+                    keep.append(r)
+            pending = keep
             # completions free slots and memory
             still = []
             for L in inflight:
@@ -128,12 +161,14 @@ class Server:
                     tdone = self.clock() - t0
                     for r in L.reqs:
                         r.t_done = tdone
+                        r.cancelled = self._is_cancelled(r, tdone)
                     used -= L.bytes
                     free_slots.append(L.slot)
                     done += len(L.reqs)
                 else:
                     still.append(L)
             inflight = still
+            self.bytes_in_flight = used
             # admission
             if pending and free_slots:
                 launched = set()
@@ -166,7 +201,8 @@ class Server:
 
 def latency_stats(reqs, from_release=False):
     """Latency percentiles from arrival (or from release, for traces replayed
-    without their arrival times) to completion."""
+    without their arrival times) to completion, over the requests not cancelled."""
+    reqs = [r for r in reqs if not r.cancelled]
     t0 = [r.t_release if from_release else r.t_arrival for r in reqs]
     lat = np.array([r.t_done - t for r, t in zip(reqs, t0)])
     span = max(r.t_done for r in reqs) - min(t0)

@@ -84,3 +84,49 @@ def test_oversized_request_is_rejected():
     srv = Server(SimExecutor(), n_slots=2, hbm_budget=100)
     with pytest.raises(RuntimeError):
         srv.run(trace, realtime=False)
+
+
+def _req(rid, t, op="cg20", job=0, size=1, t_cancel=None):
+    from paper_2406_09144_amd.serving import Request
+    return Request(rid, t, job, op, size, t_cancel=t_cancel)
+
+
+def test_request_cancelled_while_pending_is_never_launched_and_frees_nothing_twice():
+    # one slot: the long request 0 holds it while 1 and 2 wait; both are cancelled
+    # before the slot frees, so only 0 and 3 ever reach the executor
+    ex = SimExecutor(per_image_s=0.05)
+    srv = Server(ex, n_slots=1, hbm_budget=10_000, max_batch=8)
+    trace = [_req(0, 0.0), _req(1, 0.001, t_cancel=0.01), _req(2, 0.001, "psf_apply", t_cancel=0.02),
+             _req(3, 0.002)]
+    out = srv.run(trace, realtime=True)
+    launched = [rid for _, _, rids, _, _ in ex.log for rid in rids]
+    assert launched == [0, 3]
+    assert [r.cancelled for r in out] == [False, True, True, False]
+    assert out[1].t_start is None and out[2].t_start is None
+    assert out[1].t_done < out[0].t_done  # dropped at its cancel time, not after the slot freed
+    assert sorted(srv.free_slots) == [0] and srv.bytes_in_flight == 0
+    st = latency_stats(out)
+    assert st["n"] == 2
+
+
+def test_request_cancelled_on_the_device_frees_its_slot_when_the_launch_ends():
+    ex = SimExecutor(per_image_s=0.03)
+    srv = Server(ex, n_slots=1, hbm_budget=10_000, max_batch=8)
+    trace = [_req(0, 0.0, t_cancel=0.005), _req(1, 0.001)]
+    out = srv.run(trace, realtime=True)
+    launched = [rid for _, _, rids, _, _ in ex.log for rid in rids]
+    assert launched == [0, 1]
+    assert out[0].cancelled and not out[1].cancelled
+    assert out[1].t_start >= out[0].t_done  # the slot came back when the launch ended
+    assert sorted(srv.free_slots) == [0] and srv.bytes_in_flight == 0
+
+
+def test_cancel_from_another_thread():
+    import threading
+    ex = SimExecutor(per_image_s=0.05)
+    srv = Server(ex, n_slots=1, hbm_budget=10_000, max_batch=8)
+    trace = [_req(0, 0.0), _req(1, 0.0), _req(2, 0.0)]
+    threading.Timer(0.01, lambda: srv.cancel(2)).start()
+    out = srv.run(trace, realtime=True)
+    launched = [rid for _, _, rids, _, _ in ex.log for rid in rids]
+    assert launched == [0, 1] and out[2].cancelled
