@@ -7,7 +7,9 @@
   * Every served result matches the FP64 oracle: PSF applies and the FAST
     likelihood gradient (FFT rounding: 1e-5 and 2e-5), degridding and gridding on sampled
     outputs (epsilon 1e-5), and the 20-iteration CG against the oracle's FP64 CG
-    (FP32 vectors drift from FP64 iterates: 1e-3).  The jobs' PSF kernels,
+    (FP32 vectors drift from FP64 iterates at about kappa * u32 per iteration;
+    with the prior floored at 1e-3 of the PSF spectrum peak the drift after 20
+    iterations stays near 1e-5: tolerance 1e-3).  The jobs' PSF kernels,
     visibilities and dirty images come from the oracle and the seeded inputs, so
     nothing the oracle sees was computed by the GPU.
   * Footprint admission keeps the in-flight scratch within the budget."""
@@ -17,7 +19,7 @@ import pytest
 
 import oracle as O
 from synthetic import make_config
-from synthetic.skies import correlated_field, inv_power_half, power_spectrum
+from synthetic.skies import correlated_field, power_spectrum
 
 pytestmark = pytest.mark.gpu
 
@@ -48,8 +50,12 @@ def build_jobs(api, torch):
         d = O.grid(o.uvw, freq, n, n, o.dx, o.dy, V, wt)
         imgs = rng.standard_normal((6, 1, n, n))
         logs = 0.3 * rng.standard_normal((6, 1, n, n))
-        ip_full = 1e-3 / power_spectrum(n, n)
-        ip = torch.from_numpy(inv_power_half(n, n) * 1e-3).float().cuda()
+        # prior floor at 1e-3 of the PSF spectrum peak (as in the 512^2 CG test):
+        # FP32 CG iterates follow the FP64 ones only while kappa * u32 stays small,
+        # and with the unscaled slope -4 spectrum kappa(A) reaches ~1e8 at 64^2
+        ip_full = 1.0 / power_spectrum(n, n)
+        ip_full = ip_full * (np.abs(K).max() * 1e-3 / ip_full.min())
+        ip = torch.from_numpy(np.ascontiguousarray(ip_full[:, : n // 2 + 1])).float().cuda()
         jobs.append(ServedJob(pl, psf, torch.from_numpy(V).to(torch.complex64).cuda(),
                               torch.from_numpy(wt).float().cuda(), torch.from_numpy(d).float().cuda(), ip,
                               torch.from_numpy(imgs).float().cuda(), torch.from_numpy(logs).float().cuda()))
