@@ -235,6 +235,24 @@ void fr_psf_destroy(fr_psf *psf);
  * reduced grid of fr_psf_reduce).  x, y device [B][n_chan][nx][ny] real, y != x. */
 int fr_apply_RNR_approx(fr_psf *psf, const void *x, void *y, int64_t B, void *stream);
 
+/* Fixed device workspace of fr_apply_RNR_approx_noalloc, per GPU (bytes). */
+#define FR_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* fr_apply_RNR_approx for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same operator, arguments and kernels, but the half-spectrum workspace is a
+ * fixed array of FR_NOALLOC_SCRATCH_BYTES in the library's device image, one per
+ * GPU, held until the process ends; the call performs no device allocation or
+ * release.  It needs B * n_chan * nx * (py/2) complex elements (py = 2ny, or the
+ * reduced grid) of the PSF's precision, at most FR_NOALLOC_SCRATCH_BYTES
+ * (e.g. FP32 512^2 with B * n_chan <= 32, 1024^2 with <= 8); larger requests
+ * return FR_EINVAL before anything is enqueued.  A context must have been created
+ * on the PSF's device (fr_ctx_create finds the workspace's device address there).
+ * Every such call on one GPU uses the same workspace, so calls that overlap on a
+ * GPU (different streams, or host threads without ordering) race on it: the
+ * caller orders them, e.g. by issuing them on one stream. */
+int fr_apply_RNR_approx_noalloc(fr_psf *psf, const void *x, void *y, int64_t B, void *stream);
+
 /* R' x = R^+ N^-1 R x evaluated exactly (major cycle, Sec. 3.3.4).
  * weight device [n_row][n_chan] or NULL; x, y device [B][n_chan][nx][ny]. */
 int fr_apply_RNR_exact(fr_plan *plan, const void *weight, const void *x, void *y, int64_t B,

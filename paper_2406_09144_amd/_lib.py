@@ -19,6 +19,8 @@ FR_CONV_MUL, FR_CONV_DIV, FR_CONV_MUL_SQRT, FR_CONV_DIV_SQRT = 0, 1, 2, 3
 (FR_OP_DEGRID, FR_OP_GRID, FR_OP_RNR_APPROX, FR_OP_RNR_EXACT, FR_OP_LIK_EXACT,
  FR_OP_LIK_FAST, FR_OP_CG, FR_OP_MAKE_PSF) = range(8)
 
+FR_NOALLOC_SCRATCH_BYTES = 64 << 20
+
 _STATUS = {FR_EINVAL: "FR_EINVAL", FR_ENOMEM: "FR_ENOMEM", FR_EHIP: "FR_EHIP",
            FR_EUNSUPPORTED: "FR_EUNSUPPORTED", FR_EBUSY: "FR_EBUSY"}
 
@@ -73,6 +75,7 @@ SIGNATURES = {
     "fr_psf_get_kernels": ([_P, _P, _P, _P], _I),
     "fr_psf_destroy": ([_P], None),
     "fr_apply_RNR_approx": ([_P, _P, _P, _I64, _P], _I),
+    "fr_apply_RNR_approx_noalloc": ([_P, _P, _P, _I64, _P], _I),
     "fr_apply_RNR_exact": ([_P, _P, _P, _P, _I64, _P], _I),
     "fr_likelihood_grad": ([_P, _P, _I, _P, _P, _P, _P, _P, _I64, _P, _P, _P], _I),
     "fr_cg_solve": ([_P, _P, _P, _P, _P, _P, _P, _I, _D, _P, _P, _P], _I),

@@ -8,6 +8,7 @@
 #include "profiler.h"
 
 #include <atomic>
+#include <mutex>
 
 namespace frmi {
 
@@ -29,6 +30,43 @@ hipError_t device_alloc(void **p, size_t bytes) {
         if (g_alloc_budget.compare_exchange_weak(b, b - 1)) break;
     }
     return hipMalloc(p, bytes);
+}
+
+// Workspace of fr_apply_RNR_approx_noalloc, for callers that cannot allocate:
+// one copy per GPU, held until the process ends, shared by every such call on
+// that GPU.  In host code `scratch` names a host-side stand-in, not device
+// memory: kernels and copies get the device address found by
+// hipGetSymbolAddress when a context is created on the device.
+static __device__ __align__(256) unsigned char scratch[FR_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_noalloc_mu;
+static void *g_noalloc_ptr[kMaxDevices] = {};
+static hipError_t g_noalloc_err[kMaxDevices] = {};
+static bool g_noalloc_done[kMaxDevices] = {};
+
+// Once per device, with that device current: the device address of `scratch`.
+static void noalloc_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return;
+    std::lock_guard<std::mutex> g(g_noalloc_mu);
+    if (g_noalloc_done[device]) return;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) (void)hipGetLastError();
+    g_noalloc_err[device] = e;
+    g_noalloc_ptr[device] = e == hipSuccess ? ptr : nullptr;
+    g_noalloc_done[device] = true;
+}
+
+static void *noalloc_ptr(int device) {
+    FR_REQUIRE(device >= 0 && device < kMaxDevices, "device index beyond the no-alloc workspace table");
+    std::lock_guard<std::mutex> g(g_noalloc_mu);
+    if (!g_noalloc_done[device])
+        throw Error(FR_EHIP, "no-alloc workspace: no context was created on this device");
+    if (g_noalloc_err[device] != hipSuccess)
+        throw Error(FR_EHIP, std::string("no-alloc workspace: hipGetSymbolAddress failed: ") +
+                                 hipGetErrorString(g_noalloc_err[device]));
+    return g_noalloc_ptr[device];
 }
 
 }  // namespace frmi
@@ -97,6 +135,7 @@ int fr_ctx_create(int device, fr_ctx **out) {
     for (int o = 0; o < 2; ++o)
         for (int l = 0; l <= kMaxLog2Odd; ++l)
             make_table(int64_t(o == 0 ? 3 : 5) << l, &ctx->c.tw64o[o][l], &ctx->c.tw32o[o][l]);
+    noalloc_setup(device);
     *out = ctx.release();
     FR_API_END
 }
@@ -185,6 +224,30 @@ int fr_apply_RNR_approx(fr_psf *psf, const void *x, void *y, int64_t B, void *st
         apply_rnr_approx<double>(psf, (const double *)x, (double *)y, B, as_stream(stream));
     else
         apply_rnr_approx<float>(psf, (const float *)x, (float *)y, B, as_stream(stream));
+    FR_API_END
+}
+
+int fr_apply_RNR_approx_noalloc(fr_psf *psf, const void *x, void *y, int64_t B, void *stream) {
+    FR_API_BEGIN
+    FR_REQUIRE(psf, "psf is NULL");
+    FR_REQUIRE(B >= 0, "B must be >= 0");
+    if (B == 0) return FR_OK;
+    FR_REQUIRE(x && y, "x and y are required");
+    FR_REQUIRE(x != y, "y must not alias x");
+    const size_t need = rnr_approx_scratch(psf, B);
+    if (need > (size_t)FR_NOALLOC_SCRATCH_BYTES)
+        throw Error(FR_EINVAL, "fr_apply_RNR_approx_noalloc: this call needs " + std::to_string(need) +
+                                   " bytes of workspace, above the fixed " +
+                                   std::to_string((size_t)FR_NOALLOC_SCRATCH_BYTES) +
+                                   " (use fr_apply_RNR_approx or a smaller batch)");
+    DeviceGuard dg(psf->ctx->device);
+    void *ws = noalloc_ptr(psf->ctx->device);
+    if (psf->fp64)
+        apply_rnr_approx_ex<double>(psf, (const double *)x, nullptr, (double *)y, nullptr, nullptr, B,
+                                    as_stream(stream), ws);
+    else
+        apply_rnr_approx_ex<float>(psf, (const float *)x, nullptr, (float *)y, nullptr, nullptr, B,
+                                   as_stream(stream), ws);
     FR_API_END
 }
 

@@ -129,9 +129,11 @@ void mgvi_solve(const fr_psf *psf, const T *power, const T *diag, const T *b, T 
 // psfconv.hip
 template <typename T>
 void apply_rnr_approx(const fr_psf *psf, const T *x, T *y, int64_t B, hipStream_t st);
+// ws: caller-provided workspace of rnr_approx_scratch(psf, B) bytes, or NULL for the
+// stream's arena
 template <typename T>
 void apply_rnr_approx_ex(const fr_psf *psf, const T *x, const T *d_in, T *y, const T *d_out, const T *add,
-                         int64_t B, hipStream_t st);
+                         int64_t B, hipStream_t st, void *ws = nullptr);
 template <typename T>
 void periodic_conv(const Ctx &ctx, const T *x, T *y, int64_t n_img, int64_t nx, int64_t ny, const T *K, int nk,
                    int mode, hipStream_t st);

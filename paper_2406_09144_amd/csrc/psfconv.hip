@@ -13,10 +13,12 @@ namespace frmi {
 // the nx wanted rows are kept after the column pass.
 // y = d_out D P^+ irfft2(K_R rfft2(P D d_in x)) + add, every extra factor optional:
 // the diagonal metric factors and the prior term of CG fused into the first and
-// last pass.
+// last pass.  The half-spectrum buffer comes from the stream's arena, or from `ws`
+// (at least rnr_approx_scratch bytes, 256-byte aligned) when that is given; the
+// first pass writes every element of it, so it needs no clearing.
 template <typename T>
 void apply_rnr_approx_ex(const fr_psf *psf, const T *x, const T *d_in, T *y, const T *d_out, const T *add,
-                         int64_t B, hipStream_t st) {
+                         int64_t B, hipStream_t st, void *ws) {
     const int64_t nx = psf->nx, ny = psf->ny, nc = psf->n_chan;
     const int64_t n_img = B * nc;
     if (n_img == 0) return;
@@ -29,23 +31,25 @@ void apply_rnr_approx_ex(const fr_psf *psf, const T *x, const T *d_in, T *y, con
     FR_REQUIRE(split_len(psf->py / 2, &g.odd_M, &g.log2M) && split_len(psf->px, &g.odd_Lc, &g.log2Lc),
                "padded kernel sizes must be 2^p, 3 2^p or 5 2^p");
     const int64_t M = g.M();
-    Scratch Y((size_t)n_img * nx * M * sizeof(c2<T>), st);
+    Scratch Yarena;
+    if (!ws) Yarena = Scratch((size_t)n_img * nx * M * sizeof(c2<T>), st);
+    c2<T> *const Yp = ws ? (c2<T> *)ws : Yarena.as<c2<T>>();
     const T *a = psf->nfac.as<T>();
     with_odd(g.odd_M, [&](auto odd) {
         ProfScope prof("psfconv_rows_r2c", st);
         launch_rfft_rows<T, decltype(odd)::value>(*psf->ctx, g, ProDiagScaled<T>{x, d_in, a, (int)nx, (int)ny},
-                                                  Y.as<c2<T>>(), st);
+                                                  Yp, st);
     });
     const T scale = T(1) / (T(g.Lc()) * T(M));
     with_odd(g.odd_Lc, [&](auto odd) {
         ProfScope prof("psfconv_cols", st);
-        launch_conv_cols<T, decltype(odd)::value>(*psf->ctx, g, Y.as<c2<T>>(), psf->KR.as<T>(), (int)nc, 0, scale,
+        launch_conv_cols<T, decltype(odd)::value>(*psf->ctx, g, Yp, psf->KR.as<T>(), (int)nc, 0, scale,
                                                   st);
     });
     with_odd(g.odd_M, [&](auto odd) {
         ProfScope prof("psfconv_rows_c2r", st);
         launch_irfft_rows<T, decltype(odd)::value>(*psf->ctx, g, EpiDiagScaledAdd<T>{y, d_out, a, add, (int)nx, (int)ny},
-                                                   Y.as<c2<T>>(), st);
+                                                   Yp, st);
     });
 }
 
@@ -116,9 +120,9 @@ void fft2_inplace(const Ctx &ctx, c2<T> *data, int64_t batch, int64_t n0, int64_
 }
 
 template void apply_rnr_approx_ex<float>(const fr_psf *, const float *, const float *, float *, const float *,
-                                         const float *, int64_t, hipStream_t);
+                                         const float *, int64_t, hipStream_t, void *);
 template void apply_rnr_approx_ex<double>(const fr_psf *, const double *, const double *, double *, const double *,
-                                          const double *, int64_t, hipStream_t);
+                                          const double *, int64_t, hipStream_t, void *);
 template void apply_rnr_approx<float>(const fr_psf *, const float *, float *, int64_t, hipStream_t);
 template void apply_rnr_approx<double>(const fr_psf *, const double *, double *, int64_t, hipStream_t);
 template void periodic_conv<float>(const Ctx &, const float *, float *, int64_t, int64_t, int64_t, const float *, int,
