@@ -878,7 +878,8 @@ __global__ __launch_bounds__(kTile * kTile) void k_grid_assemble(const c2<T> *__
 // row transform of degridding: line = p * nx + i
 // (image sides are powers of two: line = p nx + i splits with shifts)
 template <typename T> struct DegridRowPro {
-    const T *img, *fac, *tpix;
+    const T *img, *fac, *tpix;  // tpix: Taylor variable tau per pixel (Taylor plans)
+    const double *tpix_w;       // (n - 1) - yc per pixel (w-stacked plans)
     const double *wplane;
     int nx, ny, nv, coplanar, taylor;
     __device__ c2<T> operator()(int64_t line, int b) const {
@@ -900,10 +901,11 @@ template <typename T> struct DegridRowPro {
                 default: return mk<T>(T(0), g);
             }
         }
-        T ph = (T)wplane[p] * tpix[q];
+        // the plane phase w_p t in cycles, reduced modulo 1 in double before rounding
+        double ph = wplane[p] * tpix_w[q];
         ph -= rint(ph);
         T s, c;
-        sincos_cycles(-ph, &s, &c);
+        sincos_cycles(-(T)ph, &s, &c);
         return mk<T>(f * c, f * s);
     }
 };
@@ -964,7 +966,8 @@ template <typename T> struct BandColEpi {
 template <typename T, int NTHR, int BPT, int ACC, bool TWL>
 __global__ __launch_bounds__(NTHR) void k_grid_rows(const c2<T> *__restrict__ planes, int n_planes, int log2nu,
                                                     int log2nv, int nx, int ny, const T *__restrict__ fac,
-                                                    const T *__restrict__ tpix, const double *__restrict__ wplane,
+                                                    const T *__restrict__ tpix, const double *__restrict__ tpix_w,
+                                                    const double *__restrict__ wplane,
                                                     int coplanar, int taylor, T *__restrict__ img, int lines,
                                                     const c2<T> *__restrict__ tw) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -989,7 +992,7 @@ __global__ __launch_bounds__(NTHR) void k_grid_rows(const c2<T> *__restrict__ pl
         __syncthreads();
         lds_fft<T, NTHR, BPT>(buf, ld, nl, log2nv, +1, twp);
         for (int l = 0; l < nl; ++l) {
-            const T wp = (T)wplane[p0 + l];
+            const double wp = wplane[p0 + l];
             const c2<T> *line = buf + l * ld;
 #pragma unroll
             for (int k = 0; k < ACC; ++k) {
@@ -1006,10 +1009,10 @@ __global__ __launch_bounds__(NTHR) void k_grid_rows(const c2<T> *__restrict__ pl
                         const T re = (p & 1) ? ((p & 2) ? g.y : -g.y) : ((p & 2) ? -g.x : g.x);
                         acc[k] += tp * re;
                     } else {
-                        T ph = wp * tpix[(int64_t)i * ny + j];
+                        double ph = wp * tpix_w[(int64_t)i * ny + j];
                         ph -= rint(ph);
                         T s, c;
-                        sincos_cycles(ph, &s, &c);
+                        sincos_cycles((T)ph, &s, &c);
                         acc[k] += g.x * c - g.y * s;
                     }
                 }
@@ -1198,7 +1201,7 @@ size_t psf_grid_scratch_bound(const fr_plan *pl) {
 template <typename T>
 void image_to_planes(const fr_plan *pl, const T *img_c, c2<T> *planes, hipStream_t st) {
     const int l2u = ilog2(pl->nu), l2v = ilog2(pl->nv);
-    DegridRowPro<T> pro{img_c, pl->fac.as<T>(), pl->tpix.as<T>(), pl->wplane.as<double>(),
+    DegridRowPro<T> pro{img_c, pl->fac.as<T>(), pl->tpix.as<T>(), pl->tpix_w.as<double>(), pl->wplane.as<double>(),
                         (int)pl->nx, (int)pl->ny, (int)pl->nv, pl->coplanar ? 1 : 0, pl->taylor ? 1 : 0};
     DegridRowEpi<T> epi{planes, (int)pl->nx, l2u, l2v};
     {
@@ -1231,7 +1234,8 @@ void planes_to_image(const fr_plan *pl, const c2<T> *planes_c, const uint8_t *ac
         auto kern = k_grid_rows<T, NT, 4, 8, TW>;                                                               \
         allow_lds(kern, lds);                                                                                   \
         kern<<<dim3((unsigned)pl->nx), NT, lds, st>>>(planes, pl->n_planes, l2u, l2v, (int)pl->nx, (int)pl->ny, \
-                                                      pl->fac.as<T>(), pl->tpix.as<T>(), pl->wplane.as<double>(), \
+                                                      pl->fac.as<T>(), pl->tpix.as<T>(), pl->tpix_w.as<double>(),   \
+                                                      pl->wplane.as<double>(),                                        \
                                                       pl->coplanar ? 1 : 0, pl->taylor ? 1 : 0, img_c, (LINES),       \
                                                       pl->ctx->tw<T>(l2v));                                           \
     } while (0)
@@ -1660,7 +1664,7 @@ void plan_build(fr_plan *pl, const double *uvw_m, const double *freq_hz) {
     std::vector<double> cu(nx), cv(ny);
     for (int64_t i = 0; i < nx; ++i) cu[i] = 1.0 / kuv.psi_hat((double)(i - nx / 2) / (double)pl->nu);
     for (int64_t j = 0; j < ny; ++j) cv[j] = 1.0 / kuv.psi_hat((double)(j - ny / 2) / (double)pl->nv);
-    std::vector<double> fac(nx * ny), tpix(nx * ny, 0.0), nfac(nx * ny);
+    std::vector<double> fac(nx * ny), tpix(nx * ny, 0.0), tpix_w(nx * ny, 0.0), nfac(nx * ny);
     Cheb psiw([&](double t) { return kw.psi_hat(t); }, 0.25, 40);
     for (int64_t i = 0; i < nx; ++i) {
         const double l = (double)(i - nx / 2) * pl->dx_;
@@ -1673,7 +1677,7 @@ void plan_build(fr_plan *pl, const double *uvw_m, const double *freq_hz) {
                 tpix[i * ny + j] = (y - pl->yc) / pl->taylor_h;
             } else if (!coplanar) {
                 const double t = y - pl->yc;
-                tpix[i * ny + j] = t;
+                tpix_w[i * ny + j] = t;
                 f /= psiw(pl->dw * t);
             }
             fac[i * ny + j] = f;
@@ -1684,13 +1688,16 @@ void plan_build(fr_plan *pl, const double *uvw_m, const double *freq_hz) {
     for (int p = 0; p < pl->n_planes; ++p) wpl[p] = coplanar || pl->taylor ? 0.0 : pl->w0 + p * pl->dw;
     if (pl->fp64) {
         pl->fac = upload<double>(fac);
-        pl->tpix = upload<double>(tpix);
+        if (pl->taylor) pl->tpix = upload<double>(tpix);
         pl->nfac = upload<double>(nfac);
     } else {
         pl->fac = upload<float>(fac);
-        pl->tpix = upload<float>(tpix);
+        if (pl->taylor) pl->tpix = upload<float>(tpix);
         pl->nfac = upload<float>(nfac);
     }
+    // w-stacked plans of either precision keep (n - 1) - yc in double: the plane
+    // phases w_p t are formed and reduced modulo one cycle in double
+    if (!coplanar && !pl->taylor) pl->tpix_w = upload<double>(tpix_w);
     pl->wplane = upload<double>(wpl);
     // --- visibility records
     DevBuf d_uvw(std::max<int64_t>(1, pl->n_row) * 3 * sizeof(double));
@@ -1714,7 +1721,7 @@ void plan_build(fr_plan *pl, const double *uvw_m, const double *freq_hz) {
         pl->tile_active = DevBuf((size_t)pl->n_chan * pl->n_tiles);
         HIP_CHECK(hipMemset(pl->tile_active.p, 0, pl->tile_active.bytes));
     }
-    pl->resident = pl->fac.bytes + pl->tpix.bytes + pl->nfac.bytes + pl->wplane.bytes + pl->r_idx.bytes +
+    pl->resident = pl->fac.bytes + pl->tpix.bytes + pl->tpix_w.bytes + pl->nfac.bytes + pl->wplane.bytes + pl->r_idx.bytes +
                    pl->r_cell.bytes + pl->r_du.bytes + pl->r_dv.bytes + pl->r_dw.bytes + pl->r_ph.bytes +
                    pl->wi.bytes + pl->gwi.bytes + pl->gorder.bytes + pl->gkey_first.bytes + pl->atile.bytes +
                    pl->tile_active.bytes;

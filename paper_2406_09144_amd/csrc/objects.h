@@ -43,7 +43,8 @@ struct fr_plan {
     int64_t max_wi_count = 0;
     // per-pixel factors (precision of the plan)
     frmi::DevBuf fac;   // [nx][ny] a / (Psi_u Psi_v Psi_w)
-    frmi::DevBuf tpix;  // [nx][ny] (n - 1) - yc (w-stacking) or ((n - 1) - yc) / h (Taylor)
+    frmi::DevBuf tpix;    // [nx][ny] ((n - 1) - yc) / h (Taylor plans only, plan precision)
+    frmi::DevBuf tpix_w;  // [nx][ny] double (n - 1) - yc (w-stacked plans only)
     frmi::DevBuf nfac;  // [nx][ny] a (1/n or 1)
     frmi::DevBuf wplane;  // [n_planes] double: w of each plane
     // sorted visibility records (structure of arrays)

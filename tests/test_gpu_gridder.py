@@ -32,6 +32,20 @@ def wide_field(seed=3, n=64, nvis=3000, dx=0.008, wfac=2.0):
     return dict(uvw=uvw, freq=np.array([1.0e9]), nx=n, ny=n, dx=dx, dy=dx * 1.1)
 
 
+def offset_w_field(seed=4, n=64, nvis=3000, dx=0.008, w0=5000.0, span=300.0):
+    """Every |w| far from zero: w uniform in +-[w0, w0 + span] wavelengths on a wide
+    field, so the plane phases w_p ((n - 1) - yc) reach about 85 cycles and their
+    rounding must happen after the reduction modulo one cycle."""
+    rng = np.random.default_rng(seed)
+    uvmax = 0.45 / dx
+    uvw = np.empty((nvis, 3))
+    uvw[:, 0] = rng.uniform(-uvmax, uvmax, nvis) * LAM_1GHZ
+    uvw[:, 1] = rng.uniform(-uvmax, uvmax, nvis) * LAM_1GHZ
+    sign = np.where(rng.uniform(size=nvis) < 0.5, -1.0, 1.0)
+    uvw[:, 2] = sign * rng.uniform(w0, w0 + span, nvis) * LAM_1GHZ
+    return dict(uvw=uvw, freq=np.array([1.0e9]), nx=n, ny=n, dx=dx, dy=dx)
+
+
 def case(name):
     if name == "cfg0_coplanar":
         o = make_config(0, n=64, n_int=16, with_sky=False)
@@ -41,13 +55,15 @@ def case(name):
         o = make_config(3, n=64, n_int=3, n_chan=3, with_sky=False)
     elif name == "wide_w":
         return wide_field()
+    elif name == "offset_w":
+        return offset_w_field()
     elif name == "rect":
         o = make_config(1, n=32, n_int=12, with_sky=False)
         return dict(uvw=o.uvw, freq=o.freq, nx=32, ny=64, dx=o.dx * 2, dy=o.dy)
     return dict(uvw=o.uvw, freq=o.freq, nx=o.nx, ny=o.ny, dx=o.dx, dy=o.dy)
 
 
-CASES = ["cfg0_coplanar", "cfg1_wstack", "cfg3_multichan", "wide_w", "rect"]
+CASES = ["cfg0_coplanar", "cfg1_wstack", "cfg3_multichan", "wide_w", "offset_w", "rect"]
 
 
 def _plan(c, fp64, eps=None, divide_by_n=True):
