@@ -437,3 +437,44 @@ def metric_apply(x, K_R, inv_power, a=None, diag=None):
     if diag is not None:
         y = diag * y
     return y + prior_inv_apply(x, inv_power)
+
+
+# ---------------------------------------------------------------- Algorithm 1
+def algorithm1(uvw_m, freq_hz, nx, ny, dx, dy, vis, weight, K_R, K_N, a, inv_power, s0, n_major, n_minor,
+               cg_iters, lam, max_step):
+    """The major/minor scheme of Algorithm 1 (Sec. 3.3.4) for one channel, with a
+    fixed minor-cycle schedule:
+
+        I_D = R^+ N^-1 V  (exact);  d_0 = I_D
+        for each major cycle i:
+            minor cycle on d_i = I_PSF * (I - I_i-1) + n' (FAST likelihood, eq. ham_new,
+            with the prior 1/2 s^T S^-1 s): n_minor damped Gauss-Newton steps
+                (D R' D + S^-1 + lam) ds = -g,   s <- s + t ds,   D = diag(exp s),
+            each solved by cg_iters conjugate-gradient iterations, with
+            t = min(1, max_step / max|ds|) bounding the change of the log-sky
+            (exp is nonlinear);
+            I_i = exp(s);  d_i+1 = I_D - R^+ N^-1 R I_i  (exact).
+
+    The Gauss-Newton metric D R' D stands in for D R' N'^-1 R' D (reading of the
+    minor cycle: the paper runs MGVI there).  K_R [2nx, ny + 1] and K_N [nx, ny]
+    (full) as response_kernel and noise_kernel; inv_power the full [nx, ny] 1/P.
+    Returns the log-sky after the last minor cycle, the residual images d_1 ..
+    d_n_major and the FAST H after each minor cycle."""
+    I_D = dirty_image(uvw_m, freq_hz, nx, ny, dx, dy, vis, weight)[0]
+    d = I_D
+    s = _f64(s0)
+    I_prev = None
+    ds_out, Hs = [], []
+    for _ in range(n_major):
+        for _ in range(n_minor):
+            ifix = None if I_prev is None else -I_prev
+            _, g = likelihood_fast(s, d, K_R, K_N, a, i_fixed=ifix, inv_power=inv_power)
+            D = np.exp(s)
+            ds, _ = cg(lambda p: metric_apply(p, K_R, inv_power + lam, a, D), -g, cg_iters)
+            s = s + min(1.0, max_step / np.max(np.abs(ds))) * ds
+        Hs.append(likelihood_fast(s, d, K_R, K_N, a, i_fixed=None if I_prev is None else -I_prev,
+                                  inv_power=inv_power)[0])
+        I_prev = np.exp(s)
+        d = I_D - rnr_exact(uvw_m, freq_hz, nx, ny, dx, dy, I_prev, weight)[0]
+        ds_out.append(d)
+    return s, ds_out, Hs

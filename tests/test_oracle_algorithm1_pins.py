@@ -1,0 +1,102 @@
+"""Pins of the oracle's Algorithm 1 (Sec. 3.3.4) run, on the CPU.
+
+  * Coplanar array: the PSF convolution is then exact (Sec. 3.3.2), so a major
+    cycle only re-expresses the minor cycle's data: the minor-cycle model with the
+    previous sky subtracted, d_1 - R'(exp s - I_1), equals d_0 - R' exp s.  Two major
+    cycles of k steps must therefore equal one of 2k steps (a wrong sign of the
+    subtracted sky, a residual not refreshed, or the dirty image used in place of
+    the residual breaks this).
+  * One Gauss-Newton step of one major cycle on an 8 x 8 sky equals the same
+    step written with dense matrices built from the definitions (brute force)."""
+
+import numpy as np
+
+import oracle as O
+from synthetic import make_config
+from synthetic.skies import power_spectrum
+
+
+def setup(cfg, n=16, n_int=40, seed=3):
+    obs = make_config(cfg, n=n, n_int=n_int, with_sky=False)
+    rng = np.random.default_rng(seed)
+    sky = np.exp(0.5 * rng.standard_normal((n, n)))
+    V = O.degrid(obs.uvw, obs.freq, n, n, obs.dx, obs.dy, sky[None])
+    V = V + 0.01 * np.abs(V).mean() * (rng.standard_normal(V.shape) + 1j * rng.standard_normal(V.shape))
+    wt = rng.uniform(0.5, 2.0, V.shape)
+    p0 = O.psf0(obs.uvw, obs.freq, n, n, obs.dx, obs.dy, wt)
+    K = O.response_kernel(p0)
+    KN = O.noise_kernel(p0, 0.1 * p0.max())
+    a = O.n_factor(n, n, obs.dx, obs.dy)
+    ip = 1.0 / power_spectrum(n, n)
+    s0 = np.full((n, n), np.log(sky.mean()))
+    lam = 0.05 * float(np.abs(K).max())
+    return obs, V, wt, K, KN, a, ip, s0, lam
+
+
+def test_algorithm1_coplanar_major_cycle_changes_nothing(oracle_lib):
+    obs, V, wt, K, KN, a, ip, s0, lam = setup(0)
+    n = obs.nx
+    args = (obs.uvw, obs.freq, n, n, obs.dx, obs.dy, V, wt, K, KN, a, ip, s0)
+    s2, d2, _ = O.algorithm1(*args, n_major=2, n_minor=3, cg_iters=30, lam=lam, max_step=0.5)
+    s1, d1, _ = O.algorithm1(*args, n_major=1, n_minor=6, cg_iters=30, lam=lam, max_step=0.5)
+    # equal up to FP64 rounding carried through the Gauss-Newton solves (measured
+    # 3e-9 and 2e-8; with w below the two paths differ by 3e-5 and 3e-4)
+    assert np.linalg.norm(s2 - s1) <= 1e-7 * np.linalg.norm(s1)
+    assert np.linalg.norm(d2[-1] - d1[-1]) <= 1e-6 * np.linalg.norm(d1[-1])
+    # with w the approximation is not exact and the major cycle does change the path
+    obs, V, wt, K, KN, a, ip, s0, lam = setup(1)
+    argsw = (obs.uvw, obs.freq, n, n, obs.dx, obs.dy, V, wt, K, KN, a, ip, s0)
+    s2w, _, _ = O.algorithm1(*argsw, n_major=2, n_minor=3, cg_iters=30, lam=lam, max_step=0.5)
+    s1w, _, _ = O.algorithm1(*argsw, n_major=1, n_minor=6, cg_iters=30, lam=lam, max_step=0.5)
+    assert np.linalg.norm(s2w - s1w) > 1e-6 * np.linalg.norm(s1w)
+
+
+def test_algorithm1_one_step_equals_dense_brute_force(oracle_lib):
+    """One major cycle of one Gauss-Newton step on an 8 x 8 sky, against the same
+    step written with dense matrices built from the definitions: the measurement
+    matrix of Eq. 1 (pixel sums), R' = Re(R^H W R) exact and the PSF matrix
+    a_i PSF0[i - i'] a_i' with PSF0 summed directly, the circulant noise-kernel
+    and prior matrices, the FAST gradient -D R' N'^-1 (d - R' e^s) + S^-1 s, the
+    metric D R' D + S^-1 + lam, an exact linear solve, and the exact residual."""
+    n = 8
+    obs, V, wt, K, KN, a, ip, s0, lam = setup(1, n=n, n_int=20, seed=9)
+    s0 = s0 + 0.2 * np.random.default_rng(2).standard_normal((n, n))
+    u, v, w = O.uvw_lambda(obs.uvw, obs.freq)
+    u, v, w, wv = u[:, 0], v[:, 0], w[:, 0], wt[:, 0]
+    l = (np.arange(n) - n / 2) * obs.dx
+    m = (np.arange(n) - n / 2) * obs.dy
+    L, Mm = np.meshgrid(l, m, indexing="ij")
+    nn = np.sqrt(1 - L ** 2 - Mm ** 2)
+    af = (1 / nn).ravel()
+    ph = np.outer(u, L.ravel()) + np.outer(v, Mm.ravel()) + np.outer(w, (nn - 1).ravel())
+    Rm = np.exp(-2j * np.pi * ph) * af[None, :]                      # [n_vis, n^2]
+    R_exact = np.real(Rm.conj().T @ (wv[:, None] * Rm))
+    I_D = np.real(Rm.conj().T @ (wv * V[:, 0]))
+    # PSF matrix: a_q PSF0(l_q - l_q', m_q - m_q') a_q'
+    dl = L.ravel()[:, None] - L.ravel()[None, :]
+    dm = Mm.ravel()[:, None] - Mm.ravel()[None, :]
+    P = np.zeros((n * n, n * n))
+    for k in range(len(u)):
+        P += wv[k] * np.cos(2 * np.pi * (u[k] * dl + v[k] * dm))
+    Rp = af[:, None] * P * af[None, :]
+    # circulant matrices of the periodic convolutions
+    idx = np.arange(n)
+    di = (idx[:, None, None, None] - idx[None, None, :, None]) % n
+    dj = (idx[None, :, None, None] - idx[None, None, None, :]) % n
+
+    def circ(spec):
+        kern = np.real(np.fft.ifft2(spec))
+        return kern[di, dj].reshape(n * n, n * n)
+
+    Ninv = circ(1.0 / KN)
+    Sinv = circ(ip)
+    s = s0.ravel()
+    D = np.exp(s)
+    g = -D * (Rp @ (Ninv @ (I_D - Rp @ D))) + Sinv @ s
+    M = D[:, None] * Rp * D[None, :] + Sinv + lam * np.eye(n * n)
+    s1 = s - np.linalg.solve(M, g)
+    d1 = I_D - R_exact @ np.exp(s1)
+    so, do, _ = O.algorithm1(obs.uvw, obs.freq, n, n, obs.dx, obs.dy, V, wt, K, KN, a, ip, s0, n_major=1,
+                             n_minor=1, cg_iters=64, lam=lam, max_step=1e9)
+    assert np.linalg.norm(so.ravel() - s1) <= 1e-9 * np.linalg.norm(s1)
+    assert np.linalg.norm(do[0].ravel() - d1) <= 1e-9 * np.linalg.norm(d1)
