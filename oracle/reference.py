@@ -478,3 +478,93 @@ def algorithm1(uvw_m, freq_hz, nx, ny, dx, dy, vis, weight, K_R, K_N, a, inv_pow
         d = I_D - rnr_exact(uvw_m, freq_hz, nx, ny, dx, dy, I_prev, weight)[0]
         ds_out.append(d)
     return s, ds_out, Hs
+
+
+# ---------------------------------------------------------------- correlated-field amplitude model
+# The diffuse-emission prior is an exponentiated Gaussian process (Sec. 3.1.1)
+# whose power spectrum is itself inferred, with the hyperparameters listed in the
+# prior-parameter appendices (zero mode offset; zero mode, fluctuations,
+# loglogavgslope, flexibility and asperity, each with a mean and a standard
+# deviation).  The paper defers their definition to earlier work; the reading
+# written out here:
+#   * positive hyperparameters (zero-mode std, fluctuations, flexibility,
+#     asperity) are lognormal with the given mean and standard deviation
+#     (x = exp(mu + sigma xi), sigma^2 = ln(1 + std^2/mean^2), mu = ln mean -
+#     sigma^2 / 2); a mean of 0 gives exactly 0; the average slope is normal;
+#   * on the log of the spatial frequency, t = ln|k| over the distinct non-zero
+#     |k| of the grid, the log-amplitude is the average slope times (t - t_0) plus
+#     a deviation: a Wiener process v (the local slope, variance flexibility^2
+#     per unit t) integrated over t, plus a rougher Wiener part scaled by
+#     flexibility * asperity, with its straight line between the first and last
+#     bin removed (so loglogavgslope is the average log-log slope of the
+#     amplitude);
+#   * the power is the squared amplitude, normalised so that the variance of the
+#     field without its zero mode is fluctuations^2; the zero mode has variance
+#     (zero-mode std)^2; the log-sky is offset + F^-1 sqrt(P) F xi_field.
+CF_PRIOR_KEYS = ("offset", "zm_mean", "zm_std", "fluct_mean", "fluct_std", "slope_mean", "slope_std",
+                 "flex_mean", "flex_std", "asp_mean", "asp_std")
+
+
+def lognormal_from_moments(mean, std, xi):
+    """exp(mu + sigma xi) with mean `mean` and standard deviation `std` (0 if mean is 0)."""
+    if mean == 0.0:
+        return 0.0 * np.asarray(xi, np.float64)
+    s2 = np.log1p((std / mean) ** 2)
+    return np.exp(np.log(mean) - 0.5 * s2 + np.sqrt(s2) * np.asarray(xi, np.float64))
+
+
+def cf_bins(nx, ny):
+    """Distinct non-zero |k|^2 of the nx x ny grid (integer frequency units), their
+    multiplicity over the full grid, and the bin of every full-grid frequency (-1
+    for k = 0)."""
+    kx = np.fft.fftfreq(nx) * nx
+    ky = np.fft.fftfreq(ny) * ny
+    k2 = np.rint(kx[:, None] ** 2 + ky[None, :] ** 2).astype(np.int64)
+    vals, inv, counts = np.unique(k2, return_inverse=True, return_counts=True)
+    assert vals[0] == 0
+    return vals[1:], counts[1:], inv.reshape(nx, ny) - 1
+
+
+def cf_hyper(prior, xi_h):
+    """(zero-mode std, fluctuations, slope, flexibility, asperity) from the standardised
+    excitations xi_h[0..4]."""
+    return (float(lognormal_from_moments(prior["zm_mean"], prior["zm_std"], xi_h[0])),
+            float(lognormal_from_moments(prior["fluct_mean"], prior["fluct_std"], xi_h[1])),
+            float(prior["slope_mean"] + prior["slope_std"] * xi_h[2]),
+            float(lognormal_from_moments(prior["flex_mean"], prior["flex_std"], xi_h[3])),
+            float(lognormal_from_moments(prior["asp_mean"], prior["asp_std"], xi_h[4])))
+
+
+def cf_log_amplitude(t, slope, flex, asp, xi_v, xi_y):
+    """The log-amplitude on the log-frequencies t (ascending) and its two Wiener
+    processes: v_j = flex sum_{i<=j} sqrt(d_i) xi_v_i (local slope),
+    y_j = sum_{i<=j} [(v_i-1 + v_i) d_i / 2 + flex asp sqrt(d_i) xi_y_i], d_i = t_i - t_i-1
+    (d_0 = 0), and logA = slope (t - t_0) + y - y_J (t - t_0) / (t_J - t_0)."""
+    t = _f64(t)
+    d = np.concatenate([[0.0], np.diff(t)])
+    v = flex * np.cumsum(np.sqrt(d) * xi_v)
+    v_prev = np.concatenate([[0.0], v[:-1]])
+    y = np.cumsum(0.5 * (v_prev + v) * d + flex * asp * np.sqrt(d) * xi_y)
+    span = t[-1] - t[0]
+    frac = (t - t[0]) / span if span > 0 else np.zeros_like(t)
+    return slope * (t - t[0]) + y - y[-1] * frac, v, y
+
+
+def cf_power(nx, ny, prior, xi_h, xi_v, xi_y):
+    """Full [nx, ny] power spectrum P(k) of the correlated field for the given
+    excitations (xi_h: 5 hyperparameter excitations; xi_v, xi_y: one per bin)."""
+    vals, mult, idx = cf_bins(nx, ny)
+    zm, fluct, slope, flex, asp = cf_hyper(prior, xi_h)
+    t = 0.5 * np.log(vals.astype(np.float64))
+    logA, _, _ = cf_log_amplitude(t, slope, flex, asp, _f64(xi_v), _f64(xi_y))
+    a2 = np.exp(2.0 * (logA - logA.max()))  # the normalisation removes any common factor
+    P_bin = fluct ** 2 * (nx * ny) * a2 / np.sum(mult * a2)
+    P = np.empty((nx, ny))
+    P[idx >= 0] = P_bin[idx[idx >= 0]]
+    P[0, 0] = zm ** 2 * (nx * ny)
+    return P
+
+
+def cf_logsky(P, xi_field, offset):
+    """offset + F^-1 sqrt(P) F xi: the Gaussian-process log-sky."""
+    return offset + gp_apply(xi_field, P)
