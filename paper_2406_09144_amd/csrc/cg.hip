@@ -12,6 +12,7 @@
 #include "conv.h"
 #include "elementwise.h"
 #include "objects.h"
+#include "profiler.h"
 
 namespace frmi {
 
@@ -134,6 +135,237 @@ __global__ void k_cg_report(const CGState *st, int *iters_done) {
     if (threadIdx.x == 0) *iters_done = st->iters;
 }
 
+// ------------------------------------------------------------------ fused PSF-form iteration
+// For A = D_s R'_PSF D_s + S^-1 with the full doubled-grid PSF, one iteration is
+// four launches instead of nine:
+//   1. row transforms of two images per channel on the doubled grid: a D_s p and p
+//      (p = r + beta p updated on the fly; beta, the residual history and the stop
+//      test of the previous iteration are done by each workgroup at its start);
+//   2. column transforms, the first image multiplied by K_R, the second by the
+//      prior embedded in the doubled grid (below);
+//   3. inverse row transforms of both images of a row in one workgroup:
+//      A p = D_s a y_R + y_S, and the partial sums of <p, A p>;
+//   4. alpha; x += alpha p, r -= alpha A p; partial sums of <r, r>.
+// The prior S^-1 = F^-1 diag(1/P) F on the nx x ny periodic grid embeds in the
+// doubled grid: the 2n-point transform of the zero-padded p at even frequencies
+// 2k is the n-point transform of p at k, and a spectrum living on the even
+// frequencies only transforms back to the n-periodic signal repeated, scaled by
+// 1/4 (one 1/2 per axis).  So with H[2k1][2k2] = 4 / P(k1, k2) and H = 0 at every
+// other frequency, the cropped linear convolution of the padded p with H is
+// S^-1 p exactly (the same operator, in the same pipeline as R').
+
+// H [2nx][ny + 1] from 1/P [nx][ny/2 + 1] (r2c halves)
+template <typename T> struct PriorEmbed {
+    const T *ip;
+    T *H;
+    int nx, ny;
+    __device__ void operator()(int64_t i) const {
+        const int w = ny + 1;
+        const int f1 = (int)(i / w), f2 = (int)(i - (int64_t)f1 * w);
+        H[i] = ((f1 | f2) & 1) ? T(0) : T(4) * ip[(int64_t)(f1 >> 1) * (ny / 2 + 1) + (f2 >> 1)];
+    }
+};
+
+template <typename T> struct CGInitXR {
+    const T *b;
+    T *x, *r;
+    __device__ void operator()(int64_t i) const {
+        x[i] = T(0);
+        r[i] = b[i];
+    }
+};
+
+// FP64 sum of n partials over the workgroup (any size up to 1024 threads),
+// fixed order, returned to every thread
+__device__ __forceinline__ double block_sum_partials_all(const double *partials, int n) {
+    __shared__ double sh[16];
+    __shared__ double total;
+    double v = 0;
+    for (int k = threadIdx.x; k < n; k += blockDim.x)
+        v += __hip_atomic_load(partials + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += sh[k];
+        total = t;
+    }
+    __syncthreads();
+    return total;
+}
+
+// Pass-1 prologue of iteration k.  Rows [0, n0) are the first image set (a D_s p),
+// rows [n0, 2 n0) the second (p).  For k > 0 each workgroup first forms
+// beta = <r_k, r_k> / <r_k-1, r_k-1> from the step's partials; workgroup 0 also
+// records <r_k, r_k>, the history and the stop flag (as the separate update
+// kernel of the generic loop does).  p_k = r_k + beta p_k-1 goes to p_new (written
+// by the first image set only).
+template <typename T> struct CGRowPro {
+    const T *r, *p_old;
+    T *p_new;
+    const T *d, *a;
+    int nx, ny;
+    int64_t n0;
+    CGState *st;
+    const double *rr_partials;
+    int n_rr;
+    double *rr, *hist;
+    int k;
+    T beta;
+    __device__ bool begin() {
+        if (cg_done(st)) return false;
+        beta = T(0);
+        if (k == 0) return true;
+        const double rn = block_sum_partials_all(rr_partials, n_rr);
+        const double prev = rr[(k - 1) & 1];
+        beta = (T)(rn / prev);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            rr[k & 1] = rn;
+            hist[k] = sqrt(rn);
+            st->iters = k;
+            if (sqrt(rn) <= st->stop) __hip_atomic_store(&st->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        return true;
+    }
+    __device__ T operator()(int64_t row, int col) const {
+        const bool second = row >= n0;
+        const int64_t prow = second ? row - n0 : row;
+        const int64_t q = prow * ny + col;
+        const T pv = k == 0 ? r[q] : r[q] + beta * p_old[q];
+        if (second) return pv;
+        p_new[q] = pv;
+        T v = pv;
+        if (d) v *= d[q];
+        if (a) v *= a[((int)prow & (nx - 1)) * ny + col];
+        return v;
+    }
+};
+
+// Pass-3 epilogue: A p = D_s a y_R + y_S; returns the pixel pair's share of <p, A p>
+template <typename T> struct CGPairEpi {
+    T *Ap;
+    const T *p, *d, *a;
+    int nx, ny;
+    __device__ double operator()(int64_t row, int col, T y0, T y1, T s0, T s1) const {
+        const int64_t q = row * ny + col;
+        if (d) {
+            y0 *= d[q];
+            y1 *= d[q + 1];
+        }
+        if (a) {
+            const T *pa = a + ((int)row & (nx - 1)) * ny + col;
+            y0 *= pa[0];
+            y1 *= pa[1];
+        }
+        y0 += s0;
+        y1 += s1;
+        Ap[q] = y0;
+        Ap[q + 1] = y1;
+        return (double)p[q] * (double)y0 + (double)p[q + 1] * (double)y1;
+    }
+};
+
+// <r_K, r_K> of the last iteration into the history, and the iteration count
+__global__ __launch_bounds__(kRedThreads) void k_cg_finish(CGState *st, const double *rr_partials, int n_rr,
+                                                           int K, double *rr, double *hist, int *iters_done) {
+    if (!cg_done(st) && K > 0) {
+        const double rn = block_sum_partials(rr_partials, n_rr);
+        if (threadIdx.x == 0) {
+            rr[K & 1] = rn;
+            hist[K] = sqrt(rn);
+            st->iters = K;
+        }
+    }
+    if (threadIdx.x == 0) *iters_done = st->iters;
+}
+
+// The fused form applies to the full doubled-grid PSF (the prior embedding needs
+// the 2n grid) with rows that fit the paired inverse pass.
+static bool cg_fused_applies(const fr_psf *psf, bool prior) {
+    return psf && psf->px == 2 * psf->nx && psf->py == 2 * psf->ny && (prior ? 2 : 1) * psf->ny <= 8192;
+}
+
+static size_t cg_fused_scratch(const fr_psf *psf, bool prior) {
+    const size_t rs = psf->fp64 ? 8 : 4;
+    const int64_t nx = psf->nx, ny = psf->ny, nc = psf->n_chan, n = nc * nx * ny;
+    const int npart = prior ? 2 : 1;
+    const int64_t nb3 = irfft_pair_blocks((int)ny, nc * nx, npart, 256, nullptr, nullptr);
+    const size_t vec = scratch_round((size_t)n * rs);
+    // partials: the pass-3 block count depends on the device's CU count; bound it by one block per row
+    const size_t parts = scratch_round((size_t)(red_blocks(n) + std::max<int64_t>(nb3, nc * nx)) * 8);
+    return scratch_round(sizeof(CGState)) + parts + scratch_round(2 * sizeof(double)) + 4 * vec +
+           scratch_round((size_t)npart * nc * nx * ny * 2 * rs) + (prior ? scratch_round((size_t)2 * nx * (ny + 1) * rs) : 0);
+}
+
+template <typename T>
+static void cg_solve_psf_fused(const fr_psf *psf, const T *inv_power, const T *diag, const T *b, T *x, int maxiter,
+                               double rtol, double *hist, int *iters_done, hipStream_t st) {
+    const int64_t nx = psf->nx, ny = psf->ny, nc = psf->n_chan, n = nc * nx * ny;
+    const Ctx &ctx = *psf->ctx;
+    const int npart = inv_power ? 2 : 1;
+    const int M = (int)ny;  // packed width of the doubled rows
+    const int log2M = ilog2(M);
+    const int nb = red_blocks(n);
+    const int64_t nb3 = irfft_pair_blocks(M, nc * nx, npart, ctx.n_cu, nullptr, nullptr);
+    Scratch state(sizeof(CGState), st);
+    Scratch partials((size_t)(nb + std::max<int64_t>(nb3, nc * nx)) * sizeof(double), st);
+    double *rr_part = partials.as<double>(), *pAp_part = partials.as<double>() + nb;
+    Scratch rr(2 * sizeof(double), st);
+    Scratch r(n * sizeof(T), st), pA(n * sizeof(T), st), pB(n * sizeof(T), st), Ap(n * sizeof(T), st);
+    Scratch Y((size_t)npart * nc * nx * M * sizeof(c2<T>), st);
+    Scratch H;
+    if (inv_power) {
+        H = Scratch((size_t)2 * nx * (ny + 1) * sizeof(T), st);
+        map_async(PriorEmbed<T>{inv_power, H.as<T>(), (int)nx, (int)ny}, 2 * nx * (ny + 1), st);
+    }
+    CGState *S = state.as<CGState>();
+    map_async(CGInitXR<T>{b, x, r.as<T>()}, n, st);
+    k_dot_partials<T><<<dim3((unsigned)nb, 1), kRedThreads, 0, st>>>(r.as<T>(), nullptr, n, rr_part);
+    LAUNCH_CHECK();
+    k_cg_start<<<1, kRedThreads, 0, st>>>(S, rr_part, nb, rtol, maxiter, rr.as<double>(), hist);
+    LAUNCH_CHECK();
+    ConvGeom g;
+    g.n_img = npart * nc;
+    g.rows_in = (int)nx;
+    g.rows_out = (int)nx;
+    g.n_in_cols = (int)ny;
+    g.n_out_cols = (int)ny;
+    g.log2M = log2M;
+    g.log2Lc = ilog2(2 * nx);
+    const T scale = T(1) / (T(2 * nx) * T(M));
+    const T *a = psf->nfac.as<T>();
+    T *p_old = pA.as<T>(), *p_new = pB.as<T>();
+    for (int k = 0; k < maxiter; ++k) {
+        CGRowPro<T> pro{r.as<T>(), p_old, p_new, diag, a, (int)nx, (int)ny, nc * nx, S, rr_part, nb,
+                        rr.as<double>(), hist, k, T(0)};
+        {
+            ProfScope prof("cg_rows_r2c", st);
+            launch_rfft_rows<T>(ctx, g, pro, Y.as<c2<T>>(), st);
+        }
+        {
+            ProfScope prof("cg_cols", st);
+            launch_conv_cols<T>(ctx, g, Y.as<c2<T>>(), psf->KR.as<T>(), (int)nc, 0, scale, st, H.as<T>(),
+                                inv_power ? nc : INT64_MAX, &S->done);
+        }
+        {
+            ProfScope prof("cg_rows_c2r", st);
+            launch_irfft_rows_pair<T>(ctx, log2M, nc * nx, nc * nx, npart, (int)ny,
+                                      CGPairEpi<T>{Ap.as<T>(), p_new, diag, a, (int)nx, (int)ny}, Y.as<c2<T>>(),
+                                      pAp_part, &S->done, st);
+        }
+        ProfScope prof("cg_step", st);
+        k_cg_step<T><<<dim3((unsigned)nb), kRedThreads, 0, st>>>(S, x, r.as<T>(), p_new, Ap.as<T>(), n, pAp_part,
+                                                                  (int)nb3, rr.as<double>(), k, rr_part);
+        LAUNCH_CHECK();
+        std::swap(p_old, p_new);
+    }
+    k_cg_finish<<<1, kRedThreads, 0, st>>>(S, rr_part, nb, maxiter, rr.as<double>(), hist, iters_done);
+    LAUNCH_CHECK();
+}
+
 // The Hestenes-Stiefel loop around an operator apply(p, Ap) on n values.
 template <typename T, class Apply>
 void cg_run(int64_t n, const T *b, T *x, int maxiter, double rtol, double *hist, int *iters_done, hipStream_t st,
@@ -166,6 +398,7 @@ void cg_run(int64_t n, const T *b, T *x, int maxiter, double rtol, double *hist,
 }
 
 size_t cg_scratch(const fr_plan *pl, const fr_psf *psf, bool prior) {
+    if (cg_fused_applies(psf, prior)) return std::max(cg_fused_scratch(psf, prior), cg_fused_scratch(psf, false));
     const bool fp64 = psf ? psf->fp64 : pl->fp64;
     const size_t rs = fp64 ? 8 : 4;
     const int64_t nx = psf ? psf->nx : pl->nx, ny = psf ? psf->ny : pl->ny, nc = psf ? psf->n_chan : pl->n_chan;
@@ -180,6 +413,10 @@ size_t cg_scratch(const fr_plan *pl, const fr_psf *psf, bool prior) {
 template <typename T>
 void cg_solve(const fr_plan *pl, const fr_psf *psf, const T *weight, const T *inv_power, const T *diag, const T *b,
               T *x, int maxiter, double rtol, double *hist, int *iters_done, hipStream_t st) {
+    if (cg_fused_applies(psf, inv_power != nullptr)) {
+        cg_solve_psf_fused<T>(psf, inv_power, diag, b, x, maxiter, rtol, hist, iters_done, st);
+        return;
+    }
     const int64_t nx = psf ? psf->nx : pl->nx, ny = psf ? psf->ny : pl->ny;
     const int64_t nc = psf ? psf->n_chan : pl->n_chan;
     const int64_t n = nc * nx * ny;

@@ -20,16 +20,28 @@
 // exp(s), residuals, gradient products) into the first and last pass.
 #pragma once
 
+#include <type_traits>
+
 #include "fft.h"
 
 namespace frmi {
 
+// A row prologue may carry per-block set-up: `bool begin()` runs once per
+// workgroup before any element is loaded (every thread calls it; it may use
+// barriers) and returns false to skip the block's work.
+template <class P, class = void> struct has_begin : std::false_type {};
+template <class P> struct has_begin<P, std::void_t<decltype(std::declval<P &>().begin())>> : std::true_type {};
+
 // ------------------------------------------------------------------ pass 1
 template <typename T, int NTHR, int BPT, bool TWL, class Pro, int ODD = 1>
-__global__ __launch_bounds__(NTHR) void k_rfft_rows(Pro pro, c2<T> *__restrict__ Y, int64_t nrows,
+__global__ __launch_bounds__(NTHR) void k_rfft_rows(Pro pro_arg, c2<T> *__restrict__ Y, int64_t nrows,
                                                      int log2M, int n_in, int lines_per_wg,
                                                      const c2<T> *__restrict__ tw,
                                                      const c2<T> *__restrict__ tw2) {
+    Pro pro = pro_arg;
+    if constexpr (has_begin<Pro>::value) {
+        if (!pro.begin()) return;
+    }
     extern __shared__ __align__(16) unsigned char smem_raw[];
     c2<T> *buf = reinterpret_cast<c2<T> *>(smem_raw);
     const int M = ODD << log2M;
@@ -86,13 +98,17 @@ template <typename T> __device__ __forceinline__ T kernel_factor(T k, int mode) 
     return mode == 2 ? r : T(1) / r;
 }
 
-// K: [nk][Lc][M + 1] real, image g uses kernel g % nk; `mode` as kernel_factor.
-// M: packed row width; Lc = ODD 2^log2Lc.
+// K: [nk][Lc][M + 1] real, image g uses kernel g % nk, or K_alt [Lc][M + 1] for
+// images g >= g_alt; `mode` as kernel_factor.  M: packed row width; Lc = ODD
+// 2^log2Lc.  A non-zero *skip (device flag, optional) turns the launch into a no-op.
 template <typename T, int NTHR, int BPT, bool TWL, int ODD = 1>
 __global__ __launch_bounds__(NTHR) void k_conv_cols(c2<T> *__restrict__ Y, int M, int log2Lc,
                                                      int n_in, int n_out, int C,
                                                      const T *__restrict__ K, int nk, int mode,
-                                                     T scale, const c2<T> *__restrict__ tw) {
+                                                     T scale, const c2<T> *__restrict__ tw,
+                                                     const T *__restrict__ K_alt, int64_t g_alt,
+                                                     const int *__restrict__ skip) {
+    if (skip && __hip_atomic_load(skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     c2<T> *buf = reinterpret_cast<c2<T> *>(smem_raw);
     const int Lc = ODD << log2Lc;
@@ -102,7 +118,7 @@ __global__ __launch_bounds__(NTHR) void k_conv_cols(c2<T> *__restrict__ Y, int M
     const int64_t g = w / gridDim.x;
     const int log2C = 31 - __builtin_clz(C);  // strips are a power of two wide
     c2<T> *Yg = Y + g * n_in * (int64_t)M;  // packed rows of image g (n_in rows stored)
-    const T *Kg = K + (g % nk) * (int64_t)Lc * (M + 1);
+    const T *Kg = g >= g_alt ? K_alt : K + (g % nk) * (int64_t)Lc * (M + 1);
     const c2<T> *twp = stage_twiddles<T, NTHR, TWL>(buf + C * ld, tw, Lc);
     staged_copy<NTHR>(
         C * Lc,
@@ -155,25 +171,11 @@ __global__ __launch_bounds__(NTHR) void k_conv_cols(c2<T> *__restrict__ Y, int M
 }
 
 // ------------------------------------------------------------------ pass 3
-template <typename T, int NTHR, int BPT, bool TWL, class Epi, int ODD = 1>
-__global__ __launch_bounds__(NTHR) void k_irfft_rows(Epi epi, const c2<T> *__restrict__ Y, int64_t nrows,
-                                                      int log2M, int n_out_cols, int lines_per_wg,
-                                                      const c2<T> *__restrict__ tw,
-                                                      const c2<T> *__restrict__ tw2) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    c2<T> *buf = reinterpret_cast<c2<T> *>(smem_raw);
-    const int M = ODD << log2M;
-    const int64_t row0 = (int64_t)blockIdx.x * lines_per_wg;
-    const int nl = (int)min<int64_t>(lines_per_wg, nrows - row0);
-    const int ld = plen(M);
-    const c2<T> *twp = stage_twiddles<T, NTHR, TWL>(buf + lines_per_wg * ld, tw, M);
-    staged_copy<NTHR>(
-        nl * M, [&](int idx) { return Y[row0 * M + idx]; },
-        [&](int idx, c2<T> v) {
-            const int c = line_of<ODD>(idx, log2M);
-            buf[c * ld + padx(elem_of<ODD>(idx, c, M))] = v;
-        });
-    __syncthreads();
+// Packed half-spectrum lines (M complex values each; slot 0 holds the real DC and
+// Nyquist values) -> the spectra of the complex lines z[e] = x[2e] + i x[2e + 1]
+// whose inverse FFT gives the real rows (inverse of the half-length trick).
+template <typename T, int NTHR>
+__device__ __forceinline__ void irfft_unpack(c2<T> *buf, int ld, int nl, int M, const c2<T> *__restrict__ tw2) {
     const int half = M / 2 + 1;
     for (int c = 0; c < nl; ++c)
     for (int k = threadIdx.x; k < half; k += NTHR) {
@@ -195,6 +197,28 @@ __global__ __launch_bounds__(NTHR) void k_irfft_rows(Epi epi, const c2<T> *__res
             }
         }
     }
+}
+
+template <typename T, int NTHR, int BPT, bool TWL, class Epi, int ODD = 1>
+__global__ __launch_bounds__(NTHR) void k_irfft_rows(Epi epi, const c2<T> *__restrict__ Y, int64_t nrows,
+                                                      int log2M, int n_out_cols, int lines_per_wg,
+                                                      const c2<T> *__restrict__ tw,
+                                                      const c2<T> *__restrict__ tw2) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    c2<T> *buf = reinterpret_cast<c2<T> *>(smem_raw);
+    const int M = ODD << log2M;
+    const int64_t row0 = (int64_t)blockIdx.x * lines_per_wg;
+    const int nl = (int)min<int64_t>(lines_per_wg, nrows - row0);
+    const int ld = plen(M);
+    const c2<T> *twp = stage_twiddles<T, NTHR, TWL>(buf + lines_per_wg * ld, tw, M);
+    staged_copy<NTHR>(
+        nl * M, [&](int idx) { return Y[row0 * M + idx]; },
+        [&](int idx, c2<T> v) {
+            const int c = line_of<ODD>(idx, log2M);
+            buf[c * ld + padx(elem_of<ODD>(idx, c, M))] = v;
+        });
+    __syncthreads();
+    irfft_unpack<T, NTHR>(buf, ld, nl, M, tw2);
     __syncthreads();
     lds_fft<T, NTHR, BPT, ODD>(buf, ld, nl, log2M, +1, twp);
     const int npair = n_out_cols / 2;
@@ -203,6 +227,116 @@ __global__ __launch_bounds__(NTHR) void k_irfft_rows(Epi epi, const c2<T> *__res
             c2<T> z = buf[c * ld + padx(e)];
             epi(row0 + c, 2 * e, z.x, z.y);
         }
+}
+
+
+// Sum of v over the workgroup (NTHR threads), FP64, fixed order; valid in thread 0.
+template <int NTHR> __device__ __forceinline__ double block_sum_n(double v) {
+    __shared__ double sh[NTHR / 64];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double t = 0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < NTHR / 64; ++k) t += sh[k];
+    return t;
+}
+
+// Pass 3 over pairs of images: row r of the first n_rows packed rows goes with
+// row r + pair_offset (NPART = 2; NPART = 1 has no partner), both inverse
+// transformed in the same workgroup so that the epilogue sees the two real
+// values of a pixel together: epi(r, col, a0, a1, b0, b1) receives columns col
+// and col + 1 of the row and of its partner, stores what it needs and returns a
+// contribution to a sum; partials[blockIdx.x] gets the workgroup's FP64 sum.
+// A non-zero *skip turns the launch into a no-op.
+template <typename T, int NTHR, int BPT, bool TWL, class Epi, int NPART>
+__global__ __launch_bounds__(NTHR) void k_irfft_rows_pair(Epi epi, const c2<T> *__restrict__ Y, int64_t n_rows,
+                                                           int64_t pair_offset, int log2M, int n_out_cols,
+                                                           int lines_per_wg, const c2<T> *__restrict__ tw,
+                                                           const c2<T> *__restrict__ tw2,
+                                                           double *__restrict__ partials,
+                                                           const int *__restrict__ skip) {
+    if (skip && __hip_atomic_load(skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    c2<T> *buf = reinterpret_cast<c2<T> *>(smem_raw);
+    const int M = 1 << log2M;
+    const int64_t row0 = (int64_t)blockIdx.x * lines_per_wg;
+    const int nl = (int)min<int64_t>(lines_per_wg, n_rows - row0);
+    const int ld = plen(M);
+    const c2<T> *twp = stage_twiddles<T, NTHR, TWL>(buf + NPART * lines_per_wg * ld, tw, M);
+    staged_copy<NTHR>(
+        NPART * nl * M,
+        [&](int idx) {
+            const int c = idx >> log2M;  // line: part c / nl, row c % nl
+            const int64_t src = (c < nl ? row0 + c : row0 + (c - nl) + pair_offset);
+            return Y[src * M + (idx & (M - 1))];
+        },
+        [&](int idx, c2<T> v) { buf[(idx >> log2M) * ld + padx(idx & (M - 1))] = v; });
+    __syncthreads();
+    irfft_unpack<T, NTHR>(buf, ld, NPART * nl, M, tw2);
+    __syncthreads();
+    lds_fft<T, NTHR, BPT>(buf, ld, NPART * nl, log2M, +1, twp);
+    const int npair = n_out_cols / 2;
+    double acc = 0.0;
+    for (int c = 0; c < nl; ++c)
+        for (int e = threadIdx.x; e < npair; e += NTHR) {
+            const c2<T> z = buf[c * ld + padx(e)];
+            const c2<T> w = NPART == 2 ? buf[(nl + c) * ld + padx(e)] : mk<T>(T(0), T(0));
+            acc += epi(row0 + c, 2 * e, z.x, z.y, w.x, w.y);
+        }
+    acc = block_sum_n<NTHR>(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+}
+
+// Workgroups of launch_irfft_rows_pair for n_rows row pairs of packed width M.
+inline int64_t irfft_pair_blocks(int M, int64_t n_rows, int npart, int n_cu, int *lpw_out, int *nthr_out) {
+    int lpw = 1, nthr = 1024;
+    if (npart * M <= 4096) {
+        nthr = 256;
+        lpw = std::max(1, 4096 / (npart * M));
+        while (lpw > 1 && n_rows / lpw < 4 * (int64_t)std::max(n_cu, 1)) lpw >>= 1;
+    }
+    if (lpw_out) *lpw_out = lpw;
+    if (nthr_out) *nthr_out = nthr;
+    return (n_rows + lpw - 1) / lpw;
+}
+
+// Paired inverse row pass (power-of-two packed width M = 2^log2M <= 8192 / npart).
+template <typename T, class Epi>
+void launch_irfft_rows_pair(const Ctx &ctx, int log2M, int64_t n_rows, int64_t pair_offset, int npart,
+                            int n_out_cols, Epi epi, const c2<T> *Y, double *partials, const int *skip,
+                            hipStream_t st) {
+    const int M = 1 << log2M;
+    FR_REQUIRE(npart == 1 || npart == 2, "one or two images per pixel");
+    FR_REQUIRE(npart * M <= 8192, "paired rows too long for one workgroup");
+    int lpw = 1, nthr = 256;
+    const int64_t nblk = irfft_pair_blocks(M, n_rows, npart, ctx.n_cu, &lpw, &nthr);
+    const size_t lines = (size_t)npart * lpw * plen(M) * sizeof(c2<T>);
+    const size_t twb = (size_t)M * sizeof(c2<T>);
+    const c2<T> *tw = ctx.tw<T>(log2M), *tw2 = ctx.tw<T>(log2M + 1);
+    FR_REQUIRE(lines <= (size_t)kLdsBytes, "paired rows exceed LDS");
+    const bool twl = lines + twb <= (size_t)kLdsBytes;
+    const size_t lds = twl ? lines + twb : lines;
+#define FR_PAIR(NT, TW, NP)                                                                                   \
+    do {                                                                                                      \
+        allow_lds(k_irfft_rows_pair<T, NT, 4, TW, Epi, NP>, lds);                                             \
+        k_irfft_rows_pair<T, NT, 4, TW, Epi, NP><<<dim3((unsigned)nblk), NT, lds, st>>>(                       \
+            epi, Y, n_rows, pair_offset, log2M, n_out_cols, lpw, tw, tw2, partials, skip);                    \
+    } while (0)
+    if (nthr == 256) {
+        if (npart == 2) FR_PAIR(256, true, 2);
+        else FR_PAIR(256, true, 1);
+    } else if (twl) {
+        if (npart == 2) FR_PAIR(1024, true, 2);
+        else FR_PAIR(1024, true, 1);
+    } else {
+        if (npart == 2) FR_PAIR(1024, false, 2);
+        else FR_PAIR(1024, false, 1);
+    }
+#undef FR_PAIR
+    LAUNCH_CHECK();
 }
 
 // ------------------------------------------------------------------ launchers
@@ -252,7 +386,8 @@ void launch_rfft_rows(const Ctx &ctx, const ConvGeom &g, Pro pro, c2<T> *Y, hipS
 // ODD must equal g.odd_Lc
 template <typename T, int ODD = 1>
 void launch_conv_cols(const Ctx &ctx, const ConvGeom &g, c2<T> *Y, const T *K, int nk, int mode, T scale,
-                      hipStream_t st) {
+                      hipStream_t st, const T *K_alt = nullptr, int64_t g_alt = INT64_MAX,
+                      const int *skip = nullptr) {
     FR_REQUIRE(g.odd_Lc == ODD, "column length and kernel variant disagree");
     const int M = g.M();
     const int Lc = g.Lc();
@@ -274,7 +409,8 @@ void launch_conv_cols(const Ctx &ctx, const ConvGeom &g, c2<T> *Y, const T *K, i
     do {                                                                                                 \
         allow_lds(k_conv_cols<T, NT, 4, TW, ODD>, ldst);                                                 \
         k_conv_cols<T, NT, 4, TW, ODD><<<grid, NT, ldst, st>>>(Y, M, g.log2Lc, g.rows_in, g.rows_out, C, \
-                                                               K, nk, mode, scale, ctx.tw<T>(ODD, g.log2Lc)); \
+                                                               K, nk, mode, scale, ctx.tw<T>(ODD, g.log2Lc), \
+                                                               K_alt, g_alt, skip);                          \
     } while (0)
     // one radix-4 butterfly per thread where the strip allows (the strip's load ->
     // FFT -> multiply -> FFT -> store chain is latency-bound; measured at
