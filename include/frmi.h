@@ -52,6 +52,7 @@ extern "C" {
 typedef struct fr_ctx fr_ctx;   /* one device */
 typedef struct fr_plan fr_plan; /* uvw/frequencies bucketed on the grid, kernel parameters */
 typedef struct fr_psf fr_psf;   /* response kernel K_R and noise kernel K_N per channel */
+typedef struct fr_cf fr_cf;     /* correlated-field amplitude model on one grid */
 
 enum fr_status {
     FR_OK = 0,
@@ -337,6 +338,45 @@ int fr_mgvi_draw(fr_psf *psf, const void *power, const void *diag, const void *e
                  const void *eta1, void *xi, void *stream);
 int fr_mgvi_solve(fr_psf *psf, const void *power, const void *diag, const void *b, void *x,
                   int maxiter, double rtol, double *resid_hist, int *iters_done, void *stream);
+
+/*
+ * Correlated-field amplitude model of the diffuse-emission prior (the power
+ * spectrum of the exponentiated Gaussian process of Sec. 3.1.1, inferred with
+ * the hyperparameters listed in the prior-parameter appendices).  Reading of the
+ * model, whose definition the paper defers to earlier work:
+ *   - zero-mode std, fluctuations, flexibility and asperity are lognormal with
+ *     the given mean and standard deviation (exp(mu + sigma xi), sigma^2 =
+ *     ln(1 + std^2/mean^2), mu = ln mean - sigma^2/2; a mean of 0 gives 0);
+ *     the average log-log slope is normal (mean + std xi);
+ *   - over the J distinct non-zero |k| of the grid (integer frequency units), at
+ *     t = ln|k| ascending with steps d_j (d_0 = 0): the local slope
+ *     v_j = flex sum_{i<=j} sqrt(d_i) xi_v_i (a Wiener process), its integral with
+ *     a rougher part y_j = sum_{i<=j} [(v_i-1 + v_i) d_i / 2 + flex asp sqrt(d_i) xi_y_i],
+ *     and the log-amplitude logA_j = slope (t_j - t_0) + y_j - y_J (t_j - t_0)/(t_J - t_0);
+ *   - P = fluct^2 nx ny A^2 / sum_j mult_j A_j^2 at k != 0 (mult_j: frequencies
+ *     of the full grid in bin j), P(0) = zm^2 nx ny: the field without its zero
+ *     mode has variance fluct^2;
+ *   - log-sky s = offset + F^-1 sqrt(P) F xi_field.
+ * fr_cf_create: bins of an nx x ny grid (powers of two in [4, 8192]); synchronous.
+ * fr_cf_power:
+ *   prior     host double [11]: zero-mode offset, zero-mode std mean, std;
+ *             fluctuations mean, std; slope mean, std; flexibility mean, std;
+ *             asperity mean, std
+ *   xi_hyper  device double [5] standardised excitations (zero-mode std,
+ *             fluctuations, slope, flexibility, asperity)
+ *   xi_v, xi_y device double [J] (fr_cf_num_bins)
+ *   power     device [nx][ny/2 + 1] real (r2c half spectrum; fp64 selects double),
+ *             usable as the power of fr_periodic_conv and of the MGVI calls.
+ * fr_cf_logsky: s = offset + F^-1 sqrt(P) F xi for n_img images; power as
+ *   written by fr_cf_power, xi and s device [n_img][nx][ny] real, s != xi.
+ */
+int fr_cf_create(fr_ctx *ctx, int64_t nx, int64_t ny, fr_cf **out);
+int fr_cf_num_bins(const fr_cf *cf, int64_t *n_bins);
+int fr_cf_power(fr_cf *cf, const double *prior, const double *xi_hyper, const double *xi_v,
+                const double *xi_y, void *power, int fp64, void *stream);
+int fr_cf_logsky(fr_cf *cf, const void *power, double offset, const void *xi, void *s, int64_t n_img,
+                 int fp64, void *stream);
+void fr_cf_destroy(fr_cf *cf);
 
 /* Device bytes a call of `op` with batch B needs beyond its inputs and outputs,
  * plus the resident plan/psf bytes.  Host-only, no GPU work.  scratch_bytes bounds

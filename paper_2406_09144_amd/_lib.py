@@ -83,6 +83,11 @@ SIGNATURES = {
     "fr_mgvi_metric_apply": ([_P, _P, _P, _P, _P, _P], _I),
     "fr_mgvi_draw": ([_P, _P, _P, _P, _P, _P, _P], _I),
     "fr_mgvi_solve": ([_P, _P, _P, _P, _P, _I, _D, _P, _P, _P], _I),
+    "fr_cf_create": ([_P, _I64, _I64, _PP], _I),
+    "fr_cf_num_bins": ([_P, ctypes.POINTER(_I64)], _I),
+    "fr_cf_power": ([_P, _P, _P, _P, _P, _P, _I, _P], _I),
+    "fr_cf_logsky": ([_P, _P, _D, _P, _P, _I64, _I, _P], _I),
+    "fr_cf_destroy": ([_P], None),
     "fr_query_footprint": ([_P, _P, _I, _I64, ctypes.POINTER(ctypes.c_size_t),
                             ctypes.POINTER(ctypes.c_size_t)], _I),
     "fr_scratch_stats": ([_P, _P, _I, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)], _I),

@@ -471,3 +471,53 @@ def profile_query(name):
 PROFILED_KERNELS = ["degrid", "grid", "grid_assemble", "zero", "wplane_rows_fwd", "wplane_cols_fwd", "wplane_cols_inv",
                     "wplane_rows_inv", "psfconv_rows_r2c", "psfconv_cols", "psfconv_rows_c2r",
                     "pconv_rows_r2c", "pconv_cols", "pconv_rows_c2r"]
+
+
+class CorrelatedField:
+    """Amplitude model of the correlated-field prior on an nx x ny grid
+    (fr_cf_*): `power` turns hyperparameter excitations into the r2c half power
+    spectrum [nx, ny/2+1], `logsky` turns field excitations into log-skies."""
+
+    PRIOR_KEYS = ("offset", "zm_mean", "zm_std", "fluct_mean", "fluct_std", "slope_mean", "slope_std",
+                  "flex_mean", "flex_std", "asp_mean", "asp_std")
+
+    def __init__(self, nx, ny, ctx=None, device=None):
+        self.ctx = ctx or Context.get(device)
+        h = ctypes.c_void_p()
+        L.check(_lib().fr_cf_create(self.ctx.handle, int(nx), int(ny), ctypes.byref(h)))
+        self.handle = h
+        self.nx, self.ny = int(nx), int(ny)
+        J = ctypes.c_int64()
+        L.check(_lib().fr_cf_num_bins(h, ctypes.byref(J)))
+        self.n_bins = J.value
+
+    def power(self, prior, xi_hyper, xi_v, xi_y, fp64=False, stream=None):
+        import numpy as np
+        pr = np.ascontiguousarray([float(prior[k]) for k in self.PRIOR_KEYS], dtype=np.float64)
+        dev = torch.device("cuda", self.ctx.device)
+        xi_hyper = _need(xi_hyper.to(dev).contiguous(), torch.float64, (5,), "xi_hyper")
+        xi_v = _need(xi_v.to(dev).contiguous(), torch.float64, (self.n_bins,), "xi_v")
+        xi_y = _need(xi_y.to(dev).contiguous(), torch.float64, (self.n_bins,), "xi_y")
+        P = torch.empty((self.nx, self.ny // 2 + 1), dtype=_real_dtype(fp64), device=dev)
+        L.check(_lib().fr_cf_power(self.handle, pr.ctypes.data_as(ctypes.c_void_p), _ptr(xi_hyper), _ptr(xi_v),
+                                   _ptr(xi_y), _ptr(P), int(fp64), _stream(stream)))
+        return P
+
+    def logsky(self, power, offset, xi, stream=None):
+        fp64 = power.dtype == torch.float64
+        rd = _real_dtype(fp64)
+        power = _need(power, rd, (self.nx, self.ny // 2 + 1), "power")
+        shape = tuple(xi.shape)
+        xi = _need(xi.reshape(-1, self.nx, self.ny).contiguous(), rd, (xi.numel() // (self.nx * self.ny),
+                                                                      self.nx, self.ny), "xi")
+        s = torch.empty_like(xi)
+        L.check(_lib().fr_cf_logsky(self.handle, _ptr(power), float(offset), _ptr(xi), _ptr(s), xi.shape[0],
+                                    int(fp64), _stream(stream)))
+        return s.reshape(shape)
+
+    def __del__(self):
+        try:
+            if self.handle:
+                _lib().fr_cf_destroy(self.handle)
+        except Exception:
+            pass

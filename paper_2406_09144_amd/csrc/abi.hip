@@ -542,6 +542,76 @@ int fr_periodic_conv(fr_ctx *ctx, const void *K, int64_t nk, int mode, const voi
     FR_API_END
 }
 
+int fr_cf_create(fr_ctx *ctx, int64_t nx, int64_t ny, fr_cf **out) {
+    FR_API_BEGIN
+    FR_REQUIRE(ctx && out, "ctx and out are required");
+    *out = nullptr;
+    FR_REQUIRE(is_pow2(nx) && is_pow2(ny) && nx >= 4 && ny >= 4 && nx <= 8192 && ny <= 8192,
+               "nx, ny must be powers of two in [4, 8192]");
+    DeviceGuard dg(ctx->c.device);
+    auto cf = std::make_unique<fr_cf>();
+    cf->ctx = &ctx->c;
+    cf->nx = nx;
+    cf->ny = ny;
+    cf_build(cf.get());
+    *out = cf.release();
+    FR_API_END
+}
+
+int fr_cf_num_bins(const fr_cf *cf, int64_t *n_bins) {
+    FR_API_BEGIN
+    FR_REQUIRE(cf && n_bins, "cf and n_bins are required");
+    *n_bins = cf->J;
+    FR_API_END
+}
+
+void fr_cf_destroy(fr_cf *cf) {
+    if (!cf) return;
+    try {
+        DeviceGuard dg(cf->ctx->device);
+        delete cf;
+    } catch (...) {
+        // the HIP runtime is already gone (process teardown): its memory goes with it
+    }
+}
+
+int fr_cf_power(fr_cf *cf, const double *prior, const double *xi_hyper, const double *xi_v, const double *xi_y,
+                void *power, int fp64, void *stream) {
+    FR_API_BEGIN
+    FR_REQUIRE(cf && prior && xi_hyper && xi_v && xi_y && power, "every argument is required");
+    for (int k : {1, 3, 7, 9}) {
+        FR_REQUIRE(std::isfinite(prior[k]) && prior[k] >= 0.0, "lognormal means must be >= 0");
+        FR_REQUIRE(std::isfinite(prior[k + 1]) && prior[k + 1] >= 0.0, "standard deviations must be >= 0");
+    }
+    FR_REQUIRE(prior[1] > 0.0 && prior[3] > 0.0, "zero-mode std and fluctuations means must be > 0");
+    FR_REQUIRE(std::isfinite(prior[0]) && std::isfinite(prior[5]) && std::isfinite(prior[6]) && prior[6] >= 0.0,
+               "offset and slope must be finite, slope std >= 0");
+    DeviceGuard dg(cf->ctx->device);
+    if (fp64)
+        cf_power<double>(cf, prior, xi_hyper, xi_v, xi_y, (double *)power, as_stream(stream));
+    else
+        cf_power<float>(cf, prior, xi_hyper, xi_v, xi_y, (float *)power, as_stream(stream));
+    FR_API_END
+}
+
+int fr_cf_logsky(fr_cf *cf, const void *power, double offset, const void *xi, void *s, int64_t n_img, int fp64,
+                 void *stream) {
+    FR_API_BEGIN
+    FR_REQUIRE(cf && power, "cf and power are required");
+    FR_REQUIRE(n_img >= 0, "n_img must be >= 0");
+    FR_REQUIRE(std::isfinite(offset), "offset must be finite");
+    if (n_img == 0) return FR_OK;
+    FR_REQUIRE(xi && s && xi != s, "xi and s are required and must differ");
+    FR_REQUIRE(!fp64 || cf->nx <= 4096, "FP64 needs nx <= 4096");
+    DeviceGuard dg(cf->ctx->device);
+    if (fp64)
+        cf_logsky<double>(cf, (const double *)power, offset, (const double *)xi, (double *)s, n_img,
+                          as_stream(stream));
+    else
+        cf_logsky<float>(cf, (const float *)power, offset, (const float *)xi, (float *)s, n_img, as_stream(stream));
+    FR_API_END
+}
+
 static void mgvi_check(const fr_psf *psf, const void *power) {
     FR_REQUIRE(psf && power, "psf and power are required");
     FR_REQUIRE(psf->KN.p, "the PSF object has no noise kernel (N'^-1 is part of the metric)");

@@ -22,6 +22,16 @@ struct fr_psf {
 };
 
 
+// Correlated-field amplitude model on an nx x ny grid: the distinct non-zero |k|
+// (bins), their log-frequencies and steps, multiplicities, and the bin of every
+// r2c half-spectrum cell.
+struct fr_cf {
+    frmi::Ctx *ctx = nullptr;
+    int64_t nx = 0, ny = 0, J = 0;
+    frmi::DevBuf t, d, mult;  // double [J]
+    frmi::DevBuf bin;         // int32 [nx][ny/2 + 1], -1 at k = 0
+};
+
 struct fr_plan {
     frmi::Ctx *ctx = nullptr;
     int64_t nx = 0, ny = 0, nu = 0, nv = 0, n_row = 0, n_chan = 0;
@@ -126,6 +136,15 @@ void mgvi_draw(const fr_psf *psf, const T *power, const T *diag, const T *eta0, 
 template <typename T>
 void mgvi_solve(const fr_psf *psf, const T *power, const T *diag, const T *b, T *x, int maxiter, double rtol,
                 double *hist, int *iters_done, hipStream_t st);
+
+// cf.hip
+void cf_build(fr_cf *cf);
+size_t cf_scratch(const fr_cf *cf);
+template <typename T>
+void cf_power(const fr_cf *cf, const double *prior, const double *xi_h, const double *xi_v, const double *xi_y,
+              T *power, hipStream_t st);
+template <typename T>
+void cf_logsky(const fr_cf *cf, const T *power, double offset, const T *xi, T *s, int64_t n_img, hipStream_t st);
 
 // psfconv.hip
 template <typename T>
