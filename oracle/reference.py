@@ -459,12 +459,12 @@ def algorithm1(uvw_m, freq_hz, nx, ny, dx, dy, vis, weight, K_R, K_N, a, inv_pow
     minor cycle: the paper runs MGVI there).  K_R [2nx, ny + 1] and K_N [nx, ny]
     (full) as response_kernel and noise_kernel; inv_power the full [nx, ny] 1/P.
     Returns the log-sky after the last minor cycle, the residual images d_1 ..
-    d_n_major and the FAST H after each minor cycle."""
+    d_n_major, the FAST H after each minor cycle and the log-sky after each."""
     I_D = dirty_image(uvw_m, freq_hz, nx, ny, dx, dy, vis, weight)[0]
     d = I_D
     s = _f64(s0)
     I_prev = None
-    ds_out, Hs = [], []
+    ds_out, Hs, s_out = [], [], []
     for _ in range(n_major):
         for _ in range(n_minor):
             ifix = None if I_prev is None else -I_prev
@@ -474,10 +474,11 @@ def algorithm1(uvw_m, freq_hz, nx, ny, dx, dy, vis, weight, K_R, K_N, a, inv_pow
             s = s + min(1.0, max_step / np.max(np.abs(ds))) * ds
         Hs.append(likelihood_fast(s, d, K_R, K_N, a, i_fixed=None if I_prev is None else -I_prev,
                                   inv_power=inv_power)[0])
+        s_out.append(s)
         I_prev = np.exp(s)
         d = I_D - rnr_exact(uvw_m, freq_hz, nx, ny, dx, dy, I_prev, weight)[0]
         ds_out.append(d)
-    return s, ds_out, Hs
+    return s, ds_out, Hs, s_out
 
 
 # ---------------------------------------------------------------- correlated-field amplitude model

@@ -31,10 +31,13 @@ def _H_and_grad(psf, s, d, i_fixed, inv_power):
     return api.likelihood_grad(FR_LIK_FAST, s, d, psf=psf, i_fixed=i_fixed, inv_power=inv_power)
 
 
-def minor_cycle(psf, d, s, i_prev, inv_power, lam, n_steps=8, cg_iters=20, max_step=2.0, log=None):
+def minor_cycle(psf, d, s, i_prev, inv_power, lam, n_steps=8, cg_iters=20, max_step=2.0, log=None,
+                adaptive=True):
     """Damped Gauss-Newton MAP steps on the FAST likelihood; d is the minor cycle's
     data image, i_prev the sky the previous major cycle subtracted (None at first).
-    Returns the log-sky, its FAST H and the damping to continue with."""
+    Returns the log-sky, its FAST H and the damping to continue with.  With
+    adaptive=False the schedule is fixed: every step is taken (no acceptance
+    test) and lambda stays as given."""
     ifix = None if i_prev is None else (-i_prev).contiguous()
     sb = s[None].contiguous()
     H, g = _H_and_grad(psf, sb, d, ifix, inv_power)
@@ -48,10 +51,11 @@ def minor_cycle(psf, d, s, i_prev, inv_power, lam, n_steps=8, cg_iters=20, max_s
         t = min(1.0, max_step / dmax)  # exp(s) is nonlinear: bound the log-sky change
         cand = (sb + t * ds[None]).contiguous()
         Hc, gc = _H_and_grad(psf, cand, d, ifix, inv_power)
-        accepted = float(Hc[0]) <= float(H[0])
+        accepted = (not adaptive) or float(Hc[0]) <= float(H[0])
         if accepted:
             sb, H, g = cand, Hc, gc
-            lam *= 0.3
+            if adaptive:
+                lam *= 0.3
         else:
             lam *= 10.0
         if log is not None:

@@ -149,3 +149,66 @@ def test_mgvi_minor_cycle_lowers_the_exact_likelihood():
     assert len(samples) == 4
     assert torch.equal(samples[0], -samples[1]) and torch.equal(samples[2], -samples[3])
     assert all("step" in l for l in lines[:1])
+
+
+def test_major_minor_fixed_schedule_matches_oracle_algorithm1():
+    """Algorithm 1 with a fixed minor-cycle schedule (damping lambda constant, every
+    step taken with t = min(1, 0.5 / max|ds|)), two major cycles of three
+    Gauss-Newton steps and 10 CG iterations each, on the 32^2 VLA-like layout:
+    the GPU driver's log-sky and major-cycle residual after each cycle against the
+    oracle's run of the same scheme with the direct-sum operators and its own PSF
+    and noise kernels.
+
+    Tolerances come from how the scheme carries rounding: the oracle rerun on the
+    CPU with its vectors rounded to FP32 after every operator and with relative
+    errors of 1e-5 (the gridder's eps) on the exact operators moves s_1 and d_1 by
+    1.3e-4 and 2.4e-4, and s_2 and d_2 by 4e-3 and 1.6e-2: the residual d is a
+    small difference (||d_1|| ~ ||I_D|| / 12, ||d_2|| ~ ||I_D|| / 32) and the
+    second cycle's deconvolution amplifies what the first left.  Bounds: 2e-3 on
+    s_1 and d_1, 2e-2 on s_2, and d_2 against the scale of the data, ||I_D||, 2e-3."""
+    import torch
+    import oracle as O
+    from paper_2406_09144_amd import api, major_minor
+    from synthetic.skies import power_spectrum
+    n = 32
+    obs = make_config(1, n=n, n_int=120, with_sky=False)
+    sky_np = np.exp(correlated_field(np.random.default_rng(5), n, n))
+    model = O.degrid(obs.uvw, obs.freq, n, n, obs.dx, obs.dy, sky_np[None])
+    noise, wt = noise_from_model(config_rng(1, "noise"), model, rel=0.05)
+    Vn = model + noise
+    p0 = O.psf0(obs.uvw, obs.freq, n, n, obs.dx, obs.dy, wt)
+    K = O.response_kernel(p0)
+    KN = O.noise_kernel(p0, 0.1 * p0.max())
+    a = O.n_factor(n, n, obs.dx, obs.dy)
+    ipf = 1.0 / power_spectrum(n, n)
+    s0 = np.full((n, n), np.log(sky_np.mean()))
+    lam = 0.05 * float(np.abs(K).max())
+    _, d_ref, H_ref, s_ref = O.algorithm1(obs.uvw, obs.freq, n, n, obs.dx, obs.dy, Vn, wt, K, KN, a, ipf, s0,
+                                          n_major=2, n_minor=3, cg_iters=10, lam=lam, max_step=0.5)
+    I_D_ref = O.dirty_image(obs.uvw, obs.freq, n, n, obs.dx, obs.dy, Vn, wt)[0]
+    # the GPU driver: same data, GPU plan, GPU PSF and noise kernels
+    pl = api.Plan(obs.uvw, obs.freq, n, n, obs.dx, obs.dy, eps=1e-5)
+    V = torch.from_numpy(Vn).to(torch.complex64).cuda()
+    w = torch.from_numpy(wt).float().cuda()
+    psf = api.make_psf_kernel(pl, w, eps_noise=-1e-1)
+    ip = torch.from_numpy(np.ascontiguousarray(ipf[:, : n // 2 + 1])).float().cuda()
+    I_D = api.grid(pl, V, w)
+    d = I_D
+    s = torch.from_numpy(s0[None]).float().cuda()
+    I_prev = None
+    err_s, err_d, err_d_data = [], [], []
+    for i in range(2):
+        s, _, _ = major_minor.minor_cycle(psf, d, s, I_prev, ip, lam, n_steps=3, cg_iters=10, max_step=0.5,
+                                          adaptive=False)
+        I_prev = torch.exp(s)
+        d = (I_D - api.apply_RNR_exact(pl, I_prev, w)).contiguous()
+        dg = d.cpu().numpy().astype(np.float64)[0]
+        sg = s.cpu().numpy().astype(np.float64)[0]
+        err_s.append(float(np.linalg.norm(sg - s_ref[i]) / np.linalg.norm(s_ref[i])))
+        err_d.append(float(np.linalg.norm(dg - d_ref[i]) / np.linalg.norm(d_ref[i])))
+        err_d_data.append(float(np.linalg.norm(dg - d_ref[i]) / np.linalg.norm(I_D_ref)))
+    print(f"Algorithm 1, fixed schedule: ||d_i|| oracle {[float(np.linalg.norm(x)) for x in d_ref]}, "
+          f"||I_D|| {float(np.linalg.norm(I_D_ref)):.1f}; rel err of s_i {err_s}, of d_i {err_d}, "
+          f"of d_i against ||I_D|| {err_d_data}; oracle FAST H {H_ref}", flush=True)
+    assert err_s[0] < 2e-3 and err_d[0] < 2e-3
+    assert err_s[1] < 2e-2 and err_d_data[1] < 2e-3

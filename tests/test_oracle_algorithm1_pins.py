@@ -37,8 +37,8 @@ def test_algorithm1_coplanar_major_cycle_changes_nothing(oracle_lib):
     obs, V, wt, K, KN, a, ip, s0, lam = setup(0)
     n = obs.nx
     args = (obs.uvw, obs.freq, n, n, obs.dx, obs.dy, V, wt, K, KN, a, ip, s0)
-    s2, d2, _ = O.algorithm1(*args, n_major=2, n_minor=3, cg_iters=30, lam=lam, max_step=0.5)
-    s1, d1, _ = O.algorithm1(*args, n_major=1, n_minor=6, cg_iters=30, lam=lam, max_step=0.5)
+    s2, d2, _, _ = O.algorithm1(*args, n_major=2, n_minor=3, cg_iters=30, lam=lam, max_step=0.5)
+    s1, d1, _, _ = O.algorithm1(*args, n_major=1, n_minor=6, cg_iters=30, lam=lam, max_step=0.5)
     # equal up to FP64 rounding carried through the Gauss-Newton solves (measured
     # 3e-9 and 2e-8; with w below the two paths differ by 3e-5 and 3e-4)
     assert np.linalg.norm(s2 - s1) <= 1e-7 * np.linalg.norm(s1)
@@ -46,8 +46,8 @@ def test_algorithm1_coplanar_major_cycle_changes_nothing(oracle_lib):
     # with w the approximation is not exact and the major cycle does change the path
     obs, V, wt, K, KN, a, ip, s0, lam = setup(1)
     argsw = (obs.uvw, obs.freq, n, n, obs.dx, obs.dy, V, wt, K, KN, a, ip, s0)
-    s2w, _, _ = O.algorithm1(*argsw, n_major=2, n_minor=3, cg_iters=30, lam=lam, max_step=0.5)
-    s1w, _, _ = O.algorithm1(*argsw, n_major=1, n_minor=6, cg_iters=30, lam=lam, max_step=0.5)
+    s2w, _, _, _ = O.algorithm1(*argsw, n_major=2, n_minor=3, cg_iters=30, lam=lam, max_step=0.5)
+    s1w, _, _, _ = O.algorithm1(*argsw, n_major=1, n_minor=6, cg_iters=30, lam=lam, max_step=0.5)
     assert np.linalg.norm(s2w - s1w) > 1e-6 * np.linalg.norm(s1w)
 
 
@@ -96,7 +96,7 @@ def test_algorithm1_one_step_equals_dense_brute_force(oracle_lib):
     M = D[:, None] * Rp * D[None, :] + Sinv + lam * np.eye(n * n)
     s1 = s - np.linalg.solve(M, g)
     d1 = I_D - R_exact @ np.exp(s1)
-    so, do, _ = O.algorithm1(obs.uvw, obs.freq, n, n, obs.dx, obs.dy, V, wt, K, KN, a, ip, s0, n_major=1,
+    so, do, _, _ = O.algorithm1(obs.uvw, obs.freq, n, n, obs.dx, obs.dy, V, wt, K, KN, a, ip, s0, n_major=1,
                              n_minor=1, cg_iters=64, lam=lam, max_step=1e9)
     assert np.linalg.norm(so.ravel() - s1) <= 1e-9 * np.linalg.norm(s1)
     assert np.linalg.norm(do[0].ravel() - d1) <= 1e-9 * np.linalg.norm(d1)
