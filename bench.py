@@ -20,8 +20,20 @@ spread, a contraction on the matrix cores: algorithmic FLOPs against the FP32
 MFMA peak),
 from the library's per-kernel hipEvent timing over a second pass of the same
 steps (per-launch event brackets are kept out of the step timings);
-"roofline_hbm" lists the memory-bound kernels of the same path against HBM.
-PSF applies/s is the sustained rate of back-to-back batch-8 applies.
+"roofline_hbm" lists the memory-bound kernels of the same path against HBM, and
+the whole degrid and grid calls and the batch-8 PSF apply on the bytes the method
+must move (every w-plane written once by its FFT and read once; x, y and the
+kernel once per apply); "roofline_lds" rates the degridding kernel against the LDS
+(every visibility reads its W^2 Ww footprint values from LDS).
+PSF applies/s is the sustained rate of back-to-back batch-8 applies;
+"psf_apply_4096" times the apply at the MeerKAT-like channel shape (16 x 4096^2,
+8192^2 kernels), the HBM-bound size.  "meerkat_like" is the multi-channel
+(de)gridding with the w-planes derived from eps, "meerkat_like_stated_wplanes" the
+same with the 32 planes the workload states, each with its HBM fractions.
+"served" runs the served mix for 60 s of a Poisson trace at 200 req/s (FP32
+continuous batching on 4 streams, with the device overlap of their launches),
+replays it unbatched and serially on the plain FP64 form, then sweeps the rate
+towards saturation.
 "reduced_psf" measures the PSF cut to |offset| <= h on the n + h padded grid:
 applies/s, accuracy against the exact R^+ N^-1 R, and the major cycles of the
 major/minor scheme it needs.  "mgvi" times the MGVI metric apply, a draw and a
@@ -42,6 +54,8 @@ sys.path.insert(0, ROOT)
 METRIC = "vis/s (de)gridding at eps=1e-5; PSF-conv R^dagger N^-1 R applies/s; p99 latency"
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3  # dense FP32 matrix-core peak of the MI355X
+# LDS: 128 bytes per clock per CU, 256 CUs at 2.4 GHz
+LDS_PEAK_GBS = 128 * 256 * 2.4
 PSF_APPLY_REPS = 20
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "grid_traffic.txt")
 
@@ -108,7 +122,69 @@ def algorithmic_bytes(name, info, n_vis, n_row, B_conv, nx, ny):
     return None
 
 
-def scale_workload(api, torch, steps=3):
+def call_bytes(op, info, n_vis_per_chan, n_row, nx, ny, n_chan=1):
+    """Bytes a whole (de)gridding call must move (FP32): the image, every w-plane
+    grid written once by its FFT and read once, the visibilities (and weights for
+    gridding) and uvw, per channel."""
+    per = 4 * nx * ny + info["n_planes"] * 2 * 8 * info["nu"] * info["nv"] + 8 * n_vis_per_chan + 24 * n_row
+    if op == "grid":
+        per += 4 * n_vis_per_chan
+    return n_chan * per
+
+
+def psf_apply_bytes(n, B, n_chan=1):
+    """Bytes of a batch-B PSF-convolution apply per channel kernel (FP32): x and y
+    (4 N^2 each per image) and the real half-spectrum kernel K_R, 4 2N (N + 1),
+    read once per call: (8 + 8/B) N^2 per image."""
+    return n_chan * (B * 8 * n * n + 4 * 2 * n * (n + 1))
+
+
+def hbm_entry(name, byts, ms):
+    ach = byts / (ms * 1e-3) / 1e9
+    return {"kernel": name, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "bytes_per_launch": int(byts), "avg_launch_ms": round(ms, 5)}
+
+
+def psf_apply_4096(api, torch, n=4096, n_chan=16, reps=5):
+    """The PSF-convolution apply at the MeerKAT-like channel shape (4096^2 per
+    channel, per-channel 8192^2 kernels, 16 channels, B = 1): the HBM-bound size.
+    Kernel values do not change the work; they are random positive numbers."""
+    g = torch.Generator(device="cuda").manual_seed(12)
+    K = torch.rand((n_chan, 2 * n, n + 1), device="cuda", generator=g) + 0.5
+    psf = api.PSF.from_kernels(K)
+    del K
+    x = torch.rand((1, n_chan, n, n), device="cuda", generator=g)
+    y = api.apply_RNR_approx(psf, x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        api.apply_RNR_approx(psf, x, out=y)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    api.profile_reset()
+    api.profile_enable(True)
+    for _ in range(reps):
+        api.apply_RNR_approx(psf, x, out=y)
+    torch.cuda.synchronize()
+    api.profile_enable(False)
+    kern = {}
+    for kname in ("psfconv_rows_r2c", "psfconv_cols", "psfconv_rows_c2r"):
+        cnt, tot = api.profile_query(kname)
+        if cnt:
+            kern[kname] = round(tot / cnt, 4)
+    byts = psf_apply_bytes(n, 1, n_chan)
+    res = {"workload": f"{n_chan} channels x {n}x{n}, per-channel {2 * n}x{2 * n} kernels, B = 1, FP32",
+           "call_ms": round(ms, 4), "applies_per_s": round(n_chan / (ms * 1e-3), 1), "kernels_ms": kern,
+           "hbm": hbm_entry("psf_apply_call_4096", byts, ms),
+           "two_pass_bytes": int(byts + n_chan * 32 * n * n)}
+    del psf, x, y
+    torch.cuda.empty_cache()
+    return res
+
+
+def scale_workload(api, torch, steps=3, n_wplanes=0):
     """(De)gridding on the MeerKAT-like multi-channel workload (7,257,600 rows x 16
     channels = 116,121,600 visibilities, 4096 x 4096 per channel, FP32, eps 1e-5):
     the HBM-bound regime at the paper's data scale."""
@@ -118,7 +194,7 @@ def scale_workload(api, torch, steps=3):
     obs = make_config(3, with_sky=False)
     t_gen = time.time() - t0
     t0 = time.time()
-    plan = api.Plan(obs.uvw, obs.freq, obs.nx, obs.ny, obs.dx, obs.dy, eps=1e-5)
+    plan = api.Plan(obs.uvw, obs.freq, obs.nx, obs.ny, obs.dx, obs.dy, eps=1e-5, n_wplanes=n_wplanes)
     torch.cuda.synchronize()
     t_plan = time.time() - t0
     info = plan.info
@@ -141,9 +217,15 @@ def scale_workload(api, torch, steps=3):
     gr = e[1].elapsed_time(e[2]) / steps
     n_vis = obs.n_row * obs.n_chan
     res = {"workload": f"MeerKAT-like: {obs.n_row} rows x {obs.n_chan} channels, {obs.nx}x{obs.ny} per channel, "
-                       f"eps=1e-5, FP32", "n_vis": n_vis, "support": info["support"], "n_planes": info["n_planes"],
+                       f"eps=1e-5, FP32, " + (f"{n_wplanes} w-planes (as stated)" if n_wplanes else
+                                              "w-planes derived from eps"),
+           "n_vis": n_vis, "support": info["support"], "n_planes": info["n_planes"],
            "degrid_ms": dg, "grid_ms": gr, "vis_per_s": 2 * n_vis / ((dg + gr) * 1e-3),
-           "plan_create_s": t_plan, "inputs_generated_s": t_gen}
+           "plan_create_s": t_plan, "inputs_generated_s": t_gen,
+           "hbm": [hbm_entry("degrid_call", call_bytes("degrid", info, obs.n_row, obs.n_row, obs.nx, obs.ny,
+                                                       obs.n_chan), dg),
+                   hbm_entry("grid_call", call_bytes("grid", info, obs.n_row, obs.n_row, obs.nx, obs.ny,
+                                                     obs.n_chan), gr)]}
     del plan, sky, w, vis, img
     torch.cuda.empty_cache()
     return res
@@ -289,27 +371,35 @@ def build_served_jobs(api, torch, n_jobs, fp64):
     return jobs
 
 
-def served_workload(api, torch, seconds, rate, n_jobs, fp64_requests):
+def served_workload(api, torch, seconds, rate, n_jobs, fp64_requests, sweep_rates=(), sweep_requests=2000):
     """p50/p99 of the served mix (FP32, continuous batching, 4 streams) against the
-    same trace replayed unbatched and serially on the plain FP64 form."""
-    from paper_2406_09144_amd.serving import GpuExecutor, Server, latency_stats, make_trace
+    same trace replayed unbatched and serially on the plain FP64 form; the device
+    intervals of the FP32 launches give their overlap across streams; then a rate
+    sweep towards saturation."""
+    from paper_2406_09144_amd.serving import GpuExecutor, Server, latency_stats, make_trace, overlap_stats
     t0 = time.time()
     jobs = build_served_jobs(api, torch, n_jobs, fp64=False)
     log(f"[bench] served jobs built in {time.time() - t0:.1f}s")
     trace = make_trace(len(jobs), rate, seconds)
-    ex = GpuExecutor(jobs, n_slots=4)
+    ex = GpuExecutor(jobs, n_slots=4, timeline=True)
     srv = Server(ex, n_slots=4, hbm_budget=64 << 30, max_batch=8)
     out = srv.run(trace, realtime=True)
     torch.cuda.synchronize()
     st = latency_stats(out)
     st["launches"] = len(srv.launches)
     st["peak_scratch_GB"] = srv.peak_bytes / 2 ** 30
+    iv = ex.timeline_intervals()
+    st["device"] = {k: (round(v, 3) if isinstance(v, float) else v)
+                    for k, v in overlap_stats([(a, b) for _, _, a, b in iv]).items()}
+    st["device"]["busy_fraction"] = round(st["device"]["busy_ms"] / (seconds * 1e3), 4)
+    st["coalesced_requests_per_launch"] = round(sum(n for _, _, n, _, _ in srv.launches) / max(1, len(srv.launches)), 3)
     st["per_op"] = {op: {k: round(v, 3) for k, v in latency_stats([r for r in out if r.op == op]).items()
                          if k in ("n", "p50_ms", "p99_ms")}
                     for op in sorted({r.op for r in out})}
     log(f"[bench] served FP32: {json.dumps(st)}")
     res = {"fp32_batched": st, "rate_hz": rate, "seconds": seconds, "n_jobs": n_jobs}
-    del ex, srv, jobs
+    del ex, srv
+    jobs64 = None
     if fp64_requests >= 0:
         jobs64 = build_served_jobs(api, torch, n_jobs, fp64=True)
         trace64 = make_trace(len(jobs64), rate, seconds)
@@ -322,7 +412,30 @@ def served_workload(api, torch, seconds, rate, n_jobs, fp64_requests):
         st64 = latency_stats(out64)
         log(f"[bench] served FP64 unbatched serial: {json.dumps(st64)}")
         res["fp64_unbatched_serial"] = st64
-        del ex64, srv64, jobs64
+        del ex64, srv64
+    # rate sweep to saturation: the same mix at higher Poisson rates, a fixed
+    # number of requests per point, FP32 continuous batching against the plain
+    # FP64 form served unbatched and serially
+    sweep = []
+    for r_hz in sweep_rates:
+        tr = make_trace(len(jobs), r_hz, sweep_requests / r_hz, seed=240609149)
+        ex = GpuExecutor(jobs, n_slots=4)
+        srv = Server(ex, n_slots=4, hbm_budget=64 << 30, max_batch=8)
+        o32 = srv.run(tr, realtime=True)
+        torch.cuda.synchronize()
+        s32 = latency_stats(o32)
+        point = {"rate_hz": r_hz, "fp32_batched": {k: round(v, 3) for k, v in s32.items()}}
+        if jobs64 is not None:
+            tr = make_trace(len(jobs64), r_hz, sweep_requests / r_hz, seed=240609149)
+            ex = GpuExecutor(jobs64, n_slots=1)
+            srv = Server(ex, n_slots=1, hbm_budget=64 << 30, max_batch=1)
+            o64 = srv.run(tr, realtime=True)
+            torch.cuda.synchronize()
+            point["fp64_unbatched_serial"] = {k: round(v, 3) for k, v in latency_stats(o64).items()}
+        log(f"[bench] served sweep: {json.dumps(point)}")
+        sweep.append(point)
+    res["rate_sweep"] = sweep
+    res["sweep_requests_per_point"] = sweep_requests
     return res
 
 
@@ -334,8 +447,13 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=32768,
                     help="visibilities of the oracle CPU-baseline sample (0 disables)")
     ap.add_argument("--fp64-steps", type=int, default=3, help="timed (de)grid passes of the plain FP64 form")
-    ap.add_argument("--serve-seconds", type=float, default=2.0, help="served-mix trace length (0 disables)")
+    ap.add_argument("--serve-seconds", type=float, default=60.0, help="served-mix trace length (0 disables)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-sweep", type=str, default="1000,3000,10000",
+                    help="Poisson rates (req/s) of the saturation sweep, comma-separated ('' disables)")
+    ap.add_argument("--serve-sweep-requests", type=int, default=2000, help="requests per sweep point")
+    ap.add_argument("--psf4096", type=int, default=1,
+                    help="time the PSF apply at 16 x 4096^2 with 8192^2 kernels (0 disables)")
     ap.add_argument("--serve-jobs", type=int, default=16)
     ap.add_argument("--serve-fp64-requests", type=int, default=0,
                     help="requests of the FP64 replay (0: the whole trace, -1: skip it)")
@@ -343,6 +461,8 @@ def main():
                     help="only run 5 plain copies of this many bytes (counter calibration)")
     ap.add_argument("--scale-steps", type=int, default=2,
                     help="timed (de)grid passes of the MeerKAT-like workload (0 disables)")
+    ap.add_argument("--scale-wplanes", type=int, default=32,
+                    help="w-planes of the MeerKAT-like workload as stated (0: derive from eps only)")
     ap.add_argument("--reduced-psf", type=int, default=1,
                     help="measure the reduced-PSF-support trade-off (0 disables)")
     ap.add_argument("--n", type=int, default=512)
@@ -486,6 +606,22 @@ def main():
             roof_hbm.append({"kernel": kname, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": round(ach / HBM_PEAK_GBS, 4), "bytes_per_launch": int(byts),
                              "avg_launch_ms": round(kern[kname]["avg_ms"], 5)})
+    # whole calls on the method's bytes (every w-plane written once by its FFT and
+    # read once, image, visibilities, weights, uvw)
+    roof_hbm.append(hbm_entry("degrid_call", call_bytes("degrid", info, n_vis, obs.n_row, n, n), comp["degrid"]))
+    roof_hbm.append(hbm_entry("grid_call", call_bytes("grid", info, n_vis, obs.n_row, n, n), comp["grid"]))
+    # the degridding kernel against the LDS: every visibility reads its W^2 Ww
+    # complex footprint values from the LDS tile, and every item writes its planes'
+    # tiles (halo included) once
+    lds = None
+    if "degrid" in kern:
+        W, Ww = info["support"], info["w_support"]
+        ts = info["tile"] + W - 1
+        lds_bytes = n_vis * W * W * Ww * 8 + info["n_workitems"] * Ww * ts * ts * 8
+        ach = lds_bytes / (kern["degrid"]["avg_ms"] * 1e-3) / 1e9
+        lds = {"kernel": "degrid", "bound": "lds", "achieved": round(ach, 1), "peak": round(LDS_PEAK_GBS, 1),
+               "unit": "GB/s", "frac": round(ach / LDS_PEAK_GBS, 4), "bytes_per_launch": int(lds_bytes),
+               "avg_launch_ms": round(kern["degrid"]["avg_ms"], 5)}
     log("[bench] per-kernel: " + json.dumps({k: round(v["avg_ms"], 4) for k, v in kern.items()}))
 
     # sustained PSF-convolution applies (batch 8, back to back), then the same
@@ -498,6 +634,7 @@ def main():
     e1.record()
     torch.cuda.synchronize()
     psf_ms = e0.elapsed_time(e1) / PSF_APPLY_REPS
+    roof_hbm.append(hbm_entry("psf_apply_call_b8", psf_apply_bytes(n, 8), psf_ms))
     api.profile_reset()
     api.profile_enable(True)
     for _ in range(PSF_APPLY_REPS):
@@ -533,10 +670,17 @@ def main():
                 "support": plan64.info["support"], "n_planes": plan64.info["n_planes"]}
         del plan64
 
-    scale = None
+    scale = scale32 = None
     if args.scale_steps > 0:
         scale = scale_workload(api, torch, args.scale_steps)
         log(f"[bench] MeerKAT-like: {json.dumps(scale)}")
+        if args.scale_wplanes > 0:
+            scale32 = scale_workload(api, torch, args.scale_steps, n_wplanes=args.scale_wplanes)
+            log(f"[bench] MeerKAT-like, {args.scale_wplanes} planes: {json.dumps(scale32)}")
+    psf4096 = None
+    if args.psf4096:
+        psf4096 = psf_apply_4096(api, torch)
+        log(f"[bench] PSF apply 4096^2: {json.dumps(psf4096)}")
 
     reduced = None
     if args.reduced_psf:
@@ -551,8 +695,10 @@ def main():
 
     served = None
     if args.serve_seconds > 0:
+        rates = [float(r) for r in args.serve_sweep.split(",") if r.strip()]
         served = served_workload(api, torch, args.serve_seconds, args.serve_rate, args.serve_jobs,
-                                 args.serve_fp64_requests)
+                                 args.serve_fp64_requests, sweep_rates=rates,
+                                 sweep_requests=args.serve_sweep_requests)
 
     cpu = None
     if args.cpu_sample > 0:
@@ -585,6 +731,8 @@ def main():
             "cg50_ms": comp["cg50"], "plan_create_s": t_plan, "make_psf_s": t_psf,
             "fp64_plain_form": fp64,
             "meerkat_like": scale,
+            "meerkat_like_stated_wplanes": scale32,
+            "psf_apply_4096": psf4096,
             "reduced_psf": reduced,
             "mgvi": mgvi,
             "taylor_w": taylor,
@@ -593,6 +741,7 @@ def main():
         "kernels_ms": {k: round(v["avg_ms"], 5) for k, v in kern.items()},
         "roofline": roof,
         "roofline_hbm": roof_hbm,
+        "roofline_lds": lds,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -226,9 +226,12 @@ class ServedJob:
 
 
 class GpuExecutor:
-    """Launches batches through libfrmi on a pool of streams (default priority)."""
+    """Launches batches through libfrmi on a pool of streams (default priority).
+    With timeline=True every launch is bracketed by timing events on its stream,
+    so that the device intervals of the launches (and their overlap across
+    streams) can be read back after the run (`timeline_intervals`)."""
 
-    def __init__(self, jobs, n_slots=4, keep_outputs=False):
+    def __init__(self, jobs, n_slots=4, keep_outputs=False, timeline=False):
         import torch
         from . import api
         self.api = api
@@ -237,6 +240,12 @@ class GpuExecutor:
         self.streams = [torch.cuda.Stream() for _ in range(n_slots)]
         self.keep = keep_outputs
         self.results = {}
+        self.timeline = [] if timeline else None
+        self._t_ref = None
+        if timeline:
+            torch.cuda.synchronize()
+            self._t_ref = torch.cuda.Event(enable_timing=True)
+            self._t_ref.record()
         from ._lib import FR_OP_CG, FR_OP_DEGRID, FR_OP_GRID, FR_OP_LIK_FAST, FR_OP_RNR_APPROX
         self.opcode = {"psf_apply": FR_OP_RNR_APPROX, "degrid": FR_OP_DEGRID, "grid": FR_OP_GRID,
                        "lik_fast": FR_OP_LIK_FAST, "cg20": FR_OP_CG}
@@ -259,6 +268,9 @@ class GpuExecutor:
         st = self.streams[slot]
         st.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(st):
+            if self.timeline is not None:
+                e_start = torch.cuda.Event(enable_timing=True)
+                e_start.record(st)
             if op == "psf_apply":
                 x = torch.stack([self._input(J.images, r, k) for r in reqs for k in range(r.size)])
                 y = api.apply_RNR_approx(J.psf, x, stream=st)
@@ -275,8 +287,13 @@ class GpuExecutor:
                 x, hist, it = api.cg_solve(self._input(J.images, reqs[0], 0), psf=J.psf, inv_power=J.inv_power,
                                            maxiter=20, stream=st)
                 outs = [x]
-            ev = torch.cuda.Event()
-            ev.record(st)
+            if self.timeline is not None:
+                ev = torch.cuda.Event(enable_timing=True)
+                ev.record(st)
+                self.timeline.append((slot, op, e_start, ev))
+            else:
+                ev = torch.cuda.Event()
+                ev.record(st)
         if self.keep:
             for r, o in zip(reqs, outs):
                 self.results[r.rid] = o
@@ -292,3 +309,30 @@ class GpuExecutor:
 
     def done(self, handle):
         return handle[0].query()
+
+    def timeline_intervals(self):
+        """(slot, op, start_ms, end_ms) of every launch, device time from the
+        executor's creation (call after the stream work has finished)."""
+        self.torch.cuda.synchronize()
+        return [(slot, op, self._t_ref.elapsed_time(a), self._t_ref.elapsed_time(b))
+                for slot, op, a, b in self.timeline]
+
+
+def overlap_stats(intervals):
+    """Device-side concurrency of launch intervals (start, end) on several streams:
+    the summed launch time, the time at least one launch was running, their ratio
+    (> 1 when launches of different streams ran together) and the largest number
+    running at once."""
+    if not intervals:
+        return {"launches": 0}
+    ev = sorted([(a, 1) for a, b in intervals] + [(b, -1) for a, b in intervals])
+    busy, cur, peak, last = 0.0, 0, 0, None
+    for t, d in ev:
+        if cur > 0 and last is not None:
+            busy += t - last
+        cur += d
+        peak = max(peak, cur)
+        last = t
+    total = sum(b - a for a, b in intervals)
+    return {"launches": len(intervals), "launch_ms_sum": total, "busy_ms": busy,
+            "concurrency": total / busy if busy > 0 else float("nan"), "max_concurrent": peak}

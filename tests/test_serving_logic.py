@@ -130,3 +130,14 @@ def test_cancel_from_another_thread():
     out = srv.run(trace, realtime=True)
     launched = [rid for _, _, rids, _, _ in ex.log for rid in rids]
     assert launched == [0, 1] and out[2].cancelled
+
+
+def test_overlap_stats_of_launch_intervals():
+    from paper_2406_09144_amd.serving import overlap_stats
+    st = overlap_stats([(0.0, 2.0), (1.0, 3.0), (5.0, 6.0)])
+    assert st["launches"] == 3 and st["max_concurrent"] == 2
+    assert abs(st["launch_ms_sum"] - 5.0) < 1e-12 and abs(st["busy_ms"] - 4.0) < 1e-12
+    assert abs(st["concurrency"] - 1.25) < 1e-12
+    # serial launches: no overlap
+    st = overlap_stats([(0.0, 1.0), (1.0, 2.0)])
+    assert st["max_concurrent"] == 1 and abs(st["concurrency"] - 1.0) < 1e-12
