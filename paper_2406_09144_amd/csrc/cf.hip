@@ -25,6 +25,7 @@
 #include <cmath>
 #include <numeric>
 
+#include "cfbins.h"
 #include "conv.h"
 #include "elementwise.h"
 #include "objects.h"
@@ -142,44 +143,23 @@ template <typename T> struct CFScatter {
 };
 
 void cf_build(fr_cf *cf) {
-    const int64_t nx = cf->nx, ny = cf->ny, h = ny / 2 + 1;
-    // |k|^2 in integer frequency units over the full grid (numpy fftfreq order)
-    auto fk = [](int64_t i, int64_t n) { return i < (n + 1) / 2 ? i : i - n; };
-    std::vector<int64_t> k2full((size_t)(nx * ny));
-    for (int64_t i = 0; i < nx; ++i)
-        for (int64_t j = 0; j < ny; ++j) {
-            const int64_t a = fk(i, nx), b = fk(j, ny);
-            k2full[(size_t)(i * ny + j)] = a * a + b * b;
-        }
-    std::vector<int64_t> vals(k2full);
-    std::sort(vals.begin(), vals.end());
-    vals.erase(std::unique(vals.begin(), vals.end()), vals.end());
-    FR_REQUIRE(!vals.empty() && vals[0] == 0 && vals.size() >= 2, "grid too small for the amplitude model");
-    vals.erase(vals.begin());  // k = 0 is the zero mode
-    const int64_t J = (int64_t)vals.size();
-    auto bin_of = [&](int64_t k2) -> int32_t {
-        if (k2 == 0) return -1;
-        return (int32_t)(std::lower_bound(vals.begin(), vals.end(), k2) - vals.begin());
-    };
-    std::vector<double> mult((size_t)J, 0.0), t((size_t)J), d((size_t)J);
-    for (int64_t k2 : k2full)
-        if (k2) mult[(size_t)bin_of(k2)] += 1.0;
-    for (int64_t j = 0; j < J; ++j) {
-        t[(size_t)j] = 0.5 * std::log((double)vals[(size_t)j]);
-        d[(size_t)j] = j ? t[(size_t)j] - t[(size_t)(j - 1)] : 0.0;
+    CFBins b;
+    try {
+        b = cf_bins_host(cf->nx, cf->ny);
+    } catch (const std::invalid_argument &e) {
+        throw Error(FR_EINVAL, e.what());
     }
-    std::vector<int32_t> bin((size_t)(nx * h));
-    for (int64_t i = 0; i < nx; ++i)
-        for (int64_t j = 0; j < h; ++j) bin[(size_t)(i * h + j)] = bin_of(k2full[(size_t)(i * ny + j)]);
+    const int64_t J = (int64_t)b.k2.size();
+    FR_REQUIRE(J >= 1, "grid too small for the amplitude model");
     cf->J = J;
     cf->t = DevBuf((size_t)J * 8);
     cf->d = DevBuf((size_t)J * 8);
     cf->mult = DevBuf((size_t)J * 8);
-    cf->bin = DevBuf(bin.size() * 4);
-    HIP_CHECK(hipMemcpy(cf->t.p, t.data(), cf->t.bytes, hipMemcpyHostToDevice));
-    HIP_CHECK(hipMemcpy(cf->d.p, d.data(), cf->d.bytes, hipMemcpyHostToDevice));
-    HIP_CHECK(hipMemcpy(cf->mult.p, mult.data(), cf->mult.bytes, hipMemcpyHostToDevice));
-    HIP_CHECK(hipMemcpy(cf->bin.p, bin.data(), cf->bin.bytes, hipMemcpyHostToDevice));
+    cf->bin = DevBuf(b.bin.size() * 4);
+    HIP_CHECK(hipMemcpy(cf->t.p, b.t.data(), cf->t.bytes, hipMemcpyHostToDevice));
+    HIP_CHECK(hipMemcpy(cf->d.p, b.d.data(), cf->d.bytes, hipMemcpyHostToDevice));
+    HIP_CHECK(hipMemcpy(cf->mult.p, b.mult.data(), cf->mult.bytes, hipMemcpyHostToDevice));
+    HIP_CHECK(hipMemcpy(cf->bin.p, b.bin.data(), cf->bin.bytes, hipMemcpyHostToDevice));
 }
 
 size_t cf_scratch(const fr_cf *cf) { return scratch_round((size_t)(3 * cf->J + 1) * 8); }
