@@ -194,7 +194,7 @@ __global__ __launch_bounds__(NTHR) void k_degrid(const WorkItem *__restrict__ wi
                                                  const uint32_t *__restrict__ r_cell, const T *__restrict__ r_du,
                                                  const T *__restrict__ r_dv, const T *__restrict__ r_dw,
                                                  const T *__restrict__ r_ph, const T *__restrict__ weight,
-                                                 c2<T> *__restrict__ vis) {
+                                                 c2<T> *__restrict__ vis, int sorted_out) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     c2<T> *tile = reinterpret_cast<c2<T> *>(smem_raw);
     constexpr int TS = kTile + W - 1;
@@ -290,6 +290,18 @@ __global__ __launch_bounds__(NTHR) void k_degrid(const WorkItem *__restrict__ wi
         if (!ok[k]) continue;
         const int64_t pos = it.start + threadIdx.x + k * NTHR;
         c2<T> v = acc[k];
+        if (sorted_out) {
+            // w times the interpolated plane values in record order, for gridding
+            // straight back (R^+ N^-1 R): the centring phase and the conjugation of
+            // w < 0 records cancel between R and R^+
+            if (weight) {
+                const T wt = weight[r_idx[pos] & 0x7fffffffu];
+                v.x *= wt;
+                v.y *= wt;
+            }
+            vis[pos] = v;
+            continue;
+        }
         if (!coplanar) {
             T s, c;
             sincos_cycles(-r_ph[pos], &s, &c);
@@ -369,7 +381,8 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial(const WorkItem *__restric
                                                        const T *__restrict__ r_du, const T *__restrict__ r_dv,
                                                        const T *__restrict__ r_dw, const T *__restrict__ r_ph,
                                                        const c2<T> *__restrict__ vis, const T *__restrict__ weight,
-                                                       const float *__restrict__ ybound_partials, int n_ybound) {
+                                                       const float *__restrict__ ybound_partials, int n_ybound,
+                                                       int sorted_in) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     long long *tile = reinterpret_cast<long long *>(smem_raw);  // [ppass][2][TS * TS]
     constexpr int TS = kTile + W - 1;
@@ -458,21 +471,28 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial(const WorkItem *__restric
             if (lane < nb) {
                 const int64_t pos = it.start + b0 + lane;
                 l_cell = (int)r_cell[pos];
-                const uint32_t id = r_idx[pos];
-                const uint32_t vi = id & 0x7fffffffu;
-                c2<T> y = vis ? vis[vi] : mk<T>(T(1), T(0));
-                if (weight) {
-                    const T wt = weight[vi];
-                    y.x *= wt;
-                    y.y *= wt;
+                c2<T> y;
+                if (sorted_in) {
+                    y = vis[pos];  // weighted values already in record order and frame
+                } else {
+                    const uint32_t id = r_idx[pos];
+                    const uint32_t vi = id & 0x7fffffffu;
+                    y = vis ? vis[vi] : mk<T>(T(1), T(0));
+                    if (weight) {
+                        const T wt = weight[vi];
+                        y.x *= wt;
+                        y.y *= wt;
+                    }
+                    if (id >> 31) y.y = -y.y;
                 }
-                if (id >> 31) y.y = -y.y;
                 l_xu = r_du[pos];
                 l_xv = r_dv[pos];
                 if (!coplanar) {
-                    T sn, cs;
-                    sincos_cycles(r_ph[pos], &sn, &cs);
-                    y = cmul<T>(y, mk<T>(cs, sn));
+                    if (!sorted_in) {
+                        T sn, cs;
+                        sincos_cycles(r_ph[pos], &sn, &cs);
+                        y = cmul<T>(y, mk<T>(cs, sn));
+                    }
                     const T xw = r_dw[pos];
 #pragma unroll
                     for (int p = 0; p < PR; ++p)
@@ -572,7 +592,7 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial_mfma(
     int coplanar, int taylor, const uint32_t *__restrict__ r_idx, const uint32_t *__restrict__ r_cell,
     const float *__restrict__ r_du, const float *__restrict__ r_dv, const float *__restrict__ r_dw,
     const float *__restrict__ r_ph, const c2<float> *__restrict__ vis, const float *__restrict__ weight,
-    const float *__restrict__ ybound_partials, int n_ybound) {
+    const float *__restrict__ ybound_partials, int n_ybound, int sorted_in) {
     static_assert(W <= 8, "one lane per 1-D kernel value of 8 visibilities");
     typedef float v4f __attribute__((ext_vector_type(4)));
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -657,21 +677,28 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial_mfma(
             if (lane < nb) {
                 const int64_t pos = it.start + b0 + lane;
                 l_cell = (int)r_cell[pos];
-                const uint32_t id = r_idx[pos];
-                const uint32_t vi = id & 0x7fffffffu;
-                c2<float> y = vis ? vis[vi] : mk<float>(1.0f, 0.0f);
-                if (weight) {
-                    const float wt = weight[vi];
-                    y.x *= wt;
-                    y.y *= wt;
+                c2<float> y;
+                if (sorted_in) {
+                    y = vis[pos];  // weighted values already in record order and frame
+                } else {
+                    const uint32_t id = r_idx[pos];
+                    const uint32_t vi = id & 0x7fffffffu;
+                    y = vis ? vis[vi] : mk<float>(1.0f, 0.0f);
+                    if (weight) {
+                        const float wt = weight[vi];
+                        y.x *= wt;
+                        y.y *= wt;
+                    }
+                    if (id >> 31) y.y = -y.y;
                 }
-                if (id >> 31) y.y = -y.y;
                 l_xu = r_du[pos];
                 l_xv = r_dv[pos];
                 if (!coplanar) {
-                    float sn, cs;
-                    sincos_cycles(r_ph[pos], &sn, &cs);
-                    y = cmul<float>(y, mk<float>(cs, sn));
+                    if (!sorted_in) {
+                        float sn, cs;
+                        sincos_cycles(r_ph[pos], &sn, &cs);
+                        y = cmul<float>(y, mk<float>(cs, sn));
+                    }
                     l_xw = r_dw[pos];
                 }
                 l_y = y;
@@ -1048,7 +1075,7 @@ template <typename T> constexpr int chunk() { return std::is_same<T, float>::val
 
 template <typename T, int W>
 void launch_degrid_w(const fr_plan *pl, const WorkItem *wis, int64_t nwi, const c2<T> *planes, const T *weight,
-                     c2<T> *vis, hipStream_t st) {
+                     c2<T> *vis, hipStream_t st, int sorted_out) {
     constexpr int TS = kTile + W - 1;
     const size_t lds = (size_t)TS * TS * sizeof(c2<T>);
     auto kern = k_degrid<T, W, chunk<T>(), 1>;
@@ -1057,13 +1084,13 @@ void launch_degrid_w(const fr_plan *pl, const WorkItem *wis, int64_t nwi, const 
     kern<<<dim3((unsigned)nwi), chunk<T>(), lds, st>>>(
         wis, planes, ilog2(pl->nu), ilog2(pl->nv), pl->Ww, (T)pl->beta, (T)pl->wbeta, pl->coplanar ? 1 : 0,
         pl->taylor ? 1 : 0, pl->r_idx.as<uint32_t>(), pl->r_cell.as<uint32_t>(), pl->r_du.as<T>(), pl->r_dv.as<T>(), pl->r_dw.as<T>(),
-        pl->r_ph.as<T>(), weight, vis);
+        pl->r_ph.as<T>(), weight, vis, sorted_out);
     LAUNCH_CHECK();
 }
 
 template <typename T, int W>
 void launch_grid_w(const fr_plan *pl, int64_t chan, c2<T> *planes, const c2<T> *vis, const T *weight,
-                   const float *ybound, int nbb, hipStream_t st) {
+                   const float *ybound, int nbb, hipStream_t st, int sorted_in) {
     constexpr int TS = kTile + W - 1;
     // FP64 and wide kernels hold more registers per lane: smaller groups, larger register share
     constexpr int NTHR = (sizeof(T) == 8 || W * W > 64) ? 512 : 1024;
@@ -1085,7 +1112,7 @@ void launch_grid_w(const fr_plan *pl, int64_t chan, c2<T> *planes, const c2<T> *
                     pl->gwi.as<WorkItem>() + i0, pl->gorder.as<int32_t>() + i0, partial.as<c2<T>>(), pl->Ww, ppass,
                     (T)pl->beta, (T)pl->wbeta, pl->coplanar ? 1 : 0, pl->taylor ? 1 : 0, pl->r_idx.as<uint32_t>(),
                     pl->r_cell.as<uint32_t>(), pl->r_du.as<T>(), pl->r_dv.as<T>(), pl->r_dw.as<T>(), pl->r_ph.as<T>(),
-                    vis, weight, ybound, nbb);
+                    vis, weight, ybound, nbb, sorted_in);
             };
             if constexpr (std::is_same<T, float>::value && W <= 8) {
                 // FP32, footprint <= 64 cells and runs of several records (an MFMA
@@ -1099,7 +1126,7 @@ void launch_grid_w(const fr_plan *pl, int64_t chan, c2<T> *planes, const c2<T> *
                         pl->gwi.as<WorkItem>() + i0, pl->gorder.as<int32_t>() + i0, partial.as<c2<T>>(), pl->Ww,
                         ppass, (T)pl->beta, (T)pl->wbeta, pl->coplanar ? 1 : 0, pl->taylor ? 1 : 0,
                         pl->r_idx.as<uint32_t>(), pl->r_cell.as<uint32_t>(), pl->r_du.as<T>(), pl->r_dv.as<T>(),
-                        pl->r_dw.as<T>(), pl->r_ph.as<T>(), vis, weight, ybound, nbb);
+                        pl->r_dw.as<T>(), pl->r_ph.as<T>(), vis, weight, ybound, nbb, sorted_in);
                 } else {
                     launch_vector();
                 }
@@ -1247,14 +1274,15 @@ void planes_to_image(const fr_plan *pl, const c2<T> *planes_c, const uint8_t *ac
 }
 
 template <typename T>
-void degrid(const fr_plan *pl, const T *img, c2<T> *vis, hipStream_t st, const T *weight) {
+void degrid(const fr_plan *pl, const T *img, c2<T> *vis, hipStream_t st, const T *weight, bool sorted_out) {
     Scratch planes(planes_bytes(pl), st);
     const WorkItem *wis = pl->wi.as<WorkItem>();
     for (int64_t c = 0; c < pl->n_chan; ++c) {
         image_to_planes<T>(pl, img + c * pl->nx * pl->ny, planes.as<c2<T>>(), st);
         const int64_t w0 = pl->wi_chan[c], w1 = pl->wi_chan[c + 1];
         if (w1 > w0) {
-#define FR_CALL_DEGRID(WW) launch_degrid_w<T, WW>(pl, wis + w0, w1 - w0, planes.as<c2<T>>(), weight, vis, st)
+#define FR_CALL_DEGRID(WW) \
+    launch_degrid_w<T, WW>(pl, wis + w0, w1 - w0, planes.as<c2<T>>(), weight, vis, st, sorted_out ? 1 : 0)
             FR_W_DISPATCH(pl->W, FR_CALL_DEGRID)
 #undef FR_CALL_DEGRID
         }
@@ -1262,7 +1290,7 @@ void degrid(const fr_plan *pl, const T *img, c2<T> *vis, hipStream_t st, const T
 }
 
 template <typename T>
-void grid(const fr_plan *pl, const c2<T> *vis, const T *weight, T *img, hipStream_t st) {
+void grid(const fr_plan *pl, const c2<T> *vis, const T *weight, T *img, hipStream_t st, bool sorted_in) {
     Scratch planes(planes_bytes(pl), st);
     // bound on every gridded contribution (sets the fixed-point scale of the tiles)
     const int nbb = vis_bound_blocks(pl->n_vis);
@@ -1272,7 +1300,8 @@ void grid(const fr_plan *pl, const c2<T> *vis, const T *weight, T *img, hipStrea
         LAUNCH_CHECK();
     }
     for (int64_t c = 0; c < pl->n_chan; ++c) {
-#define FR_CALL_GRID(WW) launch_grid_w<T, WW>(pl, c, planes.as<c2<T>>(), vis, weight, ybound.as<float>(), nbb, st)
+#define FR_CALL_GRID(WW) \
+    launch_grid_w<T, WW>(pl, c, planes.as<c2<T>>(), vis, weight, ybound.as<float>(), nbb, st, sorted_in ? 1 : 0)
         FR_W_DISPATCH(pl->W, FR_CALL_GRID)
 #undef FR_CALL_GRID
         planes_to_image<T>(pl, planes.as<c2<T>>(), pl->tile_active.as<uint8_t>() + c * pl->n_tiles,
@@ -1280,10 +1309,10 @@ void grid(const fr_plan *pl, const c2<T> *vis, const T *weight, T *img, hipStrea
     }
 }
 
-template void degrid<float>(const fr_plan *, const float *, float2 *, hipStream_t, const float *);
-template void degrid<double>(const fr_plan *, const double *, double2 *, hipStream_t, const double *);
-template void grid<float>(const fr_plan *, const float2 *, const float *, float *, hipStream_t);
-template void grid<double>(const fr_plan *, const double2 *, const double *, double *, hipStream_t);
+template void degrid<float>(const fr_plan *, const float *, float2 *, hipStream_t, const float *, bool);
+template void degrid<double>(const fr_plan *, const double *, double2 *, hipStream_t, const double *, bool);
+template void grid<float>(const fr_plan *, const float2 *, const float *, float *, hipStream_t, bool);
+template void grid<double>(const fr_plan *, const double2 *, const double *, double *, hipStream_t, bool);
 
 // ------------------------------------------------------------------ plan creation
 static double n_minus_1(double l, double m) {

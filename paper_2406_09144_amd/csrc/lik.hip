@@ -28,13 +28,16 @@ size_t lik_scratch(const fr_plan *pl, const fr_psf *psf, int mode, int64_t B, bo
     return per + std::max(body, prior ? scratch_round(n_all * rs) + yper : size_t(0));
 }
 
+// R^+ N^-1 R x: the degridded values of every record, times its weight, go back
+// to the spread in record order (coalesced stores and loads, no gathers; the
+// centring phase and the conjugation of w < 0 records cancel between R and R^+)
 template <typename T>
 void apply_rnr_exact(const fr_plan *pl, const T *weight, const T *x, T *y, int64_t B, hipStream_t st) {
     const int64_t n_img = pl->n_chan * pl->nx * pl->ny;
     Scratch vis((size_t)pl->n_vis * sizeof(c2<T>), st);
     for (int64_t b = 0; b < B; ++b) {
-        degrid<T>(pl, x + b * n_img, vis.as<c2<T>>(), st);
-        grid<T>(pl, vis.as<c2<T>>(), weight, y + b * n_img, st);
+        degrid<T>(pl, x + b * n_img, vis.as<c2<T>>(), st, weight, true);
+        grid<T>(pl, vis.as<c2<T>>(), nullptr, y + b * n_img, st, true);
     }
 }
 

@@ -106,11 +106,15 @@ size_t periodic_conv_scratch(int64_t n_img, int64_t nx, int64_t ny, bool fp64);
 size_t rnr_exact_scratch(const fr_plan *pl);
 size_t lik_scratch(const fr_plan *pl, const fr_psf *psf, int mode, int64_t B, bool prior);
 size_t cg_scratch(const fr_plan *pl, const fr_psf *psf, bool prior);
-// vis = R img, or diag(weight) R img when weight is given
+// vis = R img, or diag(weight) R img when weight is given.  sorted_out: write, in
+// the plan's record order, weight times the interpolated plane values without the
+// centring phase and conjugation (what grid with sorted_in takes back: the two
+// cancel between R and R^+), for R^+ N^-1 R without visibilities in input order.
 template <typename T>
-void degrid(const fr_plan *pl, const T *img, c2<T> *vis, hipStream_t st, const T *weight = nullptr);
+void degrid(const fr_plan *pl, const T *img, c2<T> *vis, hipStream_t st, const T *weight = nullptr,
+            bool sorted_out = false);
 template <typename T>
-void grid(const fr_plan *pl, const c2<T> *vis, const T *weight, T *img, hipStream_t st);
+void grid(const fr_plan *pl, const c2<T> *vis, const T *weight, T *img, hipStream_t st, bool sorted_in = false);
 
 // psf.hip
 template <typename T>
