@@ -1625,11 +1625,8 @@ void plan_build(fr_plan *pl, const double *uvw_m, const double *freq_hz) {
         pl->dw = 1;
         pl->yc = 0;
     } else {
-        pl->Ww = pl->W;
-        pl->wbeta = pl->beta;
         const double h = -ymin / 2;  // (n - 1) - yc lies in [-h, h]
         pl->yc = ymin / 2;
-        double dw = 1.0 / (4.0 * h);  // sigma_w = 2: dw h = 1/4
         // With w0 = wmin - (Ww/2 - 1 + delta) dw, the first plane a visibility
         // touches is ceil((w - wmin)/dw + delta - 1), so delta in (0, 1] can be
         // chosen to centre the w-range inside the fewest first-plane slots:
@@ -1645,6 +1642,31 @@ void plan_build(fr_plan *pl, const double *uvw_m, const double *freq_hz) {
                 n_p0 = (int)cf + 1;
             }
         };
+        // The kernel along w: support Ww, shape and plane spacing dw = xmax / h
+        // chosen together for the fewest planes n_p0 + Ww - 1 whose aliasing bound
+        // fits the accuracy the uv kernel leaves (then the narrower kernel, then the
+        // coarser grid); the 2x-oversampled kernel of the uv support always fits.
+        const double eps_w = pl->eps - 2 * kESAliasBound[pl->W];
+        int best_npl = INT32_MAX, best_ww = pl->W, best_x = 0;
+        for (int ww = 4; ww <= pl->W; ++ww)
+            for (int xi = 0; xi < 5; ++xi) {
+                if (kESwTable[ww][xi].bound > eps_w && !(ww == pl->W && xi == 0)) continue;
+                double dl = 1.0;
+                int p0 = 1;
+                layout(kESwXmax[xi] / h, dl, p0);
+                const int npl_c = p0 + ww - 1;
+                if (npl_c < best_npl || (npl_c == best_npl && ww < best_ww)) {
+                    best_npl = npl_c;
+                    best_ww = ww;
+                    best_x = xi;
+                }
+            }
+        pl->Ww = best_ww;
+        pl->wbeta = best_ww == pl->W && best_x == 0 ? pl->beta : kESwTable[best_ww][best_x].beta_over_w * best_ww;
+        pl->w_xmax = kESwXmax[best_x];
+        pl->eps_bound = 2 * kESAliasBound[pl->W] +
+                        (best_ww == pl->W && best_x == 0 ? kESAliasBound[pl->W] : kESwTable[best_ww][best_x].bound);
+        double dw = pl->w_xmax / h;
         double delta = 1.0;
         int n_p0 = 1;
         layout(dw, delta, n_p0);
@@ -1689,12 +1711,14 @@ void plan_build(fr_plan *pl, const double *uvw_m, const double *freq_hz) {
         }
     }
     ESKernel kw(pl->Ww > 1 && !pl->taylor ? pl->Ww : 4, pl->Ww > 1 && !pl->taylor ? pl->wbeta : 9.2);
+    // the w correction is evaluated at xi = dw t, |xi| <= h dw (<= w_xmax, less when
+    // extra planes refined the grid)
     // --- per-pixel factors
     std::vector<double> cu(nx), cv(ny);
     for (int64_t i = 0; i < nx; ++i) cu[i] = 1.0 / kuv.psi_hat((double)(i - nx / 2) / (double)pl->nu);
     for (int64_t j = 0; j < ny; ++j) cv[j] = 1.0 / kuv.psi_hat((double)(j - ny / 2) / (double)pl->nv);
     std::vector<double> fac(nx * ny), tpix(nx * ny, 0.0), tpix_w(nx * ny, 0.0), nfac(nx * ny);
-    Cheb psiw([&](double t) { return kw.psi_hat(t); }, 0.25, 40);
+    Cheb psiw([&](double t) { return kw.psi_hat(t); }, pl->w_xmax, 40);
     for (int64_t i = 0; i < nx; ++i) {
         const double l = (double)(i - nx / 2) * pl->dx_;
         for (int64_t j = 0; j < ny; ++j) {

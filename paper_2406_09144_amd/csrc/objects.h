@@ -40,6 +40,7 @@ struct fr_plan {
     double beta = 0;    // uv kernel shape
     int Ww = 1;         // w kernel support (planes)
     double wbeta = 0;
+    double w_xmax = 0.25;  // bound of the w-image coordinate dw |t| the kernel was chosen for
     int n_planes = 1;
     double w0 = 0, dw = 1, yc = 0;  // plane p at w0 + p dw; n - 1 measured from yc
     bool want_taylor = false;       // FR_W_TAYLOR requested

@@ -4,7 +4,8 @@
 //     exactly; the Fourier transform psi_hat(0) equals the integral of the kernel
 //     by a fine midpoint rule; psi_hat is even; the aliasing bound of W = 5..8
 //     with beta = 2.30 W matches the table the plans use (computed once with 3000
-//     nodes) to 5%; the support chosen for an epsilon meets it;
+//     nodes) to 5%; the support chosen for an epsilon meets it; the w-kernel
+//     table (finer w-grids) spot-checked the same way, its shapes local minima;
 //   * the amplitude-model bins: every non-zero frequency of the full grid counted
 //     once, the half-spectrum map pointing at the bin of its |k|^2, ascending
 //     log-frequencies with steps that sum to the span.
@@ -54,6 +55,21 @@ static void check_eskernel() {
         const double b = e.alias_bound(0.25);
         CHECK(std::fabs(b / frmi::kESAliasBound[W] - 1.0) < 0.05, "alias bound W=%d: %g vs table %g", W, b,
               frmi::kESAliasBound[W]);
+    }
+    // the w-kernel table: spot checks with 3000 nodes (the shape and the bound)
+    const int wws[3] = {5, 6, 8};
+    const int xis[3] = {4, 2, 1};
+    for (int q = 0; q < 3; ++q) {
+        const int Ww = wws[q], xi = xis[q];
+        const frmi::ESwEntry e = frmi::kESwTable[Ww][xi];
+        frmi::ESKernel k(Ww, e.beta_over_w * Ww, 3000);
+        const double b = k.alias_bound(frmi::kESwXmax[xi]);
+        CHECK(std::fabs(b / e.bound - 1.0) < 0.05, "w table Ww=%d xmax=%g: %g vs %g", Ww, frmi::kESwXmax[xi], b,
+              e.bound);
+        // the tabulated shape is no worse than its neighbours on the beta grid
+        frmi::ESKernel lo(Ww, (e.beta_over_w - 0.1) * Ww, 3000), hi(Ww, (e.beta_over_w + 0.1) * Ww, 3000);
+        CHECK(lo.alias_bound(frmi::kESwXmax[xi]) >= 0.99 * b && hi.alias_bound(frmi::kESwXmax[xi]) >= 0.99 * b,
+              "w table shape Ww=%d xmax=%g is not a minimum", Ww, frmi::kESwXmax[xi]);
     }
     for (double eps : {1e-3, 1e-5, 1e-8, 1e-11}) {
         const int W = frmi::es_support(eps, 2);
