@@ -67,8 +67,11 @@ enum fr_plan_flags {
     FR_FP64 = 1,        /* double precision buffers and arithmetic */
     FR_DIVIDE_BY_N = 2, /* include the 1/n factor of the w-term C(l, w) (Sec. 2) */
     FR_COPLANAR = 4,    /* treat every w as 0 (the paper's coplanar case, Sec. 3.3.2) */
-    FR_W_TAYLOR = 8     /* expand the w-term in a Taylor series when that needs fewer
+    FR_W_TAYLOR = 8,    /* expand the w-term in a Taylor series when that needs fewer
                            planes than improved w-stacking at this epsilon */
+    FR_VECTOR_SPREAD = 16 /* grid with the vector-unit spread even where the plan
+                             would take the matrix-core one (FP32, W <= 8, runs of
+                             4 or more records on average); same tiles, same bound */
 };
 
 enum fr_lik_mode { FR_LIK_EXACT = 0, FR_LIK_FAST = 1 };
@@ -129,7 +132,7 @@ void fr_ctx_destroy(fr_ctx *ctx);
  *   dx, dy   pixel sizes (radians, > 0); the field must satisfy l^2 + m^2 < 1
  *   epsilon  requested relative L2 accuracy of R and R^+ against the direct
  *            sums, in [1e-14, 1e-1]; FP32 plans accept epsilon >= 1e-6
- *   flags    FR_FP64 | FR_DIVIDE_BY_N | FR_COPLANAR | FR_W_TAYLOR
+ *   flags    FR_FP64 | FR_DIVIDE_BY_N | FR_COPLANAR | FR_W_TAYLOR | FR_VECTOR_SPREAD
  *            FR_W_TAYLOR: with t = (n - 1) - yc in [-h, h] over the image, write
  *            exp(-2 pi i w t) = sum_j (2 pi w h)^j / j! (-i t / h)^j and keep the
  *            J + 1 terms whose truncation, (2 pi w_max h)^(J+1) / (J+1)!, is below

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfrmi.so")
 
 FR_OK, FR_EINVAL, FR_ENOMEM, FR_EHIP, FR_EUNSUPPORTED, FR_EBUSY = 0, -1, -2, -3, -4, -5
-FR_FP64, FR_DIVIDE_BY_N, FR_COPLANAR, FR_W_TAYLOR = 1, 2, 4, 8
+FR_FP64, FR_DIVIDE_BY_N, FR_COPLANAR, FR_W_TAYLOR, FR_VECTOR_SPREAD = 1, 2, 4, 8, 16
 FR_LIK_EXACT, FR_LIK_FAST = 0, 1
 FR_CONV_MUL, FR_CONV_DIV, FR_CONV_MUL_SQRT, FR_CONV_DIV_SQRT = 0, 1, 2, 3
 (FR_OP_DEGRID, FR_OP_GRID, FR_OP_RNR_APPROX, FR_OP_RNR_EXACT, FR_OP_LIK_EXACT,

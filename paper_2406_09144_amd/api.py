@@ -159,16 +159,18 @@ class Plan:
     uvw: host float64 [n_row, 3] metres; freq: host float64 [n_chan] Hz;
     nx, ny image size; dx, dy pixel sizes (radians); eps requested accuracy;
     w_taylor: expand the w-term in a Taylor series when that needs fewer planes
-    than improved w-stacking (FR_W_TAYLOR)."""
+    than improved w-stacking (FR_W_TAYLOR); vector_spread: grid on the vector units
+    even where the matrix-core spread applies (FR_VECTOR_SPREAD)."""
 
     def __init__(self, uvw, freq, nx, ny, dx, dy, eps=1e-5, fp64=False, divide_by_n=True,
-                 coplanar=False, n_wplanes=0, w_taylor=False, ctx=None, device=None):
+                 coplanar=False, n_wplanes=0, w_taylor=False, vector_spread=False, ctx=None, device=None):
         import numpy as np
         self.ctx = ctx or Context.get(device)
         uvw = np.ascontiguousarray(uvw, dtype=np.float64).reshape(-1, 3)
         freq = np.ascontiguousarray(np.atleast_1d(freq), dtype=np.float64)
         flags = (L.FR_FP64 if fp64 else 0) | (L.FR_DIVIDE_BY_N if divide_by_n else 0) | \
-            (L.FR_COPLANAR if coplanar else 0) | (L.FR_W_TAYLOR if w_taylor else 0)
+            (L.FR_COPLANAR if coplanar else 0) | (L.FR_W_TAYLOR if w_taylor else 0) | \
+            (L.FR_VECTOR_SPREAD if vector_spread else 0)
         h = ctypes.c_void_p()
         L.check(_lib().fr_plan_create(self.ctx.handle, uvw.ctypes.data_as(ctypes.c_void_p), uvw.shape[0],
                                       freq.ctypes.data_as(ctypes.c_void_p), freq.shape[0], int(nx), int(ny),

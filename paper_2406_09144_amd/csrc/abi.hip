@@ -280,7 +280,8 @@ int fr_plan_create(fr_ctx *ctx, const double *uvw_m, int64_t n_row, const double
     FR_REQUIRE(freq_hz, "freq_hz is NULL");
     FR_REQUIRE(is_pow2(nx) && is_pow2(ny) && nx >= 16 && ny >= 16 && nx <= 8192 && ny <= 8192,
                "nx, ny must be powers of two in [16, 8192]");
-    FR_REQUIRE((flags & ~(FR_FP64 | FR_DIVIDE_BY_N | FR_COPLANAR | FR_W_TAYLOR)) == 0, "unknown flag");
+    FR_REQUIRE((flags & ~(FR_FP64 | FR_DIVIDE_BY_N | FR_COPLANAR | FR_W_TAYLOR | FR_VECTOR_SPREAD)) == 0,
+               "unknown flag");
     const bool fp64 = flags & FR_FP64;
     FR_REQUIRE(!fp64 || (nx <= 4096 && ny <= 4096), "FP64 plans support nx, ny <= 4096");
     FR_REQUIRE(dx > 0 && dy > 0 && std::isfinite(dx) && std::isfinite(dy), "pixel sizes must be > 0");
@@ -309,6 +310,7 @@ int fr_plan_create(fr_ctx *ctx, const double *uvw_m, int64_t n_row, const double
     pl->divide_by_n = flags & FR_DIVIDE_BY_N;
     pl->coplanar = flags & FR_COPLANAR;
     pl->want_taylor = flags & FR_W_TAYLOR;
+    pl->vector_spread = flags & FR_VECTOR_SPREAD;
     pl->eps = epsilon;
     pl->dx_ = dx;
     pl->dy_ = dy;

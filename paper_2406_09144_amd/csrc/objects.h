@@ -44,6 +44,7 @@ struct fr_plan {
     int n_planes = 1;
     double w0 = 0, dw = 1, yc = 0;  // plane p at w0 + p dw; n - 1 measured from yc
     bool want_taylor = false;       // FR_W_TAYLOR requested
+    bool vector_spread = false;     // FR_VECTOR_SPREAD: never the matrix-core spread
     bool taylor = false;            // planes are the Taylor terms of exp(-2 pi i w t)
     double taylor_h = 0;            // |t| <= h over the image
     int tile = 32;
@@ -89,7 +90,9 @@ namespace frmi {
 // FP32 gridding of plans with W <= 8 runs the spread on the matrix cores when the
 // sorted records average at least 4 per run of equal base cell (one MFMA step
 // takes four records of a run); otherwise it stays on the vector units.
-inline bool matrix_spread(const fr_plan *pl) { return !pl->fp64 && pl->W <= 8 && pl->vis_per_run >= 4.0; }
+inline bool matrix_spread(const fr_plan *pl) {
+    return !pl->fp64 && !pl->vector_spread && pl->W <= 8 && pl->vis_per_run >= 4.0;
+}
 
 // gridder.hip
 void plan_build(fr_plan *pl, const double *uvw_m, const double *freq_hz);

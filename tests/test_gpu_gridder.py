@@ -307,3 +307,31 @@ def test_both_spread_kernels_vs_oracle(kind):
     err = rel(img, ref)
     print(kind, info["records_per_run"], info["matrix_spread"], err)
     assert err < 1e-5, (err, info)
+
+
+def test_vector_spread_flag_same_plan_both_kernels():
+    """FR_VECTOR_SPREAD makes a plan whose runs would take the matrix cores grid on
+    the vector units: the two kernels on the same layout agree with each other and
+    with the oracle to the FP32 bound, and each is bitwise reproducible."""
+    import torch
+    from paper_2406_09144_amd import api
+    c = dense_tracks()
+    args = (c["uvw"], c["freq"], c["nx"], c["ny"], c["dx"], c["dy"])
+    pm = api.Plan(*args, eps=1e-5)
+    pv = api.Plan(*args, eps=1e-5, vector_spread=True)
+    assert pm.info["matrix_spread"] == 1 and pv.info["matrix_spread"] == 0
+    assert pm.info["n_planes"] == pv.info["n_planes"]
+    rng = np.random.default_rng(22)
+    nrow = c["uvw"].shape[0]
+    vis = rng.standard_normal((nrow, 1)) + 1j * rng.standard_normal((nrow, 1))
+    wt = rng.uniform(0.2, 3.0, (nrow, 1))
+    vd = torch.from_numpy(vis).to(torch.complex64).cuda()
+    wd = torch.from_numpy(wt).to(torch.float32).cuda()
+    im = api.grid(pm, vd, wd)
+    iv = api.grid(pv, vd, wd)
+    assert torch.equal(im, api.grid(pm, vd, wd)) and torch.equal(iv, api.grid(pv, vd, wd))
+    ref = O.grid(*args, vis, wt)
+    em, ev = rel(im.cpu().numpy(), ref), rel(iv.cpu().numpy(), ref)
+    ed = rel(im.cpu().numpy(), iv.cpu().numpy().astype(np.float64))
+    print("matrix", em, "vector", ev, "between", ed)
+    assert em < 1e-5 and ev < 1e-5 and ed < 1e-5
