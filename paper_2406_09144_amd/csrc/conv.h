@@ -170,6 +170,192 @@ __global__ __launch_bounds__(NTHR) void k_conv_cols(c2<T> *__restrict__ Y, int M
     }
 }
 
+
+// ------------------------------------------------------------------ pass 2, long columns
+// For columns of L = L1 L2 points (L >= 8192) a strip of a few columns no longer
+// fits the LDS, and single-column strips read each row with one isolated 8-byte
+// access.  The column convolution then runs as a four-step FFT over strips of C
+// adjacent columns (one row access moves C values), through a scratch Z of L rows:
+//   step 1: for each n2 < L2, the L1-point FFTs of x[L2 n1 + n2] over n1 (strided
+//           rows), times exp(-2 pi i n2 k1 / L), into Z row L2 k1 + n2;
+//   step 2: for each k1 < L1, the L2-point FFT of Z rows L2 k1 + (0 .. L2-1) gives
+//           X[k1 + L1 k2] at row L2 k1 + k2; multiply by the kernel at frequency
+//           k1 + L1 k2; the inverse L2-point FFT over k2 and exp(+2 pi i m2 k1 / L)
+//           give the partial inverse at row L2 k1 + m2;
+//   step 3: for each m2 < L2, the inverse L1-point FFT over k1 of the rows
+//           L2 k1 + m2 gives y[L2 m1 + m2], of which rows < n_out are stored.
+// The packed column 0 (DC and Nyquist columns, whose kernel multiply needs the
+// mirrored frequency -k) is left to the single-column kernel.
+// Thread layout of a load or store: column fastest (C values of a row), then the
+// group member (adjacent rows in steps 1 and 3), then the element along the line.
+template <typename T, int NTHR, int BPT>
+__global__ __launch_bounds__(NTHR) void k_conv4_outer(const c2<T> *__restrict__ src, int64_t src_rows_img,
+                                                       c2<T> *__restrict__ dst, int64_t dst_rows_img, int M,
+                                                       int log2L1, int log2L2, int n_valid_src, int n_valid_dst,
+                                                       int log2C, int log2G, int sign, int skip_col0,
+                                                       const c2<T> *__restrict__ tw1,
+                                                       const c2<T> *__restrict__ twL,
+                                                       const int *__restrict__ skip) {
+    if (skip && __hip_atomic_load(skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    c2<T> *buf = reinterpret_cast<c2<T> *>(smem_raw);
+    const int L1 = 1 << log2L1, L2 = 1 << log2L2, C = 1 << log2C, G = 1 << log2G;
+    const int ld = plen(L1) + 1;
+    const int nlines = C * G;
+    const int col0 = blockIdx.x << log2C;
+    const int n2_0 = blockIdx.y << log2G;
+    const int64_t img = blockIdx.z;
+    const c2<T> *S = src + img * src_rows_img * (int64_t)M;
+    c2<T> *D = dst + img * dst_rows_img * (int64_t)M;
+    const int log2L = log2L1 + log2L2;
+    // the forward pass's split twiddles exp(-2 pi i n2 k1 / L) of this thread's
+    // stores, fetched before the line loads so that they arrive during the FFT
+    // (a load inside the store loop would put one memory round trip per element
+    // on the thread's critical path)
+    constexpr int EPT = 4 * BPT;  // elements per thread: nlines L1 <= 4 BPT NTHR
+    c2<T> twr[EPT];
+    if (sign < 0) {
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            const int idx = threadIdx.x + j * NTHR;
+            const int gg = (idx >> log2C) & (G - 1), k1 = idx >> (log2C + log2G);
+            twr[j] = idx < nlines * L1 ? twL[((n2_0 + gg) * k1) & ((1 << log2L) - 1)] : mk<T>(T(1), T(0));
+        }
+    }
+    const c2<T> *twp = stage_twiddles<T, NTHR, true>(buf + nlines * ld, tw1, L1);
+    // load: element n1 of line (g, c) is row L2 n1 + n2_0 + g of column col0 + c
+    staged_copy<NTHR>(
+        nlines * L1,
+        [&](int idx) {
+            const int c = idx & (C - 1), gg = (idx >> log2C) & (G - 1), n1 = idx >> (log2C + log2G);
+            const int r = (n1 << log2L2) + n2_0 + gg;
+            return r < n_valid_src ? S[(int64_t)r * M + col0 + c] : mk<T>(T(0), T(0));
+        },
+        [&](int idx, c2<T> v) {
+            const int c = idx & (C - 1), gg = (idx >> log2C) & (G - 1), n1 = idx >> (log2C + log2G);
+            buf[(gg * C + c) * ld + padx(n1)] = v;
+        });
+    __syncthreads();
+    lds_fft<T, NTHR, BPT>(buf, ld, nlines, log2L1, sign, twp);
+    // store: element k1 of line (g, c) to row L2 k1 + n2 (forward: times the twiddle
+    // exp(-2 pi i n2 k1 / L) of the four-step split)
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+        const int idx = threadIdx.x + j * NTHR;
+        if (idx >= nlines * L1) break;
+        const int c = idx & (C - 1), gg = (idx >> log2C) & (G - 1), k1 = idx >> (log2C + log2G);
+        const int r = (k1 << log2L2) + n2_0 + gg;
+        if (r >= n_valid_dst || (skip_col0 && col0 + c == 0)) continue;
+        c2<T> v = buf[(gg * C + c) * ld + padx(k1)];
+        if (sign < 0) v = cmul<T>(v, twr[j]);
+        D[(int64_t)r * M + col0 + c] = v;
+    }
+}
+
+// step 2: for k1 in this workgroup's group, forward L2-point FFT, kernel multiply,
+// inverse L2-point FFT, inverse twiddle; in place on Z.
+template <typename T, int NTHR, int BPT>
+__global__ __launch_bounds__(NTHR) void k_conv4_middle(c2<T> *__restrict__ Z, int64_t z_rows_img, int M,
+                                                        int log2L1, int log2L2, int log2C, int log2G,
+                                                        const T *__restrict__ K, int nk, int mode, T scale,
+                                                        const c2<T> *__restrict__ tw2,
+                                                        const c2<T> *__restrict__ twL,
+                                                        const T *__restrict__ K_alt, int64_t g_alt,
+                                                        const int *__restrict__ skip) {
+    if (skip && __hip_atomic_load(skip, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    c2<T> *buf = reinterpret_cast<c2<T> *>(smem_raw);
+    const int L1 = 1 << log2L1, L2 = 1 << log2L2, C = 1 << log2C, G = 1 << log2G;
+    const int L = L1 * L2;
+    const int ld = plen(L2) + 1;
+    const int nlines = C * G;
+    const int col0 = blockIdx.x << log2C;
+    const int k1_0 = blockIdx.y << log2G;
+    const int64_t img = blockIdx.z;
+    c2<T> *Zi = Z + img * z_rows_img * (int64_t)M;
+    const T *Kg = img >= g_alt ? K_alt : K + (img % nk) * (int64_t)L * (M + 1);
+    // this thread's kernel values, fetched before the line loads so that they
+    // arrive during the forward FFT (element idx = threadIdx.x + j NTHR: column
+    // fastest, then the element k2 (or m2) along the line, then the group member)
+    constexpr int EPT = 4 * BPT;  // nlines L2 <= 4 BPT NTHR
+    T kr[EPT];
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+        const int idx = threadIdx.x + j * NTHR;
+        const int c = idx & (C - 1), e = (idx >> log2C) & (L2 - 1), gg = idx >> (log2C + log2L2);
+        kr[j] = idx < nlines * L2 ? Kg[(int64_t)((k1_0 + gg) + (e << log2L1)) * (M + 1) + col0 + c] : T(0);
+    }
+    const c2<T> *twp = stage_twiddles<T, NTHR, true>(buf + nlines * ld, tw2, L2);
+    auto row_of = [&](int gg, int e) { return ((k1_0 + gg) << log2L2) + e; };
+    staged_copy<NTHR>(
+        nlines * L2,
+        [&](int idx) {
+            const int c = idx & (C - 1), e = (idx >> log2C) & (L2 - 1), gg = idx >> (log2C + log2L2);
+            return Zi[(int64_t)row_of(gg, e) * M + col0 + c];
+        },
+        [&](int idx, c2<T> v) {
+            const int c = idx & (C - 1), e = (idx >> log2C) & (L2 - 1), gg = idx >> (log2C + log2L2);
+            buf[(gg * C + c) * ld + padx(e)] = v;
+        });
+    __syncthreads();
+    lds_fft<T, NTHR, BPT>(buf, ld, nlines, log2L2, -1, twp);
+    // the inverse split twiddles of this thread's stores, in flight during the
+    // multiply and the inverse FFT
+    c2<T> twr[EPT];
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+        const int idx = threadIdx.x + j * NTHR;
+        const int e = (idx >> log2C) & (L2 - 1), gg = idx >> (log2C + log2L2);
+        twr[j] = idx < nlines * L2 ? twL[(e * (k1_0 + gg)) & (L - 1)] : mk<T>(T(1), T(0));
+    }
+    // element k2 of line (g, c) holds frequency k = k1 + L1 k2 of column col0 + c
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+        const int idx = threadIdx.x + j * NTHR;
+        if (idx >= nlines * L2) break;
+        const int c = idx & (C - 1), k2 = (idx >> log2C) & (L2 - 1), gg = idx >> (log2C + log2L2);
+        const T kv = kernel_factor(kr[j], mode) * scale;
+        c2<T> &v = buf[(gg * C + c) * ld + padx(k2)];
+        v = mk<T>(v.x * kv, v.y * kv);
+    }
+    __syncthreads();
+    lds_fft<T, NTHR, BPT>(buf, ld, nlines, log2L2, +1, twp);
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+        const int idx = threadIdx.x + j * NTHR;
+        if (idx >= nlines * L2) break;
+        const int c = idx & (C - 1), m2 = (idx >> log2C) & (L2 - 1), gg = idx >> (log2C + log2L2);
+        const c2<T> v = buf[(gg * C + c) * ld + padx(m2)];
+        const c2<T> w = cconj<T>(twr[j]);  // exp(+2 pi i m2 k1 / L)
+        Zi[(int64_t)row_of(gg, m2) * M + col0 + c] = cmul<T>(v, w);
+    }
+}
+
+// Columns per strip and group sizes of the four-step column pass (C columns of
+// 8 or 16 bytes: 128-byte row segments; G lines per workgroup so that C G L_i is
+// 4096 elements, one radix-16 butterfly per thread of 256).
+inline void conv4_shape(int log2L, int M, int esize, int *log2L1, int *log2L2, int *log2C, int *log2G1,
+                        int *log2G2) {
+    *log2L1 = log2L / 2;
+    *log2L2 = log2L - *log2L1;
+    int lc = esize == 8 ? 4 : 3;  // 16 or 8 columns: 128 bytes
+    while (lc > 0 && (M % (1 << lc))) --lc;
+    *log2C = lc;
+    *log2G1 = std::max(0, 12 - *log2L1 - lc);
+    *log2G2 = std::max(0, 12 - *log2L2 - lc);
+    *log2G1 = std::min(*log2G1, *log2L2);  // groups of n2 < L2
+    *log2G2 = std::min(*log2G2, *log2L1);  // groups of k1 < L1
+}
+
+inline bool conv4_applies(int Lc, int odd, int M, size_t esize) {
+    return odd == 1 && Lc >= 8192 && M >= 8 && M % 2 == 0 && (esize == 8 || esize == 16);
+}
+
+// scratch of the four-step pass: L rows of M complex values per image
+inline size_t conv4_scratch(int64_t n_img, int Lc, int M, size_t csize) {
+    return (size_t)n_img * Lc * M * csize;
+}
+
 // ------------------------------------------------------------------ pass 3
 // Packed half-spectrum lines (M complex values each; slot 0 holds the real DC and
 // Nyquist values) -> the spectra of the complex lines z[e] = x[2e] + i x[2e + 1]
@@ -355,6 +541,12 @@ struct ConvGeom {
 
 template <typename T> inline int max_line_elems() { return kLdsBytes / (int)sizeof(c2<T>); }
 
+// Row passes keep the twiddle table in LDS only while it is at most half the
+// lines' size: a 4096-point line (lines and table of about 33 KB each) then runs
+// four workgroups per CU instead of two (4096^2 PSF apply, 16 images: both row
+// passes 1.7 -> 1.25-1.3 ms)
+inline bool twl_small(size_t line_bytes, size_t tw_bytes) { return 2 * tw_bytes <= line_bytes; }
+
 // ODD must equal g.odd_M
 template <typename T, int ODD = 1, class Pro>
 void launch_rfft_rows(const Ctx &ctx, const ConvGeom &g, Pro pro, c2<T> *Y, hipStream_t st) {
@@ -368,9 +560,15 @@ void launch_rfft_rows(const Ctx &ctx, const ConvGeom &g, Pro pro, c2<T> *Y, hipS
     if (M <= 4096) {
         const int lpw = rows_per_wg(M, nrows, ctx.n_cu);
         const int64_t nblk = (nrows + lpw - 1) / lpw;
-        allow_lds(k_rfft_rows<T, 256, 4, true, Pro, ODD>, lpw * line + twb);
-        k_rfft_rows<T, 256, 4, true, Pro, ODD><<<dim3((unsigned)nblk), 256, lpw * line + twb, st>>>(
-            pro, Y, nrows, g.log2M, g.n_in_cols, lpw, tw, tw2);
+        if (twl_small(lpw * line, twb)) {
+            allow_lds(k_rfft_rows<T, 256, 4, true, Pro, ODD>, lpw * line + twb);
+            k_rfft_rows<T, 256, 4, true, Pro, ODD><<<dim3((unsigned)nblk), 256, lpw * line + twb, st>>>(
+                pro, Y, nrows, g.log2M, g.n_in_cols, lpw, tw, tw2);
+        } else {
+            allow_lds(k_rfft_rows<T, 256, 4, false, Pro, ODD>, lpw * line);
+            k_rfft_rows<T, 256, 4, false, Pro, ODD><<<dim3((unsigned)nblk), 256, lpw * line, st>>>(
+                pro, Y, nrows, g.log2M, g.n_in_cols, lpw, tw, tw2);
+        }
     } else if (line + twb <= (size_t)kLdsBytes) {
         allow_lds(k_rfft_rows<T, 1024, 4, true, Pro, ODD>, line + twb);
         k_rfft_rows<T, 1024, 4, true, Pro, ODD><<<dim3((unsigned)nrows), 1024, line + twb, st>>>(
@@ -383,14 +581,83 @@ void launch_rfft_rows(const Ctx &ctx, const ConvGeom &g, Pro pro, c2<T> *Y, hipS
     LAUNCH_CHECK();
 }
 
-// ODD must equal g.odd_Lc
+// Scratch bytes of the column pass beyond Y: the four-step path's Z, else 0.
+template <typename T> inline size_t conv_cols_scratch(const ConvGeom &g) {
+    return conv4_applies(g.Lc(), g.odd_Lc, g.M(), sizeof(c2<T>))
+               ? conv4_scratch(g.n_img, g.Lc(), g.M(), sizeof(c2<T>))
+               : 0;
+}
+
+// Four-step column convolution of long power-of-two columns (see k_conv4_outer);
+// Z: conv_cols_scratch bytes, from the stream's arena when null.
+template <typename T>
+void launch_conv_cols_4step(const Ctx &ctx, const ConvGeom &g, c2<T> *Y, const T *K, int nk, int mode, T scale,
+                            hipStream_t st, const T *K_alt, int64_t g_alt, const int *skip, void *zws) {
+    const int M = g.M();
+    const int Lc = g.Lc();
+    int l1, l2, lc, lg1, lg2;
+    conv4_shape(g.log2Lc, M, (int)sizeof(c2<T>), &l1, &l2, &lc, &lg1, &lg2);
+    FR_REQUIRE(lc >= 1 && (M % (1 << lc)) == 0, "four-step column pass needs an even packed width");
+    FR_REQUIRE(g.n_img <= 65535, "too many images for one column pass");
+    FR_REQUIRE(g.rows_in == g.rows_out && g.rows_in <= Lc, "column pass works in place");
+    // the packed column 0 (DC and Nyquist columns) first, by the strip kernel with
+    // one single-column strip per image: it reads and writes column 0 of Y only,
+    // which the last four-step pass leaves alone
+    {
+        const int ld = plen(Lc) + 1;
+        const size_t lds = (size_t)ld * sizeof(c2<T>);
+        const bool twl = lds + (size_t)Lc * sizeof(c2<T>) <= (size_t)kLdsBytes;
+        FR_REQUIRE(lds <= (size_t)kLdsBytes, "column length too large for LDS");
+        const dim3 grid0(1u, (unsigned)g.n_img);
+        if (twl) {
+            const size_t b = lds + (size_t)Lc * sizeof(c2<T>);
+            allow_lds(k_conv_cols<T, 1024, 4, true, 1>, b);
+            k_conv_cols<T, 1024, 4, true, 1><<<grid0, 1024, b, st>>>(Y, M, g.log2Lc, g.rows_in, g.rows_out, 1, K,
+                                                                     nk, mode, scale, ctx.tw<T>(g.log2Lc), K_alt,
+                                                                     g_alt, skip);
+        } else {
+            allow_lds(k_conv_cols<T, 1024, 4, false, 1>, lds);
+            k_conv_cols<T, 1024, 4, false, 1><<<grid0, 1024, lds, st>>>(Y, M, g.log2Lc, g.rows_in, g.rows_out, 1,
+                                                                        K, nk, mode, scale, ctx.tw<T>(g.log2Lc),
+                                                                        K_alt, g_alt, skip);
+        }
+        LAUNCH_CHECK();
+    }
+    Scratch Zarena;
+    if (!zws) Zarena = Scratch(conv4_scratch(g.n_img, Lc, M, sizeof(c2<T>)), st);
+    c2<T> *const Z = zws ? (c2<T> *)zws : Zarena.as<c2<T>>();
+    const int L1 = 1 << l1, L2 = 1 << l2, C = 1 << lc;
+    const size_t lds1 = ((size_t)(C << lg1) * (plen(L1) + 1) + L1) * sizeof(c2<T>);
+    const size_t lds2 = ((size_t)(C << lg2) * (plen(L2) + 1) + L2) * sizeof(c2<T>);
+    const dim3 grid1((unsigned)(M / C), (unsigned)(L2 >> lg1), (unsigned)g.n_img);
+    const dim3 grid2((unsigned)(M / C), (unsigned)(L1 >> lg2), (unsigned)g.n_img);
+    const c2<T> *twL = ctx.tw<T>(g.log2Lc);
+    allow_lds(k_conv4_outer<T, 256, 4>, lds1);
+    allow_lds(k_conv4_middle<T, 256, 4>, lds2);
+    k_conv4_outer<T, 256, 4><<<grid1, 256, lds1, st>>>(Y, g.rows_in, Z, Lc, M, l1, l2, g.rows_in, Lc, lc, lg1, -1, 0,
+                                                       ctx.tw<T>(l1), twL, skip);
+    LAUNCH_CHECK();
+    k_conv4_middle<T, 256, 4><<<grid2, 256, lds2, st>>>(Z, Lc, M, l1, l2, lc, lg2, K, nk, mode, scale,
+                                                        ctx.tw<T>(l2), twL, K_alt, g_alt, skip);
+    LAUNCH_CHECK();
+    k_conv4_outer<T, 256, 4><<<grid1, 256, lds1, st>>>(Z, Lc, Y, g.rows_out, M, l1, l2, Lc, g.rows_out, lc, lg1, +1, 1,
+                                                       ctx.tw<T>(l1), twL, skip);
+    LAUNCH_CHECK();
+}
+
+// ODD must equal g.odd_Lc.  zws: conv_cols_scratch bytes (only the four-step path
+// of long columns uses it), from the stream's arena when null.
 template <typename T, int ODD = 1>
 void launch_conv_cols(const Ctx &ctx, const ConvGeom &g, c2<T> *Y, const T *K, int nk, int mode, T scale,
                       hipStream_t st, const T *K_alt = nullptr, int64_t g_alt = INT64_MAX,
-                      const int *skip = nullptr) {
+                      const int *skip = nullptr, void *zws = nullptr) {
     FR_REQUIRE(g.odd_Lc == ODD, "column length and kernel variant disagree");
     const int M = g.M();
     const int Lc = g.Lc();
+    if (conv4_applies(Lc, ODD, M, sizeof(c2<T>))) {
+        launch_conv_cols_4step<T>(ctx, g, Y, K, nk, mode, scale, st, K_alt, g_alt, skip, zws);
+        return;
+    }
     const int budget = 65536 / (int)sizeof(c2<T>);  // <= 64 KiB: two workgroups per CU
     const int cap = std::max(1, std::min(16, budget / Lc));
     int C = 1;
@@ -398,6 +665,9 @@ void launch_conv_cols(const Ctx &ctx, const ConvGeom &g, c2<T> *Y, const T *K, i
     while (C > 1 && (M % C)) C >>= 1;
     // small batches: narrower strips so the grid still covers every CU a few times
     while (C > 2 && (int64_t)(M / C) * g.n_img < 2 * (int64_t)std::max(ctx.n_cu, 1)) C >>= 1;
+    // long columns (one line already fills 64 KiB): strips of two columns, so that
+    // each row access moves two adjacent values, at one workgroup per CU
+    if (C == 1 && M % 2 == 0 && (int64_t)2 * (plen(Lc) + 1) <= max_line_elems<T>()) C = 2;
     FR_REQUIRE((int64_t)C * (plen(Lc) + 1) <= max_line_elems<T>(), "column length too large for LDS");
     FR_REQUIRE(is_pow2(C), "column strip width must be a power of two");
     const size_t lds = (size_t)C * (plen(Lc) + 1) * sizeof(c2<T>);
@@ -442,9 +712,15 @@ void launch_irfft_rows(const Ctx &ctx, const ConvGeom &g, Epi epi, const c2<T> *
     if (M <= 4096) {
         const int lpw = rows_per_wg(M, nrows, ctx.n_cu);
         const int64_t nblk = (nrows + lpw - 1) / lpw;
-        allow_lds(k_irfft_rows<T, 256, 4, true, Epi, ODD>, lpw * line + twb);
-        k_irfft_rows<T, 256, 4, true, Epi, ODD><<<dim3((unsigned)nblk), 256, lpw * line + twb, st>>>(
-            epi, Y, nrows, g.log2M, g.n_out_cols, lpw, tw, tw2);
+        if (twl_small(lpw * line, twb)) {
+            allow_lds(k_irfft_rows<T, 256, 4, true, Epi, ODD>, lpw * line + twb);
+            k_irfft_rows<T, 256, 4, true, Epi, ODD><<<dim3((unsigned)nblk), 256, lpw * line + twb, st>>>(
+                epi, Y, nrows, g.log2M, g.n_out_cols, lpw, tw, tw2);
+        } else {
+            allow_lds(k_irfft_rows<T, 256, 4, false, Epi, ODD>, lpw * line);
+            k_irfft_rows<T, 256, 4, false, Epi, ODD><<<dim3((unsigned)nblk), 256, lpw * line, st>>>(
+                epi, Y, nrows, g.log2M, g.n_out_cols, lpw, tw, tw2);
+        }
     } else if (line + twb <= (size_t)kLdsBytes) {
         allow_lds(k_irfft_rows<T, 1024, 4, true, Epi, ODD>, line + twb);
         k_irfft_rows<T, 1024, 4, true, Epi, ODD><<<dim3((unsigned)nrows), 1024, line + twb, st>>>(

@@ -13,9 +13,10 @@ namespace frmi {
 // the nx wanted rows are kept after the column pass.
 // y = d_out D P^+ irfft2(K_R rfft2(P D d_in x)) + add, every extra factor optional:
 // the diagonal metric factors and the prior term of CG fused into the first and
-// last pass.  The half-spectrum buffer comes from the stream's arena, or from `ws`
-// (at least rnr_approx_scratch bytes, 256-byte aligned) when that is given; the
-// first pass writes every element of it, so it needs no clearing.
+// last pass.  The half-spectrum buffer (and, for columns of 8192 points or more,
+// the four-step column pass's buffer after it) comes from the stream's arena, or
+// from `ws` (at least rnr_approx_scratch bytes, 256-byte aligned) when that is
+// given; every element is written before it is read, so it needs no clearing.
 template <typename T>
 void apply_rnr_approx_ex(const fr_psf *psf, const T *x, const T *d_in, T *y, const T *d_out, const T *add,
                          int64_t B, hipStream_t st, void *ws) {
@@ -43,8 +44,9 @@ void apply_rnr_approx_ex(const fr_psf *psf, const T *x, const T *d_in, T *y, con
     const T scale = T(1) / (T(g.Lc()) * T(M));
     with_odd(g.odd_Lc, [&](auto odd) {
         ProfScope prof("psfconv_cols", st);
+        void *zws = ws ? (char *)ws + scratch_round((size_t)n_img * nx * M * sizeof(c2<T>)) : nullptr;
         launch_conv_cols<T, decltype(odd)::value>(*psf->ctx, g, Yp, psf->KR.as<T>(), (int)nc, 0, scale,
-                                                  st);
+                                                  st, nullptr, INT64_MAX, nullptr, zws);
     });
     with_odd(g.odd_M, [&](auto odd) {
         ProfScope prof("psfconv_rows_c2r", st);
@@ -53,13 +55,22 @@ void apply_rnr_approx_ex(const fr_psf *psf, const T *x, const T *d_in, T *y, con
     });
 }
 
+// four-step buffer of a column pass of Lc points over n_img images of M packed columns
+static size_t cols_extra(int64_t n_img, int64_t Lc, int64_t M, size_t cs) {
+    int odd = 1, l = 0;
+    if (!split_len(Lc, &odd, &l)) return 0;
+    return conv4_applies((int)Lc, odd, (int)M, cs) ? scratch_round(conv4_scratch(n_img, (int)Lc, (int)M, cs)) : 0;
+}
+
 size_t rnr_approx_scratch(const fr_psf *psf, int64_t B) {
     const size_t cs = psf->fp64 ? sizeof(double2) : sizeof(float2);
-    return scratch_round((size_t)B * psf->n_chan * psf->nx * (psf->py / 2) * cs);
+    const int64_t n_img = B * psf->n_chan, M = psf->py / 2;
+    return scratch_round((size_t)n_img * psf->nx * M * cs) + cols_extra(n_img, psf->px, M, cs);
 }
 
 size_t periodic_conv_scratch(int64_t n_img, int64_t nx, int64_t ny, bool fp64) {
-    return scratch_round((size_t)n_img * nx * (ny / 2) * (fp64 ? sizeof(double2) : sizeof(float2)));
+    const size_t cs = fp64 ? sizeof(double2) : sizeof(float2);
+    return scratch_round((size_t)n_img * nx * (ny / 2) * cs) + cols_extra(n_img, nx, ny / 2, cs);
 }
 
 template <typename T>

@@ -1,0 +1,104 @@
+"""Convolutions whose column transforms are 8192 or 16384 points long (the doubled
+grid of a 4096^2 or 8192^2 image, Sec. 3.3.2; periodic noise and prior
+convolutions on grids of 8192 rows, Sec. 3.3.3).  Those columns go through the
+four-step column pass; narrow images keep the oracle's transforms cheap while
+the column length is that of the full-size workloads.  Packed widths 8, 16 and
+32 cover strips of 8 and 16 columns, and a batch of several images with two
+kernels covers the per-image kernel choice.  FP64 takes the four-step pass for
+the 8192-point columns of a 4096-row PSF apply; FP64 PSF applies of more rows are
+refused."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+def even_psf(rng, nx, ny):
+    """A periodically even PSF-like array on the 2nx x 2ny grid, peak at (nx, ny),
+    random sidelobes decaying away from it, offset -n row and column zero."""
+    gx = np.fft.fftfreq(2 * nx) * 2 * nx
+    gy = np.fft.fftfreq(2 * ny) * 2 * ny
+    r = np.sqrt(gx[:, None] ** 2 + gy[None, :] ** 2)
+    g = rng.standard_normal((2 * nx, 2 * ny)) * (0.05 / (1.0 + r / 64.0))
+    g = g + np.roll(g[::-1, ::-1], (1, 1), axis=(0, 1))
+    g[0, 0] = 1.0
+    p = np.fft.fftshift(g)
+    p[0, :] = 0.0
+    p[:, 0] = 0.0
+    return p
+
+
+def tdev(a, fp64):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(torch.float64 if fp64 else torch.float32).cuda()
+
+
+@pytest.mark.parametrize("nx,ny,fp64", [(4096, 16, False), (4096, 32, False), (8192, 16, False),
+                                         (4096, 16, True), (4096, 32, True)])
+def test_psf_apply_long_columns(nx, ny, fp64):
+    from paper_2406_09144_amd import api
+    rng = np.random.default_rng(nx + ny + int(fp64))
+    psfs = [even_psf(rng, nx, ny) for _ in range(2)]
+    K = np.stack([O.response_kernel(p) for p in psfs])
+    a = rng.uniform(0.5, 1.5, (nx, ny))
+    print(f"[long cols] psf apply {nx}x{ny}, column length {2 * nx}, fp64={fp64}", flush=True)
+    psf = api.PSF.from_kernels(tdev(K, fp64), nfac=tdev(a, fp64))
+    B = 2
+    x = rng.standard_normal((B, 2, nx, ny))
+    y = api.apply_RNR_approx(psf, tdev(x, fp64)).cpu().numpy()
+    tol = 1e-12 if fp64 else 1e-6
+    for b in range(B):
+        for c in range(2):
+            e = rel(y[b, c], O.psf_conv_fft(x[b, c], K[c], a))
+            assert e < tol, (b, c, e)
+    # sampled pixels against the brute-force convolution with the PSF itself
+    pix = rng.choice(nx * ny, 64, replace=False)
+    ref = O.psf_conv_direct(x[1, 1], psfs[1], a, pix=pix)
+    assert rel(y[1, 1].ravel()[pix], ref) < tol
+
+
+def positive_even_spectrum(rng, nx, ny):
+    """A positive spectrum with K[-k] = K[k] on the full nx x ny grid."""
+    kx = np.minimum(np.arange(nx), nx - np.arange(nx))
+    ky = np.minimum(np.arange(ny), ny - np.arange(ny))
+    base = 1.0 / (1.0 + (kx[:, None] / 50.0) ** 2 + (ky[None, :] / 3.0) ** 2)
+    jitter = rng.uniform(0.5, 1.5, (nx, ny))
+    jitter = 0.5 * (jitter + np.roll(jitter[::-1, ::-1], (1, 1), axis=(0, 1)))
+    return 0.05 + base * jitter
+
+
+@pytest.mark.parametrize("nx,ny", [(8192, 64), (8192, 16)])
+def test_periodic_conv_long_columns(nx, ny):
+    """FP32 only: FP64 periodic convolutions are limited to 4096 rows."""
+    fp64 = False
+    from paper_2406_09144_amd import api
+    from paper_2406_09144_amd import _lib as L
+    rng = np.random.default_rng(nx * 3 + ny + int(fp64))
+    KN = np.stack([positive_even_spectrum(rng, nx, ny) for _ in range(2)])
+    half = KN[..., : ny // 2 + 1]
+    x = rng.standard_normal((3, 2, nx, ny))
+    print(f"[long cols] periodic conv {nx}x{ny}, fp64={fp64}", flush=True)
+    tol = 1e-11 if fp64 else 1e-5
+    for mode, ref in ((L.FR_CONV_MUL, O.noise_apply), (L.FR_CONV_DIV, O.noise_inv_apply)):
+        y = api.periodic_conv(tdev(half, fp64), tdev(x, fp64), mode).cpu().numpy()
+        for b in range(3):
+            for c in range(2):
+                e = rel(y[b, c], ref(x[b, c], KN[c]))
+                assert e < tol, (mode, b, c, e)
+
+
+def test_fp64_16384_columns_refused():
+    """An FP64 PSF apply with 16384-point columns (8192 rows) is refused, not run."""
+    import torch
+    from paper_2406_09144_amd import api, FrError
+    with pytest.raises(FrError):
+        K = torch.ones((1, 16384, 17), dtype=torch.float64, device="cuda")
+        psf = api.PSF.from_kernels(K)
+        api.apply_RNR_approx(psf, torch.zeros((1, 1, 8192, 16), dtype=torch.float64, device="cuda"))
