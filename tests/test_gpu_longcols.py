@@ -102,3 +102,36 @@ def test_fp64_16384_columns_refused():
         K = torch.ones((1, 16384, 17), dtype=torch.float64, device="cuda")
         psf = api.PSF.from_kernels(K)
         api.apply_RNR_approx(psf, torch.zeros((1, 1, 8192, 16), dtype=torch.float64, device="cuda"))
+
+
+@pytest.mark.parametrize("B", [1, 3])
+def test_footprint_bounds_long_column_scratch(B):
+    """The four-step pass's buffer is part of the reported footprint: the arena's
+    high-water mark of a 4096-row PSF apply and FAST likelihood stays within
+    fr_query_footprint, at batch 1 and 3."""
+    import torch
+    from paper_2406_09144_amd import api
+    from paper_2406_09144_amd import _lib as L
+    nx, ny = 4096, 16
+    rng = np.random.default_rng(61)
+    K = np.stack([O.response_kernel(even_psf(rng, nx, ny)) for _ in range(2)])
+    KN = np.stack([positive_even_spectrum(rng, nx, ny)[:, : ny // 2 + 1] for _ in range(2)])
+    psf = api.PSF.from_kernels(tdev(K, False), K_N=tdev(KN, False))
+    x = tdev(rng.standard_normal((B, 2, nx, ny)), False)
+    d = tdev(rng.standard_normal((2, nx, ny)), False)
+    calls = [(L.FR_OP_RNR_APPROX, lambda st: api.apply_RNR_approx(psf, x, stream=st)),
+             (L.FR_OP_LIK_FAST, lambda st: api.likelihood_grad(L.FR_LIK_FAST, 0.1 * x, d, psf=psf, stream=st))]
+    for op, call in calls:
+        print(f"[long cols] footprint op {op} B={B}", flush=True)
+        st = torch.cuda.Stream()
+        st.wait_stream(torch.cuda.current_stream())
+        api.scratch_stats(st, reset=True)
+        with torch.cuda.stream(st):
+            call(st)
+        st.synchronize()
+        peak, _ = api.scratch_stats(st)
+        fp, _ = api.query_footprint(op, B, psf=psf)
+        assert 0 < peak <= fp, (op, peak, fp)
+        # the four-step buffer (2 B images of 8192 x 16 complex) is inside the peak
+        assert peak >= 2 * B * 2 * nx * ny * 8
+        api.scratch_trim(st)
