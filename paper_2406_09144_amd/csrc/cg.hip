@@ -20,6 +20,9 @@ struct CGState {
     double stop;  // rtol ||b||
     int done;
     int iters;
+    // fused PSF-form loop: flag[k & 1] != 0 once iteration k (or an earlier one)
+    // met the stopping test; flag[1] also carries the start test for k = 0
+    int flag[2];
 };
 
 template <typename T> struct CGInit {
@@ -42,6 +45,8 @@ __global__ __launch_bounds__(kRedThreads) void k_cg_start(CGState *st, const dou
     st->stop = rtol * sqrt(s);
     st->iters = 0;
     st->done = (s == 0.0 || maxiter == 0) ? 1 : 0;
+    st->flag[0] = 0;
+    st->flag[1] = st->done;
     hist[0] = sqrt(s);
 }
 
@@ -137,15 +142,27 @@ __global__ void k_cg_report(const CGState *st, int *iters_done) {
 
 // ------------------------------------------------------------------ fused PSF-form iteration
 // For A = D_s R'_PSF D_s + S^-1 with the full doubled-grid PSF, one iteration is
-// four launches instead of nine:
-//   1. row transforms of two images per channel on the doubled grid: a D_s p and p
-//      (p = r + beta p updated on the fly; beta, the residual history and the stop
-//      test of the previous iteration are done by each workgroup at its start);
+// three launches instead of nine:
+//   1. row transforms of two images per channel on the doubled grid, a D_s p_k
+//      and p_k, whose prologue first completes the previous step: with
+//      alpha = <r, r> / <p, A p> of iteration k - 1,
+//        x += alpha p_k-1,  r_k = r_k-1 - alpha A p_k-1,
+//        <r_k, r_k> = <r, r> - 2 alpha <r, A p> + alpha^2 <A p, A p>,
+//        beta = <r_k, r_k> / <r, r>,  p_k = r_k + beta p_k-1
+//      (each workgroup forms the scalars from the partial sums of pass 3 of
+//      iteration k - 1; workgroup 0 records the residual history and the stop
+//      test);
 //   2. column transforms, the first image multiplied by K_R, the second by the
 //      prior embedded in the doubled grid (below);
 //   3. inverse row transforms of both images of a row in one workgroup:
-//      A p = D_s a y_R + y_S, and the partial sums of <p, A p>;
-//   4. alpha; x += alpha p, r -= alpha A p; partial sums of <r, r>.
+//      A p = D_s a y_R + y_S, and the partial sums of <p, A p>, <r, A p>,
+//      <A p, A p> and <r, r> (r = r_k).
+// A final launch applies the last step to x.  The scalars are those of the
+// Hestenes-Stiefel recurrences (alpha and beta from the residual norms); only
+// <r_k, r_k> is formed from the expansion of |r_k-1 - alpha A p_k-1|^2 with
+// the dot products of the vectors themselves (as in the single-reduction CG of
+// Chronopoulos and Gear), so that no separate pass over r_k is needed before
+// beta.  The next iteration's pass 3 sums <r_k, r_k> from r_k directly.
 // The prior S^-1 = F^-1 diag(1/P) F on the nx x ny periodic grid embeds in the
 // doubled grid: the 2n-point transform of the zero-padded p at even frequencies
 // 2k is the n-point transform of p at k, and a spectrum living on the even
@@ -175,58 +192,83 @@ template <typename T> struct CGInitXR {
     }
 };
 
-// FP64 sum of n partials over the workgroup (any size up to 1024 threads),
-// fixed order, returned to every thread
-__device__ __forceinline__ double block_sum_partials_all(const double *partials, int n) {
-    __shared__ double sh[16];
-    __shared__ double total;
-    double v = 0;
+// The four FP64 sums of pass 3 over its n blocks (partials [block][4]), fixed
+// order, returned to every thread of the workgroup
+__device__ __forceinline__ void block_sum4_partials_all(const double *partials, int n, double out[4]) {
+    __shared__ double sh[4][16];
+    double v[4] = {0, 0, 0, 0};
     for (int k = threadIdx.x; k < n; k += blockDim.x)
-        v += __hip_atomic_load(partials + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            v[j] += __hip_atomic_load(partials + 4 * (int64_t)k + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        for (int o = 32; o > 0; o >>= 1) v[j] += __shfl_down(v[j], o, 64);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     __syncthreads();
-    if (lane == 0) sh[wid] = v;
+    if (lane == 0)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) sh[j][wid] = v[j];
     __syncthreads();
-    if (threadIdx.x == 0) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
         double t = 0;
-        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += sh[k];
-        total = t;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += sh[j][k];
+        out[j] = t;
     }
     __syncthreads();
-    return total;
+}
+
+// Scalars of the step from iteration k - 1 to k: alpha, <r_k, r_k> and beta from
+// <p, A p>, <r, A p>, <A p, A p>, <r, r> of iteration k - 1
+struct CGStepScalars {
+    double alpha, rn, beta;
+};
+__device__ __forceinline__ CGStepScalars cg_step_scalars(const double s[4]) {
+    CGStepScalars c;
+    c.alpha = s[3] / s[0];
+    c.rn = fmax(s[3] - 2.0 * c.alpha * s[1] + c.alpha * c.alpha * s[2], 0.0);
+    c.beta = c.rn / s[3];
+    return c;
 }
 
 // Pass-1 prologue of iteration k.  Rows [0, n0) are the first image set (a D_s p),
-// rows [n0, 2 n0) the second (p).  For k > 0 each workgroup first forms
-// beta = <r_k, r_k> / <r_k-1, r_k-1> from the step's partials; workgroup 0 also
-// records <r_k, r_k>, the history and the stop flag (as the separate update
-// kernel of the generic loop does).  p_k = r_k + beta p_k-1 goes to p_new (written
-// by the first image set only).
+// rows [n0, 2 n0) the second (p).  Workgroups skip the pass once an earlier
+// iteration met the stopping test (and pass the flag on).  For k > 0 the first
+// image set completes the previous step (x, r_k and p_k written); the second
+// recomputes p_k from the same inputs without writing.
 template <typename T> struct CGRowPro {
-    const T *r, *p_old;
-    T *p_new;
+    T *x;
+    const T *r_prev;  // r_k-1 (r_0 = b when k = 0)
+    T *r_cur;         // r_k (k > 0)
+    const T *p_prev, *Ap;
+    T *p_cur;
     const T *d, *a;
     int nx, ny;
     int64_t n0;
     CGState *st;
-    const double *rr_partials;
-    int n_rr;
-    double *rr, *hist;
+    const double *parts;  // pass-3 partials of iteration k - 1, [n_parts][4]
+    int n_parts;
+    double *hist;
     int k;
-    T beta;
+    T alpha, beta;
     __device__ bool begin() {
-        if (cg_done(st)) return false;
-        beta = T(0);
+        if (__hip_atomic_load(&st->flag[(k + 1) & 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            if (threadIdx.x == 0) __hip_atomic_store(&st->flag[k & 1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        alpha = beta = T(0);
         if (k == 0) return true;
-        const double rn = block_sum_partials_all(rr_partials, n_rr);
-        const double prev = rr[(k - 1) & 1];
-        beta = (T)(rn / prev);
+        double s[4];
+        block_sum4_partials_all(parts, n_parts, s);
+        const CGStepScalars c = cg_step_scalars(s);
+        alpha = (T)c.alpha;
+        beta = (T)c.beta;
         if (blockIdx.x == 0 && threadIdx.x == 0) {
-            rr[k & 1] = rn;
-            hist[k] = sqrt(rn);
+            hist[k] = sqrt(c.rn);
             st->iters = k;
-            if (sqrt(rn) <= st->stop) __hip_atomic_store(&st->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (sqrt(c.rn) <= st->stop)
+                __hip_atomic_store(&st->flag[k & 1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         return true;
     }
@@ -234,9 +276,20 @@ template <typename T> struct CGRowPro {
         const bool second = row >= n0;
         const int64_t prow = second ? row - n0 : row;
         const int64_t q = prow * ny + col;
-        const T pv = k == 0 ? r[q] : r[q] + beta * p_old[q];
+        T pv;
+        if (k == 0) {
+            pv = r_prev[q];
+        } else {
+            const T po = p_prev[q];
+            const T rv = r_prev[q] - alpha * Ap[q];
+            pv = rv + beta * po;
+            if (!second) {
+                x[q] += alpha * po;
+                r_cur[q] = rv;
+            }
+        }
         if (second) return pv;
-        p_new[q] = pv;
+        p_cur[q] = pv;
         T v = pv;
         if (d) v *= d[q];
         if (a) v *= a[((int)prow & (nx - 1)) * ny + col];
@@ -244,12 +297,13 @@ template <typename T> struct CGRowPro {
     }
 };
 
-// Pass-3 epilogue: A p = D_s a y_R + y_S; returns the pixel pair's share of <p, A p>
+// Pass-3 epilogue: A p = D_s a y_R + y_S; returns the pixel pair's shares of
+// <p, A p>, <r, A p>, <A p, A p> and <r, r>
 template <typename T> struct CGPairEpi {
     T *Ap;
-    const T *p, *d, *a;
+    const T *p, *r, *d, *a;
     int nx, ny;
-    __device__ double operator()(int64_t row, int col, T y0, T y1, T s0, T s1) const {
+    __device__ SumN<4> operator()(int64_t row, int col, T y0, T y1, T s0, T s1) const {
         const int64_t q = row * ny + col;
         if (d) {
             y0 *= d[q];
@@ -264,22 +318,34 @@ template <typename T> struct CGPairEpi {
         y1 += s1;
         Ap[q] = y0;
         Ap[q + 1] = y1;
-        return (double)p[q] * (double)y0 + (double)p[q + 1] * (double)y1;
+        const double p0 = p[q], p1 = p[q + 1], r0 = r[q], r1 = r[q + 1];
+        return SumN<4>{{p0 * y0 + p1 * y1, r0 * y0 + r1 * y1, (double)y0 * y0 + (double)y1 * y1,
+                        r0 * r0 + r1 * r1}};
     }
 };
 
-// <r_K, r_K> of the last iteration into the history, and the iteration count
-__global__ __launch_bounds__(kRedThreads) void k_cg_finish(CGState *st, const double *rr_partials, int n_rr,
-                                                           int K, double *rr, double *hist, int *iters_done) {
-    if (!cg_done(st) && K > 0) {
-        const double rn = block_sum_partials(rr_partials, n_rr);
-        if (threadIdx.x == 0) {
-            rr[K & 1] = rn;
-            hist[K] = sqrt(rn);
+// The last step: x += alpha p_K-1 and <r_K, r_K> into the history, unless an
+// earlier iteration stopped; the iteration count.
+template <typename T>
+__global__ __launch_bounds__(kRedThreads) void k_cg_finish_fused(CGState *st, T *__restrict__ x,
+                                                                 const T *__restrict__ p, int64_t n,
+                                                                 const double *parts, int n_parts, int K,
+                                                                 double *hist, int *iters_done) {
+    const bool skip = K == 0 ||
+                      __hip_atomic_load(&st->flag[(K + 1) & 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+    if (!skip) {
+        double s[4];
+        block_sum4_partials_all(parts, n_parts, s);
+        const CGStepScalars c = cg_step_scalars(s);
+        const T alpha = (T)c.alpha;
+        for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kRedThreads)
+            x[i] += alpha * p[i];
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            hist[K] = sqrt(c.rn);
             st->iters = K;
         }
     }
-    if (threadIdx.x == 0) *iters_done = st->iters;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *iters_done = st->iters;
 }
 
 // The fused form applies to the full doubled-grid PSF (the prior embedding needs
@@ -295,8 +361,8 @@ static size_t cg_fused_scratch(const fr_psf *psf, bool prior) {
     const int64_t nb3 = irfft_pair_blocks((int)ny, nc * nx, npart, 256, nullptr, nullptr);
     const size_t vec = scratch_round((size_t)n * rs);
     // partials: the pass-3 block count depends on the device's CU count; bound it by one block per row
-    const size_t parts = scratch_round((size_t)(red_blocks(n) + std::max<int64_t>(nb3, nc * nx)) * 8);
-    return scratch_round(sizeof(CGState)) + parts + scratch_round(2 * sizeof(double)) + 4 * vec +
+    const size_t parts = scratch_round((size_t)(red_blocks(n) + 4 * std::max<int64_t>(nb3, nc * nx)) * 8);
+    return scratch_round(sizeof(CGState)) + parts + scratch_round(2 * sizeof(double)) + 5 * vec +
            scratch_round((size_t)npart * nc * nx * ny * 2 * rs) + (prior ? scratch_round((size_t)2 * nx * (ny + 1) * rs) : 0);
 }
 
@@ -311,10 +377,11 @@ static void cg_solve_psf_fused(const fr_psf *psf, const T *inv_power, const T *d
     const int nb = red_blocks(n);
     const int64_t nb3 = irfft_pair_blocks(M, nc * nx, npart, ctx.n_cu, nullptr, nullptr);
     Scratch state(sizeof(CGState), st);
-    Scratch partials((size_t)(nb + std::max<int64_t>(nb3, nc * nx)) * sizeof(double), st);
-    double *rr_part = partials.as<double>(), *pAp_part = partials.as<double>() + nb;
+    Scratch partials((size_t)(nb + 4 * std::max<int64_t>(nb3, nc * nx)) * sizeof(double), st);
+    double *rr_part = partials.as<double>(), *part3 = partials.as<double>() + nb;
     Scratch rr(2 * sizeof(double), st);
-    Scratch r(n * sizeof(T), st), pA(n * sizeof(T), st), pB(n * sizeof(T), st), Ap(n * sizeof(T), st);
+    Scratch rA(n * sizeof(T), st), rB(n * sizeof(T), st), pA(n * sizeof(T), st), pB(n * sizeof(T), st),
+        Ap(n * sizeof(T), st);
     Scratch Y((size_t)npart * nc * nx * M * sizeof(c2<T>), st);
     Scratch H;
     if (inv_power) {
@@ -322,8 +389,9 @@ static void cg_solve_psf_fused(const fr_psf *psf, const T *inv_power, const T *d
         map_async(PriorEmbed<T>{inv_power, H.as<T>(), (int)nx, (int)ny}, 2 * nx * (ny + 1), st);
     }
     CGState *S = state.as<CGState>();
-    map_async(CGInitXR<T>{b, x, r.as<T>()}, n, st);
-    k_dot_partials<T><<<dim3((unsigned)nb, 1), kRedThreads, 0, st>>>(r.as<T>(), nullptr, n, rr_part);
+    T *rbuf[2] = {rA.as<T>(), rB.as<T>()}, *pbuf[2] = {pA.as<T>(), pB.as<T>()};
+    map_async(CGInitXR<T>{b, x, rbuf[0]}, n, st);
+    k_dot_partials<T><<<dim3((unsigned)nb, 1), kRedThreads, 0, st>>>(rbuf[0], nullptr, n, rr_part);
     LAUNCH_CHECK();
     k_cg_start<<<1, kRedThreads, 0, st>>>(S, rr_part, nb, rtol, maxiter, rr.as<double>(), hist);
     LAUNCH_CHECK();
@@ -337,10 +405,12 @@ static void cg_solve_psf_fused(const fr_psf *psf, const T *inv_power, const T *d
     g.log2Lc = ilog2(2 * nx);
     const T scale = T(1) / (T(2 * nx) * T(M));
     const T *a = psf->nfac.as<T>();
-    T *p_old = pA.as<T>(), *p_new = pB.as<T>();
     for (int k = 0; k < maxiter; ++k) {
-        CGRowPro<T> pro{r.as<T>(), p_old, p_new, diag, a, (int)nx, (int)ny, nc * nx, S, rr_part, nb,
-                        rr.as<double>(), hist, k, T(0)};
+        // r_k in rbuf[k & 1], p_k in pbuf[k & 1]
+        T *r_cur = rbuf[k & 1], *p_cur = pbuf[k & 1];
+        const T *r_prev = rbuf[(k + 1) & 1], *p_prev = pbuf[(k + 1) & 1];
+        CGRowPro<T> pro{x, k == 0 ? r_cur : r_prev, r_cur, p_prev, Ap.as<T>(), p_cur, diag, a, (int)nx, (int)ny,
+                        nc * nx, S, part3, (int)nb3, hist, k, T(0), T(0)};
         {
             ProfScope prof("cg_rows_r2c", st);
             launch_rfft_rows<T>(ctx, g, pro, Y.as<c2<T>>(), st);
@@ -348,21 +418,17 @@ static void cg_solve_psf_fused(const fr_psf *psf, const T *inv_power, const T *d
         {
             ProfScope prof("cg_cols", st);
             launch_conv_cols<T>(ctx, g, Y.as<c2<T>>(), psf->KR.as<T>(), (int)nc, 0, scale, st, H.as<T>(),
-                                inv_power ? nc : INT64_MAX, &S->done);
+                                inv_power ? nc : INT64_MAX, &S->flag[k & 1]);
         }
         {
             ProfScope prof("cg_rows_c2r", st);
             launch_irfft_rows_pair<T>(ctx, log2M, nc * nx, nc * nx, npart, (int)ny,
-                                      CGPairEpi<T>{Ap.as<T>(), p_new, diag, a, (int)nx, (int)ny}, Y.as<c2<T>>(),
-                                      pAp_part, &S->done, st);
+                                      CGPairEpi<T>{Ap.as<T>(), p_cur, r_cur, diag, a, (int)nx, (int)ny},
+                                      Y.as<c2<T>>(), part3, &S->flag[k & 1], st);
         }
-        ProfScope prof("cg_step", st);
-        k_cg_step<T><<<dim3((unsigned)nb), kRedThreads, 0, st>>>(S, x, r.as<T>(), p_new, Ap.as<T>(), n, pAp_part,
-                                                                  (int)nb3, rr.as<double>(), k, rr_part);
-        LAUNCH_CHECK();
-        std::swap(p_old, p_new);
     }
-    k_cg_finish<<<1, kRedThreads, 0, st>>>(S, rr_part, nb, maxiter, rr.as<double>(), hist, iters_done);
+    k_cg_finish_fused<T><<<dim3((unsigned)nb), kRedThreads, 0, st>>>(S, x, pbuf[(maxiter + 1) & 1], n, part3,
+                                                                      (int)nb3, maxiter, hist, iters_done);
     LAUNCH_CHECK();
 }
 

@@ -430,13 +430,27 @@ template <int NTHR> __device__ __forceinline__ double block_sum_n(double v) {
     return t;
 }
 
+// Several FP64 sums carried together (an epilogue may return one of these
+// instead of a double to contribute to N sums at once).
+template <int N> struct SumN {
+    double v[N];
+};
+template <class R> struct sum_count { static constexpr int n = 1; };
+template <int N> struct sum_count<SumN<N>> { static constexpr int n = N; };
+template <int N> __device__ __forceinline__ void sum_add(double (&acc)[N], const SumN<N> &x) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) acc[j] += x.v[j];
+}
+__device__ __forceinline__ void sum_add(double (&acc)[1], double x) { acc[0] += x; }
+
 // Pass 3 over pairs of images: row r of the first n_rows packed rows goes with
 // row r + pair_offset (NPART = 2; NPART = 1 has no partner), both inverse
 // transformed in the same workgroup so that the epilogue sees the two real
 // values of a pixel together: epi(r, col, a0, a1, b0, b1) receives columns col
 // and col + 1 of the row and of its partner, stores what it needs and returns a
-// contribution to a sum; partials[blockIdx.x] gets the workgroup's FP64 sum.
-// A non-zero *skip turns the launch into a no-op.
+// contribution to a sum (a double) or to N sums (SumN<N>); the workgroup's FP64
+// sums go to partials[blockIdx.x * N + j].  A non-zero *skip turns the launch
+// into a no-op.
 template <typename T, int NTHR, int BPT, bool TWL, class Epi, int NPART>
 __global__ __launch_bounds__(NTHR) void k_irfft_rows_pair(Epi epi, const c2<T> *__restrict__ Y, int64_t n_rows,
                                                            int64_t pair_offset, int log2M, int n_out_cols,
@@ -465,15 +479,21 @@ __global__ __launch_bounds__(NTHR) void k_irfft_rows_pair(Epi epi, const c2<T> *
     __syncthreads();
     lds_fft<T, NTHR, BPT>(buf, ld, NPART * nl, log2M, +1, twp);
     const int npair = n_out_cols / 2;
-    double acc = 0.0;
+    constexpr int NS = sum_count<decltype(epi(int64_t(0), 0, T(0), T(0), T(0), T(0)))>::n;
+    double acc[NS];
+#pragma unroll
+    for (int j = 0; j < NS; ++j) acc[j] = 0.0;
     for (int c = 0; c < nl; ++c)
         for (int e = threadIdx.x; e < npair; e += NTHR) {
             const c2<T> z = buf[c * ld + padx(e)];
             const c2<T> w = NPART == 2 ? buf[(nl + c) * ld + padx(e)] : mk<T>(T(0), T(0));
-            acc += epi(row0 + c, 2 * e, z.x, z.y, w.x, w.y);
+            sum_add(acc, epi(row0 + c, 2 * e, z.x, z.y, w.x, w.y));
         }
-    acc = block_sum_n<NTHR>(acc);
-    if (threadIdx.x == 0) partials[blockIdx.x] = acc;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+        const double t = block_sum_n<NTHR>(acc[j]);
+        if (threadIdx.x == 0) partials[(int64_t)blockIdx.x * NS + j] = t;
+    }
 }
 
 // Workgroups of launch_irfft_rows_pair for n_rows row pairs of packed width M.
