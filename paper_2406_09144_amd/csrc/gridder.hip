@@ -148,11 +148,15 @@ __global__ void k_gather_records(int64_t n, const uint32_t *__restrict__ perm, c
                                  const uint32_t *__restrict__ i_cell, const T *__restrict__ i_du,
                                  const T *__restrict__ i_dv, const T *__restrict__ i_dw, const T *__restrict__ i_ph,
                                  uint32_t *__restrict__ o_idx, uint32_t *__restrict__ o_cell, T *__restrict__ o_du,
-                                 T *__restrict__ o_dv, T *__restrict__ o_dw, T *__restrict__ o_ph) {
+                                 T *__restrict__ o_dv, T *__restrict__ o_dw, T *__restrict__ o_ph,
+                                 uint32_t *__restrict__ o_pos) {
     const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (pos >= n) return;
     const uint32_t v = perm[pos];
-    o_idx[pos] = i_idx[v];
+    const uint32_t id = i_idx[v];
+    o_idx[pos] = id;
+    // record position of visibility v (= id & 0x7fffffff), with its conjugation flag
+    o_pos[id & 0x7fffffffu] = (uint32_t)pos | (id & 0x80000000u);
     o_cell[pos] = i_cell[v];
     o_du[pos] = i_du[v];
     o_dv[pos] = i_dv[v];
@@ -376,11 +380,10 @@ template <typename T, int W, int NTHR>
 __global__ __launch_bounds__(NTHR) void k_grid_partial(const WorkItem *__restrict__ wis,
                                                        const int32_t *__restrict__ order, c2<T> *__restrict__ partial,
                                                        int Ww, int ppass, T beta, T wbeta, int coplanar,
-                                                       int taylor, const uint32_t *__restrict__ r_idx,
-                                                       const uint32_t *__restrict__ r_cell,
+                                                       int taylor, const uint32_t *__restrict__ r_cell,
                                                        const T *__restrict__ r_du, const T *__restrict__ r_dv,
                                                        const T *__restrict__ r_dw, const T *__restrict__ r_ph,
-                                                       const c2<T> *__restrict__ vis, const T *__restrict__ weight,
+                                                       const c2<T> *__restrict__ y_rec,
                                                        const float *__restrict__ ybound_partials, int n_ybound,
                                                        int sorted_in) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -471,20 +474,7 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial(const WorkItem *__restric
             if (lane < nb) {
                 const int64_t pos = it.start + b0 + lane;
                 l_cell = (int)r_cell[pos];
-                c2<T> y;
-                if (sorted_in) {
-                    y = vis[pos];  // weighted values already in record order and frame
-                } else {
-                    const uint32_t id = r_idx[pos];
-                    const uint32_t vi = id & 0x7fffffffu;
-                    y = vis ? vis[vi] : mk<T>(T(1), T(0));
-                    if (weight) {
-                        const T wt = weight[vi];
-                        y.x *= wt;
-                        y.y *= wt;
-                    }
-                    if (id >> 31) y.y = -y.y;
-                }
+                c2<T> y = y_rec[pos];  // weighted (w < 0: conjugated) value in record order
                 l_xu = r_du[pos];
                 l_xv = r_dv[pos];
                 if (!coplanar) {
@@ -589,9 +579,9 @@ template <int W, int NTHR>
 __global__ __launch_bounds__(NTHR) void k_grid_partial_mfma(
     const WorkItem *__restrict__ wis, const int32_t *__restrict__ order, c2<float> *__restrict__ partial, int Ww,
     int ppass, float beta, float wbeta,
-    int coplanar, int taylor, const uint32_t *__restrict__ r_idx, const uint32_t *__restrict__ r_cell,
+    int coplanar, int taylor, const uint32_t *__restrict__ r_cell,
     const float *__restrict__ r_du, const float *__restrict__ r_dv, const float *__restrict__ r_dw,
-    const float *__restrict__ r_ph, const c2<float> *__restrict__ vis, const float *__restrict__ weight,
+    const float *__restrict__ r_ph, const c2<float> *__restrict__ y_rec,
     const float *__restrict__ ybound_partials, int n_ybound, int sorted_in) {
     static_assert(W <= 8, "one lane per 1-D kernel value of 8 visibilities");
     typedef float v4f __attribute__((ext_vector_type(4)));
@@ -677,20 +667,7 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial_mfma(
             if (lane < nb) {
                 const int64_t pos = it.start + b0 + lane;
                 l_cell = (int)r_cell[pos];
-                c2<float> y;
-                if (sorted_in) {
-                    y = vis[pos];  // weighted values already in record order and frame
-                } else {
-                    const uint32_t id = r_idx[pos];
-                    const uint32_t vi = id & 0x7fffffffu;
-                    y = vis ? vis[vi] : mk<float>(1.0f, 0.0f);
-                    if (weight) {
-                        const float wt = weight[vi];
-                        y.x *= wt;
-                        y.y *= wt;
-                    }
-                    if (id >> 31) y.y = -y.y;
-                }
+                c2<float> y = y_rec[pos];  // weighted (w < 0: conjugated) value in record order
                 l_xu = r_du[pos];
                 l_xv = r_dv[pos];
                 if (!coplanar) {
@@ -800,6 +777,53 @@ __global__ __launch_bounds__(256) void k_vis_bound(const c2<T> *__restrict__ vis
         if (vis) a = fabs((double)vis[i].x) + fabs((double)vis[i].y);
         if (weight) a *= fabs((double)weight[i]);
         m = fmaxf(m, __double2float_ru(a));
+    }
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    __shared__ float sh[4];
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) partials[blockIdx.x] = fmaxf(fmaxf(sh[0], sh[1]), fmaxf(sh[2], sh[3]));
+}
+
+// The same bound, and the weighted values y = w v (v = 1 without visibilities,
+// conjugated for records folded from w < 0) scattered into record order through
+// the plan's record positions, so that the spread reads them with coalesced
+// loads instead of gathering each record's visibility and weight by its
+// original index.  The centring phase stays with the spread.
+template <typename T>
+__global__ __launch_bounds__(256) void k_vis_prepare(const c2<T> *__restrict__ vis, const T *__restrict__ weight,
+                                                     const uint32_t *__restrict__ r_pos, int64_t n,
+                                                     float *__restrict__ partials, c2<T> *__restrict__ y_rec) {
+    // four values per thread and pass, their loads issued before any store
+    constexpr int U = 4;
+    float m = 0.0f;
+    for (int64_t base = (int64_t)blockIdx.x * 256 * U + threadIdx.x; base < n; base += (int64_t)gridDim.x * 256 * U) {
+        c2<T> y[U];
+        T wt[U];
+        uint32_t ps[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = base + u * 256;
+            if (i < n) {
+                y[u] = vis ? vis[i] : mk<T>(T(1), T(0));
+                wt[u] = weight ? weight[i] : T(1);
+                ps[u] = r_pos[i];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (base + u * 256 >= n) break;
+            c2<T> v = y[u];
+            double a = fabs((double)v.x) + fabs((double)v.y);
+            if (weight) {
+                a *= fabs((double)wt[u]);
+                v.x *= wt[u];
+                v.y *= wt[u];
+            }
+            m = fmaxf(m, __double2float_ru(a));
+            if (ps[u] >> 31) v.y = -v.y;
+            y_rec[ps[u] & 0x7fffffffu] = v;
+        }
     }
     for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
     __shared__ float sh[4];
@@ -1089,8 +1113,8 @@ void launch_degrid_w(const fr_plan *pl, const WorkItem *wis, int64_t nwi, const 
 }
 
 template <typename T, int W>
-void launch_grid_w(const fr_plan *pl, int64_t chan, c2<T> *planes, const c2<T> *vis, const T *weight,
-                   const float *ybound, int nbb, hipStream_t st, int sorted_in) {
+void launch_grid_w(const fr_plan *pl, int64_t chan, c2<T> *planes, const c2<T> *y_rec, const float *ybound,
+                   int nbb, hipStream_t st, int sorted_in) {
     constexpr int TS = kTile + W - 1;
     // FP64 and wide kernels hold more registers per lane: smaller groups, larger register share
     constexpr int NTHR = (sizeof(T) == 8 || W * W > 64) ? 512 : 1024;
@@ -1110,9 +1134,9 @@ void launch_grid_w(const fr_plan *pl, int64_t chan, c2<T> *planes, const c2<T> *
                 allow_lds(kern, lds);
                 kern<<<dim3((unsigned)(i1 - i0)), NTHR, lds, st>>>(
                     pl->gwi.as<WorkItem>() + i0, pl->gorder.as<int32_t>() + i0, partial.as<c2<T>>(), pl->Ww, ppass,
-                    (T)pl->beta, (T)pl->wbeta, pl->coplanar ? 1 : 0, pl->taylor ? 1 : 0, pl->r_idx.as<uint32_t>(),
+                    (T)pl->beta, (T)pl->wbeta, pl->coplanar ? 1 : 0, pl->taylor ? 1 : 0,
                     pl->r_cell.as<uint32_t>(), pl->r_du.as<T>(), pl->r_dv.as<T>(), pl->r_dw.as<T>(), pl->r_ph.as<T>(),
-                    vis, weight, ybound, nbb, sorted_in);
+                    y_rec, ybound, nbb, sorted_in);
             };
             if constexpr (std::is_same<T, float>::value && W <= 8) {
                 // FP32, footprint <= 64 cells and runs of several records (an MFMA
@@ -1125,8 +1149,8 @@ void launch_grid_w(const fr_plan *pl, int64_t chan, c2<T> *planes, const c2<T> *
                     kern<<<dim3((unsigned)(i1 - i0)), NTHR, lds, st>>>(
                         pl->gwi.as<WorkItem>() + i0, pl->gorder.as<int32_t>() + i0, partial.as<c2<T>>(), pl->Ww,
                         ppass, (T)pl->beta, (T)pl->wbeta, pl->coplanar ? 1 : 0, pl->taylor ? 1 : 0,
-                        pl->r_idx.as<uint32_t>(), pl->r_cell.as<uint32_t>(), pl->r_du.as<T>(), pl->r_dv.as<T>(),
-                        pl->r_dw.as<T>(), pl->r_ph.as<T>(), vis, weight, ybound, nbb, sorted_in);
+                        pl->r_cell.as<uint32_t>(), pl->r_du.as<T>(), pl->r_dv.as<T>(),
+                        pl->r_dw.as<T>(), pl->r_ph.as<T>(), y_rec, ybound, nbb, sorted_in);
                 } else {
                     launch_vector();
                 }
@@ -1184,22 +1208,25 @@ size_t degrid_scratch(const fr_plan *pl) { return scratch_round(planes_bytes(pl)
 size_t grid_scratch(const fr_plan *pl) {
     int64_t items = 0;
     for (int64_t c = 0; c < pl->n_chan; ++c) items = std::max(items, pl->gwi_chan[c + 1] - pl->gwi_chan[c]);
+    // values in record order (input-order calls; an upper bound for record-order ones)
+    const size_t yrec = scratch_round((size_t)pl->n_vis * (pl->fp64 ? sizeof(double2) : sizeof(float2)));
     return scratch_round(planes_bytes(pl)) + scratch_round((size_t)vis_bound_blocks(pl->n_vis) * sizeof(float)) +
-           scratch_round(grid_partial_bytes(items, pl->Ww, pl->W, pl->fp64));
+           yrec + scratch_round(grid_partial_bytes(items, pl->Ww, pl->W, pl->fp64));
 }
 
 static int grid_chunk(int64_t n_vis_per_chan, int n_cu);
 
 // Bound on the arena scratch of gridding with the coplanar plan of the doubled
 // field that fr_make_psf_kernel derives (built inside the call): one plane of
-// 4 nx x 4 ny cells, and at most one gridding item per non-empty tile plus one per
-// chunk of records in each channel.
+// 4 nx x 4 ny cells, the weighted values in record order, and at most one
+// gridding item per non-empty tile plus one per chunk of records in each channel.
 // Device memory a plan build takes per visibility at its peak: the coordinate
 // and key arrays of k_vis_coords (idx, cell, key, du, dv, dw, ph), the two key and
 // permutation buffers of the sort and its tables (12 bytes per 16 keys), and the
-// sorted records the plan keeps (idx, cell, du, dv, dw, ph); per bucket, its
+// sorted records the plan keeps (idx, cell, du, dv, dw, ph, and the record
+// position of each visibility); per bucket, its
 // first record and first gridding item, and the tile maps.
-static size_t plan_bytes_per_vis(size_t rs) { return 12 + 4 * rs + 24 + 1 + 8 + 4 * rs; }
+static size_t plan_bytes_per_vis(size_t rs) { return 12 + 4 * rs + 24 + 1 + 12 + 4 * rs; }
 static size_t plan_bytes_per_key() { return 8 + 4 + 4 + 1; }
 
 // Bound on the device memory of building the coplanar doubled-field plan inside
@@ -1221,6 +1248,7 @@ size_t psf_grid_scratch_bound(const fr_plan *pl) {
                           (pl->n_row + grid_chunk(pl->n_row, pl->ctx->n_cu) - 1) / grid_chunk(pl->n_row, pl->ctx->n_cu);
     const size_t planes = (size_t)nu * nv * (fp64 ? sizeof(double2) : sizeof(float2));
     return scratch_round(planes) + scratch_round((size_t)vis_bound_blocks(pl->n_vis) * sizeof(float)) +
+           scratch_round((size_t)pl->n_vis * (fp64 ? sizeof(double2) : sizeof(float2))) +
            scratch_round(grid_partial_bytes(items, 1, W, fp64));
 }
 
@@ -1292,16 +1320,26 @@ void degrid(const fr_plan *pl, const T *img, c2<T> *vis, hipStream_t st, const T
 template <typename T>
 void grid(const fr_plan *pl, const c2<T> *vis, const T *weight, T *img, hipStream_t st, bool sorted_in) {
     Scratch planes(planes_bytes(pl), st);
-    // bound on every gridded contribution (sets the fixed-point scale of the tiles)
+    // bound on every gridded contribution (sets the fixed-point scale of the tiles);
+    // values in input order are weighted and moved into record order on the way
     const int nbb = vis_bound_blocks(pl->n_vis);
     Scratch ybound((size_t)nbb * sizeof(float), st);
+    Scratch yrec;
+    const c2<T> *y_rec = vis;
     if (pl->n_vis > 0) {
-        k_vis_bound<T><<<dim3((unsigned)nbb), 256, 0, st>>>(vis, weight, pl->n_vis, ybound.as<float>());
+        if (sorted_in) {
+            k_vis_bound<T><<<dim3((unsigned)nbb), 256, 0, st>>>(vis, weight, pl->n_vis, ybound.as<float>());
+        } else {
+            yrec = Scratch((size_t)pl->n_vis * sizeof(c2<T>), st);
+            y_rec = yrec.as<c2<T>>();
+            k_vis_prepare<T><<<dim3((unsigned)nbb), 256, 0, st>>>(vis, weight, pl->r_pos.as<uint32_t>(), pl->n_vis,
+                                                                  ybound.as<float>(), yrec.as<c2<T>>());
+        }
         LAUNCH_CHECK();
     }
     for (int64_t c = 0; c < pl->n_chan; ++c) {
 #define FR_CALL_GRID(WW) \
-    launch_grid_w<T, WW>(pl, c, planes.as<c2<T>>(), vis, weight, ybound.as<float>(), nbb, st, sorted_in ? 1 : 0)
+    launch_grid_w<T, WW>(pl, c, planes.as<c2<T>>(), y_rec, ybound.as<float>(), nbb, st, sorted_in ? 1 : 0)
         FR_W_DISPATCH(pl->W, FR_CALL_GRID)
 #undef FR_CALL_GRID
         planes_to_image<T>(pl, planes.as<c2<T>>(), pl->tile_active.as<uint8_t>() + c * pl->n_tiles,
@@ -1506,10 +1544,11 @@ static void build_records(fr_plan *pl, const DevBuf &d_uvw, const DevBuf &d_freq
     pl->r_dv = DevBuf(n * sizeof(T));
     pl->r_dw = DevBuf(n * sizeof(T));
     pl->r_ph = DevBuf(n * sizeof(T));
+    pl->r_pos = DevBuf(n * 4);
     k_gather_records<T><<<dim3((unsigned)blocks), 256>>>(
         n, perm_sorted, idx.as<uint32_t>(), cell.as<uint32_t>(), du.as<T>(), dv.as<T>(), dwf.as<T>(),
         ph.as<T>(), pl->r_idx.as<uint32_t>(), pl->r_cell.as<uint32_t>(), pl->r_du.as<T>(), pl->r_dv.as<T>(),
-        pl->r_dw.as<T>(), pl->r_ph.as<T>());
+        pl->r_dw.as<T>(), pl->r_ph.as<T>(), pl->r_pos.as<uint32_t>());
     LAUNCH_CHECK();
     if (pl->n_gwi > 0) {
         k_item_rows<<<dim3((unsigned)((pl->n_gwi + 255) / 256)), 256>>>(pl->gwi.as<WorkItem>(), pl->n_gwi,
@@ -1775,7 +1814,7 @@ void plan_build(fr_plan *pl, const double *uvw_m, const double *freq_hz) {
         HIP_CHECK(hipMemset(pl->tile_active.p, 0, pl->tile_active.bytes));
     }
     pl->resident = pl->fac.bytes + pl->tpix.bytes + pl->tpix_w.bytes + pl->nfac.bytes + pl->wplane.bytes + pl->r_idx.bytes +
-                   pl->r_cell.bytes + pl->r_du.bytes + pl->r_dv.bytes + pl->r_dw.bytes + pl->r_ph.bytes +
+                   pl->r_cell.bytes + pl->r_du.bytes + pl->r_dv.bytes + pl->r_dw.bytes + pl->r_ph.bytes + pl->r_pos.bytes +
                    pl->wi.bytes + pl->gwi.bytes + pl->gorder.bytes + pl->gkey_first.bytes + pl->atile.bytes +
                    pl->tile_active.bytes;
 }

@@ -61,6 +61,7 @@ struct fr_plan {
     frmi::DevBuf wplane;  // [n_planes] double: w of each plane
     // sorted visibility records (structure of arrays)
     frmi::DevBuf r_idx;   // uint32 [n_vis]: row * n_chan + chan, bit 31 = conjugate
+    frmi::DevBuf r_pos;   // uint32 [n_vis]: record position of visibility row * n_chan + chan, bit 31 = conjugate
     frmi::DevBuf r_cell;  // uint32 [n_vis]: (a0 - tu) | (b0 - tv) << 16
     frmi::DevBuf r_du, r_dv, r_dw, r_ph;  // T [n_vis]
     frmi::DevBuf wi;      // WorkItem [n_wi]
