@@ -111,6 +111,8 @@ typedef struct fr_plan_info {
     double records_per_run; /* sorted records per run of equal (bucket, base cell) */
     int matrix_spread;      /* 1: fr_grid spreads on the matrix cores (FP32, support <= 8,
                                >= 4 records per run); 0: on the vector units */
+    int paired_degrid;      /* 1: fr_degrid interpolates two records of one base cell per
+                               thread from the same tile reads (FP32, >= 4 records per run) */
 } fr_plan_info;
 
 /* Library version string. */

@@ -359,6 +359,7 @@ int fr_plan_get_info(const fr_plan *pl, fr_plan_info *info) {
     info->w_taylor = pl->taylor ? 1 : 0;
     info->records_per_run = pl->vis_per_run;
     info->matrix_spread = frmi::matrix_spread(pl) ? 1 : 0;
+    info->paired_degrid = frmi::paired_degrid(pl) ? 1 : 0;
     FR_API_END
 }
 

@@ -191,14 +191,22 @@ template <typename T> __device__ __forceinline__ T plane_weight(T x, int p, int 
 }
 
 // ------------------------------------------------------------------ degrid
-template <typename T, int W, int NTHR, int VPT>
+// One workgroup per degridding item (records of one uv tile and first w-plane);
+// the planes' tile is staged in LDS one plane at a time.  Without PAIR, thread j
+// interpolates records j, j + NTHR, ... (VPT of them).  With PAIR (VPT = 2),
+// thread t takes entry t of the item's pair list (it.rows entries, at most NTHR):
+// two consecutive records of one base cell, or one record alone; the two share
+// every tile read of the footprint.
+template <typename T, int W, int NTHR, int VPT, bool PAIR = false>
 __global__ __launch_bounds__(NTHR) void k_degrid(const WorkItem *__restrict__ wis, const c2<T> *__restrict__ planes,
                                                  int log2nu, int log2nv, int Ww, T beta, T wbeta, int coplanar,
                                                  int taylor, const uint32_t *__restrict__ r_idx,
                                                  const uint32_t *__restrict__ r_cell, const T *__restrict__ r_du,
                                                  const T *__restrict__ r_dv, const T *__restrict__ r_dw,
                                                  const T *__restrict__ r_ph, const T *__restrict__ weight,
-                                                 c2<T> *__restrict__ vis, int sorted_out) {
+                                                 c2<T> *__restrict__ vis, int sorted_out,
+                                                 const uint32_t *__restrict__ dpair) {
+    static_assert(!PAIR || VPT == 2, "a pair is two records");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     c2<T> *tile = reinterpret_cast<c2<T> *>(smem_raw);
     constexpr int TS = kTile + W - 1;
@@ -209,15 +217,31 @@ __global__ __launch_bounds__(NTHR) void k_degrid(const WorkItem *__restrict__ wi
     T fw[VPT];
     int ru[VPT], rv[VPT];
     bool ok[VPT];
+    int jrec[VPT];  // record of slot k inside the item
     c2<T> acc[VPT];
+    if constexpr (PAIR) {
+        // pair entry: first record | second record << 10 | alone << 20
+        const bool act = (int)threadIdx.x < it.rows;
+        const uint32_t e = act ? dpair[it.start + threadIdx.x] : 0u;
+        jrec[0] = (int)(e & 1023u);
+        jrec[1] = (int)((e >> 10) & 1023u);
+        ok[0] = act;
+        ok[1] = act && !((e >> 20) & 1u);
+    } else {
+#pragma unroll
+        for (int k = 0; k < VPT; ++k) {
+            jrec[k] = threadIdx.x + k * NTHR;
+            ok[k] = jrec[k] < it.count;
+        }
+    }
 #pragma unroll
     for (int k = 0; k < VPT; ++k) {
-        const int j = threadIdx.x + k * NTHR;
-        ok[k] = j < it.count;
+        const int j = jrec[k];
         acc[k] = mk<T>(T(0), T(0));
         ru[k] = rv[k] = 0;
         fw[k] = T(0);
-        if (ok[k]) {
+        // a lone record of a pair repeats the first one (interpolated, not stored)
+        if (PAIR ? ok[0] : ok[k]) {
             const int64_t pos = it.start + j;
             const uint32_t c = r_cell[pos];
             ru[k] = (int)(c & 0xffffu);
@@ -267,32 +291,62 @@ __global__ __launch_bounds__(NTHR) void k_degrid(const WorkItem *__restrict__ wi
                 pre_y[u] = g.y;
             }
         }
+        if constexpr (PAIR) {
+            // both records of the pair from the same tile reads (one base cell)
+            if (ok[0]) {
+                const T kw0 = coplanar ? T(1) : plane_weight<T>(fw[0], pw, Ww, wbeta, taylor);
+                const T kw1 = coplanar ? T(1) : plane_weight<T>(fw[1], pw, Ww, wbeta, taylor);
+                T sx0 = 0, sy0 = 0, sx1 = 0, sy1 = 0;
 #pragma unroll
-        for (int k = 0; k < VPT; ++k) {
-            if (!ok[k]) continue;
-            const T kw = coplanar ? T(1) : plane_weight<T>(fw[k], pw, Ww, wbeta, taylor);
-            T sx = 0, sy = 0;
+                for (int a = 0; a < W; ++a) {
+                    const c2<T> *rowp = tile + (ru[0] + a) * TS + rv[0];
+                    T rx0 = 0, ry0 = 0, rx1 = 0, ry1 = 0;
 #pragma unroll
-            for (int a = 0; a < W; ++a) {
-                const c2<T> *rowp = tile + (ru[k] + a) * TS + rv[k];
-                T rx = 0, ry = 0;
-#pragma unroll
-                for (int b = 0; b < W; ++b) {
-                    const c2<T> g = rowp[b];
-                    rx += kv[k][b] * g.x;
-                    ry += kv[k][b] * g.y;
+                    for (int b = 0; b < W; ++b) {
+                        const c2<T> g = rowp[b];
+                        rx0 += kv[0][b] * g.x;
+                        ry0 += kv[0][b] * g.y;
+                        rx1 += kv[1][b] * g.x;
+                        ry1 += kv[1][b] * g.y;
+                    }
+                    sx0 += ku[0][a] * rx0;
+                    sy0 += ku[0][a] * ry0;
+                    sx1 += ku[1][a] * rx1;
+                    sy1 += ku[1][a] * ry1;
                 }
-                sx += ku[k][a] * rx;
-                sy += ku[k][a] * ry;
+                acc[0].x += kw0 * sx0;
+                acc[0].y += kw0 * sy0;
+                acc[1].x += kw1 * sx1;
+                acc[1].y += kw1 * sy1;
             }
-            acc[k].x += kw * sx;
-            acc[k].y += kw * sy;
+        } else {
+#pragma unroll
+            for (int k = 0; k < VPT; ++k) {
+                if (!ok[k]) continue;
+                const T kw = coplanar ? T(1) : plane_weight<T>(fw[k], pw, Ww, wbeta, taylor);
+                T sx = 0, sy = 0;
+#pragma unroll
+                for (int a = 0; a < W; ++a) {
+                    const c2<T> *rowp = tile + (ru[k] + a) * TS + rv[k];
+                    T rx = 0, ry = 0;
+#pragma unroll
+                    for (int b = 0; b < W; ++b) {
+                        const c2<T> g = rowp[b];
+                        rx += kv[k][b] * g.x;
+                        ry += kv[k][b] * g.y;
+                    }
+                    sx += ku[k][a] * rx;
+                    sy += ku[k][a] * ry;
+                }
+                acc[k].x += kw * sx;
+                acc[k].y += kw * sy;
+            }
         }
     }
 #pragma unroll
     for (int k = 0; k < VPT; ++k) {
         if (!ok[k]) continue;
-        const int64_t pos = it.start + threadIdx.x + k * NTHR;
+        const int64_t pos = it.start + jrec[k];
         c2<T> v = acc[k];
         if (sorted_out) {
             // w times the interpolated plane values in record order, for gridding
@@ -1096,19 +1150,32 @@ template <typename T> void zero_async(T *p, int64_t n, hipStream_t st) {
 // faster than 256 threads with two records each, the registers per thread
 // dropping enough for more resident waves).
 template <typename T> constexpr int chunk() { return std::is_same<T, float>::value ? 512 : 256; }
+// pair-list entries per paired degridding item (one per thread)
+constexpr int kPairsPerItem = 256;
 
 template <typename T, int W>
 void launch_degrid_w(const fr_plan *pl, const WorkItem *wis, int64_t nwi, const c2<T> *planes, const T *weight,
                      c2<T> *vis, hipStream_t st, int sorted_out) {
     constexpr int TS = kTile + W - 1;
     const size_t lds = (size_t)TS * TS * sizeof(c2<T>);
-    auto kern = k_degrid<T, W, chunk<T>(), 1>;
-    allow_lds(kern, lds);
     ProfScope prof("degrid", st);
-    kern<<<dim3((unsigned)nwi), chunk<T>(), lds, st>>>(
-        wis, planes, ilog2(pl->nu), ilog2(pl->nv), pl->Ww, (T)pl->beta, (T)pl->wbeta, pl->coplanar ? 1 : 0,
-        pl->taylor ? 1 : 0, pl->r_idx.as<uint32_t>(), pl->r_cell.as<uint32_t>(), pl->r_du.as<T>(), pl->r_dv.as<T>(), pl->r_dw.as<T>(),
-        pl->r_ph.as<T>(), weight, vis, sorted_out);
+    auto launch = [&](auto kern, int nthr) {
+        allow_lds(kern, lds);
+        kern<<<dim3((unsigned)nwi), nthr, lds, st>>>(
+            wis, planes, ilog2(pl->nu), ilog2(pl->nv), pl->Ww, (T)pl->beta, (T)pl->wbeta, pl->coplanar ? 1 : 0,
+            pl->taylor ? 1 : 0, pl->r_idx.as<uint32_t>(), pl->r_cell.as<uint32_t>(), pl->r_du.as<T>(),
+            pl->r_dv.as<T>(), pl->r_dw.as<T>(), pl->r_ph.as<T>(), weight, vis, sorted_out, pl->dpair.as<uint32_t>());
+    };
+    // runs of several records: two records of a base cell per thread share the tile
+    // reads; the plan cuts paired items at kPairsPerItem entries (and chunk records)
+    bool done = false;
+    if constexpr (std::is_same<T, float>::value) {
+        if (paired_degrid(pl)) {
+            launch(k_degrid<T, W, kPairsPerItem, 2, true>, kPairsPerItem);
+            done = true;
+        }
+    }
+    if (!done) launch(k_degrid<T, W, chunk<T>(), 1, false>, chunk<T>());
     LAUNCH_CHECK();
 }
 
@@ -1223,10 +1290,10 @@ static int grid_chunk(int64_t n_vis_per_chan, int n_cu);
 // Device memory a plan build takes per visibility at its peak: the coordinate
 // and key arrays of k_vis_coords (idx, cell, key, du, dv, dw, ph), the two key and
 // permutation buffers of the sort and its tables (12 bytes per 16 keys), and the
-// sorted records the plan keeps (idx, cell, du, dv, dw, ph, and the record
-// position of each visibility); per bucket, its
+// sorted records the plan keeps (idx, cell, du, dv, dw, ph, the record position
+// of each visibility and the degridding pair lists); per bucket, its
 // first record and first gridding item, and the tile maps.
-static size_t plan_bytes_per_vis(size_t rs) { return 12 + 4 * rs + 24 + 1 + 12 + 4 * rs; }
+static size_t plan_bytes_per_vis(size_t rs) { return 12 + 4 * rs + 24 + 1 + 16 + 4 * rs; }
 static size_t plan_bytes_per_key() { return 8 + 4 + 4 + 1; }
 
 // Bound on the device memory of building the coplanar doubled-field plan inside
@@ -1452,6 +1519,16 @@ static void build_records(fr_plan *pl, const DevBuf &d_uvw, const DevBuf &d_freq
         HIP_CHECK(hipMemcpy(&steps, d_steps.p, sizeof(steps), hipMemcpyDeviceToHost));
         pl->vis_per_run = (double)n / (double)(steps + 1);
     }
+    // paired degridding: the sorted keys (bucket and base cell) on the host, to cut
+    // the records into pairs of one base cell and the items at kPairsPerItem pairs
+    const bool paired = paired_degrid(pl);
+    std::vector<uint64_t> hkeys;
+    std::vector<uint32_t> hpair;
+    if (paired) {
+        hkeys.resize(n);
+        HIP_CHECK(hipMemcpy(hkeys.data(), keys_sorted, (size_t)n * 8, hipMemcpyDeviceToHost));
+        hpair.assign(n, 0u);
+    }
     int64_t run = 0;
     std::vector<WorkItem> wis, gwis;
     std::vector<uint32_t> gfirst(n_keys + 1, 0);
@@ -1474,11 +1551,35 @@ static void build_records(fr_plan *pl, const DevBuf &d_uvw, const DevBuf &d_freq
             w.p0 = p0;
             w.chan = (int32_t)chan;
             w.rows = 0;
-            for (int64_t s = 0; s < cnt; s += ch) {
-                w.start = run + s;
-                w.count = (int32_t)std::min<int64_t>(ch, cnt - s);
-                wis.push_back(w);
-                pl->wi_chan[chan + 1] = (int64_t)wis.size();
+            if (paired) {
+                // consecutive records of one base cell two at a time (a record whose
+                // successor has another cell, or lies beyond the item, alone); an item
+                // ends after kPairsPerItem entries or ch records
+                int64_t j = run;
+                const int64_t end = run + cnt;
+                while (j < end) {
+                    w.start = j;
+                    int entries = 0;
+                    while (j < end && entries < kPairsPerItem && j - w.start < ch) {
+                        const uint32_t a = (uint32_t)(j - w.start);
+                        const bool two = j + 1 < end && j + 1 - w.start < ch && hkeys[j + 1] == hkeys[j];
+                        hpair[w.start + entries] = a | ((two ? a + 1 : a) << 10) | (two ? 0u : (1u << 20));
+                        ++entries;
+                        j += two ? 2 : 1;
+                    }
+                    w.count = (int32_t)(j - w.start);
+                    w.rows = entries;
+                    wis.push_back(w);
+                    pl->wi_chan[chan + 1] = (int64_t)wis.size();
+                }
+                w.rows = 0;
+            } else {
+                for (int64_t s = 0; s < cnt; s += ch) {
+                    w.start = run + s;
+                    w.count = (int32_t)std::min<int64_t>(ch, cnt - s);
+                    wis.push_back(w);
+                    pl->wi_chan[chan + 1] = (int64_t)wis.size();
+                }
             }
             for (int64_t s = 0; s < cnt; s += gch) {
                 w.start = run + s;
@@ -1558,6 +1659,10 @@ static void build_records(fr_plan *pl, const DevBuf &d_uvw, const DevBuf &d_freq
     pl->n_wi = (int64_t)wis.size();
     pl->wi = DevBuf(std::max<size_t>(1, wis.size()) * sizeof(WorkItem));
     if (!wis.empty()) HIP_CHECK(hipMemcpy(pl->wi.p, wis.data(), wis.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
+    if (paired) {
+        pl->dpair = DevBuf((size_t)n * 4);
+        HIP_CHECK(hipMemcpy(pl->dpair.p, hpair.data(), (size_t)n * 4, hipMemcpyHostToDevice));
+    }
     HIP_CHECK(hipDeviceSynchronize());
 }
 
@@ -1815,6 +1920,7 @@ void plan_build(fr_plan *pl, const double *uvw_m, const double *freq_hz) {
     }
     pl->resident = pl->fac.bytes + pl->tpix.bytes + pl->tpix_w.bytes + pl->nfac.bytes + pl->wplane.bytes + pl->r_idx.bytes +
                    pl->r_cell.bytes + pl->r_du.bytes + pl->r_dv.bytes + pl->r_dw.bytes + pl->r_ph.bytes + pl->r_pos.bytes +
+                   pl->dpair.bytes +
                    pl->wi.bytes + pl->gwi.bytes + pl->gorder.bytes + pl->gkey_first.bytes + pl->atile.bytes +
                    pl->tile_active.bytes;
 }

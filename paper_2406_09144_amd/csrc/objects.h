@@ -62,6 +62,7 @@ struct fr_plan {
     // sorted visibility records (structure of arrays)
     frmi::DevBuf r_idx;   // uint32 [n_vis]: row * n_chan + chan, bit 31 = conjugate
     frmi::DevBuf r_pos;   // uint32 [n_vis]: record position of visibility row * n_chan + chan, bit 31 = conjugate
+    frmi::DevBuf dpair;   // uint32 [n_vis] (paired degridding): pair list of each degridding item from its start
     frmi::DevBuf r_cell;  // uint32 [n_vis]: (a0 - tu) | (b0 - tv) << 16
     frmi::DevBuf r_du, r_dv, r_dw, r_ph;  // T [n_vis]
     frmi::DevBuf wi;      // WorkItem [n_wi]
@@ -94,6 +95,8 @@ namespace frmi {
 inline bool matrix_spread(const fr_plan *pl) {
     return !pl->fp64 && !pl->vector_spread && pl->W <= 8 && pl->vis_per_run >= 4.0;
 }
+// degridding two records of one base cell per thread (the plan's pair lists)
+inline bool paired_degrid(const fr_plan *pl) { return !pl->fp64 && pl->vis_per_run >= 4.0; }
 
 // gridder.hip
 void plan_build(fr_plan *pl, const double *uvw_m, const double *freq_hz);

@@ -286,9 +286,9 @@ def dense_tracks(n=64, n_bl=12):
 
 @pytest.mark.parametrize("kind", ["dense_tracks", "random_uv"])
 def test_both_spread_kernels_vs_oracle(kind):
-    """Long runs take the matrix-core spread and single-record runs the vector one
-    (the plan reports which); both grid, and the same plans degrid, to the FP32
-    bound against the oracle."""
+    """Long runs take the matrix-core spread and the paired degridding, single-record
+    runs the vector spread and one record per thread (the plan reports which); all
+    meet the FP32 bound against the oracle."""
     import torch
     from paper_2406_09144_amd import api
     c = dense_tracks() if kind == "dense_tracks" else wide_field()
@@ -308,7 +308,8 @@ def test_both_spread_kernels_vs_oracle(kind):
     err = rel(img, ref)
     print(kind, info["records_per_run"], info["matrix_spread"], err)
     assert err < 1e-5, (err, info)
-    # degridding on the same layouts
+    # degridding on the same layouts: long runs two records of a base cell per thread
+    assert info["paired_degrid"] == (1 if long_runs else 0), info
     sky = rng.standard_normal((1, c["nx"], c["ny"]))
     got = api.degrid(pl, torch.from_numpy(sky).to(torch.float32).cuda()).cpu().numpy()
     dref = O.degrid(c["uvw"], c["freq"], c["nx"], c["ny"], c["dx"], c["dy"], sky)
