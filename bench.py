@@ -610,14 +610,15 @@ def main():
     # read once, image, visibilities, weights, uvw)
     roof_hbm.append(hbm_entry("degrid_call", call_bytes("degrid", info, n_vis, obs.n_row, n, n), comp["degrid"]))
     roof_hbm.append(hbm_entry("grid_call", call_bytes("grid", info, n_vis, obs.n_row, n, n), comp["grid"]))
-    # the degridding kernel against the LDS: every visibility reads its W^2 Ww
-    # complex footprint values from the LDS tile, and every item writes its planes'
-    # tiles (halo included) once
+    # the degridding kernel against the LDS: every thread slot (a visibility, or a
+    # pair of visibilities of one base cell when the plan pairs them) reads its
+    # W^2 Ww complex footprint values from the LDS tile, and every item writes its
+    # planes' tiles (halo included) once
     lds = None
     if "degrid" in kern:
         W, Ww = info["support"], info["w_support"]
         ts = info["tile"] + W - 1
-        lds_bytes = n_vis * W * W * Ww * 8 + info["n_workitems"] * Ww * ts * ts * 8
+        lds_bytes = info["degrid_slots"] * W * W * Ww * 8 + info["n_workitems"] * Ww * ts * ts * 8
         ach = lds_bytes / (kern["degrid"]["avg_ms"] * 1e-3) / 1e9
         lds = {"kernel": "degrid", "bound": "lds", "achieved": round(ach, 1), "peak": round(LDS_PEAK_GBS, 1),
                "unit": "GB/s", "frac": round(ach / LDS_PEAK_GBS, 4), "bytes_per_launch": int(lds_bytes),

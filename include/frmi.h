@@ -113,6 +113,8 @@ typedef struct fr_plan_info {
                                >= 4 records per run); 0: on the vector units */
     int paired_degrid;      /* 1: fr_degrid interpolates two records of one base cell per
                                thread from the same tile reads (FP32, >= 4 records per run) */
+    int64_t degrid_slots;   /* footprint interpolations fr_degrid issues: pair-list
+                               entries when paired, else one per visibility */
 } fr_plan_info;
 
 /* Library version string. */

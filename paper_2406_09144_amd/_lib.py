@@ -44,7 +44,7 @@ class fr_plan_info(ctypes.Structure):
         ("n_workitems", ctypes.c_int64), ("resident_bytes", ctypes.c_size_t),
         ("w_taylor", ctypes.c_int),
         ("records_per_run", ctypes.c_double), ("matrix_spread", ctypes.c_int),
-        ("paired_degrid", ctypes.c_int),
+        ("paired_degrid", ctypes.c_int), ("degrid_slots", ctypes.c_int64),
     ]
 
     def as_dict(self):

@@ -360,6 +360,7 @@ int fr_plan_get_info(const fr_plan *pl, fr_plan_info *info) {
     info->records_per_run = pl->vis_per_run;
     info->matrix_spread = frmi::matrix_spread(pl) ? 1 : 0;
     info->paired_degrid = frmi::paired_degrid(pl) ? 1 : 0;
+    info->degrid_slots = pl->degrid_slots;
     FR_API_END
 }
 

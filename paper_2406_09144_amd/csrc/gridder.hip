@@ -1522,6 +1522,7 @@ static void build_records(fr_plan *pl, const DevBuf &d_uvw, const DevBuf &d_freq
     // paired degridding: the sorted keys (bucket and base cell) on the host, to cut
     // the records into pairs of one base cell and the items at kPairsPerItem pairs
     const bool paired = paired_degrid(pl);
+    pl->degrid_slots = paired ? 0 : n;
     std::vector<uint64_t> hkeys;
     std::vector<uint32_t> hpair;
     if (paired) {
@@ -1569,6 +1570,7 @@ static void build_records(fr_plan *pl, const DevBuf &d_uvw, const DevBuf &d_freq
                     }
                     w.count = (int32_t)(j - w.start);
                     w.rows = entries;
+                    pl->degrid_slots += entries;
                     wis.push_back(w);
                     pl->wi_chan[chan + 1] = (int64_t)wis.size();
                 }

@@ -72,6 +72,7 @@ struct fr_plan {
     frmi::DevBuf gwi;        // WorkItem [n_gwi]
     frmi::DevBuf gorder;     // int32 [n_gwi]: per channel, item indices largest first
     double vis_per_run = 0;  // records per run of equal (bucket, base cell)
+    int64_t degrid_slots = 0;  // pair-list entries (paired degridding) or records
     int64_t n_gwi = 0;
     std::vector<int64_t> gwi_chan;
     frmi::DevBuf gkey_first;  // uint32 [n_keys + 1]
