@@ -31,10 +31,14 @@ namespace frmi {
 __host__ __device__ constexpr int padx(int e) { return e + (e >> 5); }
 __host__ __device__ constexpr int plen(int L) { return L + (L >> 5); }
 
-template <typename T>
-__device__ __forceinline__ c2<T> mul_i_sign(c2<T> a, int sign) {
-    // a * (sign * i)
-    return sign < 0 ? mk<T>(a.y, -a.x) : mk<T>(-a.y, a.x);
+// The transform direction SIGN (-1 forward, +1 inverse) is a template argument
+// throughout, so the quarter turns, the internal rotations and the twiddle
+// conjugation compile to plain operand swaps and sign modifiers.
+template <typename T, int SIGN>
+__device__ __forceinline__ c2<T> mul_i_sign(c2<T> a) {
+    // a * (SIGN * i)
+    if constexpr (SIGN < 0) return mk<T>(a.y, -a.x);
+    else return mk<T>(-a.y, a.x);
 }
 
 template <typename T>
@@ -44,80 +48,91 @@ __device__ __forceinline__ void dft2(c2<T> (&v)[2]) {
     v[1] = csub<T>(a, b);
 }
 
-template <typename T>
-__device__ __forceinline__ void dft4(c2<T> (&v)[4], int sign) {
+template <typename T, int SIGN>
+__device__ __forceinline__ void dft4(c2<T> (&v)[4]) {
     c2<T> t0 = cadd<T>(v[0], v[2]);
     c2<T> t1 = csub<T>(v[0], v[2]);
     c2<T> t2 = cadd<T>(v[1], v[3]);
-    c2<T> t3 = mul_i_sign<T>(csub<T>(v[1], v[3]), sign);
+    c2<T> t3 = mul_i_sign<T, SIGN>(csub<T>(v[1], v[3]));
     v[0] = cadd<T>(t0, t2);
     v[2] = csub<T>(t0, t2);
     v[1] = cadd<T>(t1, t3);
     v[3] = csub<T>(t1, t3);
 }
 
-// v * exp(sign 2 pi i m / 16), m < 16, from the exact values of cos and sin at
+// v * exp(SIGN 2 pi i M / 16), M < 16, from the exact values of cos and sin at
 // multiples of pi / 8
-template <typename T>
-__device__ __forceinline__ c2<T> rot16(c2<T> v, int m, int sign) {
+template <typename T, int SIGN, int M>
+__device__ __forceinline__ c2<T> rot16(c2<T> v) {
     constexpr double c1 = 0.92387953251128675613, s1 = 0.38268343236508977173, r2 = 0.70710678118654752440;
-    const double cs[5] = {1.0, c1, r2, s1, 0.0};  // cos(r pi / 8), r = 0..4
-    const int q = m >> 2, r = m & 3;              // m pi / 8 = q pi / 2 + r pi / 8
-    const T c = (T)cs[r], sn = (T)cs[4 - r];      // cos and sin of r pi / 8
-    // rotate by r pi / 8, then by q quarter turns
-    c2<T> w = mk<T>(v.x * c - (sign < 0 ? -1 : 1) * v.y * sn, v.y * c + (sign < 0 ? -1 : 1) * v.x * sn);
-    for (int t = 0; t < q; ++t) w = mul_i_sign<T>(w, sign);
+    constexpr double cs[5] = {1.0, c1, r2, s1, 0.0};  // cos(r pi / 8), r = 0..4
+    constexpr int q = M >> 2, r = M & 3;              // M pi / 8 = q pi / 2 + r pi / 8
+    c2<T> w = v;
+    if constexpr (r != 0) {
+        constexpr T c = (T)cs[r], sn = (T)(SIGN * cs[4 - r]);  // cos and SIGN sin of r pi / 8
+        w = mk<T>(v.x * c - v.y * sn, v.y * c + v.x * sn);
+    }
+    if constexpr (q >= 1) w = mul_i_sign<T, SIGN>(w);
+    if constexpr (q >= 2) w = mul_i_sign<T, SIGN>(w);
+    if constexpr (q >= 3) w = mul_i_sign<T, SIGN>(w);
     return w;
+}
+
+template <typename T, int SIGN, int N2>
+__device__ __forceinline__ void dft16_col(c2<T> (&v)[16], c2<T> (&a)[4][4]) {
+    c2<T> t[4] = {v[N2], v[4 + N2], v[8 + N2], v[12 + N2]};
+    dft4<T, SIGN>(t);
+    a[N2][0] = t[0];
+    a[N2][1] = rot16<T, SIGN, N2 * 1>(t[1]);
+    a[N2][2] = rot16<T, SIGN, N2 * 2>(t[2]);
+    a[N2][3] = rot16<T, SIGN, N2 * 3>(t[3]);
 }
 
 // 16-point DFT as 4 x 4: n = 4 n1 + n2, k = k1 + 4 k2,
 //   X[k1 + 4 k2] = sum_n2 W16^(n2 k1) W4^(n2 k2) sum_n1 x[4 n1 + n2] W4^(n1 k1)
-template <typename T>
-__device__ __forceinline__ void dft16(c2<T> (&v)[16], int sign) {
+template <typename T, int SIGN>
+__device__ __forceinline__ void dft16(c2<T> (&v)[16]) {
     c2<T> a[4][4];
-#pragma unroll
-    for (int n2 = 0; n2 < 4; ++n2) {
-        c2<T> t[4] = {v[n2], v[4 + n2], v[8 + n2], v[12 + n2]};
-        dft4<T>(t, sign);
-#pragma unroll
-        for (int k1 = 0; k1 < 4; ++k1) a[n2][k1] = (n2 * k1) ? rot16<T>(t[k1], n2 * k1, sign) : t[k1];
-    }
+    dft16_col<T, SIGN, 0>(v, a);
+    dft16_col<T, SIGN, 1>(v, a);
+    dft16_col<T, SIGN, 2>(v, a);
+    dft16_col<T, SIGN, 3>(v, a);
 #pragma unroll
     for (int k1 = 0; k1 < 4; ++k1) {
         c2<T> t[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
-        dft4<T>(t, sign);
+        dft4<T, SIGN>(t);
 #pragma unroll
         for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[k2];
     }
 }
 
-// 3-point DFT: w = exp(sign 2 pi i / 3) = -1/2 + sign i sqrt(3)/2, so
-//   X1, X2 = a - (b + c)/2 +- sign i (sqrt(3)/2)(b - c)
-template <typename T>
-__device__ __forceinline__ void dft3(c2<T> (&v)[3], int sign) {
+// 3-point DFT: w = exp(SIGN 2 pi i / 3) = -1/2 + SIGN i sqrt(3)/2, so
+//   X1, X2 = a - (b + c)/2 +- SIGN i (sqrt(3)/2)(b - c)
+template <typename T, int SIGN>
+__device__ __forceinline__ void dft3(c2<T> (&v)[3]) {
     constexpr double h3 = 0.86602540378443864676;  // sqrt(3) / 2
     const c2<T> s = cadd<T>(v[1], v[2]);
     const c2<T> m = mk<T>(v[0].x - T(0.5) * s.x, v[0].y - T(0.5) * s.y);
-    const c2<T> d = mul_i_sign<T>(cscale<T>(csub<T>(v[1], v[2]), T(h3)), sign);
+    const c2<T> d = mul_i_sign<T, SIGN>(cscale<T>(csub<T>(v[1], v[2]), T(h3)));
     v[0] = cadd<T>(v[0], s);
     v[1] = cadd<T>(m, d);
     v[2] = csub<T>(m, d);
 }
 
 // 5-point DFT from the pairs A_r = x_r + x_{5-r}, B_r = x_r - x_{5-r} (r = 1, 2):
-//   X1, X4 = x0 + c1 A1 + c2 A2 +- sign i (s1 B1 + s2 B2)
-//   X2, X3 = x0 + c2 A1 + c1 A2 +- sign i (s2 B1 - s1 B2)
+//   X1, X4 = x0 + c1 A1 + c2 A2 +- SIGN i (s1 B1 + s2 B2)
+//   X2, X3 = x0 + c2 A1 + c1 A2 +- SIGN i (s2 B1 - s1 B2)
 // with c_r = cos(2 pi r / 5), s_r = sin(2 pi r / 5).
-template <typename T>
-__device__ __forceinline__ void dft5(c2<T> (&v)[5], int sign) {
+template <typename T, int SIGN>
+__device__ __forceinline__ void dft5(c2<T> (&v)[5]) {
     constexpr double c1 = 0.30901699437494742410, c2_ = -0.80901699437494742410;
     constexpr double s1 = 0.95105651629515357212, s2 = 0.58778525229247312917;
     const c2<T> A1 = cadd<T>(v[1], v[4]), B1 = csub<T>(v[1], v[4]);
     const c2<T> A2 = cadd<T>(v[2], v[3]), B2 = csub<T>(v[2], v[3]);
     const c2<T> e1 = mk<T>(v[0].x + T(c1) * A1.x + T(c2_) * A2.x, v[0].y + T(c1) * A1.y + T(c2_) * A2.y);
     const c2<T> e2 = mk<T>(v[0].x + T(c2_) * A1.x + T(c1) * A2.x, v[0].y + T(c2_) * A1.y + T(c1) * A2.y);
-    const c2<T> o1 = mul_i_sign<T>(mk<T>(T(s1) * B1.x + T(s2) * B2.x, T(s1) * B1.y + T(s2) * B2.y), sign);
-    const c2<T> o2 = mul_i_sign<T>(mk<T>(T(s2) * B1.x - T(s1) * B2.x, T(s2) * B1.y - T(s1) * B2.y), sign);
+    const c2<T> o1 = mul_i_sign<T, SIGN>(mk<T>(T(s1) * B1.x + T(s2) * B2.x, T(s1) * B1.y + T(s2) * B2.y));
+    const c2<T> o2 = mul_i_sign<T, SIGN>(mk<T>(T(s2) * B1.x - T(s1) * B2.x, T(s2) * B1.y - T(s1) * B2.y));
     v[0] = cadd<T>(v[0], cadd<T>(A1, A2));
     v[1] = cadd<T>(e1, o1);
     v[4] = csub<T>(e1, o1);
@@ -125,13 +140,13 @@ __device__ __forceinline__ void dft5(c2<T> (&v)[5], int sign) {
     v[3] = csub<T>(e2, o2);
 }
 
-template <typename T, int R>
-__device__ __forceinline__ void dftR(c2<T> (&v)[R], int sign) {
+template <typename T, int R, int SIGN>
+__device__ __forceinline__ void dftR(c2<T> (&v)[R]) {
     if constexpr (R == 2) dft2<T>(v);
-    else if constexpr (R == 3) dft3<T>(v, sign);
-    else if constexpr (R == 4) dft4<T>(v, sign);
-    else if constexpr (R == 5) dft5<T>(v, sign);
-    else dft16<T>(v, sign);
+    else if constexpr (R == 3) dft3<T, SIGN>(v);
+    else if constexpr (R == 4) dft4<T, SIGN>(v);
+    else if constexpr (R == 5) dft5<T, SIGN>(v);
+    else dft16<T, SIGN>(v);
 }
 
 // x / ODD for x >= 0 (a multiply-high for ODD = 3, 5; nothing for ODD = 1)
@@ -144,9 +159,9 @@ template <int ODD> __device__ __forceinline__ int div_odd(int x) {
 // apart.  R is 16, 4 or 2 (a power-of-two stage, Ns = 2^log2Ns) or R = ODD (the
 // final odd stage, Ns = 2^log2P).
 // BPT: butterflies per thread this launch can need (host-checked).
-template <typename T, int R, int NTHR, int BPT, int ODD>
+template <typename T, int R, int NTHR, int BPT, int ODD, int SIGN>
 __device__ __forceinline__ void stockham_stage(c2<T> *buf, int ld, int nlines, int log2P, int log2Ns,
-                                               int sign, const c2<T> *__restrict__ tw) {
+                                               const c2<T> *__restrict__ tw) {
     constexpr bool kOddStage = (R == 3 || R == 5);
     static_assert(!kOddStage || R == ODD, "the odd stage takes the odd factor of the length");
     constexpr int LOG2R = kOddStage ? 0 : (R == 2) ? 1 : (R == 4) ? 2 : 4;
@@ -174,11 +189,11 @@ __device__ __forceinline__ void stockham_stage(c2<T> *buf, int ld, int nlines, i
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
                     c2<T> w = tw[(r * k * QODD) << twshift];
-                    if (sign > 0) w.y = -w.y;
+                    if constexpr (SIGN > 0) w.y = -w.y;
                     v[b][r] = cmul<T>(v[b][r], w);
                 }
             }
-            dftR<T, R>(v[b], sign);
+            dftR<T, R, SIGN>(v[b]);
             obase[b] = (line << 16) | (((j >> log2Ns) << (log2Ns + LOG2R)) + k);  // line, element
         }
     }
@@ -199,25 +214,32 @@ __device__ __forceinline__ void stockham_stage(c2<T> *buf, int ld, int nlines, i
 // stride ld >= plen(L), element e at padx(e); nlines < 32768).  Caller must
 // __syncthreads() after filling the lines; returns after a barrier.
 // Requires nlines * L <= 4 * BPT * NTHR.
-template <typename T, int NTHR, int BPT, int ODD = 1>
-__device__ __forceinline__ void lds_fft(c2<T> *buf, int ld, int nlines, int log2P, int sign,
-                                        const c2<T> *__restrict__ tw) {
+template <typename T, int NTHR, int BPT, int ODD, int SIGN>
+__device__ __forceinline__ void lds_fft_dir(c2<T> *buf, int ld, int nlines, int log2P,
+                                            const c2<T> *__restrict__ tw) {
     static_assert(ODD == 1 || ODD == 3 || ODD == 5, "line lengths are 2^p, 3 2^p or 5 2^p");
     // radix-16 stages (two radix-4 levels in registers, half the LDS passes),
     // then radix 4 and 2 for the remaining power of two, then the odd factor
     constexpr int BPT16 = BPT / 4 > 0 ? BPT / 4 : 1;
     int log2Ns = 0;
     while (log2P - log2Ns >= 4) {
-        stockham_stage<T, 16, NTHR, BPT16, ODD>(buf, ld, nlines, log2P, log2Ns, sign, tw);
+        stockham_stage<T, 16, NTHR, BPT16, ODD, SIGN>(buf, ld, nlines, log2P, log2Ns, tw);
         log2Ns += 4;
     }
     if (log2P - log2Ns >= 2) {
-        stockham_stage<T, 4, NTHR, BPT, ODD>(buf, ld, nlines, log2P, log2Ns, sign, tw);
+        stockham_stage<T, 4, NTHR, BPT, ODD, SIGN>(buf, ld, nlines, log2P, log2Ns, tw);
         log2Ns += 2;
     }
-    if (log2P - log2Ns == 1) stockham_stage<T, 2, NTHR, 2 * BPT, ODD>(buf, ld, nlines, log2P, log2Ns, sign, tw);
+    if (log2P - log2Ns == 1) stockham_stage<T, 2, NTHR, 2 * BPT, ODD, SIGN>(buf, ld, nlines, log2P, log2Ns, tw);
     if constexpr (ODD > 1)
-        stockham_stage<T, ODD, NTHR, (4 * BPT + ODD - 1) / ODD, ODD>(buf, ld, nlines, log2P, log2P, sign, tw);
+        stockham_stage<T, ODD, NTHR, (4 * BPT + ODD - 1) / ODD, ODD, SIGN>(buf, ld, nlines, log2P, log2P, tw);
+}
+
+template <typename T, int NTHR, int BPT, int ODD = 1>
+__device__ __forceinline__ void lds_fft(c2<T> *buf, int ld, int nlines, int log2P, int sign,
+                                        const c2<T> *__restrict__ tw) {
+    if (sign < 0) lds_fft_dir<T, NTHR, BPT, ODD, -1>(buf, ld, nlines, log2P, tw);
+    else lds_fft_dir<T, NTHR, BPT, ODD, +1>(buf, ld, nlines, log2P, tw);
 }
 
 // Element idx of a batch of lines of length L = ODD 2^log2P: line idx / L, element idx % L.
