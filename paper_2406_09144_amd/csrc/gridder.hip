@@ -130,6 +130,15 @@ __global__ void k_count_runs(const uint64_t *__restrict__ k64, int64_t n, unsign
     if ((threadIdx.x & 63) == 0 && b) atomicAdd(count, (unsigned long long)__popcll(b));
 }
 
+// flag[i] = 1 where sorted record i starts a run (its bucket and base cell differ
+// from the previous record's, or i = 0), for records first .. first + n - 1
+__global__ void k_run_flags(const uint64_t *__restrict__ k64, int64_t first, int64_t n, uint8_t *__restrict__ flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t j = first + i;
+    flag[i] = (j == 0 || k64[j] != k64[j - 1]) ? 1 : 0;
+}
+
 // rows of the tile (halo included) that gridding item i touches: its records are
 // sorted by base cell, so the first and last hold the smallest and largest
 // base row
@@ -432,7 +441,7 @@ template <typename T, int W> constexpr int grid_reg_planes() {
 // imaginary arrays.
 template <typename T, int W, int NTHR>
 __global__ __launch_bounds__(NTHR) void k_grid_partial(const WorkItem *__restrict__ wis,
-                                                       const int32_t *__restrict__ order, c2<T> *__restrict__ partial,
+                                                       const int32_t *__restrict__ seg, c2<T> *__restrict__ partial,
                                                        int Ww, int ppass, T beta, T wbeta, int coplanar,
                                                        int taylor, const uint32_t *__restrict__ r_cell,
                                                        const T *__restrict__ r_du, const T *__restrict__ r_dv,
@@ -448,9 +457,6 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial(const WorkItem *__restric
     constexpr int NWAVE = NTHR / 64;
     constexpr int PR = grid_reg_planes<T, W>() < W ? grid_reg_planes<T, W>() : W;
     constexpr int VPB = 64 / W;  // visibilities per kernel-evaluation step
-    // items run largest first (order), each writing its own slot of the partials
-    const int item = order[blockIdx.x];
-    const WorkItem it = wis[item];
     // fixed-point exponent from the bound on every contribution
     __shared__ float wmax[NWAVE];
     {
@@ -463,155 +469,160 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial(const WorkItem *__restric
     float ymax = 0.0f;
 #pragma unroll
     for (int q = 0; q < NWAVE; ++q) ymax = fmaxf(ymax, wmax[q]);
-    int kexp = 0;
-    if (ymax > 0.0f && ymax <= 3.0e38f) {
-        int e;
-        frexp(2.0 * (double)ymax * (double)it.count, &e);  // bound < 2^(e-1)
-        kexp = 62 - e;
-    }
-    c2<T> *out = partial + (int64_t)item * Ww * TT;
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar loop control
-    const T two_over_W = T(2) / T(W);
-    int ca[NCELL], cb[NCELL], au[NCELL], av[NCELL];
+    // the workgroup's items: consecutive items of about equal estimated cost,
+    // each writing its own slot of the partials
+    for (int item = seg[blockIdx.x]; item < seg[blockIdx.x + 1]; ++item) {
+        const WorkItem it = wis[item];
+        int kexp = 0;
+        if (ymax > 0.0f && ymax <= 3.0e38f) {
+            int e;
+            frexp(2.0 * (double)ymax * (double)it.count, &e);  // bound < 2^(e-1)
+            kexp = 62 - e;
+        }
+        c2<T> *out = partial + (int64_t)item * Ww * TT;
+        const int lane = threadIdx.x & 63;
+        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform: scalar loop control
+        const T two_over_W = T(2) / T(W);
+        int ca[NCELL], cb[NCELL], au[NCELL], av[NCELL];
 #pragma unroll
-    for (int q = 0; q < NCELL; ++q) {
-        const int c = lane + 64 * q;
-        ca[q] = c < W * W ? c / W : -1;
-        cb[q] = c < W * W ? c - (c / W) * W : 0;
-        au[q] = 4 * max(ca[q], 0);
-        av[q] = 4 * cb[q];
-    }
-    // this wavefront's contiguous share of the item
-    const int share = (it.count + NWAVE - 1) / NWAVE;
-    const int v_begin = min(it.count, wave * share), v_end = min(it.count, v_begin + share);
-    const int pp = min(ppass, PR);
-    for (int g0 = 0; g0 < Ww; g0 += pp) {
-        const int np = min(pp, Ww - g0);
-        for (int q = threadIdx.x; q < np * 2 * TT; q += NTHR) tile[q] = 0;
-        __syncthreads();
-        T acc_re[NCELL][PR], acc_im[NCELL][PR];
+        for (int q = 0; q < NCELL; ++q) {
+            const int c = lane + 64 * q;
+            ca[q] = c < W * W ? c / W : -1;
+            cb[q] = c < W * W ? c - (c / W) * W : 0;
+            au[q] = 4 * max(ca[q], 0);
+            av[q] = 4 * cb[q];
+        }
+        // this wavefront's contiguous share of the item
+        const int share = (it.count + NWAVE - 1) / NWAVE;
+        const int v_begin = min(it.count, wave * share), v_end = min(it.count, v_begin + share);
+        const int pp = min(ppass, PR);
+        for (int g0 = 0; g0 < Ww; g0 += pp) {
+            const int np = min(pp, Ww - g0);
+            for (int q = threadIdx.x; q < np * 2 * TT; q += NTHR) tile[q] = 0;
+            __syncthreads();
+            T acc_re[NCELL][PR], acc_im[NCELL][PR];
 #pragma unroll
-        for (int q = 0; q < NCELL; ++q)
+            for (int q = 0; q < NCELL; ++q)
 #pragma unroll
-            for (int p = 0; p < PR; ++p) acc_re[q][p] = acc_im[q][p] = T(0);
-        int run_cell = -1;  // base cell of the run held in acc (wave-uniform)
-        auto flush = [&]() {
-            const int ru = run_cell & 0xffff, rv = run_cell >> 16;
-#pragma unroll
-            for (int q = 0; q < NCELL; ++q) {
-                if (ca[q] < 0) continue;
-                const int off = (ru + ca[q]) * TS + rv + cb[q];
-#pragma unroll
-                for (int p = 0; p < PR; ++p) {
-                    if (p >= np) break;
-                    unsigned long long *tp = reinterpret_cast<unsigned long long *>(tile + 2 * p * TT);
-                    const long long vr = (long long)rint(ldexp((double)acc_re[q][p], kexp));
-                    const long long vi = (long long)rint(ldexp((double)acc_im[q][p], kexp));
-                    atomicAdd(tp + off, (unsigned long long)vr);
-                    atomicAdd(tp + TT + off, (unsigned long long)vi);
-                    acc_re[q][p] = acc_im[q][p] = T(0);
-                }
-            }
-        };
-        for (int b0 = v_begin; b0 < v_end; b0 += 64) {
-            // lane k loads visibility b0 + k (one memory round trip per 64) and
-            // forms its weighted value y and the w-kernel weight of every plane
-            // of the pass; the walk below broadcasts them with readlane
-            const int nb = min(64, v_end - b0);
-            int l_cell = 0;
-            T l_xu = T(0), l_xv = T(0);
-            c2<T> l_y = mk<T>(T(0), T(0));
-            T l_kw[PR];
-#pragma unroll
-            for (int p = 0; p < PR; ++p) l_kw[p] = T(p == 0 ? 1 : 0);
-            if (lane < nb) {
-                const int64_t pos = it.start + b0 + lane;
-                l_cell = (int)r_cell[pos];
-                c2<T> y = y_rec[pos];  // weighted (w < 0: conjugated) value in record order
-                l_xu = r_du[pos];
-                l_xv = r_dv[pos];
-                if (!coplanar) {
-                    if (!sorted_in) {
-                        T sn, cs;
-                        sincos_cycles(r_ph[pos], &sn, &cs);
-                        y = cmul<T>(y, mk<T>(cs, sn));
-                    }
-                    const T xw = r_dw[pos];
-#pragma unroll
-                    for (int p = 0; p < PR; ++p)
-                        l_kw[p] = p < np ? plane_weight<T>(xw, g0 + p, Ww, wbeta, taylor) : T(0);
-                }
-                l_y = y;
-            }
-            // the separable kernel values: lane v W + a (v < VPB, a < W) evaluates
-            // psi(du - a) and psi(dv - a) of visibility k0 + v, and lane (a, b) of
-            // the walk fetches its pair with two lane permutes
-            for (int k0 = 0; k0 < nb; k0 += VPB) {
-                const int vv = lane / W, aa = lane - (lane / W) * W;
-                const int src = min(k0 + vv, 63);
-                const T xu_v = __shfl(l_xu, src, 64), xv_v = __shfl(l_xv, src, 64);
-                const T phu = es_eval<T>((xu_v - T(aa)) * two_over_W, beta);
-                const T phv = es_eval<T>((xv_v - T(aa)) * two_over_W, beta);
-                const int kend = min(k0 + VPB, nb);
-                // the permutes for visibility k + 1 are issued before the work on k
-                // (byte addresses: lane base + a of the value psi(d - a))
-                T nu_[NCELL], nv_[NCELL];
+                for (int p = 0; p < PR; ++p) acc_re[q][p] = acc_im[q][p] = T(0);
+            int run_cell = -1;  // base cell of the run held in acc (wave-uniform)
+            auto flush = [&]() {
+                const int ru = run_cell & 0xffff, rv = run_cell >> 16;
 #pragma unroll
                 for (int q = 0; q < NCELL; ++q) {
-                    nu_[q] = lane_permute(phu, au[q]);
-                    nv_[q] = lane_permute(phv, av[q]);
+                    if (ca[q] < 0) continue;
+                    const int off = (ru + ca[q]) * TS + rv + cb[q];
+#pragma unroll
+                    for (int p = 0; p < PR; ++p) {
+                        if (p >= np) break;
+                        unsigned long long *tp = reinterpret_cast<unsigned long long *>(tile + 2 * p * TT);
+                        const long long vr = (long long)rint(ldexp((double)acc_re[q][p], kexp));
+                        const long long vi = (long long)rint(ldexp((double)acc_im[q][p], kexp));
+                        atomicAdd(tp + off, (unsigned long long)vr);
+                        atomicAdd(tp + TT + off, (unsigned long long)vi);
+                        acc_re[q][p] = acc_im[q][p] = T(0);
+                    }
                 }
-                for (int k = k0; k < kend; ++k) {
-                    T cu_[NCELL], cv_[NCELL];
+            };
+            for (int b0 = v_begin; b0 < v_end; b0 += 64) {
+                // lane k loads visibility b0 + k (one memory round trip per 64) and
+                // forms its weighted value y and the w-kernel weight of every plane
+                // of the pass; the walk below broadcasts them with readlane
+                const int nb = min(64, v_end - b0);
+                int l_cell = 0;
+                T l_xu = T(0), l_xv = T(0);
+                c2<T> l_y = mk<T>(T(0), T(0));
+                T l_kw[PR];
+#pragma unroll
+                for (int p = 0; p < PR; ++p) l_kw[p] = T(p == 0 ? 1 : 0);
+                if (lane < nb) {
+                    const int64_t pos = it.start + b0 + lane;
+                    l_cell = (int)r_cell[pos];
+                    c2<T> y = y_rec[pos];  // weighted (w < 0: conjugated) value in record order
+                    l_xu = r_du[pos];
+                    l_xv = r_dv[pos];
+                    if (!coplanar) {
+                        if (!sorted_in) {
+                            T sn, cs;
+                            sincos_cycles(r_ph[pos], &sn, &cs);
+                            y = cmul<T>(y, mk<T>(cs, sn));
+                        }
+                        const T xw = r_dw[pos];
+#pragma unroll
+                        for (int p = 0; p < PR; ++p)
+                            l_kw[p] = p < np ? plane_weight<T>(xw, g0 + p, Ww, wbeta, taylor) : T(0);
+                    }
+                    l_y = y;
+                }
+                // the separable kernel values: lane v W + a (v < VPB, a < W) evaluates
+                // psi(du - a) and psi(dv - a) of visibility k0 + v, and lane (a, b) of
+                // the walk fetches its pair with two lane permutes
+                for (int k0 = 0; k0 < nb; k0 += VPB) {
+                    const int vv = lane / W, aa = lane - (lane / W) * W;
+                    const int src = min(k0 + vv, 63);
+                    const T xu_v = __shfl(l_xu, src, 64), xv_v = __shfl(l_xv, src, 64);
+                    const T phu = es_eval<T>((xu_v - T(aa)) * two_over_W, beta);
+                    const T phv = es_eval<T>((xv_v - T(aa)) * two_over_W, beta);
+                    const int kend = min(k0 + VPB, nb);
+                    // the permutes for visibility k + 1 are issued before the work on k
+                    // (byte addresses: lane base + a of the value psi(d - a))
+                    T nu_[NCELL], nv_[NCELL];
 #pragma unroll
                     for (int q = 0; q < NCELL; ++q) {
-                        cu_[q] = nu_[q];
-                        cv_[q] = nv_[q];
+                        nu_[q] = lane_permute(phu, au[q]);
+                        nv_[q] = lane_permute(phv, av[q]);
                     }
-                    if (k + 1 < kend) {
-                        const int base1 = (k + 1 - k0) * W * 4;
+                    for (int k = k0; k < kend; ++k) {
+                        T cu_[NCELL], cv_[NCELL];
 #pragma unroll
                         for (int q = 0; q < NCELL; ++q) {
-                            nu_[q] = lane_permute(phu, base1 + au[q]);
-                            nv_[q] = lane_permute(phv, base1 + av[q]);
+                            cu_[q] = nu_[q];
+                            cv_[q] = nv_[q];
                         }
-                    }
-                    const int cell = __builtin_amdgcn_readlane(l_cell, k);
-                    if (cell != run_cell) {
-                        if (run_cell >= 0) flush();
-                        run_cell = cell;
-                    }
-                    const T yx = wave_bcast(l_y.x, k), yy = wave_bcast(l_y.y, k);
-                    T kw[PR];
+                        if (k + 1 < kend) {
+                            const int base1 = (k + 1 - k0) * W * 4;
 #pragma unroll
-                    for (int p = 0; p < PR; ++p) kw[p] = wave_bcast(l_kw[p], k);
-                    // lanes beyond the footprint (ca < 0) accumulate values that
-                    // are never flushed
+                            for (int q = 0; q < NCELL; ++q) {
+                                nu_[q] = lane_permute(phu, base1 + au[q]);
+                                nv_[q] = lane_permute(phv, base1 + av[q]);
+                            }
+                        }
+                        const int cell = __builtin_amdgcn_readlane(l_cell, k);
+                        if (cell != run_cell) {
+                            if (run_cell >= 0) flush();
+                            run_cell = cell;
+                        }
+                        const T yx = wave_bcast(l_y.x, k), yy = wave_bcast(l_y.y, k);
+                        T kw[PR];
 #pragma unroll
-                    for (int q = 0; q < NCELL; ++q) {
-                        const T w = cu_[q] * cv_[q];
-                        const T wr = w * yx, wi = w * yy;
+                        for (int p = 0; p < PR; ++p) kw[p] = wave_bcast(l_kw[p], k);
+                        // lanes beyond the footprint (ca < 0) accumulate values that
+                        // are never flushed
 #pragma unroll
-                        for (int p = 0; p < PR; ++p) {
-                            acc_re[q][p] += wr * kw[p];
-                            acc_im[q][p] += wi * kw[p];
+                        for (int q = 0; q < NCELL; ++q) {
+                            const T w = cu_[q] * cv_[q];
+                            const T wr = w * yx, wi = w * yy;
+#pragma unroll
+                            for (int p = 0; p < PR; ++p) {
+                                acc_re[q][p] += wr * kw[p];
+                                acc_im[q][p] += wi * kw[p];
+                            }
                         }
                     }
                 }
             }
+            if (run_cell >= 0) flush();
+            __syncthreads();
+            // only the rows the item touched are stored (the assembly reads no others)
+            const int r0 = it.rows & 0xffff, r1 = it.rows >> 16;
+            const int band = (r1 - r0 + 1) * TS;
+            for (int q = threadIdx.x; q < np * band; q += NTHR) {
+                const int p = q / band, r = r0 * TS + (q - p * band);
+                out[(int64_t)(g0 + p) * TT + r] = mk<T>((T)ldexp((double)tile[2 * p * TT + r], -kexp),
+                                                        (T)ldexp((double)tile[2 * p * TT + TT + r], -kexp));
+            }
+            __syncthreads();
         }
-        if (run_cell >= 0) flush();
-        __syncthreads();
-        // only the rows the item touched are stored (the assembly reads no others)
-        const int r0 = it.rows & 0xffff, r1 = it.rows >> 16;
-        const int band = (r1 - r0 + 1) * TS;
-        for (int q = threadIdx.x; q < np * band; q += NTHR) {
-            const int p = q / band, r = r0 * TS + (q - p * band);
-            out[(int64_t)(g0 + p) * TT + r] = mk<T>((T)ldexp((double)tile[2 * p * TT + r], -kexp),
-                                                    (T)ldexp((double)tile[2 * p * TT + TT + r], -kexp));
-        }
-        __syncthreads();
     }
 }
 
@@ -631,7 +642,7 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial(const WorkItem *__restric
 // the band output are as in k_grid_partial.
 template <int W, int NTHR>
 __global__ __launch_bounds__(NTHR) void k_grid_partial_mfma(
-    const WorkItem *__restrict__ wis, const int32_t *__restrict__ order, c2<float> *__restrict__ partial, int Ww,
+    const WorkItem *__restrict__ wis, const int32_t *__restrict__ seg, c2<float> *__restrict__ partial, int Ww,
     int ppass, float beta, float wbeta,
     int coplanar, int taylor, const uint32_t *__restrict__ r_cell,
     const float *__restrict__ r_du, const float *__restrict__ r_dv, const float *__restrict__ r_dw,
@@ -645,8 +656,6 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial_mfma(
     constexpr int TT = TS * TS;
     constexpr int NWAVE = NTHR / 64;
     constexpr int NBLK = (W * W + 15) / 16;  // blocks of 16 cells
-    const int item = order[blockIdx.x];  // items run largest first
-    const WorkItem it = wis[item];
     __shared__ float wmax[NWAVE];
     {
         float m = 0.0f;
@@ -658,165 +667,173 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial_mfma(
     float ymax = 0.0f;
 #pragma unroll
     for (int q = 0; q < NWAVE; ++q) ymax = fmaxf(ymax, wmax[q]);
-    int kexp = 0;
-    if (ymax > 0.0f && ymax <= 3.0e38f) {
-        int e;
-        frexp(2.0 * (double)ymax * (double)it.count, &e);  // bound < 2^(e-1)
-        kexp = 62 - e;
-    }
-    c2<float> *out = partial + (int64_t)item * Ww * TT;
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const float two_over_W = 2.0f / (float)W;
-    // A operand: row (cell) lane % 16 of each block, column (visibility) lane / 16
-    const int kk = lane >> 4;
-    int a_addr[NBLK], b_addr[NBLK];
+    // the workgroup's items: consecutive items of about equal estimated cost,
+    // each writing its own slot of the partials
+    for (int item = seg[blockIdx.x]; item < seg[blockIdx.x + 1]; ++item) {
+        const WorkItem it = wis[item];
+        int kexp = 0;
+        if (ymax > 0.0f && ymax <= 3.0e38f) {
+            int e;
+            frexp(2.0 * (double)ymax * (double)it.count, &e);  // bound < 2^(e-1)
+            kexp = 62 - e;
+        }
+        c2<float> *out = partial + (int64_t)item * Ww * TT;
+        const int lane = threadIdx.x & 63;
+        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        const float two_over_W = 2.0f / (float)W;
+        // A operand: row (cell) lane % 16 of each block, column (visibility) lane / 16
+        const int kk = lane >> 4;
+        int a_addr[NBLK], b_addr[NBLK];
 #pragma unroll
-    for (int blk = 0; blk < NBLK; ++blk) {
-        const int c = 16 * blk + (lane & 15);
-        const bool ok = c < W * W;
-        const int ca = ok ? c / W : 0, cb = ok ? c - (c / W) * W : 0;
-        a_addr[blk] = 4 * ca;  // byte offset of psi(du - a) inside a visibility's 8 lanes
-        b_addr[blk] = 4 * cb;
-    }
-    // B operand: column n = lane % 16 -> plane n / 2, real or imaginary part
-    const int n_col = lane & 15, p_col = n_col >> 1, im_col = n_col & 1;
-    // D: lane holds cells 16 blk + 4 (lane / 16) + r of column n_col
-    const int share = (it.count + NWAVE - 1) / NWAVE;
-    const int v_begin = min(it.count, wave * share), v_end = min(it.count, v_begin + share);
-    const int pp = min(ppass, 8);
-    for (int g0 = 0; g0 < Ww; g0 += pp) {
-        const int np = min(pp, Ww - g0);
-        for (int q = threadIdx.x; q < np * 2 * TT; q += NTHR) tile[q] = 0;
-        __syncthreads();
-        v4f acc[NBLK];
-#pragma unroll
-        for (int blk = 0; blk < NBLK; ++blk) acc[blk] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-        int run_cell = -1;
-        auto flush = [&]() {
-            const int ru = run_cell & 0xffff, rv = run_cell >> 16;
-            if (p_col < np) {
-                long long *tp = tile + (2 * p_col + im_col) * TT;
-#pragma unroll
-                for (int blk = 0; blk < NBLK; ++blk)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int c = 16 * blk + 4 * kk + r;
-                        if (c < W * W) {
-                            const int ca = c / W, cb = c - (c / W) * W;
-                            const long long v = (long long)rint(ldexp((double)acc[blk][r], kexp));
-                            atomicAdd(reinterpret_cast<unsigned long long *>(tp + (ru + ca) * TS + rv + cb),
-                                      (unsigned long long)v);
-                        }
-                    }
-            }
+        for (int blk = 0; blk < NBLK; ++blk) {
+            const int c = 16 * blk + (lane & 15);
+            const bool ok = c < W * W;
+            const int ca = ok ? c / W : 0, cb = ok ? c - (c / W) * W : 0;
+            a_addr[blk] = 4 * ca;  // byte offset of psi(du - a) inside a visibility's 8 lanes
+            b_addr[blk] = 4 * cb;
+        }
+        // B operand: column n = lane % 16 -> plane n / 2, real or imaginary part
+        const int n_col = lane & 15, p_col = n_col >> 1, im_col = n_col & 1;
+        // D: lane holds cells 16 blk + 4 (lane / 16) + r of column n_col
+        const int share = (it.count + NWAVE - 1) / NWAVE;
+        const int v_begin = min(it.count, wave * share), v_end = min(it.count, v_begin + share);
+        const int pp = min(ppass, 8);
+        for (int g0 = 0; g0 < Ww; g0 += pp) {
+            const int np = min(pp, Ww - g0);
+            for (int q = threadIdx.x; q < np * 2 * TT; q += NTHR) tile[q] = 0;
+            __syncthreads();
+            v4f acc[NBLK];
 #pragma unroll
             for (int blk = 0; blk < NBLK; ++blk) acc[blk] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
-        };
-        for (int b0 = v_begin; b0 < v_end; b0 += 64) {
-            const int nb = min(64, v_end - b0);
-            int l_cell = 0;
-            float l_xu = 0.0f, l_xv = 0.0f, l_xw = 0.0f;
-            c2<float> l_y = mk<float>(0.0f, 0.0f);
-            if (lane < nb) {
-                const int64_t pos = it.start + b0 + lane;
-                l_cell = (int)r_cell[pos];
-                c2<float> y = y_rec[pos];  // weighted (w < 0: conjugated) value in record order
-                l_xu = r_du[pos];
-                l_xv = r_dv[pos];
-                if (!coplanar) {
-                    if (!sorted_in) {
-                        float sn, cs;
-                        sincos_cycles(r_ph[pos], &sn, &cs);
-                        y = cmul<float>(y, mk<float>(cs, sn));
+            int run_cell = -1;
+            auto flush = [&]() {
+                const int ru = run_cell & 0xffff, rv = run_cell >> 16;
+                if (p_col < np) {
+                    long long *tp = tile + (2 * p_col + im_col) * TT;
+#pragma unroll
+                    for (int blk = 0; blk < NBLK; ++blk)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int c = 16 * blk + 4 * kk + r;
+                            if (c < W * W) {
+                                const int ca = c / W, cb = c - (c / W) * W;
+                                const long long v = (long long)rint(ldexp((double)acc[blk][r], kexp));
+                                atomicAdd(reinterpret_cast<unsigned long long *>(tp + (ru + ca) * TS + rv + cb),
+                                          (unsigned long long)v);
+                            }
+                        }
+                }
+#pragma unroll
+                for (int blk = 0; blk < NBLK; ++blk) acc[blk] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+            };
+            for (int b0 = v_begin; b0 < v_end; b0 += 64) {
+                const int nb = min(64, v_end - b0);
+                int l_cell = 0;
+                float l_xu = 0.0f, l_xv = 0.0f, l_xw = 0.0f;
+                c2<float> l_y = mk<float>(0.0f, 0.0f);
+                if (lane < nb) {
+                    const int64_t pos = it.start + b0 + lane;
+                    l_cell = (int)r_cell[pos];
+                    c2<float> y = y_rec[pos];  // weighted (w < 0: conjugated) value in record order
+                    l_xu = r_du[pos];
+                    l_xv = r_dv[pos];
+                    if (!coplanar) {
+                        if (!sorted_in) {
+                            float sn, cs;
+                            sincos_cycles(r_ph[pos], &sn, &cs);
+                            y = cmul<float>(y, mk<float>(cs, sn));
+                        }
+                        l_xw = r_dw[pos];
                     }
-                    l_xw = r_dw[pos];
+                    l_y = y;
                 }
-                l_y = y;
-            }
-            // records that start a run (base cell differs from the previous record's)
-            const int prev_cell = __shfl(l_cell, lane > 0 ? lane - 1 : 0, 64);
-            const unsigned long long starts = __ballot(lane < nb && (lane == 0 || l_cell != prev_cell));
-            for (int k0 = 0; k0 < nb; k0 += 8) {
-                // 1-D kernel values of visibilities k0 .. k0 + 7: lane 8 v + a
-                const int src = min(k0 + (lane >> 3), 63), ta = lane & 7;
-                const float xu_v = __shfl(l_xu, src, 64), xv_v = __shfl(l_xv, src, 64);
-                const float phu = ta < W ? es_eval<float>((xu_v - (float)ta) * two_over_W, beta) : 0.0f;
-                const float phv = ta < W ? es_eval<float>((xv_v - (float)ta) * two_over_W, beta) : 0.0f;
-                // plane weights of the same visibilities: lane 8 v + a holds plane g0 + a
-                float phw = 1.0f;
-                if (!coplanar) {
-                    const float xw_v = __shfl(l_xw, src, 64);
-                    phw = ta < np ? plane_weight<float>(xw_v, g0 + ta, Ww, wbeta, taylor) : 0.0f;
-                }
-                // operands of both halves of the group, gathered once for all its
-                // run segments (lanes outside a segment get B = 0).  All lane
-                // permutes are issued before the first product, so their latency
-                // is paid once per group rather than once per block.
-                float ua[2][NBLK], va[2][NBLK], kwa[2], yxa[2], yya[2];
-#pragma unroll
-                for (int s = 0; s < 2; ++s) {
-                    const int q = k0 + 4 * s + kk;  // this lane's visibility in A and B
-                    const int sq = min(q, 63);
-                    const int vbase = 32 * (4 * s + kk);  // byte offset of visibility q's 8 lanes
-                    yxa[s] = __shfl(l_y.x, sq, 64);
-                    yya[s] = __shfl(l_y.y, sq, 64);
-                    kwa[s] = lane_permute(phw, vbase + 4 * p_col);
-#pragma unroll
-                    for (int blk = 0; blk < NBLK; ++blk) {
-                        ua[s][blk] = lane_permute(phu, vbase + a_addr[blk]);
-                        va[s][blk] = lane_permute(phv, vbase + b_addr[blk]);
+                // records that start a run (base cell differs from the previous record's)
+                const int prev_cell = __shfl(l_cell, lane > 0 ? lane - 1 : 0, 64);
+                const unsigned long long starts = __ballot(lane < nb && (lane == 0 || l_cell != prev_cell));
+                for (int k0 = 0; k0 < nb; k0 += 8) {
+                    // 1-D kernel values of visibilities k0 .. k0 + 7: lane 8 v + a
+                    const int src = min(k0 + (lane >> 3), 63), ta = lane & 7;
+                    const float xu_v = __shfl(l_xu, src, 64), xv_v = __shfl(l_xv, src, 64);
+                    const float phu = ta < W ? es_eval<float>((xu_v - (float)ta) * two_over_W, beta) : 0.0f;
+                    const float phv = ta < W ? es_eval<float>((xv_v - (float)ta) * two_over_W, beta) : 0.0f;
+                    // plane weights of the same visibilities: lane 8 v + a holds plane g0 + a
+                    float phw = 1.0f;
+                    if (!coplanar) {
+                        const float xw_v = __shfl(l_xw, src, 64);
+                        phw = ta < np ? plane_weight<float>(xw_v, g0 + ta, Ww, wbeta, taylor) : 0.0f;
                     }
-                }
-                // A: psi(du_q - a) psi(dv_q - b) of the lane's cell in each block
-                // (finite everywhere; rows of cells beyond W^2 are never flushed);
-                // B before the segment mask: y_q times its plane-(g0 + p_col) weight
-                float aop[2][NBLK], bop[2];
-#pragma unroll
-                for (int s = 0; s < 2; ++s) {
-                    bop[s] = kwa[s] * (im_col ? yya[s] : yxa[s]);
-#pragma unroll
-                    for (int blk = 0; blk < NBLK; ++blk) aop[s][blk] = ua[s][blk] * va[s][blk];
-                }
-                const int kend = min(k0 + 8, nb);
-                int k = k0;
-                while (k < kend) {
-                    // the run segment [k, ke) of equal base cells inside this group
-                    const int cell = __builtin_amdgcn_readlane(l_cell, k);
-                    if (cell != run_cell) {
-                        if (run_cell >= 0) flush();
-                        run_cell = cell;
-                    }
-                    // the segment ends at the next run start inside the group
-                    // (shift counts stay below 64: k < kend <= 64)
-                    const unsigned long long above = (k >= 63) ? 0ull : (~0ull << (k + 1));
-                    const unsigned long long below = (kend >= 64) ? ~0ull : ((1ull << kend) - 1ull);
-                    const unsigned long long later = starts & above & below;
-                    const int ke = later ? __builtin_ctzll(later) : kend;  // k < ke <= kend
+                    // operands of both halves of the group, gathered once for all its
+                    // run segments (lanes outside a segment get B = 0).  All lane
+                    // permutes are issued before the first product, so their latency
+                    // is paid once per group rather than once per block.
+                    float ua[2][NBLK], va[2][NBLK], kwa[2], yxa[2], yya[2];
 #pragma unroll
                     for (int s = 0; s < 2; ++s) {
-                        // B is zero outside the segment, which also cancels A there
-                        const int q = k0 + 4 * s + kk;
-                        const bool use = q >= k && q < ke && p_col < np;
-                        const float bval = use ? bop[s] : 0.0f;
+                        const int q = k0 + 4 * s + kk;  // this lane's visibility in A and B
+                        const int sq = min(q, 63);
+                        const int vbase = 32 * (4 * s + kk);  // byte offset of visibility q's 8 lanes
+                        yxa[s] = __shfl(l_y.x, sq, 64);
+                        yya[s] = __shfl(l_y.y, sq, 64);
+                        kwa[s] = lane_permute(phw, vbase + 4 * p_col);
 #pragma unroll
-                        for (int blk = 0; blk < NBLK; ++blk)
-                            acc[blk] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop[s][blk], bval, acc[blk], 0, 0, 0);
+                        for (int blk = 0; blk < NBLK; ++blk) {
+                            ua[s][blk] = lane_permute(phu, vbase + a_addr[blk]);
+                            va[s][blk] = lane_permute(phv, vbase + b_addr[blk]);
+                        }
                     }
-                    k = ke;
+                    // A: psi(du_q - a) psi(dv_q - b) of the lane's cell in each block
+                    // (finite everywhere; rows of cells beyond W^2 are never flushed);
+                    // B before the segment mask: y_q times its plane-(g0 + p_col) weight
+                    float aop[2][NBLK], bop[2];
+#pragma unroll
+                    for (int s = 0; s < 2; ++s) {
+                        bop[s] = kwa[s] * (im_col ? yya[s] : yxa[s]);
+#pragma unroll
+                        for (int blk = 0; blk < NBLK; ++blk) aop[s][blk] = ua[s][blk] * va[s][blk];
+                    }
+                    const int kend = min(k0 + 8, nb);
+                    int k = k0;
+                    while (k < kend) {
+                        // the run segment [k, ke) of equal base cells inside this group
+                        const int cell = __builtin_amdgcn_readlane(l_cell, k);
+                        if (cell != run_cell) {
+                            if (run_cell >= 0) flush();
+                            run_cell = cell;
+                        }
+                        // the segment ends at the next run start inside the group
+                        // (shift counts stay below 64: k < kend <= 64)
+                        const unsigned long long above = (k >= 63) ? 0ull : (~0ull << (k + 1));
+                        const unsigned long long below = (kend >= 64) ? ~0ull : ((1ull << kend) - 1ull);
+                        const unsigned long long later = starts & above & below;
+                        const int ke = later ? __builtin_ctzll(later) : kend;  // k < ke <= kend
+#pragma unroll
+                        for (int s = 0; s < 2; ++s) {
+                            // a half the segment does not reach has B = 0 in every lane:
+                            // its products would add exact zeros, so they are not issued
+                            if (ke <= k0 + 4 * s || k >= k0 + 4 * s + 4) continue;
+                            // B is zero outside the segment, which also cancels A there
+                            const int q = k0 + 4 * s + kk;
+                            const bool use = q >= k && q < ke && p_col < np;
+                            const float bval = use ? bop[s] : 0.0f;
+#pragma unroll
+                            for (int blk = 0; blk < NBLK; ++blk)
+                                acc[blk] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop[s][blk], bval, acc[blk], 0, 0, 0);
+                        }
+                        k = ke;
+                    }
                 }
             }
+            if (run_cell >= 0) flush();
+            __syncthreads();
+            const int r0 = it.rows & 0xffff, r1 = it.rows >> 16;
+            const int band = (r1 - r0 + 1) * TS;
+            for (int q = threadIdx.x; q < np * band; q += NTHR) {
+                const int p = q / band, r = r0 * TS + (q - p * band);
+                out[(int64_t)(g0 + p) * TT + r] = mk<float>((float)ldexp((double)tile[2 * p * TT + r], -kexp),
+                                                            (float)ldexp((double)tile[2 * p * TT + TT + r], -kexp));
+            }
+            __syncthreads();
         }
-        if (run_cell >= 0) flush();
-        __syncthreads();
-        const int r0 = it.rows & 0xffff, r1 = it.rows >> 16;
-        const int band = (r1 - r0 + 1) * TS;
-        for (int q = threadIdx.x; q < np * band; q += NTHR) {
-            const int p = q / band, r = r0 * TS + (q - p * band);
-            out[(int64_t)(g0 + p) * TT + r] = mk<float>((float)ldexp((double)tile[2 * p * TT + r], -kexp),
-                                                        (float)ldexp((double)tile[2 * p * TT + TT + r], -kexp));
-        }
-        __syncthreads();
     }
 }
 
@@ -1179,28 +1196,53 @@ void launch_degrid_w(const fr_plan *pl, const WorkItem *wis, int64_t nwi, const 
     LAUNCH_CHECK();
 }
 
+// Launch shape of the gridding spread: threads per workgroup (FP64 and wide
+// kernels hold more registers per lane: smaller groups, larger register share),
+// planes per pass and LDS bytes (one float per wavefront is static), and how many
+// of its workgroups one CU holds.
+struct GridShape {
+    int nthr, ppass, per_cu;
+    size_t lds;
+};
+static GridShape grid_shape(int W, int Ww, bool fp64) {
+    GridShape g;
+    g.nthr = (fp64 || W * W > 64) ? 512 : 1024;
+    const size_t TS = kTile + W - 1;
+    const size_t per_plane_lds = TS * TS * 2 * sizeof(long long);
+    const size_t lds_static = (size_t)(g.nthr / 64) * sizeof(float);
+    const size_t lds_dyn = (size_t)kLdsBytes - lds_static;
+    g.ppass = (int)std::max<size_t>(1, std::min<size_t>((size_t)Ww, lds_dyn / per_plane_lds));
+    g.lds = per_plane_lds * g.ppass;
+    g.per_cu = (int)std::max<size_t>(1, std::min<size_t>((size_t)kLdsBytes / (g.lds + lds_static), 2048 / g.nthr));
+    return g;
+}
+
+// Records per gridding workgroup at least (channels of fewer records per CU use
+// fewer workgroups, so that they write few partial tiles).
+constexpr int64_t kMinRangeRecords = 2048;
+
 template <typename T, int W>
 void launch_grid_w(const fr_plan *pl, int64_t chan, c2<T> *planes, const c2<T> *y_rec, const float *ybound,
                    int nbb, hipStream_t st, int sorted_in) {
     constexpr int TS = kTile + W - 1;
-    // FP64 and wide kernels hold more registers per lane: smaller groups, larger register share
     constexpr int NTHR = (sizeof(T) == 8 || W * W > 64) ? 512 : 1024;
     const int64_t i0 = pl->gwi_chan[chan], i1 = pl->gwi_chan[chan + 1];
     const size_t per_plane = (size_t)TS * TS * sizeof(c2<T>);
-    const size_t per_plane_lds = (size_t)TS * TS * 2 * sizeof(long long);
+    const GridShape gs = grid_shape(W, pl->Ww, sizeof(T) == 8);
+    FR_REQUIRE(gs.nthr == NTHR, "gridding launch shape");
     if (i1 > i0) {
+        // the channel's workgroups, each taking a range of its items
+        const int64_t s0 = pl->gseg_chan[chan], n_wg = pl->gseg_chan[chan + 1] - s0 - 1;
         Scratch partial((size_t)(i1 - i0) * pl->Ww * per_plane, st);
-        // static LDS of the kernel: one float per wavefront
-        const size_t lds_dyn = (size_t)kLdsBytes - (NTHR / 64) * sizeof(float);
-        const int ppass = (int)std::max<size_t>(1, std::min<size_t>(pl->Ww, lds_dyn / per_plane_lds));
-        const size_t lds = per_plane_lds * ppass;
+        const int ppass = gs.ppass;
+        const size_t lds = gs.lds;
         {
             ProfScope prof("grid", st);
             auto launch_vector = [&]() {
                 auto kern = k_grid_partial<T, W, NTHR>;
                 allow_lds(kern, lds);
-                kern<<<dim3((unsigned)(i1 - i0)), NTHR, lds, st>>>(
-                    pl->gwi.as<WorkItem>() + i0, pl->gorder.as<int32_t>() + i0, partial.as<c2<T>>(), pl->Ww, ppass,
+                kern<<<dim3((unsigned)n_wg), NTHR, lds, st>>>(
+                    pl->gwi.as<WorkItem>() + i0, pl->gseg.as<int32_t>() + s0, partial.as<c2<T>>(), pl->Ww, ppass,
                     (T)pl->beta, (T)pl->wbeta, pl->coplanar ? 1 : 0, pl->taylor ? 1 : 0,
                     pl->r_cell.as<uint32_t>(), pl->r_du.as<T>(), pl->r_dv.as<T>(), pl->r_dw.as<T>(), pl->r_ph.as<T>(),
                     y_rec, ybound, nbb, sorted_in);
@@ -1213,8 +1255,8 @@ void launch_grid_w(const fr_plan *pl, int64_t chan, c2<T> *planes, const c2<T> *
                 if (matrix_spread(pl)) {
                     auto kern = k_grid_partial_mfma<W, NTHR>;
                     allow_lds(kern, lds);
-                    kern<<<dim3((unsigned)(i1 - i0)), NTHR, lds, st>>>(
-                        pl->gwi.as<WorkItem>() + i0, pl->gorder.as<int32_t>() + i0, partial.as<c2<T>>(), pl->Ww,
+                    kern<<<dim3((unsigned)n_wg), NTHR, lds, st>>>(
+                        pl->gwi.as<WorkItem>() + i0, pl->gseg.as<int32_t>() + s0, partial.as<c2<T>>(), pl->Ww,
                         ppass, (T)pl->beta, (T)pl->wbeta, pl->coplanar ? 1 : 0, pl->taylor ? 1 : 0,
                         pl->r_cell.as<uint32_t>(), pl->r_du.as<T>(), pl->r_dv.as<T>(),
                         pl->r_dw.as<T>(), pl->r_ph.as<T>(), y_rec, ybound, nbb, sorted_in);
@@ -1281,19 +1323,15 @@ size_t grid_scratch(const fr_plan *pl) {
            yrec + scratch_round(grid_partial_bytes(items, pl->Ww, pl->W, pl->fp64));
 }
 
-static int grid_chunk(int64_t n_vis_per_chan, int n_cu);
 
-// Bound on the arena scratch of gridding with the coplanar plan of the doubled
-// field that fr_make_psf_kernel derives (built inside the call): one plane of
-// 4 nx x 4 ny cells, the weighted values in record order, and at most one
-// gridding item per non-empty tile plus one per chunk of records in each channel.
 // Device memory a plan build takes per visibility at its peak: the coordinate
 // and key arrays of k_vis_coords (idx, cell, key, du, dv, dw, ph), the two key and
 // permutation buffers of the sort and its tables (12 bytes per 16 keys), and the
 // sorted records the plan keeps (idx, cell, du, dv, dw, ph, the record position
-// of each visibility and the degridding pair lists); per bucket, its
-// first record and first gridding item, and the tile maps.
-static size_t plan_bytes_per_vis(size_t rs) { return 12 + 4 * rs + 24 + 1 + 16 + 4 * rs; }
+// of each visibility and the degridding pair lists), and the run flags of the
+// sorted keys; per bucket, its first record and first gridding item, and the
+// tile maps.
+static size_t plan_bytes_per_vis(size_t rs) { return 12 + 4 * rs + 24 + 1 + 16 + 4 * rs + 1; }
 static size_t plan_bytes_per_key() { return 8 + 4 + 4 + 1; }
 
 // Bound on the device memory of building the coplanar doubled-field plan inside
@@ -1306,13 +1344,19 @@ size_t psf_plan_device_bound(const fr_plan *pl) {
     return (size_t)pl->n_vis * (plan_bytes_per_vis(rs)) + (n_keys + 1) * plan_bytes_per_key();
 }
 
+// Bound on the arena scratch of gridding with the coplanar plan of the doubled
+// field that fr_make_psf_kernel derives (built inside the call): one plane of
+// 4 nx x 4 ny cells, the weighted values in record order, and the partial tiles
+// of at most one gridding item per non-empty tile plus one per workgroup.
 size_t psf_grid_scratch_bound(const fr_plan *pl) {
     const bool fp64 = pl->fp64;
     const int W = es_support(pl->eps, 2, 4);
     const int64_t nu = 4 * pl->nx, nv = 4 * pl->ny;
     const int64_t n_tiles = (nu / kTile) * (nv / kTile);
+    // one item per non-empty bucket plus at most one more per workgroup
     const int64_t items = std::min<int64_t>(n_tiles, pl->n_row) +
-                          (pl->n_row + grid_chunk(pl->n_row, pl->ctx->n_cu) - 1) / grid_chunk(pl->n_row, pl->ctx->n_cu);
+                          std::min<int64_t>((int64_t)std::max(1, pl->ctx->n_cu) * grid_shape(W, 1, fp64).per_cu,
+                                            std::max<int64_t>(1, (pl->n_row + kMinRangeRecords - 1) / kMinRangeRecords));
     const size_t planes = (size_t)nu * nv * (fp64 ? sizeof(double2) : sizeof(float2));
     return scratch_round(planes) + scratch_round((size_t)vis_bound_blocks(pl->n_vis) * sizeof(float)) +
            scratch_round((size_t)pl->n_vis * (fp64 ? sizeof(double2) : sizeof(float2))) +
@@ -1459,15 +1503,124 @@ template <typename T> static DevBuf upload(const std::vector<double> &v) {
     return b;
 }
 
-// Visibilities per gridding item: about one item per CU (items run largest first,
-// which keeps the CUs balanced), so that few partial tiles are written and read
-// back by the assembly.  On the VLA-like workload this measured 6% faster for the
-// spread plus assembly than two items per CU.
-static int grid_chunk(int64_t n_vis_per_chan, int n_cu) {
-    const int64_t ncu = std::max(n_cu, 1);
-    int64_t c = (n_vis_per_chan + ncu - 1) / ncu;
-    c = std::min<int64_t>(std::max<int64_t>(c, 1024), 16384);
-    return (int)((c + 255) / 256 * 256);
+// Gridding items and their workgroups.  A workgroup's time grows with its
+// records, with the runs of equal base cell among them (each run ends in a flush
+// of the register sums to the LDS tiles) and with its items (tile zeroing, band
+// output, first loads); measured for the matrix-core spread at W = 7 with six
+// planes on the VLA-like workload, a run costs about ten records and an item
+// about 350.  The sorted records of each channel are cut into at most n_slots
+// consecutive ranges (and at most one per kMinRangeRecords records, which keeps
+// small channels to few items) of about equal cost, greedily with the smallest
+// cap that needs no more ranges, so that one workgroup per slot finishes at
+// about the same time; a range that crosses a bucket boundary takes one item per
+// bucket piece.  Items stay in bucket order (gfirst[k]: first item of bucket k), and
+// gseg holds per channel the first item of each range (from the channel's first
+// item) followed by the channel's item count.
+constexpr int64_t kCostRec = 10, kCostRun = 104, kCostItem = 3500;
+
+static void grid_partition(const std::vector<int64_t> &bounds, const std::vector<uint8_t> &run_flag, int64_t n_chan,
+                           int64_t keys_per_chan, int ntv, int n_tiles, int64_t n_slots, std::vector<WorkItem> &gwis,
+                           std::vector<uint32_t> &gfirst, std::vector<int32_t> &gseg, std::vector<int64_t> &gwi_chan,
+                           std::vector<int64_t> &gseg_chan) {
+    const int64_t n_keys = n_chan * keys_per_chan;
+    std::vector<int64_t> piece_key;
+    gwi_chan.assign(n_chan + 1, 0);
+    gseg_chan.assign(n_chan + 1, 0);
+    for (int64_t c = 0; c < n_chan; ++c) {
+        const int64_t k0 = c * keys_per_chan, k1 = k0 + keys_per_chan;
+        const int64_t r0 = bounds[k0], r1 = bounds[k1];
+        // runs started before each record of the channel
+        std::vector<int64_t> R((size_t)(r1 - r0 + 1), 0);
+        for (int64_t i = r0; i < r1; ++i) R[i - r0 + 1] = R[i - r0] + run_flag[i];
+        auto cost = [&](int64_t a, int64_t b) { return kCostRec * (b - a) + kCostRun * (R[b - r0] - R[a - r0]); };
+        std::vector<int64_t> nzb;
+        int64_t total = 0;
+        for (int64_t k = k0; k < k1; ++k)
+            if (bounds[k + 1] > bounds[k]) {
+                nzb.push_back(k);
+                total += kCostItem + cost(bounds[k], bounds[k + 1]);
+            }
+        const int64_t item0 = (int64_t)gwis.size();
+        // number of ranges for a cap of cap on each range's cost; emit: record them
+        auto partition = [&](int64_t cap, bool emit) -> int64_t {
+            int64_t n_rng = 0, used = 0;
+            bool open = false;
+            for (const int64_t k : nzb) {
+                int64_t a = bounds[k];
+                const int64_t b = bounds[k + 1];
+                while (a < b) {
+                    const int64_t room = cap - used - kCostItem;
+                    int64_t e = a;
+                    if (cost(a, b) <= room) {
+                        e = b;
+                    } else if (room >= 0) {
+                        int64_t lo = a, hi = b;  // cost(a, lo) <= room < cost(a, hi)
+                        while (hi - lo > 1) {
+                            const int64_t mid = lo + (hi - lo) / 2;
+                            if (cost(a, mid) <= room) lo = mid;
+                            else hi = mid;
+                        }
+                        e = lo;
+                    }
+                    if (e == a) {
+                        if (open) {  // full: the bucket continues in the next range
+                            ++n_rng;
+                            used = 0;
+                            open = false;
+                            continue;
+                        }
+                        e = a + 1;  // a range takes at least one record
+                    }
+                    if (emit) {
+                        if (!open) gseg.push_back((int32_t)((int64_t)gwis.size() - item0));
+                        const int64_t rem = k - k0;
+                        const int p0 = (int)(rem / n_tiles), t = (int)(rem - (int64_t)p0 * n_tiles);
+                        WorkItem w;
+                        w.start = a;
+                        w.count = (int32_t)(e - a);
+                        w.tu = (t / ntv) * kTile;
+                        w.tv = (t - (t / ntv) * ntv) * kTile;
+                        w.p0 = p0;
+                        w.chan = (int32_t)c;
+                        w.rows = 0;
+                        gwis.push_back(w);
+                        piece_key.push_back(k);
+                    }
+                    used += kCostItem + cost(a, e);
+                    open = true;
+                    a = e;
+                    if (a < b) {
+                        ++n_rng;
+                        used = 0;
+                        open = false;
+                    }
+                }
+            }
+            return n_rng + (open ? 1 : 0);
+        };
+        if (!nzb.empty()) {
+            // the smallest cap that needs at most n_rng ranges (a cap of total
+            // needs one)
+            const int64_t n_rng = std::max<int64_t>(
+                1, std::min<int64_t>(n_slots, (r1 - r0 + kMinRangeRecords - 1) / kMinRangeRecords));
+            int64_t lo = (total + n_rng - 1) / n_rng, hi = std::max(lo, total);
+            while (lo < hi) {
+                const int64_t mid = lo + (hi - lo) / 2;
+                if (partition(mid, false) <= n_rng) hi = mid;
+                else lo = mid + 1;
+            }
+            partition(lo, true);
+        }
+        gseg.push_back((int32_t)((int64_t)gwis.size() - item0));
+        gwi_chan[c + 1] = (int64_t)gwis.size();
+        gseg_chan[c + 1] = (int64_t)gseg.size();
+    }
+    gfirst.assign(n_keys + 1, 0);
+    int64_t it = 0;
+    for (int64_t k = 0; k <= n_keys; ++k) {
+        while (it < (int64_t)gwis.size() && piece_key[it] < k) ++it;
+        gfirst[k] = (uint32_t)it;
+    }
 }
 
 template <typename T>
@@ -1531,14 +1684,10 @@ static void build_records(fr_plan *pl, const DevBuf &d_uvw, const DevBuf &d_freq
         hpair.assign(n, 0u);
     }
     int64_t run = 0;
-    std::vector<WorkItem> wis, gwis;
-    std::vector<uint32_t> gfirst(n_keys + 1, 0);
+    std::vector<WorkItem> wis;
     pl->wi_chan.assign(pl->n_chan + 1, 0);
-    pl->gwi_chan.assign(pl->n_chan + 1, 0);
     const int ch = chunk<T>();
-    const int gch = grid_chunk(n / std::max<int64_t>(1, pl->n_chan), pl->ctx->n_cu);
     for (int64_t k = 0; k < n_keys; ++k) {
-        gfirst[k] = (uint32_t)gwis.size();
         const int64_t cnt = bounds[k + 1] - bounds[k];
         if (cnt) {
             const int64_t chan = k / ((int64_t)n_p0 * n_tiles);
@@ -1583,16 +1732,24 @@ static void build_records(fr_plan *pl, const DevBuf &d_uvw, const DevBuf &d_freq
                     pl->wi_chan[chan + 1] = (int64_t)wis.size();
                 }
             }
-            for (int64_t s = 0; s < cnt; s += gch) {
-                w.start = run + s;
-                w.count = (int32_t)std::min<int64_t>(gch, cnt - s);
-                gwis.push_back(w);
-                pl->gwi_chan[chan + 1] = (int64_t)gwis.size();
-            }
         }
         run += cnt;
     }
-    gfirst[n_keys] = (uint32_t)gwis.size();
+    // gridding items and the workgroups that take them
+    std::vector<WorkItem> gwis;
+    std::vector<uint32_t> gfirst;
+    std::vector<int32_t> gseg;
+    {
+        DevBuf d_flag((size_t)n);
+        k_run_flags<<<dim3((unsigned)blocks), 256>>>(keys_sorted, 0, n, d_flag.as<uint8_t>());
+        LAUNCH_CHECK();
+        std::vector<uint8_t> flag((size_t)n);
+        HIP_CHECK(hipMemcpy(flag.data(), d_flag.p, (size_t)n, hipMemcpyDeviceToHost));
+        const GridShape gs = grid_shape(pl->W, pl->Ww, pl->fp64);
+        const int64_t n_slots = (int64_t)std::max(1, pl->ctx->n_cu) * gs.per_cu;
+        grid_partition(bounds, flag, pl->n_chan, (int64_t)n_p0 * n_tiles, ntv, n_tiles, n_slots, gwis, gfirst,
+                       gseg, pl->gwi_chan, pl->gseg_chan);
+    }
     {
         std::vector<uint8_t> act((size_t)pl->n_chan * n_tiles, 0);
         std::vector<int32_t> alist;
@@ -1617,25 +1774,10 @@ static void build_records(fr_plan *pl, const DevBuf &d_uvw, const DevBuf &d_freq
         pl->tile_active = DevBuf(act.size());
         HIP_CHECK(hipMemcpy(pl->tile_active.p, act.data(), act.size(), hipMemcpyHostToDevice));
     }
-    for (int64_t c = 1; c <= pl->n_chan; ++c) {
-        pl->wi_chan[c] = std::max(pl->wi_chan[c], pl->wi_chan[c - 1]);
-        pl->gwi_chan[c] = std::max(pl->gwi_chan[c], pl->gwi_chan[c - 1]);
-    }
+    for (int64_t c = 1; c <= pl->n_chan; ++c) pl->wi_chan[c] = std::max(pl->wi_chan[c], pl->wi_chan[c - 1]);
     pl->n_gwi = (int64_t)gwis.size();
-    // launch order of the gridding items of each channel: largest first, so that
-    // the hardware's in-order dispatch fills the CUs like a longest-first schedule
-    {
-        std::vector<int32_t> order(gwis.size());
-        for (int64_t c = 0; c < pl->n_chan; ++c) {
-            const int64_t a = pl->gwi_chan[c], b = pl->gwi_chan[c + 1];
-            for (int64_t i = a; i < b; ++i) order[i] = (int32_t)(i - a);
-            std::stable_sort(order.begin() + a, order.begin() + b,
-                             [&](int32_t x, int32_t y) { return gwis[a + x].count > gwis[a + y].count; });
-        }
-        pl->gorder = DevBuf(std::max<size_t>(1, order.size()) * sizeof(int32_t));
-        if (!order.empty())
-            HIP_CHECK(hipMemcpy(pl->gorder.p, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    }
+    pl->gseg = DevBuf(gseg.size() * sizeof(int32_t));
+    HIP_CHECK(hipMemcpy(pl->gseg.p, gseg.data(), pl->gseg.bytes, hipMemcpyHostToDevice));
     pl->gwi = DevBuf(std::max<size_t>(1, gwis.size()) * sizeof(WorkItem));
     if (!gwis.empty())
         HIP_CHECK(hipMemcpy(pl->gwi.p, gwis.data(), gwis.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
@@ -1910,6 +2052,7 @@ void plan_build(fr_plan *pl, const double *uvw_m, const double *freq_hz) {
     } else {
         pl->wi_chan.assign(pl->n_chan + 1, 0);
         pl->gwi_chan.assign(pl->n_chan + 1, 0);
+        pl->gseg_chan.assign(pl->n_chan + 1, 0);
         pl->n_p0 = n_p0;
         pl->ntu = (int)(pl->nu / kTile);
         pl->ntv = (int)(pl->nv / kTile);
@@ -1923,7 +2066,7 @@ void plan_build(fr_plan *pl, const double *uvw_m, const double *freq_hz) {
     pl->resident = pl->fac.bytes + pl->tpix.bytes + pl->tpix_w.bytes + pl->nfac.bytes + pl->wplane.bytes + pl->r_idx.bytes +
                    pl->r_cell.bytes + pl->r_du.bytes + pl->r_dv.bytes + pl->r_dw.bytes + pl->r_ph.bytes + pl->r_pos.bytes +
                    pl->dpair.bytes +
-                   pl->wi.bytes + pl->gwi.bytes + pl->gorder.bytes + pl->gkey_first.bytes + pl->atile.bytes +
+                   pl->wi.bytes + pl->gwi.bytes + pl->gseg.bytes + pl->gkey_first.bytes + pl->atile.bytes +
                    pl->tile_active.bytes;
 }
 

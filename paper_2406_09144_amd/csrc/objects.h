@@ -68,9 +68,13 @@ struct fr_plan {
     frmi::DevBuf wi;      // WorkItem [n_wi]
     int64_t n_wi = 0;
     std::vector<int64_t> wi_chan;  // work-item range per channel, [n_chan + 1]
-    // gridding items: larger chunks of one key each, and per key the first item
+    // gridding items: pieces of one key each, and per key the first item; the
+    // items of a channel are split into consecutive ranges of about equal
+    // estimated cost, one per workgroup of the spread
     frmi::DevBuf gwi;        // WorkItem [n_gwi]
-    frmi::DevBuf gorder;     // int32 [n_gwi]: per channel, item indices largest first
+    frmi::DevBuf gseg;       // int32, per channel: first item of each workgroup (from the
+                             // channel's first item), then the channel's item count
+    std::vector<int64_t> gseg_chan;  // [n_chan + 1] offsets of each channel's block in gseg
     double vis_per_run = 0;  // records per run of equal (bucket, base cell)
     int64_t degrid_slots = 0;  // pair-list entries (paired degridding) or records
     int64_t n_gwi = 0;
