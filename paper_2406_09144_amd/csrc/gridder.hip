@@ -264,7 +264,11 @@ __global__ __launch_bounds__(NTHR) void k_degrid(const WorkItem *__restrict__ wi
             fw[k] = r_dw[pos];
         }
     }
-    // the tile of plane pw + 1 is fetched into registers while plane pw is used
+    // the tile of plane pw + 1 is fetched into registers while plane pw is used;
+    // only the rows the item's footprints reach are staged (its records are sorted
+    // by base cell: the first and the last hold the smallest and largest base row)
+    const int q0 = (int)(r_cell[it.start] & 0xffffu) * TS;
+    const int q1 = ((int)(r_cell[it.start + it.count - 1] & 0xffffu) + W) * TS;
     constexpr int NLD = (TS * TS + NTHR - 1) / NTHR;
     T pre_x[NLD], pre_y[NLD];
     int64_t toff[NLD];  // tile element offsets inside a plane
@@ -274,32 +278,28 @@ __global__ __launch_bounds__(NTHR) void k_degrid(const WorkItem *__restrict__ wi
         const int i = q / TS, jj = q - i * TS;
         toff[u] = ((int64_t)((it.tu + i) & (nu - 1)) << log2nv) + ((it.tv + jj) & (nv - 1));
     }
-    {
-        const c2<T> *P = planes + ((int64_t)it.p0 << (log2nu + log2nv));
-#pragma unroll
-        for (int u = 0; u < NLD; ++u) {
-            const c2<T> g = P[toff[u]];
-            pre_x[u] = g.x;
-            pre_y[u] = g.y;
-        }
-    }
-    for (int pw = 0; pw < Ww; ++pw) {
-        __syncthreads();
+    auto fetch = [&](int p) {
+        const c2<T> *P = planes + ((int64_t)p << (log2nu + log2nv));
 #pragma unroll
         for (int u = 0; u < NLD; ++u) {
             const int q = threadIdx.x + u * NTHR;
-            if (q < TS * TS) tile[q] = mk<T>(pre_x[u], pre_y[u]);
-        }
-        __syncthreads();
-        if (pw + 1 < Ww) {
-            const c2<T> *P = planes + ((int64_t)(it.p0 + pw + 1) << (log2nu + log2nv));
-#pragma unroll
-            for (int u = 0; u < NLD; ++u) {
+            if (q >= q0 && q < q1) {
                 const c2<T> g = P[toff[u]];
                 pre_x[u] = g.x;
                 pre_y[u] = g.y;
             }
         }
+    };
+    fetch(it.p0);
+    for (int pw = 0; pw < Ww; ++pw) {
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < NLD; ++u) {
+            const int q = threadIdx.x + u * NTHR;
+            if (q >= q0 && q < q1) tile[q] = mk<T>(pre_x[u], pre_y[u]);
+        }
+        __syncthreads();
+        if (pw + 1 < Ww) fetch(it.p0 + pw + 1);
         if constexpr (PAIR) {
             // both records of the pair from the same tile reads (one base cell)
             if (ok[0]) {
@@ -457,6 +457,9 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial(const WorkItem *__restric
     constexpr int NWAVE = NTHR / 64;
     constexpr int PR = grid_reg_planes<T, W>() < W ? grid_reg_planes<T, W>() : W;
     constexpr int VPB = 64 / W;  // visibilities per kernel-evaluation step
+    // the tiles start at zero; a pass's band output clears the rows it reads, which
+    // hold every cell the pass touched, so they are zero again for the next pass
+    for (int q = threadIdx.x; q < min(ppass, PR) * 2 * TT; q += NTHR) tile[q] = 0;
     // fixed-point exponent from the bound on every contribution
     __shared__ float wmax[NWAVE];
     {
@@ -498,8 +501,6 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial(const WorkItem *__restric
         const int pp = min(ppass, PR);
         for (int g0 = 0; g0 < Ww; g0 += pp) {
             const int np = min(pp, Ww - g0);
-            for (int q = threadIdx.x; q < np * 2 * TT; q += NTHR) tile[q] = 0;
-            __syncthreads();
             T acc_re[NCELL][PR], acc_im[NCELL][PR];
 #pragma unroll
             for (int q = 0; q < NCELL; ++q)
@@ -620,6 +621,8 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial(const WorkItem *__restric
                 const int p = q / band, r = r0 * TS + (q - p * band);
                 out[(int64_t)(g0 + p) * TT + r] = mk<T>((T)ldexp((double)tile[2 * p * TT + r], -kexp),
                                                         (T)ldexp((double)tile[2 * p * TT + TT + r], -kexp));
+                tile[2 * p * TT + r] = 0;
+                tile[2 * p * TT + TT + r] = 0;
             }
             __syncthreads();
         }
@@ -656,6 +659,9 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial_mfma(
     constexpr int TT = TS * TS;
     constexpr int NWAVE = NTHR / 64;
     constexpr int NBLK = (W * W + 15) / 16;  // blocks of 16 cells
+    // the tiles start at zero; a pass's band output clears the rows it reads, which
+    // hold every cell the pass touched, so they are zero again for the next pass
+    for (int q = threadIdx.x; q < min(ppass, 8) * 2 * TT; q += NTHR) tile[q] = 0;
     __shared__ float wmax[NWAVE];
     {
         float m = 0.0f;
@@ -700,8 +706,6 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial_mfma(
         const int pp = min(ppass, 8);
         for (int g0 = 0; g0 < Ww; g0 += pp) {
             const int np = min(pp, Ww - g0);
-            for (int q = threadIdx.x; q < np * 2 * TT; q += NTHR) tile[q] = 0;
-            __syncthreads();
             v4f acc[NBLK];
 #pragma unroll
             for (int blk = 0; blk < NBLK; ++blk) acc[blk] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
@@ -831,6 +835,8 @@ __global__ __launch_bounds__(NTHR) void k_grid_partial_mfma(
                 const int p = q / band, r = r0 * TS + (q - p * band);
                 out[(int64_t)(g0 + p) * TT + r] = mk<float>((float)ldexp((double)tile[2 * p * TT + r], -kexp),
                                                             (float)ldexp((double)tile[2 * p * TT + TT + r], -kexp));
+                tile[2 * p * TT + r] = 0;
+                tile[2 * p * TT + TT + r] = 0;
             }
             __syncthreads();
         }
@@ -1516,7 +1522,7 @@ template <typename T> static DevBuf upload(const std::vector<double> &v) {
 // bucket piece.  Items stay in bucket order (gfirst[k]: first item of bucket k), and
 // gseg holds per channel the first item of each range (from the channel's first
 // item) followed by the channel's item count.
-constexpr int64_t kCostRec = 10, kCostRun = 104, kCostItem = 3500;
+constexpr int64_t kCostRec = 10, kCostRun = 108, kCostItem = 4000;
 
 static void grid_partition(const std::vector<int64_t> &bounds, const std::vector<uint8_t> &run_flag, int64_t n_chan,
                            int64_t keys_per_chan, int ntv, int n_tiles, int64_t n_slots, std::vector<WorkItem> &gwis,
