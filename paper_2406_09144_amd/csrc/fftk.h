@@ -46,15 +46,20 @@ __global__ __launch_bounds__(NTHR) void k_fft_rows(Pro pro, Epi epi, int64_t nro
 template <typename T, int NTHR, int BPT, bool TWL, class Pro, class Epi, int ODD = 1>
 __global__ __launch_bounds__(NTHR) void k_fft_cols(Pro pro, Epi epi, int ncols, int log2P, int n_in,
                                                     int n_out, int C, int sign,
-                                                    const c2<T> *__restrict__ tw) {
+                                                    const c2<T> *__restrict__ tw,
+                                                    const int32_t *__restrict__ blk, int log2_spb) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     c2<T> *buf = reinterpret_cast<c2<T> *>(smem_raw);
     const int L = ODD << log2P;
     const int ld = plen(L) + 1;
     const unsigned w = xcd_contiguous(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
-    const int col0 = (int)(w % gridDim.x) * C;
+    const unsigned s = w % gridDim.x;
     const int64_t m = w / gridDim.x;
     const int log2C = 31 - __builtin_clz(C);  // strips are a power of two wide
+    // strip s: with a block list, strip s & (2^log2_spb - 1) of column block
+    // blk[s >> log2_spb] (blocks of C 2^log2_spb columns); else columns s C ..
+    const int col0 = blk ? (blk[s >> log2_spb] << (log2_spb + log2C)) + (int)((s & ((1u << log2_spb) - 1u)) << log2C)
+                         : (int)s * C;
     const c2<T> *twp = stage_twiddles<T, NTHR, TWL>(buf + C * ld, tw, L);
     staged_copy<NTHR>(
         C * L,
@@ -119,11 +124,17 @@ template <typename T> inline int col_strip(int L, int ncols) {
     return C;
 }
 
-// Column transforms of length L = ODD 2^log2P.
+// Column transforms of length L = ODD 2^log2P, of every column, or with blk (device
+// int32 [nblk]) only of the columns of blocks blk[0 .. nblk - 1], each blk_w (a
+// power of two) columns wide.
 template <typename T, class Pro, class Epi, int ODD = 1>
 void launch_fft_cols(const Ctx &ctx, Pro pro, Epi epi, int64_t nmat, int ncols, int log2P, int n_in, int n_out,
-                     int sign, hipStream_t st) {
+                     int sign, hipStream_t st, const int32_t *blk = nullptr, int nblk = 0, int blk_w = 0) {
     const int L = ODD << log2P;
+    if (blk) {
+        FR_REQUIRE(is_pow2(blk_w) && blk_w <= ncols, "column blocks must be a power of two wide");
+        ncols = nblk * blk_w;  // the columns transformed
+    }
     int C = col_strip<T>(L, ncols);
     bool allow_twl = true;
     // FP32 lines of 8192: strips of two columns without the LDS twiddle table
@@ -137,9 +148,11 @@ void launch_fft_cols(const Ctx &ctx, Pro pro, Epi epi, int64_t nmat, int ncols, 
     // covers every CU a couple of times
     while (C > 2 && (int64_t)(ncols / C) * nmat < 2 * (int64_t)std::max(ctx.n_cu, 1)) C >>= 1;
     FR_REQUIRE(is_pow2(C), "column strip width must be a power of two");
+    if (blk) C = std::min(C, blk_w);
+    const int log2_spb = blk ? ilog2(blk_w / C) : 0;
     const size_t lds = (size_t)C * (plen(L) + 1) * sizeof(c2<T>);
     FR_REQUIRE(lds <= (size_t)kLdsBytes && L <= 16384, "column FFT length too large");
-    if (nmat <= 0) return;
+    if (nmat <= 0 || ncols <= 0) return;
     dim3 grid((unsigned)(ncols / C), (unsigned)nmat);
     const bool twl = allow_twl && twl_fits<T>(lds, L);
     const size_t ldst = twl ? lds + (size_t)L * sizeof(c2<T>) : lds;
@@ -147,7 +160,7 @@ void launch_fft_cols(const Ctx &ctx, Pro pro, Epi epi, int64_t nmat, int ncols, 
     do {                                                                                                  \
         allow_lds(k_fft_cols<T, NT, 4, TW, Pro, Epi, ODD>, ldst);                                              \
         k_fft_cols<T, NT, 4, TW, Pro, Epi, ODD><<<grid, NT, ldst, st>>>(pro, epi, ncols, log2P, n_in, n_out, C, \
-                                                                   sign, ctx.tw<T>(ODD, log2P));               \
+                                                                   sign, ctx.tw<T>(ODD, log2P), blk, log2_spb); \
     } while (0)
     // one radix-4 butterfly per thread where the strip allows (as the convolution
     // column pass)

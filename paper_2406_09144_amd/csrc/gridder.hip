@@ -1039,8 +1039,10 @@ template <typename T> struct DegridRowPro {
 };
 template <typename T> struct DegridRowEpi {
     c2<T> *planes;
+    const uint8_t *col_active;  // [ntv] of the channel: columns no degridding reads are not stored
     int nx, log2nu, log2nv;
     __device__ void operator()(int64_t line, int b, c2<T> v) const {
+        if (!col_active[b / kTile]) return;
         const int p = (int)line >> (31 - __builtin_clz(nx));
         const int i = (int)line & (nx - 1);
         const int a = (i - nx / 2) & ((1 << log2nu) - 1);
@@ -1079,6 +1081,16 @@ template <typename T> struct FullColEpi {
         planes[(((m << log2nu) + a) << log2nv) + b] = v;
     }
 };
+// stores only the cells of active tiles (the only ones degridding reads)
+template <typename T> struct ActiveColEpi {
+    c2<T> *planes;
+    const uint8_t *active;  // [n_tiles] of the channel
+    int log2nu, log2nv, ntv;
+    __device__ void operator()(int64_t m, int a, int b, c2<T> v) const {
+        if (!active[(a / kTile) * ntv + b / kTile]) return;
+        planes[(((m << log2nu) + a) << log2nv) + b] = v;
+    }
+};
 template <typename T> struct BandColEpi {
     c2<T> *planes;
     int nx, log2nu, log2nv;
@@ -1092,7 +1104,8 @@ template <typename T> struct BandColEpi {
 // Gridding epilogue: image row i accumulates Re(exp(+2 pi i w_p t) G_p) over planes,
 // transforming `lines` plane rows at a time (all threads busy in every stage).
 template <typename T, int NTHR, int BPT, int ACC, bool TWL>
-__global__ __launch_bounds__(NTHR) void k_grid_rows(const c2<T> *__restrict__ planes, int n_planes, int log2nu,
+__global__ __launch_bounds__(NTHR) void k_grid_rows(const c2<T> *__restrict__ planes,
+                                                    const uint8_t *__restrict__ col_active, int n_planes, int log2nu,
                                                     int log2nv, int nx, int ny, const T *__restrict__ fac,
                                                     const T *__restrict__ tpix, const double *__restrict__ tpix_w,
                                                     const double *__restrict__ wplane,
@@ -1107,12 +1120,22 @@ __global__ __launch_bounds__(NTHR) void k_grid_rows(const c2<T> *__restrict__ pl
     T acc[ACC];
 #pragma unroll
     for (int k = 0; k < ACC; ++k) acc[k] = T(0);
+    // the row loads of this thread touch columns (threadIdx.x + j NTHR) mod nv,
+    // j < J: which of them lie in a tile column holding an active tile (the others
+    // are zero in every plane and not stored), as a bit mask
+    const int J = nv > NTHR ? nv / NTHR : 1;  // at most 64 (host-checked)
+    unsigned long long cmask = 0;
+    for (int j = 0; j < J; ++j)
+        if (col_active[((threadIdx.x + j * NTHR) & (nv - 1)) / kTile]) cmask |= 1ull << j;
+    constexpr int LOG2N = __builtin_ctz(NTHR);
     const c2<T> *twp = stage_twiddles<T, NTHR, TWL>(buf + lines * ld, tw, nv);
     for (int p0 = 0; p0 < n_planes; p0 += lines) {
         const int nl = min(lines, n_planes - p0);
         staged_copy<NTHR>(
             nl << log2nv,
             [&](int idx) {
+                // idx = threadIdx.x + k NTHR: column (threadIdx.x + (k mod J) NTHR) mod nv
+                if (!((cmask >> ((idx >> LOG2N) & (J - 1))) & 1ull)) return mk<T>(T(0), T(0));
                 const int64_t row = ((int64_t)(p0 + (idx >> log2nv)) << log2nu) + a;
                 return planes[(row << log2nv) + (idx & (nv - 1))];
             },
@@ -1371,30 +1394,43 @@ size_t psf_grid_scratch_bound(const fr_plan *pl) {
 
 // forward: image channel -> planes (prep, row FFT, column FFT)
 template <typename T>
-void image_to_planes(const fr_plan *pl, const T *img_c, c2<T> *planes, hipStream_t st) {
+// Only the tiles degridding reads are produced: the row pass stores the tile
+// columns that hold an active tile, the column pass transforms those columns and
+// stores the active tiles.
+void image_to_planes(const fr_plan *pl, int64_t chan, const T *img_c, c2<T> *planes, hipStream_t st) {
     const int l2u = ilog2(pl->nu), l2v = ilog2(pl->nv);
+    const int64_t c0 = pl->tcol_chan[chan], nc = pl->tcol_chan[chan + 1] - c0;
+    if (nc == 0) return;  // no visibilities in this channel
     DegridRowPro<T> pro{img_c, pl->fac.as<T>(), pl->tpix.as<T>(), pl->tpix_w.as<double>(), pl->wplane.as<double>(),
                         (int)pl->nx, (int)pl->ny, (int)pl->nv, pl->coplanar ? 1 : 0, pl->taylor ? 1 : 0};
-    DegridRowEpi<T> epi{planes, (int)pl->nx, l2u, l2v};
+    DegridRowEpi<T> epi{planes, pl->col_active.as<uint8_t>() + chan * pl->ntv, (int)pl->nx, l2u, l2v};
     {
         ProfScope prof("wplane_rows_fwd", st);
         launch_fft_rows<T>(*pl->ctx, pro, epi, (int64_t)pl->n_planes * pl->nx, l2v, -1, st);
     }
     ProfScope prof("wplane_cols_fwd", st);
-    launch_fft_cols<T>(*pl->ctx, BandColPro<T>{planes, (int)pl->nx, l2u, l2v}, FullColEpi<T>{planes, l2u, l2v},
-                       pl->n_planes, (int)pl->nv, l2u, (int)pl->nu, (int)pl->nu, -1, st);
+    launch_fft_cols<T>(*pl->ctx, BandColPro<T>{planes, (int)pl->nx, l2u, l2v},
+                       ActiveColEpi<T>{planes, pl->tile_active.as<uint8_t>() + chan * pl->n_tiles, l2u, l2v, pl->ntv},
+                       pl->n_planes, (int)pl->nv, l2u, (int)pl->nu, (int)pl->nu, -1, st, pl->tcol.as<int32_t>() + c0,
+                       (int)nc, kTile);
 }
 
 // adjoint: planes -> image channel (inverse column FFT on the band, row kernel)
 template <typename T>
-void planes_to_image(const fr_plan *pl, const c2<T> *planes_c, const uint8_t *active, T *img_c, hipStream_t st) {
+// Only the tile columns that hold an active tile are transformed and read: the
+// others are zero in every plane.
+void planes_to_image(const fr_plan *pl, int64_t chan, const c2<T> *planes_c, T *img_c, hipStream_t st) {
     c2<T> *planes = const_cast<c2<T> *>(planes_c);
     const int l2u = ilog2(pl->nu), l2v = ilog2(pl->nv);
+    const uint8_t *active = pl->tile_active.as<uint8_t>() + chan * pl->n_tiles;
+    const uint8_t *col_active = pl->col_active.as<uint8_t>() + chan * pl->ntv;
+    const int64_t c0 = pl->tcol_chan[chan], nc = pl->tcol_chan[chan + 1] - c0;
     {
         ProfScope prof("wplane_cols_inv", st);
         launch_fft_cols<T>(*pl->ctx, ActiveColPro<T>{planes, active, l2u, l2v, pl->ntv},
                            BandColEpi<T>{planes, (int)pl->nx, l2u, l2v},
-                           pl->n_planes, (int)pl->nv, l2u, (int)pl->nu, (int)pl->nu, +1, st);
+                           pl->n_planes, (int)pl->nv, l2u, (int)pl->nu, (int)pl->nu, +1, st,
+                           pl->tcol.as<int32_t>() + c0, (int)nc, kTile);
     }
     ProfScope prof("wplane_rows_inv", st);
     const int nv = (int)pl->nv;
@@ -1405,12 +1441,14 @@ void planes_to_image(const fr_plan *pl, const c2<T> *planes_c, const uint8_t *ac
         const size_t lds = (size_t)(LINES) * pl_line + ((TW) ? twb : 0);                                         \
         auto kern = k_grid_rows<T, NT, 4, 8, TW>;                                                               \
         allow_lds(kern, lds);                                                                                   \
-        kern<<<dim3((unsigned)pl->nx), NT, lds, st>>>(planes, pl->n_planes, l2u, l2v, (int)pl->nx, (int)pl->ny, \
-                                                      pl->fac.as<T>(), pl->tpix.as<T>(), pl->tpix_w.as<double>(),   \
+        kern<<<dim3((unsigned)pl->nx), NT, lds, st>>>(planes, col_active, pl->n_planes, l2u, l2v, (int)pl->nx,   \
+                                                      (int)pl->ny, pl->fac.as<T>(), pl->tpix.as<T>(),               \
+                                                      pl->tpix_w.as<double>(),                                      \
                                                       pl->wplane.as<double>(),                                        \
                                                       pl->coplanar ? 1 : 0, pl->taylor ? 1 : 0, img_c, (LINES),       \
                                                       pl->ctx->tw<T>(l2v));                                           \
     } while (0)
+    FR_REQUIRE(nv <= 64 * (nv <= 4096 ? 256 : 1024), "grid too large for the row pass");
     if (nv <= 4096) FR_GRID_ROWS(256, true, args_lines_small);
     else if (pl_line + twb <= (size_t)kLdsBytes) FR_GRID_ROWS(1024, true, 1);
     else FR_GRID_ROWS(1024, false, 1);
@@ -1423,7 +1461,7 @@ void degrid(const fr_plan *pl, const T *img, c2<T> *vis, hipStream_t st, const T
     Scratch planes(planes_bytes(pl), st);
     const WorkItem *wis = pl->wi.as<WorkItem>();
     for (int64_t c = 0; c < pl->n_chan; ++c) {
-        image_to_planes<T>(pl, img + c * pl->nx * pl->ny, planes.as<c2<T>>(), st);
+        image_to_planes<T>(pl, c, img + c * pl->nx * pl->ny, planes.as<c2<T>>(), st);
         const int64_t w0 = pl->wi_chan[c], w1 = pl->wi_chan[c + 1];
         if (w1 > w0) {
 #define FR_CALL_DEGRID(WW) \
@@ -1459,8 +1497,7 @@ void grid(const fr_plan *pl, const c2<T> *vis, const T *weight, T *img, hipStrea
     launch_grid_w<T, WW>(pl, c, planes.as<c2<T>>(), y_rec, ybound.as<float>(), nbb, st, sorted_in ? 1 : 0)
         FR_W_DISPATCH(pl->W, FR_CALL_GRID)
 #undef FR_CALL_GRID
-        planes_to_image<T>(pl, planes.as<c2<T>>(), pl->tile_active.as<uint8_t>() + c * pl->n_tiles,
-                           img + c * pl->nx * pl->ny, st);
+        planes_to_image<T>(pl, c, planes.as<c2<T>>(), img + c * pl->nx * pl->ny, st);
     }
 }
 
@@ -1779,6 +1816,21 @@ static void build_records(fr_plan *pl, const DevBuf &d_uvw, const DevBuf &d_freq
             HIP_CHECK(hipMemcpy(pl->atile.p, alist.data(), alist.size() * sizeof(int32_t), hipMemcpyHostToDevice));
         pl->tile_active = DevBuf(act.size());
         HIP_CHECK(hipMemcpy(pl->tile_active.p, act.data(), act.size(), hipMemcpyHostToDevice));
+        std::vector<uint8_t> cact((size_t)pl->n_chan * ntv, 0);
+        std::vector<int32_t> clist;
+        pl->tcol_chan.assign(pl->n_chan + 1, 0);
+        for (int64_t c = 0; c < pl->n_chan; ++c) {
+            for (int t = 0; t < n_tiles; ++t)
+                if (act[c * n_tiles + t]) cact[c * ntv + t % ntv] = 1;
+            for (int tv = 0; tv < ntv; ++tv)
+                if (cact[c * ntv + tv]) clist.push_back(tv);
+            pl->tcol_chan[c + 1] = (int64_t)clist.size();
+        }
+        pl->col_active = DevBuf(cact.size());
+        HIP_CHECK(hipMemcpy(pl->col_active.p, cact.data(), cact.size(), hipMemcpyHostToDevice));
+        pl->tcol = DevBuf(std::max<size_t>(1, clist.size()) * sizeof(int32_t));
+        if (!clist.empty())
+            HIP_CHECK(hipMemcpy(pl->tcol.p, clist.data(), clist.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     }
     for (int64_t c = 1; c <= pl->n_chan; ++c) pl->wi_chan[c] = std::max(pl->wi_chan[c], pl->wi_chan[c - 1]);
     pl->n_gwi = (int64_t)gwis.size();
@@ -2068,12 +2120,16 @@ void plan_build(fr_plan *pl, const double *uvw_m, const double *freq_hz) {
         pl->atile = DevBuf(sizeof(int32_t));
         pl->tile_active = DevBuf((size_t)pl->n_chan * pl->n_tiles);
         HIP_CHECK(hipMemset(pl->tile_active.p, 0, pl->tile_active.bytes));
+        pl->col_active = DevBuf((size_t)pl->n_chan * pl->ntv);
+        HIP_CHECK(hipMemset(pl->col_active.p, 0, pl->col_active.bytes));
+        pl->tcol = DevBuf(sizeof(int32_t));
+        pl->tcol_chan.assign(pl->n_chan + 1, 0);
     }
     pl->resident = pl->fac.bytes + pl->tpix.bytes + pl->tpix_w.bytes + pl->nfac.bytes + pl->wplane.bytes + pl->r_idx.bytes +
                    pl->r_cell.bytes + pl->r_du.bytes + pl->r_dv.bytes + pl->r_dw.bytes + pl->r_ph.bytes + pl->r_pos.bytes +
                    pl->dpair.bytes +
                    pl->wi.bytes + pl->gwi.bytes + pl->gseg.bytes + pl->gkey_first.bytes + pl->atile.bytes +
-                   pl->tile_active.bytes;
+                   pl->tile_active.bytes + pl->col_active.bytes + pl->tcol.bytes;
 }
 
 }  // namespace frmi

@@ -86,6 +86,12 @@ struct fr_plan {
     frmi::DevBuf atile;                 // int32 tile index [sum over channels]
     std::vector<int64_t> atile_chan;    // [n_chan + 1] offsets into atile
     frmi::DevBuf tile_active;           // uint8 [n_chan][n_tiles]
+    // tile columns (kTile grid columns each) holding an active tile: a map per
+    // channel, and per channel the list of them, so that the w-plane column
+    // transforms and the row passes leave the others alone
+    frmi::DevBuf col_active;            // uint8 [n_chan][ntv]
+    frmi::DevBuf tcol;                  // int32 active tile columns of each channel, ascending
+    std::vector<int64_t> tcol_chan;     // [n_chan + 1] offsets into tcol
     int n_p0 = 1, n_tiles = 1, ntu = 1, ntv = 1;
     std::vector<double> freq;
     std::vector<double> uvw_host;  // [n_row][3] metres, kept to derive the PSF plan
