@@ -98,21 +98,33 @@ def measured_traffic(kernel):
     return int(float(rec["hbm_bytes_per_launch"]))
 
 
+def active_fractions(info):
+    """Fractions of the uv tiles that can be non-zero (the only ones degridding reads
+    and the assembly writes) and of the tile columns holding one (the only columns
+    the w-plane transforms touch); the rest of every plane is zero or unread."""
+    tile, n_chan = info["tile"], info["n_chan"]
+    ntu, ntv = info["nu"] // tile, info["nv"] // tile
+    return info["active_tiles"] / (n_chan * ntu * ntv), info["active_tile_cols"] / (n_chan * ntv)
+
+
 def algorithmic_bytes(name, info, n_vis, n_row, B_conv, nx, ny):
-    """Bytes one launch of kernel `name` must move at minimum (FP32)."""
+    """Bytes one launch of kernel `name` must move at minimum (FP32): the w-plane
+    figures count only the active tiles and the tile columns holding one."""
     planes = info["n_planes"] * info["nu"] * info["nv"] * 8
+    f_tiles, f_cols = active_fractions(info)
     if name == "degrid":
-        return planes + 8 * n_vis + 24 * n_row          # every plane read once, vis written, uvw
+        return planes * f_tiles + 8 * n_vis + 24 * n_row    # active tiles read once, vis written, uvw
     if name == "grid":
         return 12 * n_vis + 24 * n_row                  # vis + weights read (spread into per-item tiles)
     if name == "grid_assemble":
-        return planes                                   # every plane cell written once
+        return planes * f_tiles                         # every active plane cell written once
     if name in ("wplane_rows_fwd",):
-        return 4 * nx * ny + info["n_planes"] * nx * info["nv"] * 8
+        return 4 * nx * ny + info["n_planes"] * nx * info["nv"] * 8 * f_cols
     if name in ("wplane_cols_fwd", "wplane_cols_inv"):
-        return info["n_planes"] * (nx * info["nv"] * 8 + info["nu"] * info["nv"] * 8)
+        # band rows of the active columns one way, the active tiles the other
+        return info["n_planes"] * 8 * (nx * info["nv"] * f_cols + info["nu"] * info["nv"] * f_tiles)
     if name == "wplane_rows_inv":
-        return info["n_planes"] * nx * info["nv"] * 8 + 4 * nx * ny
+        return info["n_planes"] * nx * info["nv"] * 8 * f_cols + 4 * nx * ny
     if name == "psfconv_rows_r2c":
         return B_conv * (4 * nx * ny + 8 * nx * ny)
     if name == "psfconv_cols":
@@ -125,7 +137,9 @@ def algorithmic_bytes(name, info, n_vis, n_row, B_conv, nx, ny):
 def call_bytes(op, info, n_vis_per_chan, n_row, nx, ny, n_chan=1):
     """Bytes a whole (de)gridding call must move (FP32): the image, every w-plane
     grid written once by its FFT and read once, the visibilities (and weights for
-    gridding) and uvw, per channel."""
+    gridding) and uvw, per channel.  This full-grid figure over-counts what the
+    calls move when the uv coverage leaves tiles empty (they touch only the active
+    tiles and the tile columns holding one)."""
     per = 4 * nx * ny + info["n_planes"] * 2 * 8 * info["nu"] * info["nv"] + 8 * n_vis_per_chan + 24 * n_row
     if op == "grid":
         per += 4 * n_vis_per_chan

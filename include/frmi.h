@@ -115,6 +115,12 @@ typedef struct fr_plan_info {
                                thread from the same tile reads (FP32, >= 4 records per run) */
     int64_t degrid_slots;   /* footprint interpolations fr_degrid issues: pair-list
                                entries when paired, else one per visibility */
+    int64_t active_tiles;   /* uv tiles (tile x tile cells) whose planes can be non-zero,
+                               summed over channels: fr_degrid reads and fr_grid writes
+                               only these */
+    int64_t active_tile_cols; /* tile columns holding an active tile, summed over
+                               channels: the w-plane column and row transforms touch only
+                               these columns */
 } fr_plan_info;
 
 /* Library version string. */

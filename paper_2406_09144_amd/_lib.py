@@ -45,6 +45,7 @@ class fr_plan_info(ctypes.Structure):
         ("w_taylor", ctypes.c_int),
         ("records_per_run", ctypes.c_double), ("matrix_spread", ctypes.c_int),
         ("paired_degrid", ctypes.c_int), ("degrid_slots", ctypes.c_int64),
+        ("active_tiles", ctypes.c_int64), ("active_tile_cols", ctypes.c_int64),
     ]
 
     def as_dict(self):

@@ -361,6 +361,8 @@ int fr_plan_get_info(const fr_plan *pl, fr_plan_info *info) {
     info->matrix_spread = frmi::matrix_spread(pl) ? 1 : 0;
     info->paired_degrid = frmi::paired_degrid(pl) ? 1 : 0;
     info->degrid_slots = pl->degrid_slots;
+    info->active_tiles = pl->atile_chan.empty() ? 0 : pl->atile_chan.back();
+    info->active_tile_cols = pl->tcol_chan.empty() ? 0 : pl->tcol_chan.back();
     FR_API_END
 }
 

@@ -65,7 +65,15 @@ def _check_plan(obs, chans, n_vis_sample=2048, n_pix_sample=96, seed=0, fp64=Fal
 def test_vla_like_full_size():
     obs = make_config(1)
     assert obs.n_vis == 1_010_880
-    _check_plan(obs, chans=[0])
+    pl = _check_plan(obs, chans=[0])
+    # the coverage leaves whole tile columns of the uv grid empty, so the parity
+    # above is that of the w-plane transforms restricted to the active columns
+    info = pl.info
+    ntu, ntv = info["nu"] // info["tile"], info["nv"] // info["tile"]
+    print(f"[fullsize] active tiles {info['active_tiles']} of {ntu * ntv}, tile columns "
+          f"{info['active_tile_cols']} of {ntv}", flush=True)
+    assert 0 < info["active_tile_cols"] < ntv
+    assert 0 < info["active_tiles"] < ntu * ntv
 
 
 def test_vla_like_full_size_fp64():
