@@ -235,11 +235,94 @@ __device__ __forceinline__ void lds_fft_dir(c2<T> *buf, int ld, int nlines, int 
         stockham_stage<T, ODD, NTHR, (4 * BPT + ODD - 1) / ODD, ODD, SIGN>(buf, ld, nlines, log2P, log2P, tw);
 }
 
-template <typename T, int NTHR, int BPT, int ODD = 1>
+// The same stage for a power-of-two length 2^LOG2P fixed at compile time.  For
+// element offsets within a line, padx(j + r Q) = padx(j) + r Q + (r Q) / 32 when
+// j < Q (Q a power of two: the low five bits of j + r Q do not carry), and
+// likewise padx(e0 + r Ns) = padx(e0) + r Ns + (r Ns) / 32 for the stores
+// (e0 = (j / Ns) Ns R + k with k < Ns), so every access of a butterfly is one base
+// address plus a constant offset.
+template <typename T, int R, int NTHR, int BPT, int SIGN, int LOG2P, int LOG2NS>
+__device__ __forceinline__ void stockham_stage_fixed(c2<T> *buf, int ld, int nlines,
+                                                     const c2<T> *__restrict__ tw) {
+    constexpr int LOG2R = (R == 2) ? 1 : (R == 4) ? 2 : 4;
+    constexpr int LOG2Q = LOG2P - LOG2R;
+    constexpr int Q = 1 << LOG2Q;
+    constexpr int Ns = 1 << LOG2NS;
+    constexpr int TWSHIFT = LOG2P - LOG2NS - LOG2R;
+    const int nb = nlines * Q;
+    c2<T> v[BPT][R];
+    int obase[BPT];
+#pragma unroll
+    for (int b = 0; b < BPT; ++b) {
+        const int f = threadIdx.x + b * NTHR;
+        obase[b] = -1;
+        if (f < nb) {
+            const int line = f >> LOG2Q;
+            const int j = f & (Q - 1);
+            const int k = j & (Ns - 1);
+            const c2<T> *pj = buf + line * ld + padx(j);
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[b][r] = pj[r * Q + ((r * Q) >> 5)];
+            if constexpr (LOG2NS > 0) {
+                const int kt = k << TWSHIFT;
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    c2<T> w = tw[r * kt];
+                    if constexpr (SIGN > 0) w.y = -w.y;
+                    v[b][r] = cmul<T>(v[b][r], w);
+                }
+            }
+            dftR<T, R, SIGN>(v[b]);
+            obase[b] = line * ld + padx(((j >> LOG2NS) << (LOG2NS + LOG2R)) + k);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < BPT; ++b) {
+        if (obase[b] >= 0) {
+            c2<T> *pe = buf + obase[b];
+#pragma unroll
+            for (int r = 0; r < R; ++r) pe[r * Ns + ((r * Ns) >> 5)] = v[b][r];
+        }
+    }
+    __syncthreads();
+}
+
+// lds_fft_dir for ODD = 1 and log2P = LOG2P fixed at compile time: radix-16 stages,
+// then radix 4 and 2, as there
+template <typename T, int NTHR, int BPT, int SIGN, int LOG2P, int LOG2NS = 0>
+__device__ __forceinline__ void lds_fft_fixed(c2<T> *buf, int ld, int nlines, const c2<T> *__restrict__ tw) {
+    constexpr int BPT16 = BPT / 4 > 0 ? BPT / 4 : 1;
+    if constexpr (LOG2P - LOG2NS >= 4) {
+        stockham_stage_fixed<T, 16, NTHR, BPT16, SIGN, LOG2P, LOG2NS>(buf, ld, nlines, tw);
+        lds_fft_fixed<T, NTHR, BPT, SIGN, LOG2P, LOG2NS + 4>(buf, ld, nlines, tw);
+    } else if constexpr (LOG2P - LOG2NS >= 2) {
+        stockham_stage_fixed<T, 4, NTHR, BPT, SIGN, LOG2P, LOG2NS>(buf, ld, nlines, tw);
+        lds_fft_fixed<T, NTHR, BPT, SIGN, LOG2P, LOG2NS + 2>(buf, ld, nlines, tw);
+    } else if constexpr (LOG2P - LOG2NS == 1) {
+        stockham_stage_fixed<T, 2, NTHR, 2 * BPT, SIGN, LOG2P, LOG2NS>(buf, ld, nlines, tw);
+    }
+}
+
+// Lines of 512 and 1024 points (the planes and padded images of the 512^2
+// workloads) take the compile-time stages; other lengths the general ones.  A
+// kernel that never sees such lines can leave them out (FIXED = false), which
+// spares its registers.
+template <typename T, int NTHR, int BPT, int ODD, int SIGN, bool FIXED>
+__device__ __forceinline__ void lds_fft_sel(c2<T> *buf, int ld, int nlines, int log2P,
+                                            const c2<T> *__restrict__ tw) {
+    if constexpr (ODD == 1 && FIXED) {
+        if (log2P == 10) return lds_fft_fixed<T, NTHR, BPT, SIGN, 10>(buf, ld, nlines, tw);
+        if (log2P == 9) return lds_fft_fixed<T, NTHR, BPT, SIGN, 9>(buf, ld, nlines, tw);
+    }
+    lds_fft_dir<T, NTHR, BPT, ODD, SIGN>(buf, ld, nlines, log2P, tw);
+}
+
+template <typename T, int NTHR, int BPT, int ODD = 1, bool FIXED = true>
 __device__ __forceinline__ void lds_fft(c2<T> *buf, int ld, int nlines, int log2P, int sign,
                                         const c2<T> *__restrict__ tw) {
-    if (sign < 0) lds_fft_dir<T, NTHR, BPT, ODD, -1>(buf, ld, nlines, log2P, tw);
-    else lds_fft_dir<T, NTHR, BPT, ODD, +1>(buf, ld, nlines, log2P, tw);
+    if (sign < 0) lds_fft_sel<T, NTHR, BPT, ODD, -1, FIXED>(buf, ld, nlines, log2P, tw);
+    else lds_fft_sel<T, NTHR, BPT, ODD, +1, FIXED>(buf, ld, nlines, log2P, tw);
 }
 
 // Element idx of a batch of lines of length L = ODD 2^log2P: line idx / L, element idx % L.
