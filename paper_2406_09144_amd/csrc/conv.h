@@ -236,7 +236,7 @@ __global__ __launch_bounds__(NTHR) void k_conv4_outer(const c2<T> *__restrict__ 
             buf[(gg * C + c) * ld + padx(n1)] = v;
         });
     __syncthreads();
-    lds_fft<T, NTHR, BPT>(buf, ld, nlines, log2L1, sign, twp);
+    lds_fft<T, NTHR, BPT, 1, kFixAll>(buf, ld, nlines, log2L1, sign, twp);
     // store: element k1 of line (g, c) to row L2 k1 + n2 (forward: times the twiddle
     // exp(-2 pi i n2 k1 / L) of the four-step split)
 #pragma unroll
@@ -298,7 +298,7 @@ __global__ __launch_bounds__(NTHR) void k_conv4_middle(c2<T> *__restrict__ Z, in
             buf[(gg * C + c) * ld + padx(e)] = v;
         });
     __syncthreads();
-    lds_fft<T, NTHR, BPT>(buf, ld, nlines, log2L2, -1, twp);
+    lds_fft<T, NTHR, BPT, 1, kFixAll>(buf, ld, nlines, log2L2, -1, twp);
     // the inverse split twiddles of this thread's stores, in flight during the
     // multiply and the inverse FFT
     c2<T> twr[EPT];
@@ -319,7 +319,7 @@ __global__ __launch_bounds__(NTHR) void k_conv4_middle(c2<T> *__restrict__ Z, in
         v = mk<T>(v.x * kv, v.y * kv);
     }
     __syncthreads();
-    lds_fft<T, NTHR, BPT>(buf, ld, nlines, log2L2, +1, twp);
+    lds_fft<T, NTHR, BPT, 1, kFixAll>(buf, ld, nlines, log2L2, +1, twp);
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
         const int idx = threadIdx.x + j * NTHR;

@@ -304,25 +304,48 @@ __device__ __forceinline__ void lds_fft_fixed(c2<T> *buf, int ld, int nlines, co
     }
 }
 
-// Lines of 512 and 1024 points (the planes and padded images of the 512^2
-// workloads) take the compile-time stages; other lengths the general ones.  A
-// kernel that never sees such lines can leave them out (FIXED = false), which
-// spares its registers.
-template <typename T, int NTHR, int BPT, int ODD, int SIGN, bool FIXED>
+// Lines of 2^p points take compile-time stages for the lengths in FIXSET (bit p),
+// other lengths the general ones.  Kernels compile 2^9 .. 2^13 (the padded images
+// and planes of the workloads); the four-step column passes also the short
+// sub-transforms.  Every length compiled adds code to the kernel, and lengths it
+// never sees cost registers and instruction cache.
+constexpr unsigned kFixLong = 0x3e00u;   // 2^9 .. 2^13
+constexpr unsigned kFixAll = 0x3fc0u;    // 2^6 .. 2^13
+
+template <typename T, int NTHR, int BPT, int SIGN, unsigned FIXSET, int LOG2P>
+__device__ __forceinline__ bool lds_fft_try(c2<T> *buf, int ld, int nlines, int log2P,
+                                            const c2<T> *__restrict__ tw) {
+    if constexpr ((FIXSET >> LOG2P) & 1u) {
+        if (log2P == LOG2P) {
+            lds_fft_fixed<T, NTHR, BPT, SIGN, LOG2P>(buf, ld, nlines, tw);
+            return true;
+        }
+    }
+    return false;
+}
+
+template <typename T, int NTHR, int BPT, int ODD, int SIGN, unsigned FIXSET>
 __device__ __forceinline__ void lds_fft_sel(c2<T> *buf, int ld, int nlines, int log2P,
                                             const c2<T> *__restrict__ tw) {
-    if constexpr (ODD == 1 && FIXED) {
-        if (log2P == 10) return lds_fft_fixed<T, NTHR, BPT, SIGN, 10>(buf, ld, nlines, tw);
-        if (log2P == 9) return lds_fft_fixed<T, NTHR, BPT, SIGN, 9>(buf, ld, nlines, tw);
+    if constexpr (ODD == 1 && FIXSET != 0u) {
+        if (lds_fft_try<T, NTHR, BPT, SIGN, FIXSET, 6>(buf, ld, nlines, log2P, tw) ||
+            lds_fft_try<T, NTHR, BPT, SIGN, FIXSET, 7>(buf, ld, nlines, log2P, tw) ||
+            lds_fft_try<T, NTHR, BPT, SIGN, FIXSET, 8>(buf, ld, nlines, log2P, tw) ||
+            lds_fft_try<T, NTHR, BPT, SIGN, FIXSET, 9>(buf, ld, nlines, log2P, tw) ||
+            lds_fft_try<T, NTHR, BPT, SIGN, FIXSET, 10>(buf, ld, nlines, log2P, tw) ||
+            lds_fft_try<T, NTHR, BPT, SIGN, FIXSET, 11>(buf, ld, nlines, log2P, tw) ||
+            lds_fft_try<T, NTHR, BPT, SIGN, FIXSET, 12>(buf, ld, nlines, log2P, tw) ||
+            lds_fft_try<T, NTHR, BPT, SIGN, FIXSET, 13>(buf, ld, nlines, log2P, tw))
+            return;
     }
     lds_fft_dir<T, NTHR, BPT, ODD, SIGN>(buf, ld, nlines, log2P, tw);
 }
 
-template <typename T, int NTHR, int BPT, int ODD = 1, bool FIXED = true>
+template <typename T, int NTHR, int BPT, int ODD = 1, unsigned FIXSET = kFixLong>
 __device__ __forceinline__ void lds_fft(c2<T> *buf, int ld, int nlines, int log2P, int sign,
                                         const c2<T> *__restrict__ tw) {
-    if (sign < 0) lds_fft_sel<T, NTHR, BPT, ODD, -1, FIXED>(buf, ld, nlines, log2P, tw);
-    else lds_fft_sel<T, NTHR, BPT, ODD, +1, FIXED>(buf, ld, nlines, log2P, tw);
+    if (sign < 0) lds_fft_sel<T, NTHR, BPT, ODD, -1, FIXSET>(buf, ld, nlines, log2P, tw);
+    else lds_fft_sel<T, NTHR, BPT, ODD, +1, FIXSET>(buf, ld, nlines, log2P, tw);
 }
 
 // Element idx of a batch of lines of length L = ODD 2^log2P: line idx / L, element idx % L.

@@ -1141,8 +1141,9 @@ __global__ __launch_bounds__(NTHR) void k_grid_rows(const c2<T> *__restrict__ pl
             },
             [&](int idx, c2<T> v) { buf[(idx >> log2nv) * ld + padx(idx & (nv - 1))] = v; });
         __syncthreads();
-        // the 1024-thread form runs rows of 8192 points and more only
-        lds_fft<T, NTHR, BPT, 1, (NTHR < 1024)>(buf, ld, nl, log2nv, +1, twp);
+        // compile-time stages for rows of 512 and 1024 points only (the 1024-thread
+        // form runs rows of 8192 points and more): this kernel is short of registers
+        lds_fft<T, NTHR, BPT, 1, (NTHR < 1024 ? 0x600u : 0u)>(buf, ld, nl, log2nv, +1, twp);
         for (int l = 0; l < nl; ++l) {
             const double wp = wplane[p0 + l];
             const c2<T> *line = buf + l * ld;
